@@ -1,0 +1,168 @@
+"""Core-hole and local-basis matrices for an L2,3 edge, by plain quadrature.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Builds, from the multiplet parameters alone:
+
+* the core matrix Hc = -(eps_c + chi) on the six 2p spin-orbitals, with
+  chi = zeta l.s (the spin-orbit term of H_h, section 2) and eps_c = 0;
+* the short-range interaction matrix on (core spin-orbital, d channel) pairs
+  (section 3.2.2: the local direct term is screened -- F2 -- and the exchange term is
+  bare -- G1, G3; F0 is the long-range W0 and is left out here);
+* dipole amplitudes <Y_2m | e.r^ | Y_1mc> for the initial vector (eq. loss.fcn,
+  dipole operator e.r).
+
+Index conventions: core index c = (m_c + 1) * 2 + sigma (sigma = 0 spin up),
+local channel mu = m + 2 for m = -2..2, pair index (c, mu) -> c * 5 + mu.
+
+Gaunt coefficients c^k(lm; l'm') = sqrt(4 pi / (2k+1)) Int Y*_{lm} Y_{k,m-m'} Y_{l'm'} dOmega are
+computed here by Gauss-Legendre x uniform-phi quadrature over the sphere (exact
+for these polynomial degrees), not by any closed form.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import sph_harm_y
+
+N_THETA = 24
+N_PHI = 48
+
+
+def _sphere_rule():
+    xs, ws = np.polynomial.legendre.leggauss(N_THETA)
+    theta = np.arccos(xs)
+    phi = 2.0 * math.pi * np.arange(N_PHI) / N_PHI
+    th, ph = np.meshgrid(theta, phi, indexing="ij")
+    wt = np.outer(ws, np.full(N_PHI, 2.0 * math.pi / N_PHI))
+    return th.ravel(), ph.ravel(), wt.ravel()
+
+
+_TH, _PH, _WT = _sphere_rule()
+
+
+def ylm(l, m):
+    """Complex spherical harmonic (Condon-Shortley phase) on the quadrature nodes."""
+    if abs(m) > l:
+        return np.zeros_like(_TH, dtype=np.complex128)
+    return sph_harm_y(l, m, _TH, _PH)
+
+
+def sphere_integral(f):
+    return np.sum(_WT * f)
+
+
+def gaunt(k, l, m, lp, mp):
+    """c^k(lm; l'm') by quadrature."""
+    q = m - mp
+    if abs(q) > k:
+        return 0.0
+    val = sphere_integral(np.conj(ylm(l, m)) * ylm(k, q) * ylm(lp, mp))
+    return float(math.sqrt(4.0 * math.pi / (2 * k + 1)) * val.real)
+
+
+def angular_momentum(l):
+    """(Lx, Ly, Lz) for angular momentum l in the basis m = -l..l, from the ladder
+    operators L+|m> = sqrt(l(l+1) - m(m+1)) |m+1>."""
+    ms = np.arange(-l, l + 1)
+    dim = 2 * l + 1
+    lz = np.diag(ms.astype(np.float64)).astype(np.complex128)
+    lp = np.zeros((dim, dim), dtype=np.complex128)
+    for i, m in enumerate(ms[:-1]):
+        lp[i + 1, i] = math.sqrt(l * (l + 1) - m * (m + 1))
+    lm = lp.conj().T
+    return 0.5 * (lp + lm), -0.5j * (lp - lm), lz
+
+
+def spin_orbit(l, zeta):
+    """chi = zeta l.s on |m, sigma> with index m_index * 2 + sigma."""
+    lx, ly, lz = angular_momentum(l)
+    sx = 0.5 * np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    sy = 0.5 * np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+    sz = 0.5 * np.array([[1, 0], [0, -1]], dtype=np.complex128)
+    return zeta * (np.kron(lx, sx) + np.kron(ly, sy) + np.kron(lz, sz))
+
+
+def core_matrix(mult):
+    """Hc = -(eps_c + chi) with eps_c = 0 (the core-hole Hamiltonian enters H_BSE as -H_h)."""
+    return -spin_orbit(1, mult["zeta"])
+
+
+def direct_matrix(f2, l_core=1, l_val=2):
+    """D[(m_c', m'), (m_c, m)] = F2 c^2(l_val m'; l_val m) c^2(l_core m_c'; l_core m_c),
+    nonzero only when m' - m = m_c' - m_c.  Index (m_c + l_core)*(2 l_val + 1) + (m + l_val)."""
+    nv = 2 * l_val + 1
+    ncr = 2 * l_core + 1
+    d = np.zeros((ncr * nv, ncr * nv))
+    for mcp in range(-l_core, l_core + 1):
+        for mp in range(-l_val, l_val + 1):
+            for mc in range(-l_core, l_core + 1):
+                for m in range(-l_val, l_val + 1):
+                    if mp - m != mcp - mc:
+                        continue
+                    d[(mcp + l_core) * nv + mp + l_val, (mc + l_core) * nv + m + l_val] = (
+                        f2 * gaunt(2, l_val, mp, l_val, m) * gaunt(2, l_core, mcp, l_core, mc))
+    return d
+
+
+def exchange_matrix(gks, l_core=1, l_val=2):
+    """X[(m_c', m'), (m_c, m)] = sum_k G^k c^k(l_val m'; l_core m_c') c^k(l_val m; l_core m_c),
+    nonzero only when m' - m_c' = m - m_c.  gks maps k -> G^k."""
+    nv = 2 * l_val + 1
+    ncr = 2 * l_core + 1
+    x = np.zeros((ncr * nv, ncr * nv))
+    for mcp in range(-l_core, l_core + 1):
+        for mp in range(-l_val, l_val + 1):
+            for mc in range(-l_core, l_core + 1):
+                for m in range(-l_val, l_val + 1):
+                    if mp - mcp != m - mc:
+                        continue
+                    s = 0.0
+                    for k, gk in gks.items():
+                        s += gk * gaunt(k, l_val, mp, l_core, mcp) * gaunt(k, l_val, m, l_core, mc)
+                    x[(mcp + l_core) * nv + mp + l_val, (mc + l_core) * nv + m + l_val] = s
+    return x
+
+
+def local_matrix(mult):
+    """K_loc on pairs ((m_c, sigma), m): -(D x I_spin) + (X x J_spin), J = all-ones 2x2.
+
+    The direct part is diagonal in spin; the exchange part couples every
+    (sigma, sigma') pair of the electron-hole spin (restricted spin model)."""
+    d = direct_matrix(mult["F2"])
+    x = exchange_matrix({1: mult["G1"], 3: mult["G3"]})
+    ncr, nv = 3, 5
+    kmat = np.zeros((6 * nv, 6 * nv), dtype=np.complex128)
+    for mcp in range(ncr):
+        for sp in range(2):
+            for mp in range(nv):
+                row = (mcp * 2 + sp) * nv + mp
+                for mc in range(ncr):
+                    for s in range(2):
+                        for m in range(nv):
+                            col = (mc * 2 + s) * nv + m
+                            val = x[mcp * nv + mp, mc * nv + m]
+                            if sp == s:
+                                val -= d[mcp * nv + mp, mc * nv + m]
+                            kmat[row, col] = val
+    return kmat
+
+
+def dipole_amplitudes(pol):
+    """d[m, m_c] = <Y_2m | e.r^ | Y_1mc> (radial integral 1), m = -2..2, m_c = -1..1."""
+    e = np.asarray(pol, dtype=np.float64)
+    rhat = np.stack([np.sin(_TH) * np.cos(_PH), np.sin(_TH) * np.sin(_PH), np.cos(_TH)])
+    edotr = np.tensordot(e, rhat, axes=1)
+    d = np.zeros((5, 3), dtype=np.complex128)
+    for m in range(-2, 3):
+        for mc in range(-1, 2):
+            d[m + 2, mc + 1] = sphere_integral(np.conj(ylm(2, m)) * edotr * ylm(1, mc))
+    return d
+
+
+def dipole_psi0(local_proj, pol):
+    """psi0[k, n, c = (m_c, sigma)] = sum_m conj(A[k, n, m]) d[m, m_c], the same for both spins."""
+    d = dipole_amplitudes(pol)
+    per_mc = np.einsum("knm,mc->knc", local_proj.conj(), d)     # [k, n, m_c]
+    return np.repeat(per_mc, 2, axis=2)

@@ -1,0 +1,215 @@
+"""Seeded synthetic inputs for the core-level BSE solver.
+
+This module is shared by the CPU oracle (``oracle/``) and by the GPU library
+tests and benchmark.  It draws random numbers and builds the *inputs* of the
+BSE stage -- the quantities that the paper's earlier stages (DFT, translator,
+screening) would otherwise supply:
+
+* quasiparticle energies E[k, n]             (stand-in for the DFT/GW stage)
+* periodic Bloch parts u_nk(x) on the x grid (stand-in for the DFT/OBF stage)
+* the radial screened core-hole potential W(r) (stand-in for the screening stage)
+* local-basis projector coefficients A[k, n, mu] ("precomputed and stored",
+  section 3.2.2 of the paper)
+* the initial exciton vector(s) psi0 (transition-operator output, eq. loss.fcn)
+* the energy grid and broadening of the spectrum.
+
+It deliberately holds none of the BSE method's arithmetic: no Hamiltonian
+pieces, no Fourier transforms, no Lanczos, no continued fraction, no angular
+algebra.  Multiplet parameters (zeta, F2, G1, G3) are passed on as plain numbers;
+each side builds its own matrices from them.
+
+Conventions shared by both sides (fixed by the paper's notation in section 3.2
+and by the published workload description):
+
+* energies in Hartree; 1 Ha = 27.211386245988 eV (CODATA 2018)
+* lengths in bohr; cubic cell of side ``a``; Gamma-centred, unshifted k grid
+  k = (2 pi / a) * (i / n_k) per axis, i = 0 .. n_k - 1
+* real-space points x = a * j / n_x per axis, j = 0 .. n_x - 1
+* flat grid indices are row-major with the last axis fastest
+* u[k, x, n] columns are orthonormal per k: sum_x |u|^2 = 1
+* exciton vectors are stored [k][n][c] (core index fastest)
+* complex Gaussian = (N(0,1) + i N(0,1)) / sqrt(2)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+HARTREE_EV = 27.211386245988
+RADIAL_POINTS = 64
+RADIAL_RMAX = 6.0
+
+
+@dataclass
+class Crystal:
+    """One BSE problem: the inputs of ``ocean_bse_create`` plus a spectrum request."""
+    name: str
+    a: float                      # cubic lattice constant, bohr
+    tau: np.ndarray               # core-site position, bohr, shape (3,)
+    nk: tuple                     # k grid (n1, n2, n3)
+    nx: tuple                     # real-space grid per cell (g1, g2, g3)
+    n_bands: int
+    n_core: int                   # 2 (1s, K edge) or 6 (2p, L2,3 edge)
+    energies: np.ndarray          # (Nk, Nb) Ha
+    u: np.ndarray                 # (Nk, Nx, Nb) complex128
+    w_r: np.ndarray               # (64,) bohr, ascending, w_r[0] = 0
+    w_val: np.ndarray             # (64,) Ha
+    local_proj: Optional[np.ndarray] = None   # (Nk, Nb, Nmu) complex128 or None
+    multiplet: Optional[dict] = None          # zeta, F2, G1, G3 in Ha (l_core=1, l_val=2)
+    psi0: Optional[np.ndarray] = None         # (n_vec, Nk, Nb, Nc) complex128, or None
+    polarisations: Optional[np.ndarray] = None  # (n_pol, 3) unit vectors for dipole psi0
+    n_steps: int = 100
+    gamma: float = 0.5 / HARTREE_EV           # Lorentzian HWHM, Ha
+    omega: np.ndarray = field(default_factory=lambda: np.zeros(0))  # Ha
+    eps: float = 5.0
+
+    @property
+    def n_k(self) -> int:
+        return int(np.prod(self.nk))
+
+    @property
+    def n_x(self) -> int:
+        return int(np.prod(self.nx))
+
+    @property
+    def n_local(self) -> int:
+        return 0 if self.local_proj is None else int(self.local_proj.shape[2])
+
+    @property
+    def dim(self) -> int:
+        return self.n_core * self.n_k * self.n_bands
+
+
+def complex_gaussian(rng: np.random.Generator, shape) -> np.ndarray:
+    """(N(0,1) + i N(0,1)) / sqrt(2), real part drawn first."""
+    re = rng.standard_normal(shape)
+    im = rng.standard_normal(shape)
+    return (re + 1j * im) / math.sqrt(2.0)
+
+
+def orthonormal_columns(z: np.ndarray) -> np.ndarray:
+    """Q of a reduced QR of z (columns orthonormal), with the phase of diag(R)
+    moved into Q so the result is unique."""
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r)
+    ph = np.where(np.abs(d) > 0, d / np.abs(d), 1.0)
+    return q * ph[None, :]
+
+
+def radial_table(eps: float) -> tuple[np.ndarray, np.ndarray]:
+    """W(r) = erf(r / 0.5) / (eps r) Ha on r_j = 6 j / 63 bohr; W(0) is the r -> 0 limit.
+
+    This stands in for the output of the screening stage (section 3.3)."""
+    r = RADIAL_RMAX * np.arange(RADIAL_POINTS) / (RADIAL_POINTS - 1)
+    w = np.empty_like(r)
+    w[0] = 2.0 / (math.sqrt(math.pi) * 0.5 * eps)
+    for j in range(1, RADIAL_POINTS):
+        w[j] = math.erf(r[j] / 0.5) / (eps * r[j])
+    return r, w
+
+
+def omega_grid(lo_ev: float, hi_ev: float, n: int = 2000) -> np.ndarray:
+    return np.linspace(lo_ev, hi_ev, n) / HARTREE_EV
+
+
+def make_crystal(name: str, *, a: float, tau, nk, nx, n_bands: int, n_core: int,
+                 e_range_ev: float, eps: float, seed: int, n_local: int = 0,
+                 multiplet_ev: Optional[dict] = None, psi0: str = "random",
+                 n_vec: int = 1, polarisations=None, n_steps: int = 100,
+                 gamma_ev: float = 0.5, omega_ev=(-20.0, 40.0), n_omega: int = 2000,
+                 u_override: Optional[np.ndarray] = None) -> Crystal:
+    """Draw one synthetic crystal.  Draw order: E, then U per k (real then
+    imaginary parts), then psi0 amplitudes, then the local projectors A."""
+    rng = np.random.default_rng(seed)
+    n_k = int(np.prod(nk))
+    n_x = int(np.prod(nx))
+    energies = np.sort(rng.uniform(0.0, e_range_ev, size=(n_k, n_bands)), axis=1) / HARTREE_EV
+    if u_override is not None:
+        u = u_override
+    else:
+        u = np.empty((n_k, n_x, n_bands), dtype=np.complex128)
+        for k in range(n_k):
+            u[k] = orthonormal_columns(complex_gaussian(rng, (n_x, n_bands)))
+    p0 = None
+    if psi0 == "random":
+        # dipole-like amplitudes M[k, n], identical for every core state (spin-
+        # independent transition operator), one independent draw per vector
+        p0 = np.empty((n_vec, n_k, n_bands, n_core), dtype=np.complex128)
+        for v in range(n_vec):
+            m = complex_gaussian(rng, (n_k, n_bands))
+            p0[v] = m[:, :, None]
+    elif psi0 == "random_full":
+        p0 = complex_gaussian(rng, (n_vec, n_k, n_bands, n_core))
+    local = None
+    if n_local > 0:
+        z = complex_gaussian(rng, (n_k * n_bands, n_local))
+        local = orthonormal_columns(z).reshape(n_k, n_bands, n_local)
+    mult = None
+    if multiplet_ev is not None:
+        mult = {key: val / HARTREE_EV for key, val in multiplet_ev.items()}
+    w_r, w_val = radial_table(eps)
+    pol = None if polarisations is None else np.asarray(polarisations, dtype=np.float64)
+    return Crystal(name=name, a=float(a), tau=np.asarray(tau, dtype=np.float64),
+                   nk=tuple(nk), nx=tuple(nx), n_bands=n_bands, n_core=n_core,
+                   energies=energies, u=u, w_r=w_r, w_val=w_val, local_proj=local,
+                   multiplet=mult, psi0=p0, polarisations=pol, n_steps=n_steps,
+                   gamma=gamma_ev / HARTREE_EV,
+                   omega=omega_grid(omega_ev[0], omega_ev[1], n_omega), eps=eps)
+
+
+L_EDGE_MULTIPLET_EV = {"zeta": 3.8, "F2": 8.0, "G1": 6.0, "G3": 3.5}
+XYZ_POLARISATIONS = np.eye(3)
+SRTIO3_A = 7.38
+
+
+def config1(seed: int = 0) -> Crystal:
+    """K edge, 1 site at the origin, a = 7.38 bohr, 2^3 k, 16 bands in [0, 30] eV,
+    8^3 x grid, eps = 5, complex-normal dipole amplitudes, 100 steps."""
+    return make_crystal("c1", a=SRTIO3_A, tau=(0.0, 0.0, 0.0), nk=(2, 2, 2), nx=(8, 8, 8),
+                        n_bands=16, n_core=2, e_range_ev=30.0, eps=5.0, seed=seed,
+                        psi0="random", n_steps=100, omega_ev=(-20.0, 40.0))
+
+
+def config2_shape(nk=(8, 8, 8), nx=(20, 20, 20), n_bands=96, seed: int = 0,
+                  eps: float = 6.0, n_steps: int = 300, psi0: str = "random", n_vec: int = 1,
+                  u_override=None, e_range_ev: float = 40.0) -> Crystal:
+    """Ti L2,3 edge in a 5-atom SrTiO3-shaped cubic cell (core site at the Ti
+    position (1/2,1/2,1/2) a): 2p core (6 spin-orbitals), d-channel local term,
+    zeta = 3.8, F2 = 8, G1 = 6, G3 = 3.5 eV.  Defaults give the full-size
+    workload (8^3 k, 96 bands, 20^3 x, H dimension 294912)."""
+    return make_crystal("c2", a=SRTIO3_A, tau=(0.5 * SRTIO3_A,) * 3, nk=nk, nx=nx,
+                        n_bands=n_bands, n_core=6, e_range_ev=e_range_ev, eps=eps, seed=seed,
+                        n_local=5, multiplet_ev=dict(L_EDGE_MULTIPLET_EV), psi0=psi0,
+                        n_vec=n_vec, polarisations=XYZ_POLARISATIONS, n_steps=n_steps,
+                        omega_ev=(-25.0, 55.0), u_override=u_override)
+
+
+def small_l_edge(seed: int = 1, nk=(2, 2, 2), nx=(6, 6, 6), n_bands=12, **kw) -> Crystal:
+    """A tiny L-edge crystal (dense H feasible) for parity and pin tests."""
+    return config2_shape(nk=nk, nx=nx, n_bands=n_bands, seed=seed, **kw)
+
+
+# --- device-side generation for the full-size workloads ---------------------------------
+
+def gpu_orthonormal_u(n_k: int, n_x: int, n_bands: int, seed: int, device="cuda"):
+    """U[k] = orthonormal columns of a complex Gaussian (n_x x n_bands) per k, drawn
+    with torch's device RNG and orthonormalised by two passes of Cholesky QR.
+    Used where a host QR of gigabytes would dominate the run; the oracle then
+    receives a host copy of exactly these values."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    u = torch.empty((n_k, n_x, n_bands), dtype=torch.complex128, device=device)
+    for k in range(n_k):
+        z = torch.randn((n_x, n_bands), dtype=torch.complex128, device=device, generator=g)
+        for _ in range(2):
+            gram = (z.conj().transpose(0, 1).contiguous() @ z)
+            gram = 0.5 * (gram + gram.conj().transpose(0, 1))
+            chol = torch.linalg.cholesky(gram)
+            z = torch.linalg.solve_triangular(chol.conj().transpose(0, 1).contiguous(), z,
+                                              upper=True, left=False)
+        u[k] = z
+    return u
