@@ -1,0 +1,202 @@
+/*
+ * ocean_bse.h -- C ABI of the MI355X (gfx950) core-level BSE solver library.
+ *
+ * The library evaluates the action of the Bethe-Salpeter Hamiltonian of a
+ * core-level excitation on exciton vectors, runs the Haydock (Lanczos) recursion
+ * with it, and turns the recursion coefficients into a spectrum, as stated in
+ * Gilmore et al., "Efficient implementation of core-excitation Bethe-Salpeter
+ * equation calculations":
+ *
+ *   sigma(w) ~ -(1/pi) Im <0| O+ G(w) O |0>,  G(w) = [w - H_BSE]^-1      (section 2, eq. loss.fcn)
+ *   H_BSE = H_e - H_h - V_D + V_X                                         (section 2, eq. H_BSE)
+ *   the exciton vector psi_{alpha,n,k}                                    (section 3.2)
+ *   W0 (long-range direct) applied as in Algorithm 1                      (section 3.2.1)
+ *   short-range direct + exchange through a local basis                   (section 3.2.2, eq. local_basis)
+ *   the Haydock iteration psi^{i+1} = H psi^i                             (section 3.2, eq. haydock1)
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Complex numbers are pairs of doubles (re, im), i.e. C99 double _Complex /
+ *    numpy complex128 / torch.complex128 memory layout.
+ *  - Energies in Hartree, lengths in bohr.
+ *  - Grids: orthorhombic cell with edge lengths cell[d]; Gamma-centred unshifted
+ *    k grid k_d = 2 pi i_d / (nk_d cell_d); real-space points x_d = cell_d j_d / nx_d.
+ *    Flat grid indices are row-major with the last axis fastest.
+ *  - An exciton vector is stored [k][n][c]: k-point slowest, core index c fastest,
+ *    Nk*Nb*Nc complex numbers.  n_vec vectors are stored one after another.
+ *  - Core index for an L2,3 edge: c = (m_c + 1) * 2 + sigma (sigma = 0 spin up);
+ *    for a K edge: c = sigma.  Local channel index mu = m + 2 (d channel, m = -2..2).
+ *  - Return codes: 0 = OK, > 0 informational, < 0 error.  After an error,
+ *    ocean_last_error() returns a message for the calling thread.  No entry
+ *    point aborts or throws across the ABI.
+ *  - Device pointers are HIP device allocations on the current device.  All
+ *    device work of a handle is enqueued on the handle's stream; entry points
+ *    that return host results synchronise that stream first.
+ *  - Handles are not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef OCEAN_BSE_H
+#define OCEAN_BSE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ocean_bse_s* ocean_bse_t;
+
+enum {
+    OCEAN_OK = 0,
+    OCEAN_INFO_INVARIANT_SUBSPACE = 1, /* Haydock stopped early: b_{i+1} ~ 0 */
+    OCEAN_ERR_INVALID_ARG = -1,
+    OCEAN_ERR_OUT_OF_MEMORY = -2,
+    OCEAN_ERR_DEVICE = -3,
+    OCEAN_ERR_UNSUPPORTED = -4
+};
+
+/* Storage / arithmetic precision of the two band-projection contractions
+ * (Algorithm 1 lines 2 and 6).  Everything else -- the diagonal, core and local
+ * terms, the Lanczos inner products, norms, coefficients and the continued
+ * fraction -- is FP64 in every mode. */
+enum {
+    OCEAN_PREC_FP64 = 0,       /* u_nk in FP64, FP64 MFMA */
+    OCEAN_PREC_FP32 = 1,       /* u_nk stored FP32, FP32 MFMA, FP32 accumulation */
+    OCEAN_PREC_SPLIT_BF16 = 2  /* u_nk stored as bf16 hi + lo, 3-product compensated bf16 MFMA, FP32 accumulation */
+};
+
+/* ocean_bse_desc.flags */
+#define OCEAN_FLAG_BORROW_DEVICE_U 0x1u  /* desc.u is a device pointer: in FP64 mode the handle uses it in
+                                            place (it must outlive the handle); in FP32 mode it is
+                                            only read during ocean_bse_create */
+#define OCEAN_FLAG_CHECK_INPUTS    0x2u  /* scan inputs for NaN/Inf and check Hermiticity of the small matrices */
+
+/* ocean_haydock flags */
+#define OCEAN_HAYDOCK_REORTH 0x1u  /* full re-orthogonalisation (two classical Gram-Schmidt passes) each step */
+
+/* ocean_spectrum terminators */
+enum { OCEAN_TERM_NONE = 0, OCEAN_TERM_SQRT = 1 };
+
+/* Description of one crystal / core site (the inputs of the BSE stage, section 2
+ * and section 3.2).  All host arrays are copied by ocean_bse_create; the caller may
+ * free them when it returns. */
+typedef struct {
+    int nk[3];            /* k grid (and Born-von-Karman supercell) n1 x n2 x n3, each >= 1 */
+    int nx[3];            /* real-space grid of one cell g1 x g2 x g3, each >= 1 */
+    int n_bands;          /* Nb >= 1 conduction bands per k */
+    int n_core;           /* Nc >= 1 core states (2: 1s with spin, 6: 2p with spin) */
+    int n_local;          /* Nmu >= 0 local channels; 0 disables the short-range term */
+    double cell[3];       /* orthorhombic cell edge lengths, bohr (> 0) */
+    double tau[3];        /* absorbing-site position, bohr */
+    const double* energies;   /* [Nk][Nb] real, Ha: H_e eigenvalues E_nk (section 2) */
+    const double* u;          /* [Nk][Nx][Nb] complex: periodic Bloch parts u_nk(x), columns
+                                 orthonormal per k (sum_x |u|^2 = 1).  Host pointer, or a
+                                 device pointer with OCEAN_FLAG_BORROW_DEVICE_U. */
+    int n_wr;                 /* number of radial table points, >= 2 */
+    const double* w_r;        /* [n_wr] radii, bohr: uniform, w_r[0] = 0, ascending */
+    const double* w_val;      /* [n_wr] W0(r), Ha (section 3.2.1); linear interpolation
+                                 between nodes and W(r_max) r_max / r beyond the last node */
+    const double* local_proj; /* [Nk][Nb][Nmu] complex A^{mu}_{nk} (eq. local_basis) or NULL */
+    const double* local_mat;  /* [(Nc Nmu)^2] complex, row-major over pairs (c, mu) -> c*Nmu+mu:
+                                 the short-range direct + exchange matrix (section 3.2.2), Hermitian, or NULL */
+    const double* core_mat;   /* [Nc^2] complex, row-major: -(eps_c + chi) acting on the core index
+                                 (the -H_h term of eq. H_BSE), Hermitian, or NULL */
+    int precision;            /* OCEAN_PREC_* */
+    unsigned flags;           /* OCEAN_FLAG_* */
+} ocean_bse_desc;
+
+/* Create a solver handle: uploads and converts u_nk, builds the W(x, R) table of
+ * the Born-von-Karman supercell (minimum image, section 3.2.1) and the phase
+ * tables of Algorithm 1.  stream: a hipStream_t to enqueue on, or NULL for a
+ * stream owned by the handle.  On success *out is a new handle.
+ * Errors: INVALID_ARG (bad sizes, NULL required arrays, NaN with CHECK_INPUTS,
+ * non-uniform radial grid), OUT_OF_MEMORY (device allocation failed or would
+ * exceed OCEAN_MAX_DEVICE_BYTES if that environment variable is set), DEVICE. */
+int ocean_bse_create(const ocean_bse_desc* desc, void* stream, ocean_bse_t* out);
+
+/* Release every device allocation of the handle (borrowed u is not freed). */
+void ocean_bse_destroy(ocean_bse_t h);
+
+/* Dimension Nk*Nb*Nc of one exciton vector (complex elements), or < 0 on error. */
+long long ocean_bse_dim(ocean_bse_t h);
+
+/* y = H_BSE x for n_vec >= 1 vectors (section 3.2: the sum of the diagonal,
+ * core-matrix, long-range W0 of Algorithm 1, and short-range local pieces).
+ * x_dev, y_dev: device arrays of n_vec * dim complex numbers, layout [v][k][n][c];
+ * they must not overlap.  Enqueued on the handle's stream; returns without
+ * synchronising.  Errors: INVALID_ARG (NULL pointers, n_vec < 1), OUT_OF_MEMORY
+ * (workspace growth), DEVICE (launch failure). */
+int ocean_bse_apply(ocean_bse_t h, const double* x_dev, double* y_dev, int n_vec);
+
+/* Haydock recursion (section 3.2, eq. haydock1, as the three-term Lanczos
+ * recursion) for n_vec independent starting vectors psi0_dev ([v][k][n][c]
+ * complex, device, not modified):
+ *   v_0 = psi0/|psi0|, b_0 = 0;  w = H v_i;  a_i = Re<v_i|w>;
+ *   w -= a_i v_i + b_i v_{i-1};  b_{i+1} = |w|;  v_{i+1} = w / b_{i+1}.
+ * Host outputs: a[v*n_steps + i] = a_i, b[v*n_steps + i] = b_{i+1} for i < n_steps,
+ * norm2[v] = |psi0_v|^2, steps_done[v] = completed steps.  A vector stops early
+ * (its remaining a, b entries are 0) when b_{i+1} <= 1e-14 max(|a_0..a_i|, b_1..b_i);
+ * the call then returns OCEAN_INFO_INVARIANT_SUBSPACE.  All inner products and
+ * norms are FP64 with a fixed reduction order (bitwise reproducible run to run).
+ * flags: OCEAN_HAYDOCK_REORTH.  Synchronises the handle's stream.
+ * Errors: INVALID_ARG (NULL pointers, n_vec < 1, n_steps < 1, psi0 = 0),
+ * OUT_OF_MEMORY, DEVICE. */
+int ocean_haydock(ocean_bse_t h, const double* psi0_dev, int n_vec, int n_steps, unsigned flags,
+                  double* a, double* b, double* norm2, int* steps_done);
+
+/* Spectra from Haydock coefficients (section 2, eq. loss.fcn with
+ * G = [w - H]^-1 as a continued fraction), evaluated on the GPU in FP64:
+ *   sigma(w) = -(1/pi) norm2 Im g(w + i gamma),
+ *   g(z) = 1/(z - a_0 - b_1^2/(z - a_1 - ... - b_{N-1}^2/(z - a_{N-1} - b_N^2 t(z)))).
+ * Host inputs: a, b [n_spec][n_steps] as written by ocean_haydock, n_used[s]
+ * (levels to use, <= n_steps; NULL = n_steps), norm2 [n_spec], omega [n_omega] (Ha).
+ * gamma (Ha, > 0) is the Lorentzian half width.  terminator: OCEAN_TERM_NONE (t = 0)
+ * or OCEAN_TERM_SQRT (constant-chain square-root terminator with a_inf, b_inf
+ * the means of the last 16 used a_i and b_{i+1}; the root with Im t <= 0).
+ * Host output sigma [n_spec][n_omega].  Synchronous; uses its own stream.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+int ocean_spectrum(const double* a, const double* b, const int* n_used, const double* norm2,
+                   int n_spec, int n_steps, int terminator, const double* omega, int n_omega,
+                   double gamma, double* sigma);
+
+/* Host helper: the L2,3-edge (2p core, d channel) matrices for ocean_bse_desc
+ * from the spin-orbit parameter zeta and the Slater integrals F2 (screened
+ * direct) and G1, G3 (bare exchange), all in Ha (section 2: H_h, V_D, V_X;
+ * section 3.2.2: multipole expansion with selection rules).
+ * core_mat [6*6] complex = -chi with chi = zeta l.s; local_mat [30*30] complex =
+ * -(D x I_spin) + (X x J_spin) with D = F2 c^2(2m';2m) c^2(1mc';1mc) and
+ * X = sum_{k=1,3} G^k c^k(2m';1mc') c^k(2m;1mc), c^k the Gaunt coefficients.
+ * Either output may be NULL.  Errors: INVALID_ARG. */
+int ocean_multiplet_matrices(double zeta, double F2, double G1, double G3,
+                             double* core_mat, double* local_mat);
+
+/* Host helper: dipole amplitudes d[m+2][mc+1] = <Y_2m| e.r^ |Y_1mc> (radial
+ * integral 1) for a polarisation e[3] (section 2: O = e.r for XAS).  d is [5][3]
+ * complex.  Errors: INVALID_ARG. */
+int ocean_dipole_amplitudes(const double* e, double* d);
+
+/* Initial vectors O|0> for an L2,3 edge on the device (section 2, eq. loss.fcn;
+ * eq. local_basis): psi0[p][k][n][(mc, s)] = sum_m conj(A[k][n][m]) d_p[m][mc] for
+ * n_pol polarisations pol[p][3], the same for both spins.  Needs Nc = 6 and
+ * Nmu = 5.  psi0_dev: device, n_pol * dim complex.  Enqueued on the handle's
+ * stream.  Errors: INVALID_ARG, UNSUPPORTED (other edge shapes), DEVICE. */
+int ocean_dipole_psi0(ocean_bse_t h, const double* pol, int n_pol, double* psi0_dev);
+
+/* Per-kernel timing.  While enabled, every launch of the handle is bracketed by
+ * HIP events on the handle's stream and its duration is accumulated per kernel
+ * name.  ocean_bse_kernel_times copies up to max_entries (name, total ms, launch
+ * count) triples; names are static strings owned by the library.  Returns the
+ * number of entries, or < 0 on error.  Enabling or resetting clears the totals. */
+int ocean_bse_set_profiling(ocean_bse_t h, int enable);
+int ocean_bse_kernel_times(ocean_bse_t h, const char** names, double* total_ms,
+                           long long* counts, int max_entries);
+
+/* Device bytes currently held by the handle (inputs, converted copies, tables,
+ * workspace), or < 0 on error. */
+long long ocean_bse_device_bytes(ocean_bse_t h);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* ocean_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCEAN_BSE_H */

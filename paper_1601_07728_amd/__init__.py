@@ -1,0 +1,311 @@
+"""MI355X (gfx950) core-level BSE solver: Python binding of libocean_bse.so.
+
+Thin ctypes marshalling over the C ABI declared in include/ocean_bse.h: every
+computation runs in the library's HIP kernels.  PyTorch is used only to hold
+device memory (exciton vectors are torch.complex128 CUDA tensors whose
+data_ptr() is handed to the library).  If the shared library has not been
+built, importing works but every call raises RuntimeError -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libocean_bse.so")
+
+OK = 0
+INFO_INVARIANT_SUBSPACE = 1
+ERR_INVALID_ARG = -1
+ERR_OUT_OF_MEMORY = -2
+ERR_DEVICE = -3
+ERR_UNSUPPORTED = -4
+
+PREC_FP64 = 0
+PREC_FP32 = 1
+PREC_SPLIT_BF16 = 2
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16}
+
+FLAG_BORROW_DEVICE_U = 0x1
+FLAG_CHECK_INPUTS = 0x2
+HAYDOCK_REORTH = 0x1
+TERM_NONE = 0
+TERM_SQRT = 1
+
+EXPORTED = [
+    "ocean_bse_create", "ocean_bse_destroy", "ocean_bse_dim", "ocean_bse_apply", "ocean_haydock",
+    "ocean_spectrum", "ocean_multiplet_matrices", "ocean_dipole_amplitudes", "ocean_dipole_psi0",
+    "ocean_bse_set_profiling", "ocean_bse_kernel_times", "ocean_bse_device_bytes",
+    "ocean_last_error",
+]
+
+
+class OceanError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("nk", ctypes.c_int * 3), ("nx", ctypes.c_int * 3), ("n_bands", ctypes.c_int),
+        ("n_core", ctypes.c_int), ("n_local", ctypes.c_int), ("cell", ctypes.c_double * 3),
+        ("tau", ctypes.c_double * 3), ("energies", ctypes.c_void_p), ("u", ctypes.c_void_p),
+        ("n_wr", ctypes.c_int), ("w_r", ctypes.c_void_p), ("w_val", ctypes.c_void_p),
+        ("local_proj", ctypes.c_void_p), ("local_mat", ctypes.c_void_p),
+        ("core_mat", ctypes.c_void_p), ("precision", ctypes.c_int), ("flags", ctypes.c_uint),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ci, cd, cu = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint
+    ll = ctypes.c_longlong
+    L.ocean_bse_create.argtypes = [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]
+    L.ocean_bse_create.restype = ci
+    L.ocean_bse_destroy.argtypes = [vp]
+    L.ocean_bse_destroy.restype = None
+    L.ocean_bse_dim.argtypes = [vp]
+    L.ocean_bse_dim.restype = ll
+    L.ocean_bse_device_bytes.argtypes = [vp]
+    L.ocean_bse_device_bytes.restype = ll
+    L.ocean_bse_apply.argtypes = [vp, vp, vp, ci]
+    L.ocean_bse_apply.restype = ci
+    L.ocean_haydock.argtypes = [vp, vp, ci, ci, cu, vp, vp, vp, vp]
+    L.ocean_haydock.restype = ci
+    L.ocean_spectrum.argtypes = [vp, vp, vp, vp, ci, ci, ci, vp, ci, cd, vp]
+    L.ocean_spectrum.restype = ci
+    L.ocean_multiplet_matrices.argtypes = [cd, cd, cd, cd, vp, vp]
+    L.ocean_multiplet_matrices.restype = ci
+    L.ocean_dipole_amplitudes.argtypes = [vp, vp]
+    L.ocean_dipole_amplitudes.restype = ci
+    L.ocean_dipole_psi0.argtypes = [vp, vp, ci, vp]
+    L.ocean_dipole_psi0.restype = ci
+    L.ocean_bse_set_profiling.argtypes = [vp, ci]
+    L.ocean_bse_set_profiling.restype = ci
+    L.ocean_bse_kernel_times.argtypes = [vp, vp, vp, vp, ci]
+    L.ocean_bse_kernel_times.restype = ci
+    L.ocean_last_error.argtypes = []
+    L.ocean_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int, allow_info: bool = False) -> int:
+    if rc < 0 or (rc > 0 and not allow_info):
+        raise OceanError(rc, lib().ocean_last_error().decode())
+    return rc
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _host_c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def _host_f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _device_sync():
+    """The library enqueues on its own stream: order it against torch's work."""
+    import torch
+    torch.cuda.synchronize()
+
+
+def _dev_ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor")
+    if t.dtype != torch.complex128:
+        raise ValueError("exciton vectors are torch.complex128")
+    return t.data_ptr()
+
+
+def multiplet_matrices(zeta: float, f2: float, g1: float, g3: float):
+    """L2,3-edge core matrix (6x6) and local interaction matrix (30x30), Ha."""
+    core = np.zeros((6, 6), dtype=np.complex128)
+    loc = np.zeros((30, 30), dtype=np.complex128)
+    _check(lib().ocean_multiplet_matrices(zeta, f2, g1, g3, _ptr(core), _ptr(loc)))
+    return core, loc
+
+
+def dipole_amplitudes(pol) -> np.ndarray:
+    e = _host_f64(pol)
+    d = np.zeros((5, 3), dtype=np.complex128)
+    _check(lib().ocean_dipole_amplitudes(_ptr(e), _ptr(d)))
+    return d
+
+
+def spectrum(a, b, norm2, omega, gamma: float, terminator: str = "none", n_used=None) -> np.ndarray:
+    """Continued-fraction spectra on the GPU.  a, b: [n_spec, n_steps]; norm2: [n_spec]."""
+    a = _host_f64(np.atleast_2d(a))
+    b = _host_f64(np.atleast_2d(b))
+    n2 = _host_f64(np.atleast_1d(norm2))
+    om = _host_f64(omega)
+    n_spec, n_steps = a.shape
+    used = None if n_used is None else np.ascontiguousarray(np.atleast_1d(n_used), dtype=np.int32)
+    sig = np.zeros((n_spec, len(om)))
+    term = {"none": TERM_NONE, "sqrt": TERM_SQRT}[terminator]
+    _check(lib().ocean_spectrum(_ptr(a), _ptr(b), _ptr(used), _ptr(n2), n_spec, n_steps, term,
+                                _ptr(om), len(om), float(gamma), _ptr(sig)))
+    return sig
+
+
+class Bse:
+    """One solver handle (ocean_bse_create ... ocean_bse_destroy)."""
+
+    def __init__(self, *, nk, nx, cell, tau, energies, u, w_r, w_val, n_core: int,
+                 local_proj=None, local_mat=None, core_mat=None, precision: str = "fp64",
+                 check_inputs: bool = False, stream=None):
+        import torch
+        nk = tuple(int(v) for v in nk)
+        nx = tuple(int(v) for v in nx)
+        cell = np.broadcast_to(np.asarray(cell, dtype=np.float64), (3,))
+        self._keep = []
+        e = _host_f64(energies)
+        n_bands = e.shape[-1]
+        flags = FLAG_CHECK_INPUTS if check_inputs else 0
+        if isinstance(u, torch.Tensor):
+            if not u.is_cuda:
+                u = u.numpy()
+            else:
+                flags |= FLAG_BORROW_DEVICE_U
+        if isinstance(u, np.ndarray) or not isinstance(u, torch.Tensor):
+            uh = _host_c128(u)
+            uptr = _ptr(uh)
+            self._keep.append(uh)
+        else:
+            if u.dtype != torch.complex128 or not u.is_contiguous():
+                raise ValueError("device u must be a contiguous complex128 tensor")
+            uptr = ctypes.c_void_p(u.data_ptr())
+            self._u_dev = u
+        wr, wv = _host_f64(w_r), _host_f64(w_val)
+        lp = None if local_proj is None else _host_c128(local_proj)
+        lm = None if local_mat is None else _host_c128(local_mat)
+        cm = None if core_mat is None else _host_c128(core_mat)
+        d = Desc()
+        d.nk[:] = nk
+        d.nx[:] = nx
+        d.n_bands = n_bands
+        d.n_core = int(n_core)
+        d.n_local = 0 if lp is None else lp.shape[-1]
+        d.cell[:] = [float(v) for v in cell]
+        d.tau[:] = [float(v) for v in np.asarray(tau, dtype=np.float64)]
+        d.energies = _ptr(e)
+        d.u = uptr
+        d.n_wr = len(wr)
+        d.w_r, d.w_val = _ptr(wr), _ptr(wv)
+        d.local_proj, d.local_mat, d.core_mat = _ptr(lp), _ptr(lm), _ptr(cm)
+        d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        d.flags = flags
+        h = ctypes.c_void_p()
+        st = None if stream is None else ctypes.c_void_p(stream)
+        if flags & FLAG_BORROW_DEVICE_U:
+            _device_sync()
+        _check(lib().ocean_bse_create(ctypes.byref(d), st, ctypes.byref(h)))
+        self._h = h
+        self.nk, self.nx, self.n_bands, self.n_core = nk, nx, n_bands, int(n_core)
+        self.n_k = int(np.prod(nk))
+        self.dim = int(lib().ocean_bse_dim(h))
+        self.precision = precision
+
+    @classmethod
+    def from_crystal(cls, cr, precision: str = "fp64", with_local: bool = True, u=None, **kw):
+        """Convenience constructor from a synth.Crystal (inputs only; the multiplet
+        matrices are built by this library's own helper)."""
+        core_mat = local_mat = None
+        lp = None
+        if cr.multiplet is not None:
+            m = cr.multiplet
+            core_mat, local_mat = multiplet_matrices(m["zeta"], m["F2"], m["G1"], m["G3"])
+            if with_local and cr.local_proj is not None:
+                lp = cr.local_proj
+            else:
+                local_mat = None
+        return cls(nk=cr.nk, nx=cr.nx, cell=cr.a, tau=cr.tau, energies=cr.energies,
+                   u=cr.u if u is None else u, w_r=cr.w_r, w_val=cr.w_val, n_core=cr.n_core,
+                   local_proj=lp, local_mat=local_mat, core_mat=core_mat, precision=precision, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ocean_bse_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, x, y=None, sync: bool = True):
+        """y = H x for x of shape [n_vec, Nk, Nb, Nc] (or [Nk, Nb, Nc]) complex128 on the GPU.
+        With sync=False the caller orders the library's stream (e.g. torch.cuda.synchronize())."""
+        import torch
+        nv = x.numel() // self.dim
+        if nv * self.dim != x.numel() or nv < 1:
+            raise ValueError("x size is not a multiple of the vector dimension")
+        if y is None:
+            y = torch.empty_like(x)
+        if sync:
+            _device_sync()
+        _check(lib().ocean_bse_apply(self._h, _dev_ptr(x), _dev_ptr(y), nv))
+        if sync:
+            _device_sync()
+        return y
+
+    def haydock(self, psi0, n_steps: int, reorth: bool = False):
+        """Run the recursion; returns (a [nv, N], b [nv, N], norm2 [nv], steps_done [nv], rc)."""
+        nv = psi0.numel() // self.dim
+        if nv * self.dim != psi0.numel() or nv < 1:
+            raise ValueError("psi0 size is not a multiple of the vector dimension")
+        a = np.zeros((nv, n_steps))
+        b = np.zeros((nv, n_steps))
+        n2 = np.zeros(nv)
+        sd = np.zeros(nv, dtype=np.int32)
+        _device_sync()
+        rc = lib().ocean_haydock(self._h, _dev_ptr(psi0), nv, int(n_steps),
+                                 HAYDOCK_REORTH if reorth else 0, _ptr(a), _ptr(b), _ptr(n2), _ptr(sd))
+        _check(rc, allow_info=True)
+        return a, b, n2, sd, rc
+
+    def dipole_psi0(self, pols):
+        import torch
+        p = _host_f64(np.atleast_2d(pols))
+        out = torch.empty((p.shape[0], self.n_k, self.n_bands, self.n_core), dtype=torch.complex128,
+                          device="cuda")
+        _device_sync()
+        _check(lib().ocean_dipole_psi0(self._h, _ptr(p), p.shape[0], _dev_ptr(out)))
+        return out
+
+    def set_profiling(self, on: bool):
+        _check(lib().ocean_bse_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_times(self) -> dict:
+        n = lib().ocean_bse_kernel_times(self._h, None, None, None, 0)
+        _check(min(n, 0))
+        names = (ctypes.c_char_p * max(n, 1))()
+        ms = np.zeros(max(n, 1))
+        cnt = np.zeros(max(n, 1), dtype=np.int64)
+        lib().ocean_bse_kernel_times(self._h, names, _ptr(ms), _ptr(cnt), n)
+        return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+    @property
+    def device_bytes(self) -> int:
+        return int(lib().ocean_bse_device_bytes(self._h))

@@ -1,0 +1,125 @@
+// Host helpers for L2,3 edges: the core spin-orbit matrix, the short-range
+// direct/exchange matrix on (core spin-orbital, d channel) pairs, and dipole
+// amplitudes.  Angular factors use closed forms: Wigner 3j symbols from the
+// Racah formula and the standard Gaunt-coefficient identity
+//   c^k(lm; l'm') = (-1)^m sqrt((2l+1)(2l'+1)) (l k l'; 0 0 0) (l k l'; -m m-m' m').
+// Physics: section 2 (H_h = eps_c + chi - i Gamma; V_D screened, V_X bare) and
+// section 3.2.2 (multipole expansion of the short-range terms with selection rules).
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+double fact(int n) {
+    double r = 1.0;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+}
+
+// Wigner 3j symbol for integer arguments (Racah formula).
+double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3) {
+    if (m1 + m2 + m3 != 0) return 0.0;
+    if (j3 < std::abs(j1 - j2) || j3 > j1 + j2) return 0.0;
+    if (std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(m3) > j3) return 0.0;
+    const double tri = fact(j1 + j2 - j3) * fact(j1 - j2 + j3) * fact(-j1 + j2 + j3) / fact(j1 + j2 + j3 + 1);
+    const double pre = std::sqrt(tri * fact(j1 + m1) * fact(j1 - m1) * fact(j2 + m2) * fact(j2 - m2) *
+                                 fact(j3 + m3) * fact(j3 - m3));
+    const int tmin = std::max(0, std::max(j2 - j3 - m1, j1 - j3 + m2));
+    const int tmax = std::min(j1 + j2 - j3, std::min(j1 - m1, j2 + m2));
+    double s = 0.0;
+    for (int t = tmin; t <= tmax; ++t) {
+        const double den = fact(t) * fact(j3 - j2 + t + m1) * fact(j3 - j1 + t - m2) * fact(j1 + j2 - j3 - t) *
+                           fact(j1 - t - m1) * fact(j2 - t + m2);
+        s += ((t & 1) ? -1.0 : 1.0) / den;
+    }
+    const int ph = j1 - j2 - m3;
+    return ((ph & 1) ? -1.0 : 1.0) * pre * s;
+}
+
+double gaunt_ck(int k, int l, int m, int lp, int mp) {
+    const int q = m - mp;
+    if (std::abs(q) > k) return 0.0;
+    const double sgn = (m & 1) ? -1.0 : 1.0;
+    return sgn * std::sqrt((2.0 * l + 1) * (2.0 * lp + 1)) * wigner3j(l, k, lp, 0, 0, 0) *
+           wigner3j(l, k, lp, -m, q, mp);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ocean_multiplet_matrices(double zeta, double F2, double G1, double G3, double* core_mat,
+                             double* local_mat) {
+    if (!std::isfinite(zeta) || !std::isfinite(F2) || !std::isfinite(G1) || !std::isfinite(G3)) {
+        ocean::set_error("ocean_multiplet_matrices: parameters must be finite");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    const int lc = 1, lv = 2;
+    if (core_mat) {
+        // -chi, chi = zeta l.s on |m_c, sigma>, index (m_c + 1) * 2 + sigma (sigma 0 = up)
+        // <m s|l.s|m s> = m s_z;  <m+1, dn|l.s|m, up> = <m, up|l.s|m+1, dn> = sqrt(l(l+1)-m(m+1))/2
+        for (int i = 0; i < 72; ++i) core_mat[i] = 0.0;
+        auto idx = [](int mc, int s) { return (mc + 1) * 2 + s; };
+        for (int mc = -lc; mc <= lc; ++mc) {
+            core_mat[2 * (idx(mc, 0) * 6 + idx(mc, 0))] = -zeta * 0.5 * mc;
+            core_mat[2 * (idx(mc, 1) * 6 + idx(mc, 1))] = zeta * 0.5 * mc;
+            if (mc < lc) {
+                const double off = -zeta * 0.5 * std::sqrt((double)(lc * (lc + 1) - mc * (mc + 1)));
+                core_mat[2 * (idx(mc + 1, 1) * 6 + idx(mc, 0))] = off;
+                core_mat[2 * (idx(mc, 0) * 6 + idx(mc + 1, 1))] = off;
+            }
+        }
+    }
+    if (local_mat) {
+        // pairs ((m_c, sigma), m) -> ((m_c + 1) * 2 + sigma) * 5 + (m + 2)
+        for (int i = 0; i < 30 * 30 * 2; ++i) local_mat[i] = 0.0;
+        for (int mcp = -lc; mcp <= lc; ++mcp)
+            for (int sp = 0; sp < 2; ++sp)
+                for (int mp = -lv; mp <= lv; ++mp) {
+                    const int row = ((mcp + 1) * 2 + sp) * 5 + (mp + 2);
+                    for (int mc = -lc; mc <= lc; ++mc)
+                        for (int s = 0; s < 2; ++s)
+                            for (int m = -lv; m <= lv; ++m) {
+                                const int col = ((mc + 1) * 2 + s) * 5 + (m + 2);
+                                double v = 0.0;
+                                // screened direct (F2), diagonal in spin, m' - m = m_c' - m_c
+                                if (sp == s && mp - m == mcp - mc)
+                                    v -= F2 * gaunt_ck(2, lv, mp, lv, m) * gaunt_ck(2, lc, mcp, lc, mc);
+                                // bare exchange (G1, G3), all spin pairs, m' - m_c' = m - m_c
+                                if (mp - mcp == m - mc)
+                                    v += G1 * gaunt_ck(1, lv, mp, lc, mcp) * gaunt_ck(1, lv, m, lc, mc) +
+                                         G3 * gaunt_ck(3, lv, mp, lc, mcp) * gaunt_ck(3, lv, m, lc, mc);
+                                local_mat[2 * (row * 30 + col)] = v;
+                            }
+                }
+    }
+    return OCEAN_OK;
+}
+
+int ocean_dipole_amplitudes(const double* e, double* d) {
+    if (!e || !d || !std::isfinite(e[0]) || !std::isfinite(e[1]) || !std::isfinite(e[2])) {
+        ocean::set_error("ocean_dipole_amplitudes: invalid argument");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    // e.r^ = e_z z^ + e_x x^ + e_y y^ with x^ = sqrt(2pi/3)(Y_{1,-1} - Y_{11}),
+    // y^ = i sqrt(2pi/3)(Y_{1,-1} + Y_{11}), z^ = sqrt(4pi/3) Y_10 and
+    // <Y_2m|Y_1q|Y_1mc> = sqrt(3/(4pi)) c^1(2m; 1mc) delta_{q, m - mc}.
+    const double r2 = 1.0 / std::sqrt(2.0);
+    for (int m = -2; m <= 2; ++m)
+        for (int mc = -1; mc <= 1; ++mc) {
+            const double c1 = gaunt_ck(1, 2, m, 1, mc);
+            const int q = m - mc;
+            std::complex<double> v(0.0, 0.0);
+            if (q == 0) v += e[2] * c1;
+            if (q == -1) v += std::complex<double>(e[0] * r2, e[1] * r2) * c1;
+            if (q == 1) v += std::complex<double>(-e[0] * r2, e[1] * r2) * c1;
+            d[2 * ((m + 2) * 3 + (mc + 1))] = v.real();
+            d[2 * ((m + 2) * 3 + (mc + 1)) + 1] = v.imag();
+        }
+    return OCEAN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,784 @@
+// C-ABI runtime: handle life cycle, device memory, workspace, the H*v pipeline,
+// the Haydock driver (optionally replayed from a captured HIP graph), spectra,
+// profiling and error reporting.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace ocean {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+size_t max_device_bytes() {
+    const char* s = std::getenv("OCEAN_MAX_DEVICE_BYTES");
+    if (!s || !*s) return (size_t)-1;
+    return (size_t)std::strtoull(s, nullptr, 10);
+}
+
+static int env_int(const char* name, int dflt) {
+    const char* s = std::getenv(name);
+    if (!s || !*s) return dflt;
+    return std::atoi(s);
+}
+
+int prof_begin(ocean_bse_s* h, const char* name) {
+    if (!h->profiling) return -1;
+    int idx = -1;
+    for (size_t i = 0; i < h->stats.size(); ++i)
+        if (std::strcmp(h->stats[i].name, name) == 0) idx = (int)i;
+    if (idx < 0) {
+        h->stats.push_back(KernelStat{name, 0.0, 0});
+        idx = (int)h->stats.size() - 1;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1;
+    }
+    (void)hipEventRecord(e0, h->stream);
+    h->pending.push_back({idx, {e0, e1}});
+    return (int)h->pending.size() - 1;
+}
+
+void prof_end(ocean_bse_s* h, int slot) {
+    if (slot < 0) return;
+    (void)hipEventRecord(h->pending[slot].second.second, h->stream);
+}
+
+static void prof_collect(ocean_bse_s* h) {
+    if (h->pending.empty()) return;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& p : h->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            h->stats[p.first].ms += ms;
+            h->stats[p.first].count += 1;
+        }
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    h->pending.clear();
+}
+
+// ---- device memory -------------------------------------------------------------------------------
+template <typename T>
+static int dalloc(ocean_bse_s* h, T** p, size_t count, const char* what) {
+    const size_t bytes = count * sizeof(T);
+    *p = nullptr;
+    if (bytes == 0) return OCEAN_OK;
+    if (h->device_bytes + bytes > max_device_bytes()) {
+        set_error(std::string("device memory cap (OCEAN_MAX_DEVICE_BYTES) exceeded allocating ") + what);
+        return OCEAN_ERR_OUT_OF_MEMORY;
+    }
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess || q == nullptr) {
+        (void)hipGetLastError();
+        set_error(std::string("hipMalloc failed for ") + what + " (" + std::to_string(bytes) + " bytes)");
+        return OCEAN_ERR_OUT_OF_MEMORY;
+    }
+    h->device_bytes += bytes;
+    *p = static_cast<T*>(q);
+    return OCEAN_OK;
+}
+
+template <typename T>
+static void dfree(ocean_bse_s* h, T*& p, size_t count) {
+    if (p) {
+        (void)hipFree((void*)p);
+        h->device_bytes -= count * sizeof(T);
+    }
+    p = nullptr;
+}
+
+static int check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return OCEAN_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return OCEAN_ERR_DEVICE;
+}
+
+#define OCEAN_TRY(expr)                 \
+    do {                                \
+        int _rc = (expr);               \
+        if (_rc != OCEAN_OK) return _rc; \
+    } while (0)
+
+#define OCEAN_HIP(expr, what) OCEAN_TRY(check_hip((expr), (what)))
+
+static size_t u_elems(const ocean_bse_s* h) { return (size_t)h->Nk * h->Nx * h->Nb; }
+
+static void release_workspace(ocean_bse_s* h) {
+    auto& w = h->ws;
+    if (w.phi) {
+        (void)hipFree(w.phi);
+        w.phi = nullptr;
+    }
+    if (w.part) (void)hipFree(w.part);
+    if (w.loc_part) (void)hipFree(w.loc_part);
+    if (w.loc_b) (void)hipFree(w.loc_b);
+    w.part = w.loc_part = w.loc_b = nullptr;
+    h->device_bytes -= w.bytes;
+    w.bytes = 0;
+    w.cols = 0;
+}
+
+static int ensure_workspace(ocean_bse_s* h, int nv) {
+    const int cols = nv * h->Nc;
+    if (h->ws.cols >= cols && h->ws.cols > 0) {
+        int bb, S, chunk;
+        bwd_geometry(h, &bb, &S, &chunk);
+        h->ws.bwd_chunks = S;
+        return OCEAN_OK;
+    }
+    release_workspace(h);
+    int bb, S, chunk;
+    bwd_geometry(h, &bb, &S, &chunk);
+    const size_t elem = h->precision == OCEAN_PREC_FP64 ? 16 : 8;
+    const size_t phi_b = (size_t)h->Nk * h->Nx * cols * elem;
+    const size_t part_b = (size_t)S * h->Nk * h->Nb * cols * 16;
+    const int NP = std::max(1, h->Nc * h->Nmu);
+    const size_t locp_b = (size_t)local_blocks(h) * nv * NP * 16;
+    const size_t locb_b = (size_t)nv * NP * 16;
+    const size_t total = phi_b + part_b + locp_b + locb_b;
+    if (h->device_bytes + total > max_device_bytes()) {
+        set_error("device memory cap (OCEAN_MAX_DEVICE_BYTES) exceeded allocating the H*v workspace");
+        return OCEAN_ERR_OUT_OF_MEMORY;
+    }
+    auto& w = h->ws;
+    void* p = nullptr;
+    if (hipMalloc(&p, phi_b) != hipSuccess) goto oom;
+    w.phi = p;
+    if (hipMalloc(&p, part_b) != hipSuccess) goto oom;
+    w.part = static_cast<double*>(p);
+    if (hipMalloc(&p, locp_b) != hipSuccess) goto oom;
+    w.loc_part = static_cast<double*>(p);
+    if (hipMalloc(&p, locb_b) != hipSuccess) goto oom;
+    w.loc_b = static_cast<double*>(p);
+    w.bytes = total;
+    h->device_bytes += total;
+    w.cols = cols;
+    w.bwd_chunks = S;
+    return OCEAN_OK;
+oom:
+    (void)hipGetLastError();
+    if (w.phi) (void)hipFree(w.phi);
+    if (w.part) (void)hipFree(w.part);
+    if (w.loc_part) (void)hipFree(w.loc_part);
+    w.phi = nullptr;
+    w.part = w.loc_part = w.loc_b = nullptr;
+    w.bytes = 0;
+    w.cols = 0;
+    set_error("hipMalloc failed for the H*v workspace (" + std::to_string(total) + " bytes)");
+    return OCEAN_ERR_OUT_OF_MEMORY;
+}
+
+// The H*v pipeline for nv vectors: y = H x.  dot_part (optional): Re<x|y> partials.
+static int apply_pipeline(ocean_bse_s* h, const double* x, double* y, int nv, double* dot_part) {
+    const int cols = nv * h->Nc;
+    for (int c0 = 0; c0 < cols; c0 += kColsPerPass)
+        OCEAN_HIP(launch_proj_fwd(h, x, nv, c0, std::min(kColsPerPass, cols - c0)), "proj_fwd launch");
+    OCEAN_HIP(launch_fft_w(h, cols), "fft_w launch");
+    for (int c0 = 0; c0 < cols; c0 += kColsPerPass)
+        OCEAN_HIP(launch_proj_bwd(h, nv, c0, std::min(kColsPerPass, cols - c0)), "proj_bwd launch");
+    if (h->Nmu > 0 && h->K != nullptr) {
+        OCEAN_HIP(launch_local_in(h, x, nv), "local_in launch");
+        OCEAN_HIP(launch_local_mat(h, nv), "local_mat launch");
+    }
+    OCEAN_HIP(launch_combine(h, x, y, nv, dot_part), "combine launch");
+    return OCEAN_OK;
+}
+
+// ---- Lanczos buffers -----------------------------------------------------------------------------
+static void release_lanczos(ocean_bse_s* h) {
+    auto& L = h->lz;
+    void* ptrs[] = {L.v, L.vprev, L.w, L.basis, L.part_a, L.part_n, L.hpart, L.hcoef, L.a, L.b, L.state, L.step};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    h->device_bytes -= L.bytes;
+    L = LanczosBuffers();
+}
+
+static int ensure_lanczos(ocean_bse_s* h, int nv, int n_steps, bool reorth) {
+    auto& L = h->lz;
+    if (L.nv == nv && L.n_steps == n_steps && L.reorth == reorth && L.v) return OCEAN_OK;
+    release_lanczos(h);
+    const size_t dim = (size_t)h->Nk * h->Nb * h->Nc;
+    const size_t vec_b = (size_t)nv * dim * 16;
+    const size_t nstore = (size_t)n_steps + 1;
+    struct Req { void** p; size_t bytes; };
+    std::vector<Req> reqs = {
+        {(void**)&L.v, vec_b}, {(void**)&L.vprev, vec_b}, {(void**)&L.w, vec_b},
+        {(void**)&L.part_a, (size_t)nv * kRedBlocks * 8}, {(void**)&L.part_n, (size_t)nv * kRedBlocks * 8},
+        {(void**)&L.a, (size_t)nv * n_steps * 8}, {(void**)&L.b, (size_t)nv * n_steps * 8},
+        {(void**)&L.state, (size_t)nv * sizeof(LzState)}, {(void**)&L.step, 16}};
+    if (reorth) {
+        reqs.push_back({(void**)&L.basis, (size_t)nv * nstore * dim * 16});
+        reqs.push_back({(void**)&L.hpart, (size_t)nv * kRedBlocks * nstore * 16});
+        reqs.push_back({(void**)&L.hcoef, (size_t)nv * nstore * 16});
+    }
+    size_t total = 0;
+    for (auto& r : reqs) total += r.bytes;
+    if (h->device_bytes + total > max_device_bytes()) {
+        set_error("device memory cap (OCEAN_MAX_DEVICE_BYTES) exceeded allocating Lanczos buffers");
+        return OCEAN_ERR_OUT_OF_MEMORY;
+    }
+    for (auto& r : reqs) {
+        if (hipMalloc(r.p, r.bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            L.bytes = 0;
+            for (auto& q : reqs)
+                if (*q.p) {
+                    (void)hipFree(*q.p);
+                    *q.p = nullptr;
+                }
+            set_error("hipMalloc failed for Lanczos buffers (" + std::to_string(total) + " bytes)");
+            return OCEAN_ERR_OUT_OF_MEMORY;
+        }
+    }
+    L.bytes = total;
+    h->device_bytes += total;
+    L.nv = nv;
+    L.n_steps = n_steps;
+    L.reorth = reorth;
+    return OCEAN_OK;
+}
+
+// One Haydock step: w = H v, then the recursion update (section 3.2).
+static int haydock_step(ocean_bse_s* h, int nv, bool reorth) {
+    auto& L = h->lz;
+    OCEAN_TRY(apply_pipeline(h, L.v, L.w, nv, L.part_a));
+    OCEAN_HIP(lz_update(h, nv, !reorth), "lz_update launch");
+    if (reorth) {
+        OCEAN_HIP(lz_reorth(h, nv), "lz_reorth launch");
+        OCEAN_HIP(lz_norm_w(h, nv), "lz_norm launch");
+    }
+    OCEAN_HIP(lz_finalize(h, nv), "lz_finalize launch");
+    OCEAN_HIP(lz_scale(h, nv), "lz_scale launch");
+    OCEAN_HIP(lz_advance(h), "lz_advance launch");
+    return OCEAN_OK;
+}
+
+static bool finite_all(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+static void destroy_handle(ocean_bse_s* h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (auto& p : h->pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    h->pending.clear();
+    release_workspace(h);
+    release_lanczos(h);
+    const size_t ue = u_elems(h);
+    dfree(h, h->E, (size_t)h->Nk * h->Nb);
+    dfree(h, h->U64_owned, ue * 2);
+    dfree(h, h->U32, ue * 2);
+    dfree(h, h->Ubf, ue * 4);
+    dfree(h, h->W64, (size_t)h->Nx * h->Nk);
+    dfree(h, h->W32, (size_t)h->Nx * h->Nk);
+    if (h->phase) (void)hipFree(h->phase);
+    if (h->twiddle) (void)hipFree(h->twiddle);
+    if (h->A) (void)hipFree(h->A);
+    if (h->K) (void)hipFree(h->K);
+    if (h->Hc) (void)hipFree(h->Hc);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) {
+    if (!d || !out) {
+        set_error("ocean_bse_create: NULL desc or out");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    for (int a = 0; a < 3; ++a) {
+        if (d->nk[a] < 1 || d->nx[a] < 1) {
+            set_error("ocean_bse_create: nk and nx must be >= 1");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        if (d->nk[a] > kMaxDft) {
+            set_error("ocean_bse_create: k-grid extent per axis above 16 is not supported");
+            return OCEAN_ERR_UNSUPPORTED;
+        }
+        if (!(d->cell[a] > 0.0) || !std::isfinite(d->cell[a]) || !std::isfinite(d->tau[a])) {
+            set_error("ocean_bse_create: cell lengths must be positive and finite");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+    }
+    if (d->n_bands < 1 || d->n_core < 1 || d->n_local < 0) {
+        set_error("ocean_bse_create: n_bands and n_core must be >= 1, n_local >= 0");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    if (d->n_core > kMaxCore || d->n_local > kMaxLocal || d->n_core * d->n_local > kMaxPairs) {
+        set_error("ocean_bse_create: n_core <= 8, n_local <= 16 and n_core*n_local <= 128 supported");
+        return OCEAN_ERR_UNSUPPORTED;
+    }
+    if (!d->energies || !d->u || !d->w_r || !d->w_val || d->n_wr < 2) {
+        set_error("ocean_bse_create: energies, u, w_r, w_val are required (n_wr >= 2)");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    if (d->n_local > 0 && (!d->local_proj || !d->local_mat)) {
+        set_error("ocean_bse_create: n_local > 0 needs local_proj and local_mat");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    if (d->precision != OCEAN_PREC_FP64 && d->precision != OCEAN_PREC_FP32) {
+        set_error("ocean_bse_create: precision not supported by this build");
+        return OCEAN_ERR_UNSUPPORTED;
+    }
+    // radial grid: uniform from 0
+    const double hr = d->w_r[1] - d->w_r[0];
+    if (d->w_r[0] != 0.0 || !(hr > 0.0)) {
+        set_error("ocean_bse_create: radial grid must start at 0 and ascend");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    for (int j = 1; j < d->n_wr; ++j) {
+        const double ex = hr * j;
+        if (std::fabs(d->w_r[j] - ex) > 1e-9 * (1.0 + ex)) {
+            set_error("ocean_bse_create: radial grid must be uniform");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+    }
+    const long long Nk = (long long)d->nk[0] * d->nk[1] * d->nk[2];
+    const long long Nx = (long long)d->nx[0] * d->nx[1] * d->nx[2];
+    if (Nx * d->n_bands > (1LL << 40) || Nx > (1LL << 30)) {
+        set_error("ocean_bse_create: grid too large");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    if (d->flags & OCEAN_FLAG_CHECK_INPUTS) {
+        const size_t ne = (size_t)Nk * d->n_bands;
+        if (!finite_all(d->energies, ne) || !finite_all(d->w_r, d->n_wr) || !finite_all(d->w_val, d->n_wr)) {
+            set_error("ocean_bse_create: NaN or Inf in energies or the radial table");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        if (!(d->flags & OCEAN_FLAG_BORROW_DEVICE_U) &&
+            !finite_all(d->u, (size_t)Nk * Nx * d->n_bands * 2)) {
+            set_error("ocean_bse_create: NaN or Inf in u");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        if (d->local_proj && !finite_all(d->local_proj, ne * d->n_local * 2)) {
+            set_error("ocean_bse_create: NaN or Inf in local_proj");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        auto herm = [](const double* m, int n, double tol) {
+            double mx = 0.0;
+            for (int i = 0; i < n * n * 2; ++i) mx = std::max(mx, std::fabs(m[i]));
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    const double* a = m + 2 * (i * n + j);
+                    const double* b = m + 2 * (j * n + i);
+                    if (!std::isfinite(a[0]) || !std::isfinite(a[1])) return false;
+                    if (std::fabs(a[0] - b[0]) > tol * (mx + 1e-300) || std::fabs(a[1] + b[1]) > tol * (mx + 1e-300))
+                        return false;
+                }
+            return true;
+        };
+        if (d->core_mat && !herm(d->core_mat, d->n_core, 1e-12)) {
+            set_error("ocean_bse_create: core_mat is not Hermitian or not finite");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        if (d->n_local > 0 && !herm(d->local_mat, d->n_core * d->n_local, 1e-12)) {
+            set_error("ocean_bse_create: local_mat is not Hermitian or not finite");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+    }
+
+    ocean_bse_s* h = new (std::nothrow) ocean_bse_s();
+    if (!h) {
+        set_error("ocean_bse_create: host allocation failed");
+        return OCEAN_ERR_OUT_OF_MEMORY;
+    }
+    for (int a = 0; a < 3; ++a) {
+        h->nk[a] = d->nk[a];
+        h->nx[a] = d->nx[a];
+        h->cell[a] = d->cell[a];
+        h->tau[a] = d->tau[a];
+    }
+    h->Nk = (int)Nk;
+    h->Nx = (int)Nx;
+    h->Nb = d->n_bands;
+    h->Nc = d->n_core;
+    h->Nmu = d->n_local;
+    h->precision = d->precision;
+    h->flags = d->flags;
+    (void)hipGetDevice(&h->device);
+    if (stream) {
+        h->stream = static_cast<hipStream_t>(stream);
+        h->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+            set_error("ocean_bse_create: hipStreamCreate failed");
+            delete h;
+            return OCEAN_ERR_DEVICE;
+        }
+        h->own_stream = true;
+    }
+    h->bwd_target_blocks = env_int("OCEAN_BWD_BLOCKS", 2048);
+
+    auto fail = [&](int rc) {
+        destroy_handle(h);
+        return rc;
+    };
+    const size_t ue = u_elems(h);
+    int rc;
+    // energies
+    if ((rc = dalloc(h, &h->E, (size_t)Nk * h->Nb, "energies")) != OCEAN_OK) return fail(rc);
+    if ((rc = check_hip(hipMemcpyAsync(h->E, d->energies, (size_t)Nk * h->Nb * 8, hipMemcpyHostToDevice, h->stream), "energies upload")) != OCEAN_OK) return fail(rc);
+    // u
+    if ((d->flags & OCEAN_FLAG_BORROW_DEVICE_U) && h->precision == OCEAN_PREC_FP64) {
+        h->U64 = d->u;
+    } else if (h->precision == OCEAN_PREC_FP64) {
+        if ((rc = dalloc(h, &h->U64_owned, ue * 2, "u (FP64)")) != OCEAN_OK) return fail(rc);
+        if ((rc = check_hip(hipMemcpyAsync(h->U64_owned, d->u, ue * 16, hipMemcpyHostToDevice, h->stream), "u upload")) != OCEAN_OK) return fail(rc);
+        h->U64 = h->U64_owned;
+    } else {
+        // FP32 copy converted on the device, staged through a bounded FP64 buffer
+        if ((rc = dalloc(h, &h->U32, ue * 2, "u (FP32)")) != OCEAN_OK) return fail(rc);
+        if (d->flags & OCEAN_FLAG_BORROW_DEVICE_U) {
+            rc = check_hip(launch_to_fp32(h, d->u, h->U32, (long long)ue * 2), "u conversion");
+            if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "u conversion");
+            if (rc != OCEAN_OK) return fail(rc);
+        } else {
+        const size_t slab = std::min<size_t>(ue, (size_t)1 << 26);
+        double* stage = nullptr;
+        if ((rc = dalloc(h, &stage, slab * 2, "u staging")) != OCEAN_OK) return fail(rc);
+        for (size_t off = 0; off < ue; off += slab) {
+            const size_t n = std::min(slab, ue - off);
+            rc = check_hip(hipMemcpyAsync(stage, d->u + 2 * off, n * 16, hipMemcpyHostToDevice, h->stream), "u upload");
+            if (rc == OCEAN_OK) rc = check_hip(launch_to_fp32(h, stage, h->U32 + 2 * off, (long long)n * 2), "u conversion");
+            if (rc != OCEAN_OK) break;
+        }
+        if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "u conversion");
+        dfree(h, stage, slab * 2);
+        if (rc != OCEAN_OK) return fail(rc);
+        }
+    }
+    // W(x, R) table
+    {
+        double* wr = nullptr;
+        double* wv = nullptr;
+        if (h->precision == OCEAN_PREC_FP64) {
+            if ((rc = dalloc(h, &h->W64, (size_t)Nx * Nk, "W table")) != OCEAN_OK) return fail(rc);
+        } else {
+            if ((rc = dalloc(h, &h->W32, (size_t)Nx * Nk, "W table")) != OCEAN_OK) return fail(rc);
+        }
+        if ((rc = dalloc(h, &wr, d->n_wr, "radial table")) != OCEAN_OK) return fail(rc);
+        if ((rc = dalloc(h, &wv, d->n_wr, "radial table")) != OCEAN_OK) {
+            dfree(h, wr, d->n_wr);
+            return fail(rc);
+        }
+        rc = check_hip(hipMemcpyAsync(wr, d->w_r, d->n_wr * 8, hipMemcpyHostToDevice, h->stream), "radial upload");
+        if (rc == OCEAN_OK) rc = check_hip(hipMemcpyAsync(wv, d->w_val, d->n_wr * 8, hipMemcpyHostToDevice, h->stream), "radial upload");
+        if (rc == OCEAN_OK) rc = check_hip(launch_build_w(h, wr, wv, d->n_wr, hr), "W table build");
+        if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "W table build");
+        dfree(h, wr, d->n_wr);
+        dfree(h, wv, d->n_wr);
+        if (rc != OCEAN_OK) return fail(rc);
+    }
+    // phase tables e^{2 pi i a b / (n g)} per axis and DFT twiddles e^{2 pi i m / n}
+    {
+        std::vector<double> ph, tw;
+        for (int a = 0; a < 3; ++a) {
+            h->phase_off[a] = (int)(ph.size() / 2);
+            const long long ng = (long long)h->nk[a] * h->nx[a];
+            for (int i = 0; i < h->nk[a]; ++i)
+                for (int j = 0; j < h->nx[a]; ++j) {
+                    const long long m = ((long long)i * j) % ng;
+                    const double ang = 2.0 * M_PI * (double)m / (double)ng;
+                    ph.push_back(std::cos(ang));
+                    ph.push_back(std::sin(ang));
+                }
+            h->tw_off[a] = (int)(tw.size() / 2);
+            for (int m = 0; m < h->nk[a]; ++m) {
+                const double ang = 2.0 * M_PI * (double)m / (double)h->nk[a];
+                tw.push_back(std::cos(ang));
+                tw.push_back(std::sin(ang));
+            }
+        }
+        if (hipMalloc((void**)&h->phase, ph.size() * 8) != hipSuccess ||
+            hipMalloc((void**)&h->twiddle, tw.size() * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("ocean_bse_create: hipMalloc failed for phase tables");
+            return fail(OCEAN_ERR_OUT_OF_MEMORY);
+        }
+        h->device_bytes += (ph.size() + tw.size()) * 8;
+        if ((rc = check_hip(hipMemcpy(h->phase, ph.data(), ph.size() * 8, hipMemcpyHostToDevice), "phase upload")) != OCEAN_OK) return fail(rc);
+        if ((rc = check_hip(hipMemcpy(h->twiddle, tw.data(), tw.size() * 8, hipMemcpyHostToDevice), "twiddle upload")) != OCEAN_OK) return fail(rc);
+    }
+    // small matrices and the local projectors
+    auto upload = [&](double** dst, const double* src, size_t ndouble, const char* what) -> int {
+        if ((size_t)h->device_bytes + ndouble * 8 > max_device_bytes()) {
+            set_error(std::string("device memory cap (OCEAN_MAX_DEVICE_BYTES) exceeded allocating ") + what);
+            return OCEAN_ERR_OUT_OF_MEMORY;
+        }
+        if (hipMalloc((void**)dst, ndouble * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            *dst = nullptr;
+            set_error(std::string("hipMalloc failed for ") + what);
+            return OCEAN_ERR_OUT_OF_MEMORY;
+        }
+        h->device_bytes += ndouble * 8;
+        return check_hip(hipMemcpy(*dst, src, ndouble * 8, hipMemcpyHostToDevice), what);
+    };
+    if (d->core_mat) {
+        if ((rc = upload(&h->Hc, d->core_mat, (size_t)h->Nc * h->Nc * 2, "core_mat")) != OCEAN_OK) return fail(rc);
+    }
+    if (h->Nmu > 0) {
+        if ((rc = upload(&h->A, d->local_proj, (size_t)Nk * h->Nb * h->Nmu * 2, "local_proj")) != OCEAN_OK) return fail(rc);
+        const size_t np = (size_t)h->Nc * h->Nmu;
+        if ((rc = upload(&h->K, d->local_mat, np * np * 2, "local_mat")) != OCEAN_OK) return fail(rc);
+    }
+    // k-transform tile: lines per block so that the LDS tile fits
+    {
+        int L = env_int("OCEAN_FFT_LINES", 0);
+        if (L <= 0) {
+            const size_t budget = (size_t)env_int("OCEAN_FFT_LDS", 80 * 1024);
+            L = 256;
+            while (L > 4 && fft_lds_bytes(h, L) > budget) L /= 2;
+        }
+        if (fft_lds_bytes(h, L) > 160 * 1024) {
+            set_error("ocean_bse_create: k grid too large for the LDS-staged transform");
+            return fail(OCEAN_ERR_UNSUPPORTED);
+        }
+        h->fft_lines = L;
+    }
+    if ((rc = check_hip(hipStreamSynchronize(h->stream), "create")) != OCEAN_OK) return fail(rc);
+    *out = h;
+    return OCEAN_OK;
+}
+
+}  // namespace ocean
+
+using namespace ocean;
+
+extern "C" {
+
+const char* ocean_last_error(void) { return g_last_error.c_str(); }
+
+int ocean_bse_create(const ocean_bse_desc* desc, void* stream, ocean_bse_t* out) {
+    g_last_error.clear();
+    try {
+        return create_impl(desc, stream, out);
+    } catch (...) {
+        set_error("ocean_bse_create: unexpected host exception");
+        return OCEAN_ERR_DEVICE;
+    }
+}
+
+void ocean_bse_destroy(ocean_bse_t h) { destroy_handle(h); }
+
+long long ocean_bse_dim(ocean_bse_t h) {
+    if (!h) {
+        set_error("ocean_bse_dim: NULL handle");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    return (long long)h->Nk * h->Nb * h->Nc;
+}
+
+long long ocean_bse_device_bytes(ocean_bse_t h) {
+    if (!h) {
+        set_error("ocean_bse_device_bytes: NULL handle");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    return (long long)h->device_bytes;
+}
+
+int ocean_bse_apply(ocean_bse_t h, const double* x_dev, double* y_dev, int n_vec) {
+    g_last_error.clear();
+    if (!h || !x_dev || !y_dev || n_vec < 1) {
+        set_error("ocean_bse_apply: NULL argument or n_vec < 1");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    const size_t vb = (size_t)n_vec * h->Nk * h->Nb * h->Nc * 16;
+    const char* xa = reinterpret_cast<const char*>(x_dev);
+    const char* ya = reinterpret_cast<const char*>(y_dev);
+    if (xa < ya + vb && ya < xa + vb) {
+        set_error("ocean_bse_apply: x and y overlap");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    (void)hipSetDevice(h->device);
+    OCEAN_TRY(ensure_workspace(h, n_vec));
+    return apply_pipeline(h, x_dev, y_dev, n_vec, nullptr);
+}
+
+int ocean_haydock(ocean_bse_t h, const double* psi0_dev, int n_vec, int n_steps, unsigned flags,
+                  double* a, double* b, double* norm2, int* steps_done) {
+    g_last_error.clear();
+    if (!h || !psi0_dev || !a || !b || !norm2 || !steps_done || n_vec < 1 || n_steps < 1) {
+        set_error("ocean_haydock: NULL argument, n_vec < 1 or n_steps < 1");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    (void)hipSetDevice(h->device);
+    const bool reorth = (flags & OCEAN_HAYDOCK_REORTH) != 0;
+    OCEAN_TRY(ensure_workspace(h, n_vec));
+    OCEAN_TRY(ensure_lanczos(h, n_vec, n_steps, reorth));
+    auto& L = h->lz;
+    OCEAN_HIP(hipMemsetAsync(L.a, 0, (size_t)n_vec * n_steps * 8, h->stream), "memset");
+    OCEAN_HIP(hipMemsetAsync(L.b, 0, (size_t)n_vec * n_steps * 8, h->stream), "memset");
+    OCEAN_HIP(lz_init(h, psi0_dev, n_vec), "lz_init launch");
+
+    const bool use_graph = !h->profiling && env_int("OCEAN_NO_GRAPH", 0) == 0 && h->own_stream;
+    bool graph_done = false;
+    if (use_graph) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            const int rc = haydock_step(h, n_vec, reorth);
+            const hipError_t ec = hipStreamEndCapture(h->stream, &graph);
+            if (rc == OCEAN_OK && ec == hipSuccess && graph &&
+                hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+                int lrc = OCEAN_OK;
+                for (int i = 0; i < n_steps && lrc == OCEAN_OK; ++i)
+                    lrc = check_hip(hipGraphLaunch(exec, h->stream), "graph launch");
+                graph_done = lrc == OCEAN_OK;
+                (void)hipGraphExecDestroy(exec);
+                (void)hipGraphDestroy(graph);
+                if (!graph_done) return lrc;
+            } else {
+                if (graph) (void)hipGraphDestroy(graph);
+                (void)hipGetLastError();
+            }
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    if (!graph_done) {
+        for (int i = 0; i < n_steps; ++i) OCEAN_TRY(haydock_step(h, n_vec, reorth));
+    }
+    OCEAN_HIP(hipStreamSynchronize(h->stream), "haydock");
+    prof_collect(h);
+    std::vector<LzState> st(n_vec);
+    OCEAN_HIP(hipMemcpy(a, L.a, (size_t)n_vec * n_steps * 8, hipMemcpyDeviceToHost), "copy a");
+    OCEAN_HIP(hipMemcpy(b, L.b, (size_t)n_vec * n_steps * 8, hipMemcpyDeviceToHost), "copy b");
+    OCEAN_HIP(hipMemcpy(st.data(), L.state, n_vec * sizeof(LzState), hipMemcpyDeviceToHost), "copy state");
+    int ret = OCEAN_OK;
+    for (int v = 0; v < n_vec; ++v) {
+        norm2[v] = st[v].norm2;
+        steps_done[v] = st[v].steps;
+        if (!(st[v].norm2 > 0.0)) {
+            set_error("ocean_haydock: a starting vector is zero");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        if (st[v].steps < n_steps) ret = OCEAN_INFO_INVARIANT_SUBSPACE;
+    }
+    return ret;
+}
+
+int ocean_spectrum(const double* a, const double* b, const int* n_used, const double* norm2,
+                   int n_spec, int n_steps, int terminator, const double* omega, int n_omega,
+                   double gamma, double* sigma) {
+    g_last_error.clear();
+    if (!a || !b || !norm2 || !omega || !sigma || n_spec < 1 || n_steps < 1 || n_omega < 1 ||
+        !(gamma > 0.0) || (terminator != OCEAN_TERM_NONE && terminator != OCEAN_TERM_SQRT)) {
+        set_error("ocean_spectrum: invalid argument");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    if (n_used)
+        for (int s = 0; s < n_spec; ++s)
+            if (n_used[s] < 0 || n_used[s] > n_steps) {
+                set_error("ocean_spectrum: n_used out of range");
+                return OCEAN_ERR_INVALID_ARG;
+            }
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        set_error("ocean_spectrum: hipStreamCreate failed");
+        return OCEAN_ERR_DEVICE;
+    }
+    const size_t nab = (size_t)n_spec * n_steps;
+    const size_t bytes = nab * 16 + n_spec * 12 + (size_t)n_omega * 8 + (size_t)n_spec * n_omega * 8;
+    char* buf = nullptr;
+    if (hipMalloc((void**)&buf, bytes + 256) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(st);
+        set_error("ocean_spectrum: hipMalloc failed");
+        return OCEAN_ERR_OUT_OF_MEMORY;
+    }
+    double* da = reinterpret_cast<double*>(buf);
+    double* db = da + nab;
+    double* dn = db + nab;
+    double* dom = dn + n_spec;
+    double* dsig = dom + n_omega;
+    int* dused = reinterpret_cast<int*>(dsig + (size_t)n_spec * n_omega);
+    int rc = OCEAN_OK;
+    rc = check_hip(hipMemcpyAsync(da, a, nab * 8, hipMemcpyHostToDevice, st), "upload");
+    if (rc == OCEAN_OK) rc = check_hip(hipMemcpyAsync(db, b, nab * 8, hipMemcpyHostToDevice, st), "upload");
+    if (rc == OCEAN_OK) rc = check_hip(hipMemcpyAsync(dn, norm2, n_spec * 8, hipMemcpyHostToDevice, st), "upload");
+    if (rc == OCEAN_OK) rc = check_hip(hipMemcpyAsync(dom, omega, n_omega * 8, hipMemcpyHostToDevice, st), "upload");
+    if (rc == OCEAN_OK && n_used) rc = check_hip(hipMemcpyAsync(dused, n_used, n_spec * 4, hipMemcpyHostToDevice, st), "upload");
+    if (rc == OCEAN_OK)
+        rc = check_hip(launch_spectrum(da, db, n_used ? dused : nullptr, dn, n_spec, n_steps, terminator,
+                                       dom, n_omega, gamma, dsig, st), "spectrum launch");
+    if (rc == OCEAN_OK) rc = check_hip(hipMemcpyAsync(sigma, dsig, (size_t)n_spec * n_omega * 8, hipMemcpyDeviceToHost, st), "download");
+    if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(st), "spectrum");
+    (void)hipFree(buf);
+    (void)hipStreamDestroy(st);
+    return rc;
+}
+
+int ocean_dipole_psi0(ocean_bse_t h, const double* pol, int n_pol, double* psi0_dev) {
+    g_last_error.clear();
+    if (!h || !pol || !psi0_dev || n_pol < 1) {
+        set_error("ocean_dipole_psi0: invalid argument");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    if (h->Nc != 6 || h->Nmu != 5 || !h->A) {
+        set_error("ocean_dipole_psi0: needs an L2,3 edge (n_core = 6) with a d-channel local basis (n_local = 5)");
+        return OCEAN_ERR_UNSUPPORTED;
+    }
+    std::vector<double> d((size_t)n_pol * 30);
+    for (int p = 0; p < n_pol; ++p) OCEAN_TRY(ocean_dipole_amplitudes(pol + 3 * p, d.data() + 30 * p));
+    double* dd = nullptr;
+    if (hipMalloc((void**)&dd, d.size() * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("ocean_dipole_psi0: hipMalloc failed");
+        return OCEAN_ERR_OUT_OF_MEMORY;
+    }
+    int rc = check_hip(hipMemcpyAsync(dd, d.data(), d.size() * 8, hipMemcpyHostToDevice, h->stream), "upload");
+    if (rc == OCEAN_OK) rc = check_hip(launch_dipole_psi0(h, dd, n_pol, psi0_dev), "dipole launch");
+    if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "dipole");
+    (void)hipFree(dd);
+    return rc;
+}
+
+int ocean_bse_set_profiling(ocean_bse_t h, int enable) {
+    if (!h) {
+        set_error("ocean_bse_set_profiling: NULL handle");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    prof_collect(h);
+    h->stats.clear();
+    h->profiling = enable != 0;
+    return OCEAN_OK;
+}
+
+int ocean_bse_kernel_times(ocean_bse_t h, const char** names, double* total_ms, long long* counts,
+                           int max_entries) {
+    if (!h || max_entries < 0) {
+        set_error("ocean_bse_kernel_times: invalid argument");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    prof_collect(h);
+    const int n = std::min<int>(max_entries, (int)h->stats.size());
+    for (int i = 0; i < n; ++i) {
+        if (names) names[i] = h->stats[i].name;
+        if (total_ms) total_ms[i] = h->stats[i].ms;
+        if (counts) counts[i] = h->stats[i].count;
+    }
+    return (int)h->stats.size();
+}
+
+}  // extern "C"

@@ -1,0 +1,664 @@
+// Vector-sized kernels of the H*v and of the Haydock recursion:
+//   - the short-range local-basis term (section 3.2.2): projection in, the small
+//     interaction matrix, projection out
+//   - the diagonal (H_e) and core-matrix (-H_h) terms, summed with the back-projection
+//     partials of the long-range W0 term into y (section 3.2: the pieces are summed)
+//   - Lanczos inner products, updates and norms (section 3.2, Haydock), FP64 with a
+//     fixed reduction order
+//   - the continued-fraction spectrum (section 2, eq. loss.fcn)
+//   - set-up: the W(x, R) table, precision copies of u, dipole initial vectors
+#include "internal.h"
+
+namespace ocean {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Fixed-order block sum of one double per thread (blockDim.x = 256).
+__device__ double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ double2 block_sum2(double2 v, double* sh) {
+    const double re = block_sum(v.x, sh);
+    const double im = block_sum(v.y, sh);
+    return make_double2(re, im);
+}
+
+// ---- local term --------------------------------------------------------------------------------
+// part[b][v][c*Nmu+mu] = sum_{kn in block b} A[kn][mu] x[v][kn][c]
+__global__ __launch_bounds__(256) void local_in_kernel(const double2* __restrict__ x,
+                                                       const double2* __restrict__ A,
+                                                       double2* __restrict__ part, int nv,
+                                                       long long NkNb, int Nc, int Nmu,
+                                                       long long chunk) {
+    __shared__ double2 red[256];
+    const int NP = Nc * Nmu;
+    const int G = 256 / NP;
+    const int t = threadIdx.x;
+    const int pair = t % NP, g = t / NP;
+    const int c = pair / Nmu, mu = pair - c * Nmu;
+    const long long kn0 = (long long)blockIdx.x * chunk;
+    const long long kn1 = min(NkNb, kn0 + chunk);
+    for (int v = 0; v < nv; ++v) {
+        double2 acc = make_double2(0.0, 0.0);
+        if (g < G) {
+            const double2* xv = x + (size_t)v * NkNb * Nc;
+            for (long long kn = kn0 + g; kn < kn1; kn += G)
+                acc = cadd(acc, cmul(A[kn * Nmu + mu], xv[kn * Nc + c]));
+        }
+        red[t] = acc;
+        __syncthreads();
+        if (t < NP) {
+            double2 s = red[t];
+            for (int gg = 1; gg < G; ++gg) s = cadd(s, red[gg * NP + t]);
+            part[((size_t)blockIdx.x * nv + v) * NP + t] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// b = sum over blocks; b' = K b
+__global__ __launch_bounds__(128) void local_mat_kernel(const double2* __restrict__ part,
+                                                        const double2* __restrict__ K,
+                                                        double2* __restrict__ bprime, int nv,
+                                                        int NP, int nblk) {
+    __shared__ double2 bsh[kMaxPairs];
+    const int v = blockIdx.x;
+    const int t = threadIdx.x;
+    if (t < NP) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int b = 0; b < nblk; ++b) s = cadd(s, part[((size_t)b * nv + v) * NP + t]);
+        bsh[t] = s;
+    }
+    __syncthreads();
+    if (t < NP) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int p = 0; p < NP; ++p) s = cadd(s, cmul(K[(size_t)t * NP + p], bsh[p]));
+        bprime[(size_t)v * NP + t] = s;
+    }
+}
+
+// ---- combine: y = E x + Hc x + conj(A) b' - sum_s part[s] -----------------------------------------
+// One thread per (v, k, n).  Optionally also the per-block partial of Re<x|y> for Lanczos.
+__global__ __launch_bounds__(256) void combine_kernel(
+    const double2* __restrict__ x, double2* __restrict__ y, const double* __restrict__ E,
+    const double2* __restrict__ Hc, const double2* __restrict__ A, const double2* __restrict__ bprime,
+    const double2* __restrict__ part, int S, int nv, long long NkNb, int Nc, int Nmu, int has_core,
+    int has_w, double* __restrict__ dot_part, long long per_block) {
+    __shared__ double sh[256];
+    const long long total = (long long)nv * NkNb;
+    const int cols = nv * Nc;
+    double dot = 0.0;
+    // blocks are laid out [v][block-in-vector] so each vector's dot partials are contiguous
+    const int v = blockIdx.y;
+    const long long start = (long long)blockIdx.x * per_block;
+    const long long stop = min(NkNb, start + per_block);
+    for (long long kn = start + threadIdx.x; kn < stop; kn += blockDim.x) {
+        const size_t base = ((size_t)v * NkNb + kn) * Nc;
+        double2 xv[kMaxCore];
+#pragma unroll
+        for (int c = 0; c < kMaxCore; ++c)
+            if (c < Nc) xv[c] = x[base + c];
+        const double e = E[kn];
+#pragma unroll
+        for (int c = 0; c < kMaxCore; ++c) {
+            if (c >= Nc) break;
+            double2 acc = make_double2(e * xv[c].x, e * xv[c].y);
+            if (has_core) {
+#pragma unroll
+                for (int d = 0; d < kMaxCore; ++d)
+                    if (d < Nc) acc = cadd(acc, cmul(Hc[c * Nc + d], xv[d]));
+            }
+            if (Nmu > 0) {
+                const double2* bp = bprime + ((size_t)v * Nc + c) * Nmu;
+                for (int mu = 0; mu < Nmu; ++mu) acc = cadd(acc, cmulc(A[kn * Nmu + mu], bp[mu]));
+            }
+            if (has_w) {
+                double2 w0 = make_double2(0.0, 0.0);
+                for (int s = 0; s < S; ++s) w0 = cadd(w0, part[((size_t)s * NkNb + kn) * cols + v * Nc + c]);
+                acc.x -= w0.x;
+                acc.y -= w0.y;
+            }
+            y[base + c] = acc;
+            dot += xv[c].x * acc.x + xv[c].y * acc.y;
+        }
+    }
+    (void)total;
+    if (dot_part != nullptr) {
+        const double s = block_sum(dot, sh);
+        if (threadIdx.x == 0) dot_part[(size_t)v * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// ---- Lanczos ------------------------------------------------------------------------------------------
+// Vectors are [v][dim] complex; block b of vector v covers [b*per, (b+1)*per).
+
+__global__ __launch_bounds__(256) void lz_norm_partial_kernel(const double2* __restrict__ p,
+                                                              double* __restrict__ part,
+                                                              long long dim, long long per) {
+    __shared__ double sh[256];
+    const int v = blockIdx.y;
+    const double2* pv = p + (size_t)v * dim;
+    const long long s0 = (long long)blockIdx.x * per, s1 = min(dim, s0 + per);
+    double acc = 0.0;
+    for (long long e = s0 + threadIdx.x; e < s1; e += blockDim.x) acc += pv[e].x * pv[e].x + pv[e].y * pv[e].y;
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(size_t)v * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void lz_dot_partial_kernel(const double2* __restrict__ a,
+                                                             const double2* __restrict__ b,
+                                                             double* __restrict__ part,
+                                                             long long dim, long long per) {
+    __shared__ double sh[256];
+    const int v = blockIdx.y;
+    const double2* av = a + (size_t)v * dim;
+    const double2* bv = b + (size_t)v * dim;
+    const long long s0 = (long long)blockIdx.x * per, s1 = min(dim, s0 + per);
+    double acc = 0.0;
+    for (long long e = s0 + threadIdx.x; e < s1; e += blockDim.x) acc += av[e].x * bv[e].x + av[e].y * bv[e].y;
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(size_t)v * gridDim.x + blockIdx.x] = s;
+}
+
+__device__ __forceinline__ double sum_parts(const double* part, int nblk) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[b];
+    return s;
+}
+
+// v = psi0 / |psi0|, vprev = 0, state reset; basis[0] = v when reorthogonalising
+__global__ __launch_bounds__(256) void lz_init_kernel(const double2* __restrict__ psi0,
+                                                      double2* __restrict__ vcur,
+                                                      double2* __restrict__ vprev,
+                                                      double2* __restrict__ basis,
+                                                      const double* __restrict__ part,
+                                                      LzState* __restrict__ st, int* __restrict__ step,
+                                                      long long dim, long long per, int nstore) {
+    const int v = blockIdx.y;
+    const double n2 = sum_parts(part + (size_t)v * gridDim.x, gridDim.x);
+    const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+    const long long s0 = (long long)blockIdx.x * per, s1 = min(dim, s0 + per);
+    for (long long e = s0 + threadIdx.x; e < s1; e += blockDim.x) {
+        const double2 p = psi0[(size_t)v * dim + e];
+        const double2 q = make_double2(p.x * inv, p.y * inv);
+        vcur[(size_t)v * dim + e] = q;
+        vprev[(size_t)v * dim + e] = make_double2(0.0, 0.0);
+        if (basis) basis[(size_t)v * nstore * dim + e] = q;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        LzState s;
+        s.b_cur = 0.0;
+        s.scale = 0.0;
+        s.norm2 = n2;
+        s.a_cur = 0.0;
+        s.done = n2 > 0.0 ? 0 : 1;
+        s.steps = 0;
+        s.pad[0] = s.pad[1] = 0;
+        st[v] = s;
+        if (v == 0) *step = 0;
+    }
+}
+
+// a_i = sum of partials; w -= a_i v + b_i vprev; optional |w|^2 partials; block 0 records a_i
+__global__ __launch_bounds__(256) void lz_update_kernel(double2* __restrict__ w,
+                                                        const double2* __restrict__ vcur,
+                                                        const double2* __restrict__ vprev,
+                                                        const double* __restrict__ part_a,
+                                                        double* __restrict__ part_n,
+                                                        LzState* __restrict__ st,
+                                                        double* __restrict__ a_out,
+                                                        const int* __restrict__ step,
+                                                        int n_steps, long long dim, long long per,
+                                                        int nblk_a) {
+    __shared__ double sh[256];
+    const int v = blockIdx.y;
+    const int i = *step;
+    const double a = sum_parts(part_a + (size_t)v * nblk_a, nblk_a);
+    const double bi = st[v].b_cur;
+    const bool done = st[v].done != 0;
+    const long long s0 = (long long)blockIdx.x * per, s1 = min(dim, s0 + per);
+    double acc = 0.0;
+    for (long long e = s0 + threadIdx.x; e < s1; e += blockDim.x) {
+        const size_t o = (size_t)v * dim + e;
+        double2 ww = w[o];
+        if (!done) {
+            const double2 vc = vcur[o], vp = vprev[o];
+            ww.x = ww.x - a * vc.x - bi * vp.x;
+            ww.y = ww.y - a * vc.y - bi * vp.y;
+            w[o] = ww;
+        }
+        acc += ww.x * ww.x + ww.y * ww.y;
+    }
+    if (part_n != nullptr) {
+        const double s = block_sum(acc, sh);
+        if (threadIdx.x == 0) part_n[(size_t)v * gridDim.x + blockIdx.x] = s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !done) {
+        a_out[(size_t)v * n_steps + i] = a;
+        st[v].a_cur = a;
+    }
+}
+
+// Re-orthogonalisation, pass 1: hpart[v][b][j] = sum_{e in block b} conj(basis_j[e]) w[e], j <= step
+__global__ __launch_bounds__(256) void lz_reorth_dot_kernel(const double2* __restrict__ basis,
+                                                            const double2* __restrict__ w,
+                                                            double2* __restrict__ hpart,
+                                                            const LzState* __restrict__ st,
+                                                            const int* __restrict__ step,
+                                                            long long dim, long long per,
+                                                            int nstore) {
+    __shared__ double sh[256];
+    const int v = blockIdx.y;
+    if (st[v].done) return;
+    const int nj = *step + 1;
+    const long long s0 = (long long)blockIdx.x * per, s1 = min(dim, s0 + per);
+    const double2* wv = w + (size_t)v * dim;
+    for (int j = 0; j < nj; ++j) {
+        const double2* bj = basis + ((size_t)v * nstore + j) * dim;
+        double2 acc = make_double2(0.0, 0.0);
+        for (long long e = s0 + threadIdx.x; e < s1; e += blockDim.x) acc = cadd(acc, cmulc(bj[e], wv[e]));
+        const double2 s = block_sum2(acc, sh);
+        if (threadIdx.x == 0) hpart[((size_t)v * gridDim.x + blockIdx.x) * nstore + j] = s;
+    }
+}
+
+// pass 2: h_j = sum over blocks (fixed order)
+__global__ __launch_bounds__(256) void lz_reorth_fin_kernel(const double2* __restrict__ hpart,
+                                                            double2* __restrict__ hcoef,
+                                                            const LzState* __restrict__ st,
+                                                            const int* __restrict__ step,
+                                                            int nblk, int nstore) {
+    const int v = blockIdx.x;
+    if (st[v].done) return;
+    const int nj = *step + 1;
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int b = 0; b < nblk; ++b) s = cadd(s, hpart[((size_t)v * nblk + b) * nstore + j]);
+        hcoef[(size_t)v * nstore + j] = s;
+    }
+}
+
+// pass 3: w -= sum_j h_j basis_j
+__global__ __launch_bounds__(256) void lz_reorth_sub_kernel(const double2* __restrict__ basis,
+                                                            double2* __restrict__ w,
+                                                            const double2* __restrict__ hcoef,
+                                                            const LzState* __restrict__ st,
+                                                            const int* __restrict__ step,
+                                                            long long dim, long long per,
+                                                            int nstore) {
+    const int v = blockIdx.y;
+    if (st[v].done) return;
+    const int nj = *step + 1;
+    const long long s0 = (long long)blockIdx.x * per, s1 = min(dim, s0 + per);
+    for (long long e = s0 + threadIdx.x; e < s1; e += blockDim.x) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int j = 0; j < nj; ++j)
+            acc = cadd(acc, cmul(hcoef[(size_t)v * nstore + j], basis[((size_t)v * nstore + j) * dim + e]));
+        const size_t o = (size_t)v * dim + e;
+        w[o] = make_double2(w[o].x - acc.x, w[o].y - acc.y);
+    }
+}
+
+// b_{i+1} = sqrt(sum |w|^2 partials); breakdown test; record b
+__global__ __launch_bounds__(64) void lz_finalize_kernel(const double* __restrict__ part_n,
+                                                         LzState* __restrict__ st,
+                                                         double* __restrict__ b_out,
+                                                         const int* __restrict__ step, int n_steps,
+                                                         int nblk) {
+    const int v = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    LzState s = st[v];
+    if (s.done) return;
+    const int i = *step;
+    const double b = sqrt(sum_parts(part_n + (size_t)v * nblk, nblk));
+    s.scale = fmax(s.scale, fmax(fabs(s.a_cur), s.b_cur));
+    b_out[(size_t)v * n_steps + i] = b;
+    s.steps = i + 1;
+    if (b <= 1e-14 * s.scale) s.done = 1;
+    s.b_cur = b;
+    st[v] = s;
+}
+
+// vprev = v; v = w / b_{i+1}; basis[i+1] = v
+__global__ __launch_bounds__(256) void lz_scale_kernel(const double2* __restrict__ w,
+                                                       double2* __restrict__ vcur,
+                                                       double2* __restrict__ vprev,
+                                                       double2* __restrict__ basis,
+                                                       const LzState* __restrict__ st,
+                                                       const int* __restrict__ step, long long dim,
+                                                       long long per, int nstore) {
+    const int v = blockIdx.y;
+    if (st[v].done) return;
+    const double inv = 1.0 / st[v].b_cur;
+    const int i = *step;
+    const long long s0 = (long long)blockIdx.x * per, s1 = min(dim, s0 + per);
+    for (long long e = s0 + threadIdx.x; e < s1; e += blockDim.x) {
+        const size_t o = (size_t)v * dim + e;
+        const double2 ww = w[o];
+        const double2 q = make_double2(ww.x * inv, ww.y * inv);
+        vprev[o] = vcur[o];
+        vcur[o] = q;
+        if (basis && i + 1 < nstore) basis[((size_t)v * nstore + i + 1) * dim + e] = q;
+    }
+}
+
+__global__ void lz_advance_kernel(int* step) { *step += 1; }
+
+// ---- continued fraction -------------------------------------------------------------------------------
+__device__ __forceinline__ double2 cdiv1(double2 z) {  // 1 / z
+    const double d = z.x * z.x + z.y * z.y;
+    return make_double2(z.x / d, -z.y / d);
+}
+
+__device__ double2 csqrt_principal(double2 w) {
+    const double r = sqrt(w.x * w.x + w.y * w.y);
+    if (r == 0.0) return make_double2(0.0, 0.0);
+    const double s = sqrt(0.5 * (r + fabs(w.x)));
+    if (w.x >= 0.0) return make_double2(s, w.y / (2.0 * s));
+    return make_double2(fabs(w.y) / (2.0 * s), copysign(s, w.y));
+}
+
+__global__ __launch_bounds__(256) void spectrum_kernel(const double* __restrict__ a,
+                                                       const double* __restrict__ b,
+                                                       const int* __restrict__ n_used,
+                                                       const double* __restrict__ norm2,
+                                                       int n_spec, int n_steps, int terminator,
+                                                       const double* __restrict__ omega,
+                                                       int n_omega, double gamma,
+                                                       double* __restrict__ sigma) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n_spec * n_omega) return;
+    const int sp = (int)(idx / n_omega), o = (int)(idx - (long long)sp * n_omega);
+    const double* as = a + (size_t)sp * n_steps;
+    const double* bs = b + (size_t)sp * n_steps;
+    const int N = n_used ? n_used[sp] : n_steps;
+    const double2 z = make_double2(omega[o], gamma);
+    double2 g = make_double2(0.0, 0.0);
+    if (terminator == OCEAN_TERM_SQRT && N > 0) {
+        const int tail = N < 16 ? N : 16;
+        double ai = 0.0, bi = 0.0;
+        for (int j = N - tail; j < N; ++j) {
+            ai += as[j];
+            bi += bs[j];
+        }
+        ai /= tail;
+        bi /= tail;
+        const double2 zz = make_double2(z.x - ai, z.y);
+        const double2 disc = make_double2(zz.x * zz.x - zz.y * zz.y - 4.0 * bi * bi, 2.0 * zz.x * zz.y);
+        const double2 sq = csqrt_principal(disc);
+        const double den = 2.0 * bi * bi;
+        const double2 t1 = make_double2((zz.x - sq.x) / den, (zz.y - sq.y) / den);
+        const double2 t2 = make_double2((zz.x + sq.x) / den, (zz.y + sq.y) / den);
+        g = t1.y <= 0.0 ? t1 : t2;
+    }
+    for (int i = N - 1; i >= 0; --i) {
+        const double bb = bs[i] * bs[i];
+        const double2 den = make_double2(z.x - as[i] - bb * g.x, z.y - bb * g.y);
+        g = cdiv1(den);
+    }
+    sigma[idx] = -norm2[sp] * g.y * 0.31830988618379067154;  // 1/pi
+}
+
+// ---- set-up kernels ---------------------------------------------------------------------------------------
+// W[x][R] = W_rad(|minimum image of x + R - tau|), linear interpolation of the radial table
+__global__ __launch_bounds__(256) void build_w_kernel(double* __restrict__ W64, float* __restrict__ W32,
+                                                      const double* __restrict__ wr,
+                                                      const double* __restrict__ wv, int n_wr,
+                                                      double hstep, int n1, int n2, int n3,
+                                                      int g1, int g2, int g3, double c1, double c2,
+                                                      double c3, double t1, double t2, double t3) {
+    const long long Nk = (long long)n1 * n2 * n3;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long Nx = (long long)g1 * g2 * g3;
+    if (idx >= Nx * Nk) return;
+    const int x = (int)(idx / Nk), r = (int)(idx - (long long)x * Nk);
+    const int j3 = x % g3, j2 = (x / g3) % g2, j1 = x / (g2 * g3);
+    const int r3 = r % n3, r2 = (r / n3) % n2, r1 = r / (n2 * n3);
+    double d[3];
+    d[0] = c1 * ((double)j1 / g1 + r1) - t1;
+    d[1] = c2 * ((double)j2 / g2 + r2) - t2;
+    d[2] = c3 * ((double)j3 / g3 + r3) - t3;
+    const double side[3] = {c1 * n1, c2 * n2, c3 * n3};
+    double dist2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double m = d[a] - side[a] * rint(d[a] / side[a]);
+        dist2 += m * m;
+    }
+    const double dist = sqrt(dist2);
+    const double rmax = wr[n_wr - 1];
+    double val;
+    if (dist >= rmax) {
+        val = wv[n_wr - 1] * rmax / dist;
+    } else {
+        const double s = dist / hstep;
+        int j = (int)floor(s);
+        if (j > n_wr - 2) j = n_wr - 2;
+        const double t = s - j;
+        val = (1.0 - t) * wv[j] + t * wv[j + 1];
+    }
+    if (W64) W64[idx] = val;
+    if (W32) W32[idx] = (float)val;
+}
+
+__global__ __launch_bounds__(256) void to_fp32_kernel(const double* __restrict__ src,
+                                                      float* __restrict__ dst, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = i; e < n; e += stride) dst[e] = (float)src[e];
+}
+
+// psi0[p][kn][(mc, s)] = sum_m conj(A[kn][m]) d_p[m][mc]
+__global__ __launch_bounds__(256) void dipole_kernel(const double2* __restrict__ A,
+                                                     const double2* __restrict__ d,
+                                                     double2* __restrict__ psi0, int n_pol,
+                                                     long long NkNb) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n_pol * NkNb) return;
+    const int p = (int)(idx / NkNb);
+    const long long kn = idx - (long long)p * NkNb;
+    const double2* dp = d + (size_t)p * 15;
+    for (int mc = 0; mc < 3; ++mc) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int m = 0; m < 5; ++m) acc = cadd(acc, cmulc(A[kn * 5 + m], dp[m * 3 + mc]));
+        psi0[idx * 6 + mc * 2 + 0] = acc;
+        psi0[idx * 6 + mc * 2 + 1] = acc;
+    }
+}
+
+inline long long per_block(long long dim) { return (dim + kRedBlocks - 1) / kRedBlocks; }
+
+}  // namespace
+
+// ---- launchers ---------------------------------------------------------------------------------------------
+long long local_blocks(const ocean_bse_s* h) {
+    const long long NkNb = (long long)h->Nk * h->Nb;
+    long long nb = (NkNb + 255) / 256;
+    return nb < 120 ? nb : 120;
+}
+
+hipError_t launch_local_in(ocean_bse_s* h, const double* x, int nv) {
+    const long long NkNb = (long long)h->Nk * h->Nb;
+    const long long nblk = local_blocks(h);
+    const long long chunk = (NkNb + nblk - 1) / nblk;
+    const int slot = prof_begin(h, "local_in");
+    local_in_kernel<<<(unsigned)nblk, 256, 0, h->stream>>>(
+        reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(h->A),
+        reinterpret_cast<double2*>(h->ws.loc_part), nv, NkNb, h->Nc, h->Nmu, chunk);
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_mat(ocean_bse_s* h, int nv) {
+    const int slot = prof_begin(h, "local_mat");
+    local_mat_kernel<<<nv, 128, 0, h->stream>>>(reinterpret_cast<const double2*>(h->ws.loc_part),
+                                                reinterpret_cast<const double2*>(h->K),
+                                                reinterpret_cast<double2*>(h->ws.loc_b), nv,
+                                                h->Nc * h->Nmu, (int)local_blocks(h));
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(ocean_bse_s* h, const double* x, double* y, int nv, double* dot_part) {
+    const long long NkNb = (long long)h->Nk * h->Nb;
+    const long long per = (NkNb + kRedBlocks - 1) / kRedBlocks;
+    dim3 grid(kRedBlocks, nv);
+    const int has_w = 1;
+    const int slot = prof_begin(h, "combine");
+    combine_kernel<<<grid, 256, 0, h->stream>>>(
+        reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), h->E,
+        reinterpret_cast<const double2*>(h->Hc), reinterpret_cast<const double2*>(h->A),
+        reinterpret_cast<const double2*>(h->ws.loc_b), reinterpret_cast<const double2*>(h->ws.part),
+        h->ws.bwd_chunks, nv, NkNb, h->Nc, h->Nmu, h->Hc != nullptr, has_w, dot_part, per);
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t lz_init(ocean_bse_s* h, const double* psi0, int nv) {
+    const long long dim = (long long)h->Nk * h->Nb * h->Nc;
+    const long long per = per_block(dim);
+    dim3 grid(kRedBlocks, nv);
+    auto& L = h->lz;
+    const int nstore = L.n_steps + 1;
+    int slot = prof_begin(h, "lz_norm");
+    lz_norm_partial_kernel<<<grid, 256, 0, h->stream>>>(reinterpret_cast<const double2*>(psi0),
+                                                        L.part_n, dim, per);
+    prof_end(h, slot);
+    slot = prof_begin(h, "lz_init");
+    lz_init_kernel<<<grid, 256, 0, h->stream>>>(
+        reinterpret_cast<const double2*>(psi0), reinterpret_cast<double2*>(L.v),
+        reinterpret_cast<double2*>(L.vprev), reinterpret_cast<double2*>(L.basis), L.part_n,
+        L.state, L.step, dim, per, nstore);
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t lz_dot_vw(ocean_bse_s* h, int nv) {
+    const long long dim = (long long)h->Nk * h->Nb * h->Nc;
+    dim3 grid(kRedBlocks, nv);
+    const int slot = prof_begin(h, "lz_dot");
+    lz_dot_partial_kernel<<<grid, 256, 0, h->stream>>>(reinterpret_cast<const double2*>(h->lz.v),
+                                                       reinterpret_cast<const double2*>(h->lz.w),
+                                                       h->lz.part_a, dim, per_block(dim));
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t lz_update(ocean_bse_s* h, int nv, bool with_norm) {
+    const long long dim = (long long)h->Nk * h->Nb * h->Nc;
+    dim3 grid(kRedBlocks, nv);
+    auto& L = h->lz;
+    const int slot = prof_begin(h, "lz_update");
+    lz_update_kernel<<<grid, 256, 0, h->stream>>>(
+        reinterpret_cast<double2*>(L.w), reinterpret_cast<const double2*>(L.v),
+        reinterpret_cast<const double2*>(L.vprev), L.part_a, with_norm ? L.part_n : nullptr,
+        L.state, L.a, L.step, L.n_steps, dim, per_block(dim), kRedBlocks);
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t lz_reorth(ocean_bse_s* h, int nv) {
+    const long long dim = (long long)h->Nk * h->Nb * h->Nc;
+    dim3 grid(kRedBlocks, nv);
+    auto& L = h->lz;
+    const int nstore = L.n_steps + 1;
+    const int slot = prof_begin(h, "lz_reorth");
+    for (int pass = 0; pass < 2; ++pass) {
+        lz_reorth_dot_kernel<<<grid, 256, 0, h->stream>>>(
+            reinterpret_cast<const double2*>(L.basis), reinterpret_cast<const double2*>(L.w),
+            reinterpret_cast<double2*>(L.hpart), L.state, L.step, dim, per_block(dim), nstore);
+        lz_reorth_fin_kernel<<<nv, 256, 0, h->stream>>>(reinterpret_cast<const double2*>(L.hpart),
+                                                        reinterpret_cast<double2*>(L.hcoef),
+                                                        L.state, L.step, kRedBlocks, nstore);
+        lz_reorth_sub_kernel<<<grid, 256, 0, h->stream>>>(
+            reinterpret_cast<const double2*>(L.basis), reinterpret_cast<double2*>(L.w),
+            reinterpret_cast<const double2*>(L.hcoef), L.state, L.step, dim, per_block(dim), nstore);
+    }
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t lz_norm_w(ocean_bse_s* h, int nv) {
+    const long long dim = (long long)h->Nk * h->Nb * h->Nc;
+    dim3 grid(kRedBlocks, nv);
+    const int slot = prof_begin(h, "lz_norm");
+    lz_norm_partial_kernel<<<grid, 256, 0, h->stream>>>(reinterpret_cast<const double2*>(h->lz.w),
+                                                        h->lz.part_n, dim, per_block(dim));
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t lz_finalize(ocean_bse_s* h, int nv) {
+    const int slot = prof_begin(h, "lz_finalize");
+    lz_finalize_kernel<<<nv, 64, 0, h->stream>>>(h->lz.part_n, h->lz.state, h->lz.b, h->lz.step,
+                                                 h->lz.n_steps, kRedBlocks);
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t lz_scale(ocean_bse_s* h, int nv) {
+    const long long dim = (long long)h->Nk * h->Nb * h->Nc;
+    dim3 grid(kRedBlocks, nv);
+    auto& L = h->lz;
+    const int slot = prof_begin(h, "lz_scale");
+    lz_scale_kernel<<<grid, 256, 0, h->stream>>>(
+        reinterpret_cast<const double2*>(L.w), reinterpret_cast<double2*>(L.v),
+        reinterpret_cast<double2*>(L.vprev), reinterpret_cast<double2*>(L.basis), L.state, L.step,
+        dim, per_block(dim), L.n_steps + 1);
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t lz_advance(ocean_bse_s* h) {
+    lz_advance_kernel<<<1, 1, 0, h->stream>>>(h->lz.step);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectrum(const double* a, const double* b, const int* n_used, const double* norm2,
+                           int n_spec, int n_steps, int terminator, const double* omega,
+                           int n_omega, double gamma, double* sigma, hipStream_t stream) {
+    const long long n = (long long)n_spec * n_omega;
+    spectrum_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(
+        a, b, n_used, norm2, n_spec, n_steps, terminator, omega, n_omega, gamma, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_w(ocean_bse_s* h, const double* wr_dev, const double* wv_dev, int n_wr,
+                          double h_r) {
+    const long long n = (long long)h->Nx * h->Nk;
+    build_w_kernel<<<(unsigned)((n + 255) / 256), 256, 0, h->stream>>>(
+        h->W64, h->W32, wr_dev, wv_dev, n_wr, h_r, h->nk[0], h->nk[1], h->nk[2], h->nx[0],
+        h->nx[1], h->nx[2], h->cell[0], h->cell[1], h->cell[2], h->tau[0], h->tau[1], h->tau[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_fp32(ocean_bse_s* h, const double* src, float* dst, long long n) {
+    to_fp32_kernel<<<4096, 256, 0, h->stream>>>(src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dipole_psi0(ocean_bse_s* h, const double* d_dev, int n_pol, double* psi0) {
+    const long long NkNb = (long long)h->Nk * h->Nb;
+    const long long n = NkNb * n_pol;
+    dipole_kernel<<<(unsigned)((n + 255) / 256), 256, 0, h->stream>>>(
+        reinterpret_cast<const double2*>(h->A), reinterpret_cast<const double2*>(d_dev),
+        reinterpret_cast<double2*>(psi0), n_pol, NkNb);
+    return hipGetLastError();
+}
+
+}  // namespace ocean

@@ -127,7 +127,9 @@ def make_crystal(name: str, *, a: float, tau, nk, nx, n_bands: int, n_core: int,
     n_k = int(np.prod(nk))
     n_x = int(np.prod(nx))
     energies = np.sort(rng.uniform(0.0, e_range_ev, size=(n_k, n_bands)), axis=1) / HARTREE_EV
-    if u_override is not None:
+    if isinstance(u_override, str) and u_override == "skip":
+        u = None          # generated elsewhere (e.g. on the device); no host draw
+    elif u_override is not None:
         u = u_override
     else:
         u = np.empty((n_k, n_x, n_bands), dtype=np.complex128)

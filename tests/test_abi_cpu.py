@@ -1,0 +1,126 @@
+"""Boundary tests that need no GPU: the library loads, exports every symbol the
+header declares, its host helpers agree with the oracle, and argument
+validation rejects bad input before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1601_07728_amd as ob
+from oracle import multiplet as mp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ocean_bse.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ocean_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ob.LIB_PATH):
+        pytest.fail("libocean_bse.so is not built (run __graft_entry__.build())")
+    return ob.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = _declared_symbols()
+    assert len(syms) >= 13
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(ob.EXPORTED) == syms
+
+
+def test_multiplet_matrices_match_oracle_quadrature(lib):
+    """Closed-form (Racah 3j) helper vs the oracle's sphere quadrature."""
+    zeta, f2, g1, g3 = 0.14, 0.29, 0.22, 0.13
+    core, loc = ob.multiplet_matrices(zeta, f2, g1, g3)
+    mult = {"zeta": zeta, "F2": f2, "G1": g1, "G3": g3}
+    assert np.abs(core - mp.core_matrix(mult)).max() <= 1e-15
+    assert np.abs(loc - mp.local_matrix(mult)).max() <= 1e-14
+
+
+def test_dipole_amplitudes_match_oracle(lib):
+    for pol in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (0.3, -0.5, 0.81)]:
+        d = ob.dipole_amplitudes(pol)
+        assert np.abs(d - mp.dipole_amplitudes(pol)).max() <= 1e-14
+
+
+def test_spectrum_rejects_bad_arguments(lib):
+    a = np.zeros((1, 4))
+    om = np.linspace(0, 1, 5)
+    with pytest.raises(ob.OceanError) as e:
+        ob.spectrum(a, a, [1.0], om, gamma=0.0)
+    assert e.value.code == ob.ERR_INVALID_ARG
+    with pytest.raises(ob.OceanError):
+        ob.spectrum(a, a, [1.0], om, gamma=0.1, n_used=[9])
+
+
+def _desc(**over):
+    d = ob.Desc()
+    d.nk[:] = (2, 2, 2)
+    d.nx[:] = (4, 4, 4)
+    d.n_bands, d.n_core, d.n_local = 4, 2, 0
+    d.cell[:] = (7.0, 7.0, 7.0)
+    keep = []
+    e = np.zeros((8, 4))
+    u = np.zeros((8, 64, 4), dtype=np.complex128)
+    wr = np.linspace(0, 6, 64)
+    wv = np.ones(64)
+    keep += [e, u, wr, wv]
+    d.energies, d.u = ob._ptr(e), ob._ptr(u)
+    d.n_wr, d.w_r, d.w_val = 64, ob._ptr(wr), ob._ptr(wv)
+    d.precision = ob.PREC_FP64
+    for k, v in over.items():
+        if k == "w_r":
+            keep.append(v)
+            d.w_r = ob._ptr(v)
+        elif k == "energies":
+            keep.append(v)
+            d.energies = ob._ptr(v)
+        elif k in ("nk", "nx", "cell"):
+            getattr(d, k)[:] = v
+        else:
+            setattr(d, k, v)
+    return d, keep
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(n_bands=0), ob.ERR_INVALID_ARG),
+    (dict(nk=(0, 2, 2)), ob.ERR_INVALID_ARG),
+    (dict(nk=(17, 1, 1)), ob.ERR_UNSUPPORTED),
+    (dict(cell=(7.0, -1.0, 7.0)), ob.ERR_INVALID_ARG),
+    (dict(n_core=9), ob.ERR_UNSUPPORTED),
+    (dict(n_local=5), ob.ERR_INVALID_ARG),          # no projectors given
+    (dict(precision=7), ob.ERR_UNSUPPORTED),
+    (dict(w_r=np.linspace(1, 6, 64)), ob.ERR_INVALID_ARG),
+    (dict(w_r=np.linspace(0, 6, 64) ** 1.5), ob.ERR_INVALID_ARG),
+    (dict(energies=np.full((8, 4), np.nan), flags=ob.FLAG_CHECK_INPUTS), ob.ERR_INVALID_ARG),
+])
+def test_create_validates_before_device_work(lib, over, code):
+    d, keep = _desc(**over)
+    h = ctypes.c_void_p()
+    rc = lib.ocean_bse_create(ctypes.byref(d), None, ctypes.byref(h))
+    assert rc == code, lib.ocean_last_error()
+    assert not h.value
+    assert len(lib.ocean_last_error()) > 0
+
+
+def test_null_handle_calls(lib):
+    assert lib.ocean_bse_dim(None) == ob.ERR_INVALID_ARG
+    assert lib.ocean_bse_apply(None, None, None, 1) == ob.ERR_INVALID_ARG
+    assert lib.ocean_haydock(None, None, 1, 1, 0, None, None, None, None) == ob.ERR_INVALID_ARG
+    lib.ocean_bse_destroy(None)
+
+
+def test_binding_has_no_fallback(monkeypatch, tmp_path):
+    """With the library missing, the binding raises instead of computing anything."""
+    monkeypatch.setattr(ob, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(ob, "_lib", None)
+    with pytest.raises(RuntimeError):
+        ob.lib()

@@ -1,0 +1,220 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Tolerances (FP64 path): H*v to 1e-13 of max|y| (the two sides differ only in
+summation order, ~1e-16 per operation over <= 1e4-term sums); Haydock
+coefficients with re-orthogonalisation to 1e-10 of the spectral scale
+S = max|a| + 2 max b; spectra to 1e-10 of max sigma.  FP32 path: spectrum L1
+<= 1e-3 relative against the converged FP64 oracle spectrum."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bse as orc
+from oracle import multiplet as omp
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ob():
+    import paper_1601_07728_amd as ob
+    return ob
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_mats(cr, with_local=True):
+    if cr.multiplet is None:
+        return None, None
+    return omp.core_matrix(cr.multiplet), (omp.local_matrix(cr.multiplet) if with_local else None)
+
+
+def _to_dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+HV_CASES = {
+    "c1": lambda: synth.config1(),
+    "l_ragged": lambda: synth.small_l_edge(seed=3, nk=(2, 1, 2), nx=(4, 5, 3), n_bands=7),
+    "l_tiles": lambda: synth.small_l_edge(seed=4, nk=(4, 2, 2), nx=(10, 9, 11), n_bands=37),
+    "gamma": lambda: synth.small_l_edge(seed=5, nk=(1, 1, 1), nx=(12, 12, 12), n_bands=53),
+    "k8_axis": lambda: synth.small_l_edge(seed=6, nk=(8, 1, 3), nx=(3, 4, 5), n_bands=19),
+}
+
+
+@pytest.mark.parametrize("case", list(HV_CASES))
+@pytest.mark.parametrize("n_vec", [1, 3, 5])
+def test_apply_fp64_matches_oracle(case, n_vec):
+    ob = _ob()
+    cr = HV_CASES[case]()
+    _say(f"[apply fp64] case={case} n_vec={n_vec} nk={cr.nk} nx={cr.nx} nb={cr.n_bands}")
+    h = ob.Bse.from_crystal(cr, precision="fp64", check_inputs=True)
+    hc, kl = _oracle_mats(cr)
+    x = synth.complex_gaussian(np.random.default_rng(100 + n_vec),
+                               (n_vec, cr.n_k, cr.n_bands, cr.n_core))
+    y = h.apply(_to_dev(x)).cpu().numpy()
+    f = orc.dft_matrix(cr)
+    ut = orc.folded_u(cr)
+    w = orc.w_supercell(cr)
+    for v in range(n_vec):
+        ref = orc.apply_h(cr, x[v], hc, kl, ut=ut, w=w, f=f)
+        assert _rel(y[v], ref) <= 1e-13, (case, v, _rel(y[v], ref))
+    h.close()
+
+
+def test_apply_w_scaled_exercises_w0():
+    """W multiplied by 50 so the long-range term is O(1) of H: a sign or index
+    error in W0 cannot hide below the diagonal."""
+    ob = _ob()
+    cr = synth.small_l_edge(seed=8, nk=(2, 2, 2), nx=(6, 6, 6), n_bands=11)
+    cr.w_val = cr.w_val * 50.0
+    _say("[apply w x50]")
+    h = ob.Bse.from_crystal(cr, precision="fp64")
+    hc, kl = _oracle_mats(cr)
+    x = synth.complex_gaussian(np.random.default_rng(7), (cr.n_k, cr.n_bands, cr.n_core))
+    y = h.apply(_to_dev(x)).cpu().numpy()
+    ref = orc.apply_h(cr, x, hc, kl)
+    w0 = orc.apply_w0(cr, x)
+    assert np.abs(w0).max() > 0.3 * np.abs(ref).max()
+    assert _rel(y, ref) <= 1e-13
+
+
+@pytest.fixture(scope="module")
+def c1_oracle():
+    cr = synth.config1()
+    psi0 = cr.psi0[0]
+    a, b, n2, s, _ = orc.haydock(lambda v: orc.apply_h(cr, v), psi0, cr.n_steps, reorth=True)
+    sig = orc.spectrum(a, b, n2, cr.omega, cr.gamma)
+    ap, bp, _, _, basis = orc.haydock(lambda v: orc.apply_h(cr, v), psi0, cr.n_steps, reorth=False)
+    vs = np.stack([q.ravel() for q in basis])
+    ov = np.abs(vs.conj() @ vs.T - np.eye(len(vs)))
+    loss = [ov[:i + 1, :i + 1].max() for i in range(len(vs))]
+    return dict(cr=cr, a=a, b=b, n2=n2, sig=sig, ap=ap, bp=bp, loss=np.array(loss))
+
+
+def test_haydock_reorth_c1_matches_oracle(c1_oracle):
+    ob = _ob()
+    o = c1_oracle
+    cr = o["cr"]
+    _say("[haydock c1 reorth]")
+    h = ob.Bse.from_crystal(cr)
+    a, b, n2, sd, rc = h.haydock(_to_dev(cr.psi0), cr.n_steps, reorth=True)
+    S = np.abs(o["a"]).max() + 2 * o["b"].max()
+    assert sd[0] == cr.n_steps and rc == 0
+    assert abs(n2[0] - o["n2"]) <= 1e-13 * o["n2"]
+    assert np.abs(a[0] - o["a"]).max() <= 1e-10 * S
+    assert np.abs(b[0] - o["b"]).max() <= 1e-10 * S
+    sig = ob.spectrum(a, b, n2, cr.omega, cr.gamma)[0]
+    assert np.abs(sig - o["sig"]).max() <= 1e-10 * o["sig"].max()
+    # bitwise reproducible run to run (fixed reduction order)
+    a2, b2, _, _, _ = h.haydock(_to_dev(cr.psi0), cr.n_steps, reorth=True)
+    assert np.array_equal(a, a2) and np.array_equal(b, b2)
+    h.close()
+
+
+def test_haydock_plain_c1_prefix(c1_oracle):
+    """Without re-orthogonalisation, coefficients are compared while the oracle's
+    Lanczos basis is still orthogonal to 1e-8."""
+    ob = _ob()
+    o = c1_oracle
+    cr = o["cr"]
+    h = ob.Bse.from_crystal(cr)
+    a, b, n2, sd, rc = h.haydock(_to_dev(cr.psi0), cr.n_steps, reorth=False)
+    S = np.abs(o["ap"]).max() + 2 * o["bp"].max()
+    good = int(np.sum(o["loss"] < 1e-8)) - 1
+    assert good >= 30
+    assert np.abs(a[0, :good] - o["ap"][:good]).max() <= 1e-10 * S
+    assert np.abs(b[0, :good] - o["bp"][:good]).max() <= 1e-10 * S
+    h.close()
+
+
+def test_haydock_l_edge_multi_vector_reorth():
+    """L edge with spin-orbit and local term, three polarisation vectors at once."""
+    ob = _ob()
+    cr = synth.small_l_edge(seed=9, nk=(2, 2, 1), nx=(5, 6, 4), n_bands=9)
+    hc, kl = _oracle_mats(cr)
+    _say("[haydock L edge 3 vectors]")
+    h = ob.Bse.from_crystal(cr)
+    psi0 = h.dipole_psi0(np.eye(3))
+    p0 = psi0.cpu().numpy()
+    n_steps = 60
+    a, b, n2, sd, rc = h.haydock(psi0, n_steps, reorth=True)
+    for v in range(3):
+        ref0 = omp.dipole_psi0(cr.local_proj, np.eye(3)[v])
+        assert np.abs(p0[v] - ref0).max() <= 1e-14
+        ra, rb, rn2, rs, _ = orc.haydock(lambda q: orc.apply_h(cr, q, hc, kl), ref0, n_steps, reorth=True)
+        S = np.abs(ra).max() + 2 * rb.max()
+        assert sd[v] == rs
+        assert abs(n2[v] - rn2) <= 1e-13 * rn2
+        assert np.abs(a[v, :rs] - ra).max() <= 1e-10 * S
+        assert np.abs(b[v, :rs] - rb).max() <= 1e-10 * S
+    h.close()
+
+
+def test_breakdown_on_eigenvector():
+    ob = _ob()
+    cr = synth.config1()
+    cr.w_val = cr.w_val * 0.0
+    h = ob.Bse.from_crystal(cr)
+    psi0 = np.zeros((1, cr.n_k, cr.n_bands, cr.n_core), dtype=np.complex128)
+    psi0[0, 1, 3, 0] = 1.0
+    a, b, n2, sd, rc = h.haydock(_to_dev(psi0), 10)
+    assert rc == ob.INFO_INVARIANT_SUBSPACE and sd[0] == 1
+    assert abs(a[0, 0] - cr.energies[1, 3]) <= 1e-15 and b[0, 0] == 0.0
+    assert np.all(a[0, 1:] == 0)
+    h.close()
+
+
+def test_spectrum_kernel_matches_oracle():
+    ob = _ob()
+    rng = np.random.default_rng(12)
+    a = rng.uniform(-0.5, 0.5, (3, 40))
+    b = rng.uniform(0.05, 0.4, (3, 40))
+    n2 = np.array([1.0, 2.5, 0.3])
+    om = np.linspace(-1.5, 1.5, 777)
+    gam = 0.02
+    used = [40, 25, 17]
+    for term in ("none", "sqrt"):
+        sig = ob.spectrum(a, b, n2, om, gam, terminator=term, n_used=used)
+        for s in range(3):
+            ref = orc.spectrum(a[s, :used[s]], b[s, :used[s]], n2[s], om, gam, terminator=term)
+            assert np.abs(sig[s] - ref).max() <= 1e-12 * np.abs(ref).max(), (term, s)
+
+
+def test_fp32_spectrum_l1_within_1e_3():
+    """Mixed precision (FP32 projections, FP64 recursion) against the FP64 oracle
+    at a step count where the oracle spectrum is converged (full Krylov depth)."""
+    ob = _ob()
+    cr = synth.small_l_edge(seed=10, nk=(2, 2, 2), nx=(6, 6, 6), n_bands=10)
+    hc, kl = _oracle_mats(cr)
+    _say("[fp32 L1]")
+    h = ob.Bse.from_crystal(cr, precision="fp32")
+    psi0 = h.dipole_psi0([0, 0, 1])
+    p0 = psi0.cpu().numpy()[0]
+    hd = orc.h_dense(cr, hc, kl)
+    ref = orc.spectrum_dense(hd, p0, cr.omega, cr.gamma)
+    a, b, n2, sd, rc = h.haydock(psi0, cr.dim + 8, reorth=True)
+    sig = ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd)[0]
+    l1 = orc.l1_relative(sig, ref)
+    _say(f"fp32 L1 = {l1:.3e}")
+    assert l1 <= 1e-3
+    x = synth.complex_gaussian(np.random.default_rng(3), (cr.n_k, cr.n_bands, cr.n_core))
+    y = h.apply(_to_dev(x)).cpu().numpy()
+    yr = orc.apply_h(cr, x, hc, kl)
+    assert _rel(y, yr) <= 1e-5
+    h.close()
