@@ -15,8 +15,8 @@
 //            B = [[re phi, im phi], [im phi, -re phi]]
 //
 // MFMA operand layout (v_mfma_{f64,f32}_16x16x4): lane l = i + 16 kq holds
-// A[i][kq] and B[kq][i]; the result lane l holds rows 4 kq + r (r = 0..3) of
-// column i.  Inside one 16x16x4 step the four K slots kq map to the contraction
+// A[i][kq] and B[kq][i]; result register r of lane l holds column i of row
+// 4 r + kq (f64) or 4 kq + r (f32), as measured on gfx950.  Inside one 16x16x4 step the four K slots kq map to the contraction
 // index ((2 kq + s/2), s%2) for step s = 0..3, so every lane reads two adjacent
 // complex values of u (32 contiguous bytes in FP64).
 #include "internal.h"
@@ -39,6 +39,12 @@ template <> struct Cplx<double> { typedef double2 c2; typedef v4d acc; };
 template <> struct Cplx<float> { typedef float2 c2; typedef v4f acc; };
 
 template <typename C2> __device__ __forceinline__ C2 czero() { C2 z; z.x = 0; z.y = 0; return z; }
+
+// Row of the 16x16 result held in accumulator register r of a lane in group kq
+// (column = lane % 16).  The f64 and f32 16x16x4 instructions differ here.
+template <typename T> __device__ __forceinline__ int acc_row(int kq, int r);
+template <> __device__ __forceinline__ int acc_row<double>(int kq, int r) { return 4 * r + kq; }
+template <> __device__ __forceinline__ int acc_row<float>(int kq, int r) { return 4 * kq + r; }
 
 // ---------------------------------------------------------------------------------------------
 // Forward projection.  Block = 4 waves; wave w owns rows [xt*64*MS + w*16*MS, +16*MS) of one k.
@@ -119,7 +125,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
             if ((jr >> 1) >= ncb) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = rowbase + 16 * ms + 4 * kq + r;
+                const int row = rowbase + 16 * ms + acc_row<T>(kq, r);
                 if (row < Nx) out[(size_t)row * 2 * cols + jr] = acc[ms][t][r];
             }
         }
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(
             if ((jr >> 1) >= ncb) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int n = nbase + 16 * ms + 4 * kq + r;
+                const int n = nbase + 16 * ms + acc_row<T>(kq, r);
                 if (n < Nb) out[(size_t)n * 2 * cols + jr] = (double)acc[ms][t][r];
             }
         }
