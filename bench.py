@@ -133,18 +133,22 @@ def main():
     results["fp32"]["spectrum_l1_vs_fp64"] = l1
     log(f"fp32 vs fp64 spectrum L1 = {l1:.2e}")
 
-    # per-kernel HIP-event timing over the same number of steps (FP64 path)
-    h64.set_profiling(True)
-    h64.haydock(psi0, args.steps)
-    kt = h64.kernel_times()
-    h64.set_profiling(False)
-    avg = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
-    log("kernel averages (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in sorted(avg.items())))
+    # per-kernel HIP-event timing over the same number of steps, each precision
+    avgs = {}
+    for name, h in (("fp64", h64), ("fp32", h32)):
+        h.set_profiling(True)
+        h.haydock(psi0, args.steps)
+        kt = h.kernel_times()
+        h.set_profiling(False)
+        avgs[name] = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
+        log(f"{name} kernel averages (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in sorted(avgs[name].items())))
+    avg = avgs["fp64"]
     dom = max(("proj_fwd", "proj_bwd"), key=lambda k: avg.get(k, 0.0))
     ach = proj_bytes(cr, cols, 16) / (avg[dom] * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS, "traffic": None,
-                "kernel_ms": {k: round(v, 4) for k, v in avg.items()}}
+                "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
+                "kernel_ms_fp32": {k: round(v, 4) for k, v in avgs["fp32"].items()}}
 
     cpu = None
     if not args.no_cpu_baseline:

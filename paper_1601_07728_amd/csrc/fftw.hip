@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void fft_w_kernel(
         v.x = 0;
         v.y = 0;
         if (line < total) {
-            v = phi[(size_t)kk * total + line];
+            v = phi[phi_index(line, kk, Nk, cols)];
             const int x = (int)(line / cols);
             const int j3 = x % g3, j2 = (x / g3) % g2, j1 = x / (g2 * g3);
             const int i3 = kk % n3, i2 = (kk / n3) % n2, i1 = kk / (n2 * n3);
@@ -152,15 +152,246 @@ __global__ __launch_bounds__(256) void fft_w_kernel(
             C2 pc;
             pc.x = (T)p.x * inv_nk;
             pc.y = -(T)p.y * inv_nk;
-            phi[(size_t)kk * total + line] = cmul(buf[e], pc);
+            phi[phi_index(line, kk, Nk, cols)] = cmul(buf[e], pc);
         }
     }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Power-of-two k grids (every axis 1, 2, 4, 8 or 16): radix-2 FFTs in registers.
+// Five phases, three of them through LDS:
+//   P1 load z-pencils from HBM, phase e^{+ik.x}, forward FFT along k3  -> LDS
+//   P2 forward FFT along k2                                            (LDS -> LDS)
+//   P3 forward FFT along k1, multiply by W(x, R), inverse FFT along k1  (LDS -> LDS)
+//   P4 inverse FFT along k2                                            (LDS -> LDS)
+//   P5 inverse FFT along k3, phase e^{-ik.x} / Nk, store z-pencils to HBM
+// Threads map to pencils with the line index fastest, so 16 consecutive lanes
+// touch 16 consecutive lines (contiguous in HBM and conflict-free in LDS).
+
+// e^{2 pi i q / 16}, q = 0..15 (cos and sin of multiples of pi/8)
+__device__ __forceinline__ void unit16(int q, double& c, double& s) {
+    constexpr double c1 = 0.92387953251128674, c2 = 0.70710678118654752, c3 = 0.38268343236508977;
+    const double cq[8] = {1.0, c1, c2, c3, 0.0, -c3, -c2, -c1};  // cos(q pi / 8), q < 8
+    const double sq[8] = {0.0, c3, c2, c1, 1.0, c1, c2, c3};     // sin(q pi / 8), q < 8
+    q &= 15;
+    const double sgn = q < 8 ? 1.0 : -1.0;
+    c = sgn * cq[q & 7];
+    s = sgn * sq[q & 7];
+}
+
+// In-place radix-2 DIT transform X[a] = sum_b x[b] e^{sgn 2 pi i a b / N}, N a power of two <= 16.
+template <typename T, int N, int NMAX>
+__device__ __forceinline__ void fft_reg(typename C2T<T>::t (&v)[NMAX], bool inverse) {
+    typedef typename C2T<T>::t C2;
+    if (N == 1) return;
+    constexpr int LOG = N == 2 ? 1 : N == 4 ? 2 : N == 8 ? 3 : 4;
+    // bit reversal
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        int r = 0;
+#pragma unroll
+        for (int b = 0; b < LOG; ++b) r |= ((i >> b) & 1) << (LOG - 1 - b);
+        if (r > i) {
+            C2 t = v[i];
+            v[i] = v[r];
+            v[r] = t;
+        }
+    }
+#pragma unroll
+    for (int m = 2; m <= N; m *= 2) {
+#pragma unroll
+        for (int j = 0; j < m / 2; ++j) {
+            double c, sn;
+            unit16(j * (16 / m), c, sn);
+            const T wr = (T)c, wi = (T)(inverse ? -sn : sn);
+#pragma unroll
+            for (int k0 = 0; k0 < N; k0 += m) {
+                C2 u = v[k0 + j], t = v[k0 + j + m / 2];
+                C2 tw;
+                tw.x = t.x * wr - t.y * wi;
+                tw.y = t.x * wi + t.y * wr;
+                v[k0 + j].x = u.x + tw.x;
+                v[k0 + j].y = u.y + tw.y;
+                v[k0 + j + m / 2].x = u.x - tw.x;
+                v[k0 + j + m / 2].y = u.y - tw.y;
+            }
+        }
+    }
+}
+
+template <typename T, int NMAX>
+__device__ __forceinline__ void fft_any(typename C2T<T>::t (&v)[NMAX], int n, bool inverse) {
+    if (NMAX >= 2 && n == 2) fft_reg<T, (NMAX >= 2 ? 2 : 1), NMAX>(v, inverse);
+    if (NMAX >= 4 && n == 4) fft_reg<T, (NMAX >= 4 ? 4 : 1), NMAX>(v, inverse);
+    if (NMAX >= 8 && n == 8) fft_reg<T, (NMAX >= 8 ? 8 : 1), NMAX>(v, inverse);
+    if (NMAX >= 16 && n == 16) fft_reg<T, (NMAX >= 16 ? 16 : 1), NMAX>(v, inverse);
+}
+
+__device__ __forceinline__ double2 phase_of(const double2* __restrict__ ph, int kk, int x, int n2, int n3,
+                                            int g1, int g2, int g3, int po1, int po2, int po3) {
+    const int j3 = x % g3, j2 = (x / g3) % g2, j1 = x / (g2 * g3);
+    const int i3 = kk % n3, i2 = (kk / n3) % n2, i1 = kk / (n2 * n3);
+    const double2 p1 = ph[po1 + i1 * g1 + j1], p2 = ph[po2 + i2 * g2 + j2], p3 = ph[po3 + i3 * g3 + j3];
+    return cmul(cmul(p1, p2), p3);
+}
+
+// One LDS pass along an axis of extent n and k-stride st (P2 and P4).
+template <typename T, int NMAX>
+__device__ __forceinline__ void lds_pass(typename C2T<T>::t* buf, int n, int st, int Nk, int L,
+                                         bool inverse) {
+    typedef typename C2T<T>::t C2;
+    const int npen = (Nk / n) * L;
+    for (int p = threadIdx.x; p < npen; p += blockDim.x) {
+        const int l = p % L, u = p / L;
+        const int base = (u / st) * (n * st) + (u % st);
+        C2 v[NMAX];
+#pragma unroll
+        for (int b = 0; b < NMAX; ++b) v[b] = buf[(base + (b < n ? b : 0) * st) * L + l];
+        fft_any<T, NMAX>(v, n, inverse);
+#pragma unroll
+        for (int b = 0; b < NMAX; ++b)
+            if (b < n) buf[(base + b * st) * L + l] = v[b];
+    }
+}
+
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) void fft_w_pow2_kernel(
+    typename C2T<T>::t* __restrict__ phi, const T* __restrict__ W, const double2* __restrict__ ph,
+    int n1, int n2, int n3, int g1, int g2, int g3, int po1, int po2, int po3, int Nx, int cols,
+    int L) {
+    typedef typename C2T<T>::t C2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2* buf = reinterpret_cast<C2*>(smem);  // [Nk][L]
+    const int Nk = n1 * n2 * n3;
+    const int s3 = __ffs(n3) - 1, s2 = __ffs(n2) - 1;   // log2 of the power-of-two extents
+    const long long total = (long long)Nx * cols;
+    const long long line0 = (long long)blockIdx.x * L;
+    // the block's L lines lie in one x-block: element (kk, l) is at kbase + kk * xbc + l
+    const long long xbc = (long long)kXB * cols;
+    const long long xblk = line0 / xbc;
+    const size_t kbase = (size_t)(xblk * Nk) * xbc + (size_t)(line0 - xblk * xbc);
+    // every pencil loop below strides by 256 = a multiple of L, so a thread keeps one line
+    const int l = threadIdx.x % L;
+    const long long line = line0 + l;
+    const bool ok = line < total;
+    const int x = ok ? (int)(line / cols) : 0;
+    const int j3 = x % g3, j2 = (x / g3) % g2, j1 = x / (g2 * g3);
+    const double2* ph1 = ph + po1 + j1;
+    const double2* ph2 = ph + po2 + j2;
+    const double2* ph3 = ph + po3 + j3;
+    const T* wrow = W + (size_t)x * Nk;
+    C2* pl = phi + kbase + l;
+
+    // P1: HBM -> registers, phase, FFT along k3 -> LDS.  Addresses are clamped instead of
+    // branched on, so all loads of a pencil are in flight together (padding rows of the
+    // x-block are inside the allocation; their values are masked to zero).
+    {
+        const int npen = (Nk >> s3) * L;
+        for (int p = threadIdx.x; p < npen; p += blockDim.x) {
+            const int u = p / L;
+            C2 v[NMAX];
+#pragma unroll
+            for (int b = 0; b < NMAX; ++b) {
+                const int bb = b < n3 ? b : 0;
+                v[b] = pl[(size_t)((u << s3) + bb) * xbc];
+            }
+#pragma unroll
+            for (int b = 0; b < NMAX; ++b) {
+                const int bb = b < n3 ? b : 0;
+                const int kk = (u << s3) + bb;
+                const int i1 = kk >> (s2 + s3), i2 = (kk >> s3) & (n2 - 1);
+                const double2 pp = cmul(cmul(ph1[i1 * g1], ph2[i2 * g2]), ph3[bb * g3]);
+                C2 pc;
+                pc.x = ok ? (T)pp.x : (T)0;
+                pc.y = ok ? (T)pp.y : (T)0;
+                v[b] = cmul(v[b], pc);
+            }
+            fft_any<T, NMAX>(v, n3, false);
+#pragma unroll
+            for (int b = 0; b < NMAX; ++b)
+                if (b < n3) buf[((u << s3) + b) * L + l] = v[b];
+        }
+    }
+    __syncthreads();
+    // P2
+    if (n2 > 1) {
+        lds_pass<T, NMAX>(buf, n2, n3, Nk, L, false);
+        __syncthreads();
+    }
+    // P3: FFT along k1, W(x, R), inverse FFT along k1
+    {
+        const int st = n2 * n3;
+        const int npen = st * L;
+        for (int p = threadIdx.x; p < npen; p += blockDim.x) {
+            const int u = p / L;  // R index within (k2, k3)
+            C2 v[NMAX];
+#pragma unroll
+            for (int b = 0; b < NMAX; ++b) v[b] = buf[(u + (b < n1 ? b : 0) * st) * L + l];
+            fft_any<T, NMAX>(v, n1, false);
+            T wv[NMAX];
+#pragma unroll
+            for (int b = 0; b < NMAX; ++b) wv[b] = wrow[u + (b < n1 ? b : 0) * st];
+#pragma unroll
+            for (int b = 0; b < NMAX; ++b) {
+                const T w = ok ? wv[b] : (T)0;
+                v[b].x *= w;
+                v[b].y *= w;
+            }
+            fft_any<T, NMAX>(v, n1, true);
+#pragma unroll
+            for (int b = 0; b < NMAX; ++b)
+                if (b < n1) buf[(u + b * st) * L + l] = v[b];
+        }
+    }
+    __syncthreads();
+    // P4
+    if (n2 > 1) {
+        lds_pass<T, NMAX>(buf, n2, n3, Nk, L, true);
+        __syncthreads();
+    }
+    // P5: inverse FFT along k3, phase e^{-ik.x} / Nk, registers -> HBM
+    if (ok) {
+        const T inv_nk = (T)(1.0 / (double)Nk);
+        const int npen = (Nk >> s3) * L;
+        for (int p = threadIdx.x; p < npen; p += blockDim.x) {
+            const int u = p / L;
+            C2 v[NMAX];
+#pragma unroll
+            for (int b = 0; b < NMAX; ++b) v[b] = buf[((u << s3) + (b < n3 ? b : 0)) * L + l];
+            fft_any<T, NMAX>(v, n3, true);
+            C2 o[NMAX];
+#pragma unroll
+            for (int b = 0; b < NMAX; ++b) {
+                const int bb = b < n3 ? b : 0;
+                const int kk = (u << s3) + bb;
+                const int i1 = kk >> (s2 + s3), i2 = (kk >> s3) & (n2 - 1);
+                const double2 pp = cmul(cmul(ph1[i1 * g1], ph2[i2 * g2]), ph3[bb * g3]);
+                C2 pc;
+                pc.x = (T)pp.x * inv_nk;
+                pc.y = -(T)pp.y * inv_nk;
+                o[b] = cmul(v[b], pc);
+            }
+#pragma unroll
+            for (int b = 0; b < NMAX; ++b)
+                if (b < n3) pl[(size_t)((u << s3) + b) * xbc] = o[b];
+        }
+    }
+}
+
+bool is_pow2_grid(const ocean_bse_s* h) {
+    for (int a = 0; a < 3; ++a) {
+        const int n = h->nk[a];
+        if (n != 1 && n != 2 && n != 4 && n != 8 && n != 16) return false;
+    }
+    return true;
 }
 
 template <typename T>
 hipError_t fft_dispatch(ocean_bse_s* h, int cols, const T* W) {
     typedef typename C2T<T>::t C2;
-    const int L = h->fft_lines;
+    // lines of one block must stay inside one x-block of the phi layout
+    int L = h->fft_lines;
+    while (L > 1 && ((long long)kXB * cols) % L != 0) L /= 2;
     const long long total = (long long)h->Nx * cols;
     const unsigned nblk = (unsigned)((total + L - 1) / L);
     const size_t lds = sizeof(C2) * (3 * kMaxDft + (size_t)h->Nk * L);
@@ -168,6 +399,22 @@ hipError_t fft_dispatch(ocean_bse_s* h, int cols, const T* W) {
     C2* phi = static_cast<C2*>(h->ws.phi);
     const double2* ph = reinterpret_cast<const double2*>(h->phase);
     const double2* tw = reinterpret_cast<const double2*>(h->twiddle);
+    if (is_pow2_grid(h)) {
+        const size_t lds2 = sizeof(C2) * (size_t)h->Nk * L;
+#define OCEAN_POW2_ARGS                                                                            \
+    phi, W, ph, h->nk[0], h->nk[1], h->nk[2], h->nx[0], h->nx[1], h->nx[2], h->phase_off[0],        \
+        h->phase_off[1], h->phase_off[2], h->Nx, cols, L
+        if (nmax <= 2)
+            fft_w_pow2_kernel<T, 2><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
+        else if (nmax <= 4)
+            fft_w_pow2_kernel<T, 4><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
+        else if (nmax <= 8)
+            fft_w_pow2_kernel<T, 8><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
+        else
+            fft_w_pow2_kernel<T, 16><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
+#undef OCEAN_POW2_ARGS
+        return hipGetLastError();
+    }
 #define OCEAN_FFT_ARGS                                                                          \
     phi, W, ph, tw, h->nk[0], h->nk[1], h->nk[2], h->nx[0], h->nx[1], h->nx[2], h->phase_off[0], \
         h->phase_off[1], h->phase_off[2], h->tw_off[0], h->tw_off[1], h->tw_off[2], h->Nx, cols, L

@@ -19,6 +19,21 @@ constexpr int kMaxPairs = 128;  // Nc * Nmu limit of the local kernels
 constexpr int kMaxDft = 16;     // largest k-grid extent per axis
 constexpr int kColsPerPass = 24;  // exciton columns per projection launch (3 MFMA column tiles)
 constexpr int kRedBlocks = 240;   // blocks per vector in the Lanczos reductions
+constexpr int kXB = 16;           // x-block of the phi work array (a power of two: phi_index_x)
+
+// phi work array layout: [x / kXB][k][x % kXB][col] (complex).  A "line" is
+// line = x * cols + col; for a fixed k the lines of one x-block are contiguous,
+// so the k-grid transform touches one contiguous region per x-block.
+__host__ __device__ inline size_t phi_index(long long line, int k, int Nk, int cols) {
+    const long long xbc = (long long)kXB * cols;
+    const long long xb = line / xbc;
+    return (size_t)((xb * Nk + k) * xbc + (line - xb * xbc));
+}
+
+// Same index from the point x and column col (no division: kXB is a power of two).
+__host__ __device__ inline size_t phi_index_x(int x, int col, int k, int Nk, int cols) {
+    return ((size_t)((x >> 4) * Nk + k) * kXB + (x & (kXB - 1))) * cols + col;
+}
 
 // Per-vector Lanczos state kept on the device.
 struct LzState {
@@ -141,7 +156,7 @@ hipError_t launch_spectrum(const double* a, const double* b, const int* n_used, 
                            int n_omega, double gamma, double* sigma, hipStream_t stream);
 
 // geometry helpers
-int bwd_ms(int Nb);
+int bwd_waves(int Nb);
 void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk);
 size_t fft_lds_bytes(const ocean_bse_s* h, int lines);
 long long local_blocks(const ocean_bse_s* h);

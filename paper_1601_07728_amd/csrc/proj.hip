@@ -46,15 +46,39 @@ template <typename T> __device__ __forceinline__ int acc_row(int kq, int r);
 template <> __device__ __forceinline__ int acc_row<double>(int kq, int r) { return 4 * r + kq; }
 template <> __device__ __forceinline__ int acc_row<float>(int kq, int r) { return 4 * kq + r; }
 
+// Raw buffer loads: the hardware returns zero for byte offsets at or beyond the
+// descriptor's extent, so masked elements are loaded from an out-of-range offset
+// instead of behind a branch (which would serialise the loads).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr unsigned kOob = 0xFFFFFFF0u;  // an offset beyond every descriptor extent
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, size_t bytes) {
+    const unsigned n = bytes >= 0xFFFFFFF0ull ? 0xFFFFFFF0u : (unsigned)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, 0x00020000);
+}
+template <typename C2> __device__ __forceinline__ C2 bload(Rsrc r, unsigned off);
+template <> __device__ __forceinline__ double2 bload<double2>(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ float2 bload<float2>(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
 // ---------------------------------------------------------------------------------------------
-// Forward projection.  Block = 4 waves; wave w owns rows [xt*64*MS + w*16*MS, +16*MS) of one k.
-template <typename T, int MS, int NT>
+// Forward projection.  Block = 4 waves and one k; wave w owns rows
+// [xt*64*MS + w*16*MS, +16*MS) and every column tile.  The bands are walked in chunks of
+// KC: the chunk of psi (the B operand, shared by all waves) is staged in LDS, double
+// buffered, while each wave keeps the u values (A operand) of the next chunk in flight in
+// registers.
+template <typename T, int MS, int NT, int KC>
 __global__ __launch_bounds__(256) void proj_fwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const double2* __restrict__ psi,
     typename Cplx<T>::c2* __restrict__ phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0,
     int ncb, int x_tiles) {
     typedef typename Cplx<T>::c2 C2;
     typedef typename Cplx<T>::acc ACC;
+    constexpr int SS = KC / 8;                 // 8-band sub-steps per chunk
+    __shared__ double2 sP[2][KC * kColsPerPass];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
     const int k = blockIdx.x / x_tiles;
@@ -63,24 +87,61 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
     const C2* Uk = U + (size_t)k * Nx * Nb;
     const int q = i & 1;
 
-    const double2* pcol[NT];
+    int lcol[NT];
     bool cval[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int cl = (16 * t + i) >> 1;
         cval[t] = cl < ncb;
-        const int col = col0 + (cval[t] ? cl : 0);
-        const int v = col / Nc, c = col - v * Nc;
-        pcol[t] = psi + ((size_t)(v * Nk + k) * Nb) * Nc + c;
+        lcol[t] = cval[t] ? cl : 0;
     }
+    // u rows of this block: [xt*64*MS, min(Nx, (xt+1)*64*MS)), all bands
+    const int brow0 = xt * (64 * MS);
+    const int brows = min(Nx - brow0, 64 * MS);
+    const Rsrc ur = make_rsrc(Uk + (size_t)brow0 * Nb, (size_t)brows * Nb * sizeof(C2));
+    const Rsrc pr = make_rsrc(psi, (size_t)(col0 + ncb + Nc) / Nc * Nk * Nb * Nc * sizeof(double2));
     bool rval[MS];
-    const C2* urow[MS];
+    unsigned urow[MS];
 #pragma unroll
     for (int ms = 0; ms < MS; ++ms) {
         const int row = rowbase + 16 * ms + i;
         rval[ms] = row < Nx;
-        urow[ms] = Uk + (size_t)(rval[ms] ? row : 0) * Nb;
+        urow[ms] = (unsigned)((row - brow0) * Nb) * sizeof(C2);
     }
+    // cooperative psi chunk loads: element e = (n_local, c_local)
+    constexpr int PER = (KC * kColsPerPass + 255) / 256;
+    auto load_p = [&](int n0, double2 (&pv)[PER]) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            const int nl = e / kColsPerPass, cl = e - nl * kColsPerPass;
+            const int n = n0 + nl;
+            const bool ok = nl < KC && cl < ncb && n < Nb;
+            const int col = col0 + cl;
+            const int vv = col / Nc, c = col - vv * Nc;
+            const unsigned off = (unsigned)((((size_t)(vv * Nk + k) * Nb + n) * Nc + c) * sizeof(double2));
+            pv[j] = bload<double2>(pr, ok ? off : kOob);
+        }
+    };
+    auto store_p = [&](int buf, const double2 (&pv)[PER]) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            if (e < KC * kColsPerPass) sP[buf][e] = pv[j];
+        }
+    };
+    auto load_a = [&](int n0, C2 (&aa)[MS][SS][2]) {
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss)
+#pragma unroll
+            for (int ns = 0; ns < 2; ++ns) {
+                const int n = n0 + 8 * ss + 2 * kq + ns;
+                const bool nok = n < Nb;
+#pragma unroll
+                for (int ms = 0; ms < MS; ++ms)
+                    aa[ms][ss][ns] = bload<C2>(ur, (nok && rval[ms]) ? urow[ms] + (unsigned)(n * sizeof(C2)) : kOob);
+            }
+    };
 
     ACC acc[MS][NT];
 #pragma unroll
@@ -88,35 +149,54 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[ms][t] = ACC{0, 0, 0, 0};
 
-    for (int n0 = 0; n0 < Nb; n0 += 8) {
-        C2 a[MS][2];
-        T bv[NT][4];
+    C2 a[MS][SS][2], an[MS][SS][2];
+    double2 pv[PER];
+    load_p(0, pv);
+    load_a(0, a);
+    // Drain the prologue loads here: otherwise the wait-count analysis merges this path into
+    // the loop header and waits for every in-flight prefetch before the first MFMA of a chunk.
+    __builtin_amdgcn_s_waitcnt(0);
+    store_p(0, pv);
+    int buf = 0;
+    for (int n0 = 0; n0 < Nb; n0 += KC) {
+        __syncthreads();
+        // next chunk (masked to zero past the last band)
+        load_p(n0 + KC, pv);
+        load_a(n0 + KC, an);
 #pragma unroll
-        for (int ns = 0; ns < 2; ++ns) {
-            const int n = n0 + 2 * kq + ns;
-            const bool nok = n < Nb;
+        for (int ss = 0; ss < SS; ++ss) {
+            T bv[NT][4];
 #pragma unroll
-            for (int ms = 0; ms < MS; ++ms) a[ms][ns] = (nok && rval[ms]) ? urow[ms][n] : czero<C2>();
+            for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                double2 p = (nok && cval[t]) ? pcol[t][(size_t)n * Nc] : czero<double2>();
-                // B[(n, 0)][(c, q)] and B[(n, 1)][(c, q)]
-                bv[t][2 * ns + 0] = (T)(q ? p.y : p.x);
-                bv[t][2 * ns + 1] = (T)(q ? p.x : -p.y);
+                for (int ns = 0; ns < 2; ++ns) {
+                    const double2 p = sP[buf][(8 * ss + 2 * kq + ns) * kColsPerPass + lcol[t]];
+                    // B[(n, 0)][(c, q)] and B[(n, 1)][(c, q)]; zero for padding columns
+                    bv[t][2 * ns + 0] = cval[t] ? (T)(q ? p.y : p.x) : (T)0;
+                    bv[t][2 * ns + 1] = cval[t] ? (T)(q ? p.x : -p.y) : (T)0;
+                }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+#pragma unroll
+                for (int ms = 0; ms < MS; ++ms) {
+                    const T av = (s & 1) ? a[ms][ss][s >> 1].y : a[ms][ss][s >> 1].x;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[ms][t] = mfma16(av, bv[t][s], acc[ms][t]);
+                }
             }
         }
+        store_p(buf ^ 1, pv);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int ms = 0; ms < MS; ++ms)
 #pragma unroll
-            for (int ms = 0; ms < MS; ++ms) {
-                const T av = (s & 1) ? a[ms][s >> 1].y : a[ms][s >> 1].x;
-#pragma unroll
-                for (int t = 0; t < NT; ++t) acc[ms][t] = mfma16(av, bv[t][s], acc[ms][t]);
+            for (int ss = 0; ss < SS; ++ss) {
+                a[ms][ss][0] = an[ms][ss][0];
+                a[ms][ss][1] = an[ms][ss][1];
             }
-        }
+        buf ^= 1;
     }
 
-    T* out = reinterpret_cast<T*>(phi) + (size_t)k * Nx * 2 * cols + 2 * col0;
+    T* out = reinterpret_cast<T*>(phi);
 #pragma unroll
     for (int ms = 0; ms < MS; ++ms)
 #pragma unroll
@@ -126,22 +206,26 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = rowbase + 16 * ms + acc_row<T>(kq, r);
-                if (row < Nx) out[(size_t)row * 2 * cols + jr] = acc[ms][t][r];
+                if (row < Nx)
+                    out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = acc[ms][t][r];
             }
         }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Backward projection with split-K over x.  Block = (k, band block, x chunk); the four waves
-// take interleaved groups of 8 points of the chunk and are summed through LDS in wave order.
-template <typename T, int MS, int NT>
-__global__ __launch_bounds__(256) void proj_bwd_kernel(
+// Backward projection with split-K over x.  Block = (k, band block of W x 16 bands,
+// x chunk); wave w owns the 16 bands [band block * 16 W + 16 w, +16).  The chunk is walked
+// in tiles of XT points: the phi' tile (B operand, shared by all waves) is staged in LDS,
+// double buffered, and every wave keeps the u values of the next tile in flight.
+template <typename T, int NT, int XT, int W>
+__global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const typename Cplx<T>::c2* __restrict__ phi,
     double* __restrict__ part, int Nk, int Nx, int Nb, int cols, int col0, int ncb,
     int band_blocks, int S, int chunk) {
     typedef typename Cplx<T>::c2 C2;
     typedef typename Cplx<T>::acc ACC;
-    __shared__ ACC red[3][64];
+    constexpr int SS = XT / 8;
+    __shared__ C2 sB[2][XT * kColsPerPass];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
     int blk = blockIdx.x;
@@ -149,98 +233,118 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(
     blk /= S;
     const int bb = blk % band_blocks;
     const int k = blk / band_blocks;
-    const int nbase = bb * 16 * MS;
+    const int nbase = bb * 16 * W + 16 * wave;
     const int x_begin = s * chunk;
     const int x_end = min(Nx, x_begin + chunk);
     const C2* Uk = U + (size_t)k * Nx * Nb;
-    const C2* Pk = phi + (size_t)k * Nx * cols;
     const int q = i & 1;
 
-    int pcol[NT];
+    int lcol[NT];
     bool cval[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int cl = (16 * t + i) >> 1;
         cval[t] = cl < ncb;
-        pcol[t] = col0 + (cval[t] ? cl : 0);
+        lcol[t] = cval[t] ? cl : 0;
     }
-    bool nval[MS];
-    int ncol[MS];
-#pragma unroll
-    for (int ms = 0; ms < MS; ++ms) {
-        const int n = nbase + 16 * ms + i;
-        nval[ms] = n < Nb;
-        ncol[ms] = nval[ms] ? n : 0;
-    }
+    const int n = nbase + i;
+    const bool nval = n < Nb;
+    // u rows [x_begin, x_end) of this k, all bands; phi' x-blocks covering the chunk
+    const Rsrc ur = make_rsrc(Uk + (size_t)x_begin * Nb, (size_t)(x_end - x_begin) * Nb * sizeof(C2));
+    const int xb0 = x_begin / kXB;
+    const C2* pbase = phi + (size_t)xb0 * Nk * kXB * cols;
+    const Rsrc prs = make_rsrc(pbase, (size_t)((x_end - 1) / kXB - xb0 + 1) * Nk * kXB * cols * sizeof(C2));
 
-    ACC acc[MS][NT];
+    constexpr int PER = (XT * kColsPerPass + 64 * W - 1) / (64 * W);
+    auto load_b = [&](int x0, C2 (&bv)[PER]) {
 #pragma unroll
-    for (int ms = 0; ms < MS; ++ms)
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + 64 * W * j;
+            const int xl = e / kColsPerPass, cl = e - xl * kColsPerPass;
+            const int x = x0 + xl;
+            const bool ok = xl < XT && cl < ncb && x < x_end;
+            const unsigned off = (unsigned)((phi_index_x(x, col0 + cl, k, Nk, cols) - (size_t)xb0 * Nk * kXB * cols) * sizeof(C2));
+            bv[j] = bload<C2>(prs, ok ? off : kOob);
+        }
+    };
+    auto store_b = [&](int buf, const C2 (&bv)[PER]) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[ms][t] = ACC{0, 0, 0, 0};
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + 64 * W * j;
+            if (e < XT * kColsPerPass) sB[buf][e] = bv[j];
+        }
+    };
+    auto load_a = [&](int x0, C2 (&aa)[SS][2]) {
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss)
+#pragma unroll
+            for (int xs = 0; xs < 2; ++xs) {
+                const int x = x0 + 8 * ss + 2 * kq + xs;
+                const bool ok = nval && x < x_end;
+                aa[ss][xs] = bload<C2>(ur, ok ? (unsigned)(((x - x_begin) * Nb + n) * sizeof(C2)) : kOob);
+            }
+    };
 
-    for (int xb = x_begin + 8 * wave; xb < x_end; xb += 32) {
-        C2 a[MS][2];
-        T bv[NT][4];
+    ACC acc[NT];
 #pragma unroll
-        for (int xs = 0; xs < 2; ++xs) {
-            const int x = xb + 2 * kq + xs;
-            const bool xok = x < x_end;
-            const C2* ur = Uk + (size_t)(xok ? x : 0) * Nb;
+    for (int t = 0; t < NT; ++t) acc[t] = ACC{0, 0, 0, 0};
+
+    C2 a[SS][2], an[SS][2];
+    C2 bl[PER];
+    load_b(x_begin, bl);
+    load_a(x_begin, a);
+    __builtin_amdgcn_s_waitcnt(0);  // drain the prologue (see the forward kernel)
+    store_b(0, bl);
+    int buf = 0;
+    for (int x0 = x_begin; x0 < x_end; x0 += XT) {
+        __syncthreads();
+        // next tile (masked to zero past the chunk end)
+        load_b(x0 + XT, bl);
+        load_a(x0 + XT, an);
 #pragma unroll
-            for (int ms = 0; ms < MS; ++ms) a[ms][xs] = (xok && nval[ms]) ? ur[ncol[ms]] : czero<C2>();
-            const C2* pr = Pk + (size_t)(xok ? x : 0) * cols;
+        for (int ss = 0; ss < SS; ++ss) {
+            T bv[NT][4];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                C2 p = (xok && cval[t]) ? pr[pcol[t]] : czero<C2>();
-                // B[(x, 0)][(c, q)] and B[(x, 1)][(c, q)]
-                bv[t][2 * xs + 0] = q ? p.y : p.x;
-                bv[t][2 * xs + 1] = q ? -p.x : p.y;
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int xs = 0; xs < 2; ++xs) {
+                    const C2 p = sB[buf][(8 * ss + 2 * kq + xs) * kColsPerPass + lcol[t]];
+                    // B[(x, 0)][(c, q)] and B[(x, 1)][(c, q)]; zero for padding columns
+                    bv[t][2 * xs + 0] = cval[t] ? (q ? p.y : p.x) : (T)0;
+                    bv[t][2 * xs + 1] = cval[t] ? (q ? -p.x : p.y) : (T)0;
+                }
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const T av = (st & 1) ? a[ss][st >> 1].y : a[ss][st >> 1].x;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = mfma16(av, bv[t][st], acc[t]);
             }
         }
+        store_b(buf ^ 1, bl);
 #pragma unroll
-        for (int st = 0; st < 4; ++st) {
-#pragma unroll
-            for (int ms = 0; ms < MS; ++ms) {
-                const T av = (st & 1) ? a[ms][st >> 1].y : a[ms][st >> 1].x;
-#pragma unroll
-                for (int t = 0; t < NT; ++t) acc[ms][t] = mfma16(av, bv[t][st], acc[ms][t]);
-            }
+        for (int ss = 0; ss < SS; ++ss) {
+            a[ss][0] = an[ss][0];
+            a[ss][1] = an[ss][1];
         }
+        buf ^= 1;
     }
-
-    // deterministic cross-wave sum: ((w0 + w1) + w2) + w3
-#pragma unroll
-    for (int ms = 0; ms < MS; ++ms)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            if (wave > 0) red[wave - 1][lane] = acc[ms][t];
-            __syncthreads();
-            if (wave == 0) {
-                ACC v = acc[ms][t];
-                v += red[0][lane];
-                v += red[1][lane];
-                v += red[2][lane];
-                acc[ms][t] = v;
-            }
-            __syncthreads();
-        }
-    if (wave != 0) return;
 
     double* out = part + ((size_t)s * Nk + k) * Nb * 2 * cols + 2 * col0;
 #pragma unroll
-    for (int ms = 0; ms < MS; ++ms)
+    for (int t = 0; t < NT; ++t) {
+        const int jr = 16 * t + i;
+        if ((jr >> 1) >= ncb) continue;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int jr = 16 * t + i;
-            if ((jr >> 1) >= ncb) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int n = nbase + 16 * ms + acc_row<T>(kq, r);
-                if (n < Nb) out[(size_t)n * 2 * cols + jr] = (double)acc[ms][t][r];
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int nn = nbase + acc_row<T>(kq, r);
+            if (nn < Nb) out[(size_t)nn * 2 * cols + jr] = (double)acc[t][r];
         }
+    }
 }
+
+template <typename T> struct Tiles;
+template <> struct Tiles<double> { static constexpr int KC = 16, XT = 32; };
+template <> struct Tiles<float> { static constexpr int KC = 32, XT = 64; };
 
 template <typename T, int MS>
 hipError_t fwd_dispatch_nt(int NT, dim3 grid, hipStream_t st, const void* U, const double* x,
@@ -251,64 +355,62 @@ hipError_t fwd_dispatch_nt(int NT, dim3 grid, hipStream_t st, const void* U, con
     C2* p = static_cast<C2*>(phi);
     const double2* ps = reinterpret_cast<const double2*>(x);
     switch (NT) {
-        case 1: proj_fwd_kernel<T, MS, 1><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
-        case 2: proj_fwd_kernel<T, MS, 2><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
-        default: proj_fwd_kernel<T, MS, 3><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
+        case 1: proj_fwd_kernel<T, MS, 1, Tiles<T>::KC><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
+        case 2: proj_fwd_kernel<T, MS, 2, Tiles<T>::KC><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
+        default: proj_fwd_kernel<T, MS, 3, Tiles<T>::KC><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
     }
     return hipGetLastError();
 }
 
-template <typename T, int MS>
-hipError_t bwd_dispatch_nt(int NT, dim3 grid, hipStream_t st, const void* U, const void* phi,
-                           double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb,
-                           int bb, int S, int chunk) {
+template <typename T, int W>
+hipError_t bwd_dispatch_w(int NT, dim3 grid, hipStream_t st, const void* U, const void* phi,
+                          double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int bb,
+                          int S, int chunk) {
     typedef typename Cplx<T>::c2 C2;
+    constexpr int XT = Tiles<T>::XT;
     const C2* u = static_cast<const C2*>(U);
     const C2* p = static_cast<const C2*>(phi);
     switch (NT) {
-        case 1: proj_bwd_kernel<T, MS, 1><<<grid, 256, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
-        case 2: proj_bwd_kernel<T, MS, 2><<<grid, 256, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
-        default: proj_bwd_kernel<T, MS, 3><<<grid, 256, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
+        case 1: proj_bwd_kernel<T, 1, XT, W><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
+        case 2: proj_bwd_kernel<T, 2, XT, W><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
+        default: proj_bwd_kernel<T, 3, XT, W><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t bwd_dispatch(int MS, int NT, dim3 grid, hipStream_t st, const void* U, const void* phi,
+hipError_t bwd_dispatch(int W, int NT, dim3 grid, hipStream_t st, const void* U, const void* phi,
                         double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int bb,
                         int S, int chunk) {
-    switch (MS) {
-        case 1: return bwd_dispatch_nt<T, 1>(NT, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
-        case 2: return bwd_dispatch_nt<T, 2>(NT, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
-        case 4: return bwd_dispatch_nt<T, 4>(NT, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
-        case 6: return bwd_dispatch_nt<T, 6>(NT, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
-        default: return bwd_dispatch_nt<T, 8>(NT, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
+    switch (W) {
+#define OCEAN_BWD_W(w) \
+        case w: return bwd_dispatch_w<T, w>(NT, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
+        OCEAN_BWD_W(1) OCEAN_BWD_W(2) OCEAN_BWD_W(3) OCEAN_BWD_W(4) OCEAN_BWD_W(5) OCEAN_BWD_W(6)
+        OCEAN_BWD_W(7)
+#undef OCEAN_BWD_W
+        default: return bwd_dispatch_w<T, 8>(NT, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
     }
 }
 
 }  // namespace
 
-// Band-subtile count per wave for the backward projection: the smallest supported
-// MS covering all bands (one band block), capped at 8.
-int bwd_ms(int Nb) {
+// Backward-projection geometry: band blocks of up to 8 waves x 16 bands, and x chunks
+// (multiples of 8 points) so that the grid holds about bwd_target_blocks blocks.
+int bwd_waves(int Nb) {
     const int nb16 = (Nb + 15) / 16;
-    if (nb16 <= 1) return 1;
-    if (nb16 <= 2) return 2;
-    if (nb16 <= 4) return 4;
-    if (nb16 <= 6) return 6;
-    return 8;
+    return nb16 < 8 ? nb16 : 8;
 }
 
 void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk) {
-    const int ms = bwd_ms(h->Nb);
-    const int bb = (h->Nb + 16 * ms - 1) / (16 * ms);
+    const int W = bwd_waves(h->Nb);
+    const int bb = (h->Nb + 16 * W - 1) / (16 * W);
     const long long per_chunk = (long long)h->Nk * bb;
     long long s = (h->bwd_target_blocks + per_chunk - 1) / per_chunk;
-    const long long smax = (h->Nx + 31) / 32;
+    const long long smax = (h->Nx + 63) / 64;
     if (s < 1) s = 1;
     if (s > smax) s = smax;
     int c = (int)((h->Nx + s - 1) / s);
-    c = (c + 31) / 32 * 32;
+    c = (c + 7) / 8 * 8;
     *chunk = c;
     *S = (h->Nx + c - 1) / c;
     *band_blocks = bb;
@@ -318,7 +420,7 @@ hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, in
     constexpr int MS = 2;
     const int cols = nv * h->Nc;
     const int NT = (2 * ncb + 15) / 16;
-    const int x_tiles = (h->Nx + 64 * MS - 1) / (64 * MS);
+    const int x_tiles = (h->Nx + 64 * MS - 1) / (64 * MS);  // rows per block: 64 MS
     dim3 grid((unsigned)(h->Nk * x_tiles));
     const int slot = prof_begin(h, "proj_fwd");
     hipError_t e;
@@ -337,15 +439,15 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     const int NT = (2 * ncb + 15) / 16;
     int bb, S, chunk;
     bwd_geometry(h, &bb, &S, &chunk);
-    const int ms = bwd_ms(h->Nb);
+    const int W = bwd_waves(h->Nb);
     dim3 grid((unsigned)((long long)h->Nk * bb * S));
     const int slot = prof_begin(h, "proj_bwd");
     hipError_t e;
     if (h->precision == OCEAN_PREC_FP64)
-        e = bwd_dispatch<double>(ms, NT, grid, h->stream, h->U64, h->ws.phi, h->ws.part, h->Nk,
+        e = bwd_dispatch<double>(W, NT, grid, h->stream, h->U64, h->ws.phi, h->ws.part, h->Nk,
                                  h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
     else
-        e = bwd_dispatch<float>(ms, NT, grid, h->stream, h->U32, h->ws.phi, h->ws.part, h->Nk,
+        e = bwd_dispatch<float>(W, NT, grid, h->stream, h->U32, h->ws.phi, h->ws.part, h->Nk,
                                 h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
     prof_end(h, slot);
     return e;

@@ -143,7 +143,8 @@ static int ensure_workspace(ocean_bse_s* h, int nv) {
     int bb, S, chunk;
     bwd_geometry(h, &bb, &S, &chunk);
     const size_t elem = h->precision == OCEAN_PREC_FP64 ? 16 : 8;
-    const size_t phi_b = (size_t)h->Nk * h->Nx * cols * elem;
+    const size_t nx_pad = ((size_t)h->Nx + kXB - 1) / kXB * kXB;
+    const size_t phi_b = (size_t)h->Nk * nx_pad * cols * elem;
     const size_t part_b = (size_t)S * h->Nk * h->Nb * cols * 16;
     const int NP = std::max(1, h->Nc * h->Nmu);
     const size_t locp_b = (size_t)local_blocks(h) * nv * NP * 16;
