@@ -160,9 +160,11 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
     int buf = 0;
     for (int n0 = 0; n0 < Nb; n0 += KC) {
         __syncthreads();
-        // next chunk (masked to zero past the last band)
+        // next chunk (masked to zero past the last band); the scheduling barrier keeps these
+        // loads at the top so that they overlap the MFMAs of the current chunk
         load_p(n0 + KC, pv);
         load_a(n0 + KC, an);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
             T bv[NT][4];
@@ -298,9 +300,10 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     int buf = 0;
     for (int x0 = x_begin; x0 < x_end; x0 += XT) {
         __syncthreads();
-        // next tile (masked to zero past the chunk end)
+        // next tile (masked to zero past the chunk end), kept ahead of the MFMAs
         load_b(x0 + XT, bl);
         load_a(x0 + XT, an);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
             T bv[NT][4];
