@@ -83,6 +83,46 @@ def cpu_baseline(cr, u_dev, psi0_host):
                       f"{dt:.1f} s, numpy FP64 with {cores} host threads"}
 
 
+def bench_batched(ob, seed, steps=200):
+    """Molecule in a box: 40 sites (K and L2,3 edges), 3 polarisations each, uneven band
+    windows, Gamma point on a 48^3 grid; all 120 solves advance together, one HIP graph per
+    Haydock step."""
+    import torch
+    import synth
+    t0 = time.time()
+    sites = synth.molecule_sites(seed=seed)
+    torch.cuda.synchronize()
+    log(f"molecule-in-box inputs: {len(sites)} sites, bands {min(c.n_bands for c, _ in sites)}.."
+        f"{max(c.n_bands for c, _ in sites)}, generated in {time.time() - t0:.1f} s")
+    out = {}
+    n_solves = sum(3 for _ in sites)
+    for prec in ("fp64", "fp32"):
+        hs = [ob.Bse.from_crystal(cr, precision=prec, u=u) for cr, u in sites]
+        p0 = [torch.from_numpy(cr.psi0).to("cuda") if cr.psi0 is not None else hs[i].dipole_psi0(np.eye(3))
+              for i, (cr, _) in enumerate(sites)]
+        ob.haydock_batch(hs, p0, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, rc = ob.haydock_batch(hs, p0, steps)
+        sig = [ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd)
+               for (a, b, n2, sd), (cr, _) in zip(res, sites)]
+        dt = time.perf_counter() - t0
+        out[prec] = {"spectra_per_s": n_solves / dt, "hv_per_s": n_solves * steps / dt,
+                     "seconds": dt, "sig": sig}
+        log(f"batched {prec}: {n_solves} solves x {steps} steps in {dt:.2f} s: "
+            f"{n_solves / dt:.1f} spectra/s, {n_solves * steps / dt:.0f} H*v/s")
+        for h in hs:
+            h.close()
+    num = sum(float(np.sum(np.abs(s32 - s64))) for s32, s64 in zip(out["fp32"]["sig"], out["fp64"]["sig"]))
+    den = sum(float(np.sum(np.abs(s64))) for s64 in out["fp64"]["sig"])
+    for prec in out:
+        out[prec].pop("sig")
+    out["fp32"]["spectrum_l1_vs_fp64"] = num / den
+    out["workload"] = (f"molecule in a 30 bohr box, Gamma point, 48^3 grid, {len(sites)} sites "
+                       f"(K and L2,3 edges), bands U{{200..800}}, 3 polarisations: {n_solves} solves x {steps} steps")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +131,7 @@ def main():
     ap.add_argument("--spectrum-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); independent solves "
@@ -150,6 +191,12 @@ def main():
                 "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
                 "kernel_ms_fp32": {k: round(v, 4) for k, v in avgs["fp32"].items()}}
 
+    batched = None
+    if not args.no_batched:
+        h64.close()
+        h32.close()
+        batched = bench_batched(ob, args.seed)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (one H*v)")
@@ -174,6 +221,7 @@ def main():
                    "n_vec_per_step": n_pol, "spectrum_steps": args.spectrum_steps},
         "fp64": results["fp64"],
         "mixed_fp32": results["fp32"],
+        "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

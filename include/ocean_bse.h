@@ -141,6 +141,34 @@ int ocean_bse_apply(ocean_bse_t h, const double* x_dev, double* y_dev, int n_vec
 int ocean_haydock(ocean_bse_t h, const double* psi0_dev, int n_vec, int n_steps, unsigned flags,
                   double* a, double* b, double* norm2, int* steps_done);
 
+/* Batched Haydock recursion for n_sys independent systems (sites, edges,
+ * polarisations: section 4.3 keeps the wavefunctions resident and amortises them over
+ * many spectra; section 4.5 runs hundreds of site-edge calculations).  System s uses
+ * handle hs[s] (distinct handles with distinct streams, one device), starting vectors
+ * psi0[s] (device, n_vec[s] vectors as in ocean_haydock).  One step of every system
+ * is captured into a single HIP graph as independent branches and replayed n_steps
+ * times.  Host outputs are concatenated over systems in order: vector j of the batch
+ * (systems in order, their vectors in order) has a[j*n_steps + i], b[j*n_steps + i],
+ * norm2[j], steps_done[j].  Each system's numbers are bitwise those of ocean_haydock on
+ * the same handle.  Returns OCEAN_INFO_INVARIANT_SUBSPACE if any vector stopped early.
+ * Errors: INVALID_ARG (NULL, shared handle or stream, mixed devices, zero psi0),
+ * OUT_OF_MEMORY, DEVICE. */
+int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* psi0,
+                        const int* n_vec, int n_steps, unsigned flags, double* a, double* b,
+                        double* norm2, int* steps_done);
+
+/* Tile autotuner: times the candidate tile shapes of the projection, back-projection
+ * and k-grid transform kernels on this handle's shape with n_vec vectors (reps applies
+ * per candidate, HIP events) and keeps the fastest.  If the environment variable
+ * OCEAN_AUTOTUNE_CACHE names a file, a cached choice for the same shape is reused and new
+ * choices are appended.  Results do not change numerics beyond summation order of the
+ * split-K partials.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps);
+
+/* Current tile choices: forward rows per wave / 16, back-projection grid target, lines
+ * per k-grid transform block.  Any pointer may be NULL.  Errors: INVALID_ARG. */
+int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_lines);
+
 /* Spectra from Haydock coefficients (section 2, eq. loss.fcn with
  * G = [w - H]^-1 as a continued fraction), evaluated on the GPU in FP64:
  *   sigma(w) = -(1/pi) norm2 Im g(w + i gamma),

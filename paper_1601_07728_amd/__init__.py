@@ -40,7 +40,7 @@ EXPORTED = [
     "ocean_bse_create", "ocean_bse_destroy", "ocean_bse_dim", "ocean_bse_apply", "ocean_haydock",
     "ocean_spectrum", "ocean_multiplet_matrices", "ocean_dipole_amplitudes", "ocean_dipole_psi0",
     "ocean_bse_set_profiling", "ocean_bse_kernel_times", "ocean_bse_device_bytes",
-    "ocean_last_error",
+    "ocean_last_error", "ocean_haydock_batch", "ocean_bse_autotune", "ocean_bse_get_tuning",
 ]
 
 
@@ -99,6 +99,12 @@ def lib() -> ctypes.CDLL:
     L.ocean_bse_set_profiling.restype = ci
     L.ocean_bse_kernel_times.argtypes = [vp, vp, vp, vp, ci]
     L.ocean_bse_kernel_times.restype = ci
+    L.ocean_haydock_batch.argtypes = [vp, ci, vp, vp, ci, cu, vp, vp, vp, vp]
+    L.ocean_haydock_batch.restype = ci
+    L.ocean_bse_autotune.argtypes = [vp, ci, ci]
+    L.ocean_bse_autotune.restype = ci
+    L.ocean_bse_get_tuning.argtypes = [vp, vp, vp, vp]
+    L.ocean_bse_get_tuning.restype = ci
     L.ocean_last_error.argtypes = []
     L.ocean_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -166,6 +172,38 @@ def spectrum(a, b, norm2, omega, gamma: float, terminator: str = "none", n_used=
     _check(lib().ocean_spectrum(_ptr(a), _ptr(b), _ptr(used), _ptr(n2), n_spec, n_steps, term,
                                 _ptr(om), len(om), float(gamma), _ptr(sig)))
     return sig
+
+
+def haydock_batch(systems, psi0s, n_steps: int, reorth: bool = False):
+    """Batched recursion over independent handles (one HIP graph per step).
+    systems: list of Bse; psi0s: matching list of device tensors [n_vec, Nk, Nb, Nc].
+    Returns a list of (a, b, norm2, steps_done) per system and the return code."""
+    n = len(systems)
+    if n < 1 or len(psi0s) != n:
+        raise ValueError("need one psi0 per system")
+    nvs = []
+    for h, p in zip(systems, psi0s):
+        nv = p.numel() // h.dim
+        if nv * h.dim != p.numel() or nv < 1:
+            raise ValueError("psi0 size is not a multiple of the vector dimension")
+        nvs.append(nv)
+    tot = sum(nvs)
+    hs = (ctypes.c_void_p * n)(*[h._h.value for h in systems])
+    ps = (ctypes.c_void_p * n)(*[_dev_ptr(p) for p in psi0s])
+    nv_arr = (ctypes.c_int * n)(*nvs)
+    a = np.zeros((tot, n_steps))
+    b = np.zeros((tot, n_steps))
+    n2 = np.zeros(tot)
+    sd = np.zeros(tot, dtype=np.int32)
+    _device_sync()
+    rc = lib().ocean_haydock_batch(hs, n, ps, nv_arr, int(n_steps), HAYDOCK_REORTH if reorth else 0,
+                                   _ptr(a), _ptr(b), _ptr(n2), _ptr(sd))
+    _check(rc, allow_info=True)
+    out, off = [], 0
+    for nv in nvs:
+        out.append((a[off:off + nv], b[off:off + nv], n2[off:off + nv], sd[off:off + nv]))
+        off += nv
+    return out, rc
 
 
 class Bse:
@@ -293,6 +331,17 @@ class Bse:
         _device_sync()
         _check(lib().ocean_dipole_psi0(self._h, _ptr(p), p.shape[0], _dev_ptr(out)))
         return out
+
+    def autotune(self, n_vec: int, reps: int = 3):
+        _device_sync()
+        _check(lib().ocean_bse_autotune(self._h, int(n_vec), int(reps)))
+        return self.tuning
+
+    @property
+    def tuning(self):
+        m, b, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().ocean_bse_get_tuning(self._h, ctypes.byref(m), ctypes.byref(b), ctypes.byref(f)))
+        return {"fwd_ms": m.value, "bwd_blocks": b.value, "fft_lines": f.value}
 
     def set_profiling(self, on: bool):
         _check(lib().ocean_bse_set_profiling(self._h, 1 if on else 0))

@@ -112,8 +112,9 @@ struct ocean_bse_s {
     ocean::LanczosBuffers lz;
 
     // tuning knobs (picked at create, overridable through the environment)
-    int fft_lines = 16;
-    int bwd_target_blocks = 2048;
+    int fft_lines = 16;          // lines per block of the k-grid transform
+    int bwd_target_blocks = 2048;  // back-projection grid size the x chunking aims at
+    int fwd_ms = 2;              // forward projection: 16 * fwd_ms rows per wave
 
     // profiling
     bool profiling = false;
@@ -158,6 +159,8 @@ hipError_t launch_spectrum(const double* a, const double* b, const int* n_used, 
 // geometry helpers
 int bwd_waves(int Nb);
 void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk);
+void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks, int* S, int* chunk);
+constexpr int kMaxBwdTarget = 8192;  // largest back-projection grid target the tuner tries
 size_t fft_lds_bytes(const ocean_bse_s* h, int lines);
 long long local_blocks(const ocean_bse_s* h);
 

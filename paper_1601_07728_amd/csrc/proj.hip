@@ -404,11 +404,11 @@ int bwd_waves(int Nb) {
     return nb16 < 8 ? nb16 : 8;
 }
 
-void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk) {
+void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks, int* S, int* chunk) {
     const int W = bwd_waves(h->Nb);
     const int bb = (h->Nb + 16 * W - 1) / (16 * W);
     const long long per_chunk = (long long)h->Nk * bb;
-    long long s = (h->bwd_target_blocks + per_chunk - 1) / per_chunk;
+    long long s = (target_blocks + per_chunk - 1) / per_chunk;
     const long long smax = (h->Nx + 63) / 64;
     if (s < 1) s = 1;
     if (s > smax) s = smax;
@@ -419,20 +419,28 @@ void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk) {
     *band_blocks = bb;
 }
 
+void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk) {
+    bwd_geometry_for(h, h->bwd_target_blocks, band_blocks, S, chunk);
+}
+
 hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, int ncb) {
-    constexpr int MS = 2;
+    const int MS = h->fwd_ms == 1 ? 1 : 2;   // 16 * MS rows per wave, 64 * MS per block
     const int cols = nv * h->Nc;
     const int NT = (2 * ncb + 15) / 16;
-    const int x_tiles = (h->Nx + 64 * MS - 1) / (64 * MS);  // rows per block: 64 MS
+    const int x_tiles = (h->Nx + 64 * MS - 1) / (64 * MS);
     dim3 grid((unsigned)(h->Nk * x_tiles));
     const int slot = prof_begin(h, "proj_fwd");
     hipError_t e;
     if (h->precision == OCEAN_PREC_FP64)
-        e = fwd_dispatch_nt<double, MS>(NT, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
-                                        h->Nb, h->Nc, cols, col0, ncb, x_tiles);
+        e = MS == 1 ? fwd_dispatch_nt<double, 1>(NT, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
+                                                 h->Nb, h->Nc, cols, col0, ncb, x_tiles)
+                    : fwd_dispatch_nt<double, 2>(NT, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
+                                                 h->Nb, h->Nc, cols, col0, ncb, x_tiles);
     else
-        e = fwd_dispatch_nt<float, MS>(NT, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
-                                       h->Nb, h->Nc, cols, col0, ncb, x_tiles);
+        e = MS == 1 ? fwd_dispatch_nt<float, 1>(NT, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
+                                                h->Nb, h->Nc, cols, col0, ncb, x_tiles)
+                    : fwd_dispatch_nt<float, 2>(NT, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
+                                                h->Nb, h->Nc, cols, col0, ncb, x_tiles);
     prof_end(h, slot);
     return e;
 }

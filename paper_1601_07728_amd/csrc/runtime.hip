@@ -140,12 +140,15 @@ static int ensure_workspace(ocean_bse_s* h, int nv) {
         return OCEAN_OK;
     }
     release_workspace(h);
-    int bb, S, chunk;
+    int bb, S, chunk, S_alloc;
     bwd_geometry(h, &bb, &S, &chunk);
+    // partials sized for the largest chunking the autotuner may select
+    bwd_geometry_for(h, std::max(h->bwd_target_blocks, kMaxBwdTarget), &bb, &S_alloc, &chunk);
+    S_alloc = std::max(S_alloc, S);
     const size_t elem = h->precision == OCEAN_PREC_FP64 ? 16 : 8;
     const size_t nx_pad = ((size_t)h->Nx + kXB - 1) / kXB * kXB;
     const size_t phi_b = (size_t)h->Nk * nx_pad * cols * elem;
-    const size_t part_b = (size_t)S * h->Nk * h->Nb * cols * 16;
+    const size_t part_b = (size_t)S_alloc * h->Nk * h->Nb * cols * 16;
     const int NP = std::max(1, h->Nc * h->Nmu);
     const size_t locp_b = (size_t)local_blocks(h) * nv * NP * 16;
     const size_t locb_b = (size_t)nv * NP * 16;
@@ -677,6 +680,250 @@ int ocean_haydock(ocean_bse_t h, const double* psi0_dev, int n_vec, int n_steps,
         if (st[v].steps < n_steps) ret = OCEAN_INFO_INVARIANT_SUBSPACE;
     }
     return ret;
+}
+
+int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* psi0, const int* n_vec,
+                        int n_steps, unsigned flags, double* a, double* b, double* norm2,
+                        int* steps_done) {
+    g_last_error.clear();
+    if (!hs || !psi0 || !n_vec || !a || !b || !norm2 || !steps_done || n_sys < 1 || n_steps < 1) {
+        set_error("ocean_haydock_batch: NULL argument, n_sys < 1 or n_steps < 1");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    const bool reorth = (flags & OCEAN_HAYDOCK_REORTH) != 0;
+    int device = -1;
+    bool profiling = false;
+    for (int s = 0; s < n_sys; ++s) {
+        if (!hs[s] || !psi0[s] || n_vec[s] < 1) {
+            set_error("ocean_haydock_batch: NULL handle or psi0, or n_vec < 1");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        for (int t = 0; t < s; ++t)
+            if (hs[t] == hs[s] || hs[t]->stream == hs[s]->stream) {
+                set_error("ocean_haydock_batch: every system needs its own handle and stream");
+                return OCEAN_ERR_INVALID_ARG;
+            }
+        if (device < 0) device = hs[s]->device;
+        if (hs[s]->device != device) {
+            set_error("ocean_haydock_batch: all handles must live on one device");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        profiling |= hs[s]->profiling;
+    }
+    (void)hipSetDevice(device);
+    for (int s = 0; s < n_sys; ++s) {
+        ocean_bse_s* h = hs[s];
+        OCEAN_TRY(ensure_workspace(h, n_vec[s]));
+        OCEAN_TRY(ensure_lanczos(h, n_vec[s], n_steps, reorth));
+        OCEAN_HIP(hipMemsetAsync(h->lz.a, 0, (size_t)n_vec[s] * n_steps * 8, h->stream), "memset");
+        OCEAN_HIP(hipMemsetAsync(h->lz.b, 0, (size_t)n_vec[s] * n_steps * 8, h->stream), "memset");
+        OCEAN_HIP(lz_init(h, psi0[s], n_vec[s]), "lz_init launch");
+    }
+    for (int s = 0; s < n_sys; ++s) OCEAN_HIP(hipStreamSynchronize(hs[s]->stream), "batch init");
+
+    // One step of every system, captured into a single graph: the systems are independent
+    // branches forked from and joined back into a master stream.
+    bool graph_done = false;
+    const bool use_graph = !profiling && env_int("OCEAN_NO_GRAPH", 0) == 0;
+    if (use_graph) {
+        hipStream_t master;
+        OCEAN_HIP(hipStreamCreateWithFlags(&master, hipStreamNonBlocking), "stream create");
+        std::vector<hipEvent_t> ev(n_sys + 1);
+        bool ok = true;
+        for (auto& e : ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        if (ok && hipStreamBeginCapture(master, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            int rc = check_hip(hipEventRecord(ev[n_sys], master), "fork");
+            for (int s = 0; s < n_sys && rc == OCEAN_OK; ++s) {
+                rc = check_hip(hipStreamWaitEvent(hs[s]->stream, ev[n_sys], 0), "fork");
+                if (rc == OCEAN_OK) rc = haydock_step(hs[s], n_vec[s], reorth);
+                if (rc == OCEAN_OK) rc = check_hip(hipEventRecord(ev[s], hs[s]->stream), "join");
+                if (rc == OCEAN_OK) rc = check_hip(hipStreamWaitEvent(master, ev[s], 0), "join");
+            }
+            const hipError_t ec = hipStreamEndCapture(master, &graph);
+            if (rc == OCEAN_OK && ec == hipSuccess && graph &&
+                hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+                int lrc = OCEAN_OK;
+                for (int i = 0; i < n_steps && lrc == OCEAN_OK; ++i)
+                    lrc = check_hip(hipGraphLaunch(exec, master), "graph launch");
+                if (lrc == OCEAN_OK) lrc = check_hip(hipStreamSynchronize(master), "batch");
+                graph_done = lrc == OCEAN_OK;
+                (void)hipGraphExecDestroy(exec);
+                if (!graph_done) {
+                    (void)hipGraphDestroy(graph);
+                    for (auto& e : ev) (void)hipEventDestroy(e);
+                    (void)hipStreamDestroy(master);
+                    return lrc;
+                }
+            } else {
+                (void)hipGetLastError();
+            }
+            if (graph) (void)hipGraphDestroy(graph);
+        } else {
+            (void)hipGetLastError();
+        }
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(master);
+    }
+    if (!graph_done) {
+        for (int i = 0; i < n_steps; ++i)
+            for (int s = 0; s < n_sys; ++s) OCEAN_TRY(haydock_step(hs[s], n_vec[s], reorth));
+    }
+    int ret = OCEAN_OK;
+    size_t off = 0;
+    for (int s = 0; s < n_sys; ++s) {
+        ocean_bse_s* h = hs[s];
+        const int nv = n_vec[s];
+        OCEAN_HIP(hipStreamSynchronize(h->stream), "batch");
+        prof_collect(h);
+        std::vector<LzState> st(nv);
+        OCEAN_HIP(hipMemcpy(a + off * n_steps, h->lz.a, (size_t)nv * n_steps * 8, hipMemcpyDeviceToHost), "copy a");
+        OCEAN_HIP(hipMemcpy(b + off * n_steps, h->lz.b, (size_t)nv * n_steps * 8, hipMemcpyDeviceToHost), "copy b");
+        OCEAN_HIP(hipMemcpy(st.data(), h->lz.state, nv * sizeof(LzState), hipMemcpyDeviceToHost), "copy state");
+        for (int v = 0; v < nv; ++v) {
+            norm2[off + v] = st[v].norm2;
+            steps_done[off + v] = st[v].steps;
+            if (!(st[v].norm2 > 0.0)) {
+                set_error("ocean_haydock_batch: a starting vector is zero");
+                return OCEAN_ERR_INVALID_ARG;
+            }
+            if (st[v].steps < n_steps) ret = OCEAN_INFO_INVARIANT_SUBSPACE;
+        }
+        off += nv;
+    }
+    return ret;
+}
+
+// Project-written tile autotuner: times the candidate tile knobs of each kernel on this
+// handle's own shape (HIP events around repeated applies) and keeps the fastest.  Results
+// are cached per shape in the file named by OCEAN_AUTOTUNE_CACHE (one line per shape).
+int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
+    g_last_error.clear();
+    if (!h || n_vec < 1) {
+        set_error("ocean_bse_autotune: NULL handle or n_vec < 1");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    if (reps < 1) reps = 3;
+    (void)hipSetDevice(h->device);
+    char key[160];
+    std::snprintf(key, sizeof key, "nk=%d,%d,%d nx=%d,%d,%d nb=%d nc=%d nmu=%d prec=%d cols=%d", h->nk[0],
+                  h->nk[1], h->nk[2], h->nx[0], h->nx[1], h->nx[2], h->Nb, h->Nc, h->Nmu, h->precision,
+                  n_vec * h->Nc);
+    const char* cache = std::getenv("OCEAN_AUTOTUNE_CACHE");
+    if (cache && *cache) {
+        if (FILE* f = std::fopen(cache, "r")) {
+            char line[320];
+            while (std::fgets(line, sizeof line, f)) {
+                const char* sep = std::strchr(line, '|');
+                if (!sep || (size_t)(sep - line) != std::strlen(key) || std::strncmp(line, key, sep - line) != 0) continue;
+                int ms, bt, fl;
+                if (std::sscanf(sep + 1, "%d %d %d", &ms, &bt, &fl) == 3) {
+                    std::fclose(f);
+                    h->fwd_ms = ms;
+                    h->bwd_target_blocks = std::min(bt, kMaxBwdTarget);
+                    h->fft_lines = fl;
+                    return OCEAN_OK;
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    OCEAN_TRY(ensure_workspace(h, n_vec));
+    const size_t vb = (size_t)n_vec * h->Nk * h->Nb * h->Nc * 16;
+    double* x = nullptr;
+    double* y = nullptr;
+    if (hipMalloc((void**)&x, vb) != hipSuccess || hipMalloc((void**)&y, vb) != hipSuccess) {
+        (void)hipGetLastError();
+        if (x) (void)hipFree(x);
+        set_error("ocean_bse_autotune: hipMalloc failed");
+        return OCEAN_ERR_OUT_OF_MEMORY;
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const bool saved_prof = h->profiling;
+    h->profiling = false;
+    auto time_apply = [&](float* ms) -> int {
+        (void)hipMemsetAsync(x, 0, vb, h->stream);
+        int rc = apply_pipeline(h, x, y, n_vec, nullptr);
+        if (rc != OCEAN_OK) return rc;
+        (void)hipEventRecord(e0, h->stream);
+        for (int r = 0; r < reps && rc == OCEAN_OK; ++r) rc = apply_pipeline(h, x, y, n_vec, nullptr);
+        (void)hipEventRecord(e1, h->stream);
+        if (rc != OCEAN_OK) return rc;
+        rc = check_hip(hipEventSynchronize(e1), "autotune");
+        if (rc == OCEAN_OK) rc = check_hip(hipEventElapsedTime(ms, e0, e1), "autotune");
+        return rc;
+    };
+    int rc = OCEAN_OK;
+    // one knob at a time, the others held at their current values
+    {
+        int best = h->fwd_ms;
+        float best_ms = 1e30f;
+        for (int ms : {1, 2}) {
+            h->fwd_ms = ms;
+            float t;
+            if ((rc = time_apply(&t)) != OCEAN_OK) break;
+            if (t < best_ms) { best_ms = t; best = ms; }
+        }
+        h->fwd_ms = best;
+    }
+    if (rc == OCEAN_OK) {
+        int best = h->bwd_target_blocks;
+        float best_ms = 1e30f;
+        for (int bt : {1024, 2048, 4096, 8192}) {
+            h->bwd_target_blocks = bt;
+            int bb, S, ch;
+            bwd_geometry(h, &bb, &S, &ch);
+            h->ws.bwd_chunks = S;
+            float t;
+            if ((rc = time_apply(&t)) != OCEAN_OK) break;
+            if (t < best_ms) { best_ms = t; best = bt; }
+        }
+        h->bwd_target_blocks = best;
+        int bb, S, ch;
+        bwd_geometry(h, &bb, &S, &ch);
+        h->ws.bwd_chunks = S;
+    }
+    if (rc == OCEAN_OK) {
+        int best = h->fft_lines;
+        float best_ms = 1e30f;
+        for (int L : {4, 8, 16, 32, 64}) {
+            if (fft_lds_bytes(h, L) > 160 * 1024) continue;
+            h->fft_lines = L;
+            float t;
+            if ((rc = time_apply(&t)) != OCEAN_OK) break;
+            if (t < best_ms) { best_ms = t; best = L; }
+        }
+        h->fft_lines = best;
+    }
+    h->profiling = saved_prof;
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    if (rc != OCEAN_OK) return rc;
+    if (cache && *cache) {
+        if (FILE* f = std::fopen(cache, "a")) {
+            std::fprintf(f, "%s|%d %d %d\n", key, h->fwd_ms, h->bwd_target_blocks, h->fft_lines);
+            std::fclose(f);
+        }
+    }
+    return OCEAN_OK;
+}
+
+int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_lines) {
+    if (!h) {
+        set_error("ocean_bse_get_tuning: NULL handle");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    if (fwd_ms) *fwd_ms = h->fwd_ms;
+    if (bwd_blocks) *bwd_blocks = h->bwd_target_blocks;
+    if (fft_lines) *fft_lines = h->fft_lines;
+    return OCEAN_OK;
 }
 
 int ocean_spectrum(const double* a, const double* b, const int* n_used, const double* norm2,

@@ -210,8 +210,60 @@ def gpu_orthonormal_u(n_k: int, n_x: int, n_bands: int, seed: int, device="cuda"
         for _ in range(2):
             gram = (z.conj().transpose(0, 1).contiguous() @ z)
             gram = 0.5 * (gram + gram.conj().transpose(0, 1))
-            chol = torch.linalg.cholesky(gram)
-            z = torch.linalg.solve_triangular(chol.conj().transpose(0, 1).contiguous(), z,
-                                              upper=True, left=False)
+            r = torch.linalg.cholesky(gram).conj().transpose(0, 1).contiguous()   # G = R^H R
+            eye = torch.eye(n_bands, dtype=z.dtype, device=device)
+            rinv = torch.linalg.solve_triangular(r, eye, upper=True)            # small solve
+            z = z @ rinv                                                        # Q = Z R^-1
         u[k] = z
     return u
+
+
+# --- molecule in a box: many absorbing sites, Gamma point only ---------------------------
+
+def molecule_sites(seed: int = 0, n_atoms: int = 52, n_sites: int = 40, box: float = 30.0,
+                   grid: int = 48, nb_range=(200, 800), p_k_edge: float = 0.5,
+                   min_spacing: float = 2.5, device_u: bool = True):
+    """An Alq3-sized molecule in a periodic cubic box (Gamma point only): atoms placed by
+    seeded rejection sampling at >= min_spacing bohr (minimum image), the first n_sites
+    of them absorbing sites.  Each site is a K edge (2 core states, no local term) with
+    probability p_k_edge, else an L2,3 edge (6 core states, d-channel local term, the
+    SrTiO3 multiplet parameters).  Per site: band count uniform in nb_range, energies
+    U[0, 40] eV, eps U[2, 10], its own u on the grid^3 box grid.  K edges get three
+    complex-normal amplitude vectors (one per polarisation); L edges carry x, y, z
+    polarisations for the dipole rule.
+
+    Returns a list of (Crystal, u) with u a device tensor (device_u) or the host array in
+    Crystal.u."""
+    rng = np.random.default_rng(seed)
+    pos = []
+    while len(pos) < n_atoms:
+        p = rng.uniform(0.0, box, size=3)
+        ok = True
+        for q in pos:
+            d = p - q
+            d = d - box * np.round(d / box)
+            if np.sqrt(np.sum(d * d)) < min_spacing:
+                ok = False
+                break
+        if ok:
+            pos.append(p)
+    sites = []
+    for s in range(n_sites):
+        k_edge = rng.uniform() < p_k_edge
+        nb = int(rng.integers(nb_range[0], nb_range[1] + 1))
+        eps = float(rng.uniform(2.0, 10.0))
+        site_seed = int(rng.integers(0, 2 ** 31 - 1))
+        common = dict(a=box, tau=pos[s], nk=(1, 1, 1), nx=(grid,) * 3, n_bands=nb,
+                      e_range_ev=40.0, eps=eps, seed=site_seed, n_steps=200,
+                      omega_ev=(-20.0, 45.0), u_override="skip" if device_u else None)
+        if k_edge:
+            cr = make_crystal(f"site{s}-K", n_core=2, psi0="random", n_vec=3, **common)
+        else:
+            cr = make_crystal(f"site{s}-L23", n_core=6, n_local=5,
+                              multiplet_ev=dict(L_EDGE_MULTIPLET_EV), psi0="none",
+                              polarisations=XYZ_POLARISATIONS, **common)
+        u = None
+        if device_u:
+            u = gpu_orthonormal_u(1, grid ** 3, nb, seed=site_seed)
+        sites.append((cr, u))
+    return sites

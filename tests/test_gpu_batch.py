@@ -1,0 +1,82 @@
+"""Batched solves (many sites / edges / polarisations in one graph per step) and the
+tile autotuner, against the stand-alone path and the CPU oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bse as orc
+from oracle import multiplet as omp
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _sites():
+    return synth.molecule_sites(seed=3, n_atoms=9, n_sites=5, box=12.0, grid=6, nb_range=(7, 29),
+                                device_u=False)
+
+
+def _psi0(h, cr):
+    import torch
+    if cr.psi0 is not None:
+        return torch.from_numpy(cr.psi0).to("cuda")
+    return h.dipole_psi0(np.eye(3))
+
+
+def test_batch_equals_standalone_and_oracle():
+    import paper_1601_07728_amd as ob
+    sites = _sites()
+    hs = [ob.Bse.from_crystal(cr) for cr, _ in sites]
+    p0 = [_psi0(h, cr) for h, (cr, _) in zip(hs, sites)]
+    n_steps = 40
+    _say(f"[batch] {len(hs)} systems, bands {[cr.n_bands for cr, _ in sites]}")
+    out, rc = ob.haydock_batch(hs, p0, n_steps, reorth=True)
+    for s, ((cr, _), h) in enumerate(zip(sites, hs)):
+        a1, b1, n21, sd1, _ = h.haydock(p0[s], n_steps, reorth=True)
+        a, b, n2, sd = out[s]
+        assert np.array_equal(a, a1) and np.array_equal(b, b1) and np.array_equal(sd, sd1), s
+        hc = omp.core_matrix(cr.multiplet) if cr.multiplet else None
+        kl = omp.local_matrix(cr.multiplet) if cr.multiplet else None
+        pv = p0[s].cpu().numpy()
+        for v in range(pv.shape[0]):
+            ra, rb, rn2, rs, _ = orc.haydock(lambda q: orc.apply_h(cr, q, hc, kl), pv[v], n_steps,
+                                             reorth=True)
+            S = np.abs(ra).max() + 2 * rb.max()
+            assert sd[v] == rs
+            assert np.abs(a[v, :rs] - ra).max() <= 1e-10 * S
+            assert np.abs(b[v, :rs] - rb).max() <= 1e-10 * S
+            assert abs(n2[v] - rn2) <= 1e-13 * rn2
+    for h in hs:
+        h.close()
+
+
+def test_autotune_and_cache(tmp_path, monkeypatch):
+    import torch
+
+    import paper_1601_07728_amd as ob
+    cr = synth.small_l_edge(seed=21, nk=(2, 2, 2), nx=(10, 10, 9), n_bands=23)
+    monkeypatch.setenv("OCEAN_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    h = ob.Bse.from_crystal(cr)
+    t = h.autotune(n_vec=3, reps=2)
+    assert t["fwd_ms"] in (1, 2) and t["bwd_blocks"] in (1024, 2048, 4096, 8192)
+    assert t["fft_lines"] in (4, 8, 16, 32, 64)
+    assert (tmp_path / "tune.txt").read_text().count("|") == 1
+    x = synth.complex_gaussian(np.random.default_rng(2), (3, cr.n_k, cr.n_bands, cr.n_core))
+    y = h.apply(torch.from_numpy(x).to("cuda")).cpu().numpy()
+    hc, kl = omp.core_matrix(cr.multiplet), omp.local_matrix(cr.multiplet)
+    for v in range(3):
+        ref = orc.apply_h(cr, x[v], hc, kl)
+        assert np.abs(y[v] - ref).max() <= 1e-13 * np.abs(ref).max()
+    # a second handle of the same shape reuses the cached choice
+    h2 = ob.Bse.from_crystal(cr)
+    assert h2.autotune(n_vec=3, reps=2) == t
+    assert (tmp_path / "tune.txt").read_text().count("|") == 1
+    h.close()
+    h2.close()
