@@ -1,0 +1,55 @@
+"""Pins of the reference MLP (the learned terminator is not in the paper; these pin
+the oracle to calculus and to the published Adam rule, not to itself)."""
+import numpy as np
+
+from oracle import mlp
+
+
+def _data(seed=0, n=6):
+    rng = np.random.default_rng(seed)
+    p = mlp.init_params(rng)
+    x = rng.standard_normal((n, 64))
+    t = rng.standard_normal((n, 448))
+    return rng, p, x, t
+
+
+def test_parameter_count():
+    assert mlp.n_params() == 263360
+
+
+def test_gradient_matches_central_differences():
+    rng, p, x, t = _data()
+    loss, g = mlp.loss_and_grad(p, x, t)
+    idx = rng.choice(p.size, 40, replace=False)
+    # include biases and every layer
+    idx = np.concatenate([idx, [0, 64 * 256 + 3, 16384 + 256 + 5, p.size - 1, p.size - 449]])
+    for i in idx:
+        h = 1e-6 * max(1.0, abs(p[i]))
+        pp = p.copy()
+        pp[i] += h
+        lp = mlp.loss_and_grad(pp, x, t)[0]
+        pp[i] -= 2 * h
+        lm = mlp.loss_and_grad(pp, x, t)[0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(abs(g[i]), 1e-3), (i, fd, g[i])
+
+
+def test_first_adam_step_is_sign_step():
+    """Kingma & Ba: after bias correction the first step is lr * g / (|g| + eps)."""
+    _, p, x, t = _data(1)
+    _, g = mlp.loss_and_grad(p, x, t)
+    p1, m, v = mlp.adam_step(p, g, np.zeros_like(p), np.zeros_like(p), 1, 1e-3)
+    assert np.allclose(p1, p - 1e-3 * g / (np.abs(g) + mlp.ADAM_EPS), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_encode_decode_round_trip():
+    rng = np.random.default_rng(3)
+    a = rng.uniform(0.2, 1.4, (4, 300))
+    b = rng.uniform(0.05, 0.3, (4, 300))
+    x, t, c, s = mlp.encode(a, b)
+    assert x.shape == (4, 64) and t.shape == (4, 448)
+    ae, be = mlp.decode(t, a, b, c, s)
+    assert np.allclose(ae, a[:, :256], rtol=0, atol=1e-14)
+    assert np.allclose(be, b[:, :256], rtol=1e-14, atol=0)
+    assert np.allclose(c, a[:, 16:32].mean(axis=1)) and np.allclose(s, b[:, 16:32].mean(axis=1))
