@@ -123,6 +123,109 @@ def bench_batched(ob, seed, steps=200):
     return out
 
 
+def he_init(rng, sizes=(64, 256, 256, 256, 448)):
+    """He-normal weights, zero biases, packed [W1, b1, ..., W4, b4] (W stored [in][out])."""
+    parts = []
+    for i, o in zip(sizes[:-1], sizes[1:]):
+        parts.append(rng.standard_normal(i * o) * np.sqrt(2.0 / i))
+        parts.append(np.zeros(o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def terminator_dataset(ob, seeds, n_steps, shape, chunk=256):
+    """(a, b, |psi0|^2, steps) of the z-polarised L-edge recursion of each seeded system,
+    generated by the solver in batches of `chunk` systems."""
+    import synth
+    A, B, N2, SD = [], [], [], []
+    seeds = list(seeds)
+    omega = gamma = None
+    for st in range(0, len(seeds), chunk):
+        crs = [synth.terminator_system(sd, n_steps=n_steps, **shape) for sd in seeds[st:st + chunk]]
+        hs = [ob.Bse.from_crystal(cr) for cr in crs]
+        p0 = [h.dipole_psi0([0.0, 0.0, 1.0]) for h in hs]
+        res, _ = ob.haydock_batch(hs, p0, n_steps)
+        for a, b, n2, sd in res:
+            A.append(a)
+            B.append(b)
+            N2.append(n2)
+            SD.append(sd)
+        omega, gamma = crs[0].omega, crs[0].gamma
+        for h in hs:
+            h.close()
+    return (np.concatenate(A), np.concatenate(B), np.concatenate(N2), np.concatenate(SD), omega, gamma)
+
+
+def bench_terminator(ob, seed, n_sys, n_held, n_steps=512, epochs=120, batch=256, lr=1e-3):
+    """Learned terminator: dataset from the solver (seeds 1..n_sys, the last n_held held
+    out), training by the library's kernels, held-out judging against the full recursion."""
+    import torch
+    from paper_1601_07728_amd import terminator as term
+    shape = dict(nk=(4, 4, 4), nx=(5, 5, 5), n_bands=24)
+    t0 = time.perf_counter()
+    a, b, n2, sd, om, gam = terminator_dataset(ob, range(1, n_sys + 1), n_steps, shape)
+    t_gen = time.perf_counter() - t0
+    log(f"terminator dataset: {n_sys} systems x {n_steps} steps in {t_gen:.1f} s")
+    ntr = n_sys - n_held
+    ad, bd = torch.from_numpy(a).to("cuda"), torch.from_numpy(b).to("cuda")
+    x, t = ob.Mlp.encode(ad, bd)
+    mlp = ob.Mlp("bf16")
+    mlp.set_params(he_init(np.random.default_rng(seed)) * 0.1)
+    t0 = time.perf_counter()
+    hist = term.train(mlp, x[:ntr].contiguous(), t[:ntr].contiguous(), epochs=epochs, batch=batch, lr=lr,
+                      seed=seed, log_every=max(1, epochs // 4))
+    t_train = time.perf_counter() - t0
+    log(f"terminator training: {epochs} epochs in {t_train:.1f} s, loss {hist}")
+    te = slice(ntr, n_sys)
+    ref = ob.spectrum(a[te], b[te], n2[te], om, gam, n_used=sd[te])
+    res, valid = term.terminated_spectra(mlp, a[te], b[te], n2[te], om, gam, a_full=a[te], b_full=b[te],
+                                         n_full=sd[te])
+    l1 = {k: float(np.mean(term.l1(v, ref))) for k, v in res.items()}
+    l1_med = {k: float(np.median(term.l1(v, ref))) for k, v in res.items()}
+    log(f"held-out mean L1 vs {n_steps}-step spectra: {l1}")
+    return mlp, {"systems": n_sys, "held_out": n_held, "steps": n_steps,
+                 "shape": "SrTiO3-shaped L2,3 edge in miniature: 4^3 k, 5^3 x, 24 bands, eps U[2,10], width U[20,60] eV",
+                 "dataset_seconds": t_gen, "train_seconds": t_train, "epochs": epochs,
+                 "loss_history": hist, "heldout_mean_l1": l1, "heldout_median_l1": l1_med,
+                 "invalid_predictions": int((~valid).sum())}
+
+
+def spectra_gain(ob, cr, h64, h32, psi0, mlp, ref_steps=600, base_steps=300):
+    """spectra/s of the plain FP64 recursion (base_steps) against the mixed path with fewer
+    steps closed by a terminator, at spectrum L1 <= 1e-3 against the FP64 reference."""
+    from paper_1601_07728_amd import terminator as term
+    n_pol = psi0.shape[0]
+    _, (a, b, n2, sd, _) = timed_haydock(h64, psi0, ref_steps)
+    ref = ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd)
+    rows = []
+    dt, (a, b, n2, sd, _) = timed_haydock(h64, psi0, base_steps)
+    t0 = time.perf_counter()
+    sig = ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd)
+    dt += time.perf_counter() - t0
+    base = {"path": "fp64", "steps": base_steps, "terminator": "none", "spectra_per_s": n_pol / dt,
+            "l1": float(np.mean(term.l1(sig, ref)))}
+    rows.append(base)
+    for steps in (32, 64, 96, 128, 192):
+        for name, h in (("fp32", h32), ("fp64", h64)):
+            dt, (a, b, n2, sd, _) = timed_haydock(h, psi0, steps)
+            for tname in ("sqrt", "mlp") if steps == 32 else ("sqrt",):
+                t0 = time.perf_counter()
+                if tname == "sqrt":
+                    sig = ob.spectrum(a, b, n2, cr.omega, cr.gamma, "sqrt", n_used=sd)
+                else:
+                    ae, be, valid = mlp.predict(a, b)
+                    sig = ob.spectrum(ae, be, n2, cr.omega, cr.gamma, "sqrt")
+                tt = dt + time.perf_counter() - t0
+                rows.append({"path": name, "steps": steps, "terminator": tname, "spectra_per_s": n_pol / tt,
+                             "l1": float(np.mean(term.l1(sig, ref)))})
+    ok = [r for r in rows if r["l1"] <= 1e-3]
+    best = max(ok, key=lambda r: r["spectra_per_s"]) if ok else None
+    for r in rows:
+        log(f"spectra: {r}")
+    return {"reference": f"FP64, {ref_steps} steps", "baseline": base, "best_at_l1_1e-3": best,
+            "gain_vs_fp64_baseline": None if best is None else best["spectra_per_s"] / base["spectra_per_s"],
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +235,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--term-systems", type=int, default=4096)
+    ap.add_argument("--term-held-out", type=int, default=256)
+    ap.add_argument("--term-epochs", type=int, default=120)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); independent solves "
@@ -191,10 +297,16 @@ def main():
                 "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
                 "kernel_ms_fp32": {k: round(v, 4) for k, v in avgs["fp32"].items()}}
 
+    mlp, terminator = bench_terminator(ob, args.seed, args.term_systems, args.term_held_out,
+                                       epochs=args.term_epochs)
+    gain = spectra_gain(ob, cr, h64, h32, psi0, mlp)
+    terminator["srtio3_spectra_gain"] = gain
+    mlp.close()
+
     batched = None
+    h64.close()
+    h32.close()
     if not args.no_batched:
-        h64.close()
-        h32.close()
         batched = bench_batched(ob, args.seed)
 
     cpu = None
@@ -222,6 +334,7 @@ def main():
         "fp64": results["fp64"],
         "mixed_fp32": results["fp32"],
         "batched": batched,
+        "terminator": terminator,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -184,6 +184,51 @@ int ocean_spectrum(const double* a, const double* b, const int* n_used, const do
                    int n_spec, int n_steps, int terminator, const double* omega, int n_omega,
                    double gamma, double* sigma);
 
+/* ---- Learned continued-fraction terminator ------------------------------------------
+ * Not part of the paper: a small network that extends the Haydock coefficients of
+ * section 3.2 from the first 32 pairs to 256, so that the continued fraction of
+ * eq. loss.fcn needs 32 H*v instead of hundreds.  Network 64 -> 256 -> 256 -> 256 -> 448,
+ * ReLU, mean-squared error, Adam (beta1 0.9, beta2 0.999, eps 1e-8).  Parameters are
+ * FP32 masters packed [W1, b1, W2, b2, W3, b3, W4, b4] with W stored [in][out]
+ * (ocean_mlp_param_count() floats).  The GEMMs run on the matrix cores: bf16 inputs
+ * with FP32 accumulation (OCEAN_MLP_BF16), or FP32 inputs (OCEAN_MLP_FP32).
+ * Encoding per sequence: c = mean(a_16..a_31), s = mean(b_17..b_32); input
+ * [(a_n - c)/s, b_{n+1}/s] for n < 32; output [(a_n - c)/s, log(b_{n+1}/s)] for
+ * 32 <= n < 256.  A handle owns its own stream; calls synchronise it before returning
+ * host data.  Not thread-safe. */
+typedef struct ocean_mlp_s* ocean_mlp_t;
+enum { OCEAN_MLP_BF16 = 0, OCEAN_MLP_FP32 = 1 };
+
+/* Number of packed parameters (263360). */
+int ocean_mlp_param_count(void);
+/* New network with zero parameters.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+int ocean_mlp_create(int precision, ocean_mlp_t* out);
+void ocean_mlp_destroy(ocean_mlp_t h);
+/* Copy parameters in (host, resets the Adam moments and step count) or out (host). */
+int ocean_mlp_set_params(ocean_mlp_t h, const float* params);
+int ocean_mlp_get_params(ocean_mlp_t h, float* params);
+/* Features x [n_seq][64] and, when t_dev is not NULL, targets t [n_seq][448] (device,
+ * FP32) from coefficient sequences a, b [n_seq][stride] (device, FP64, b[j] = b_{j+1});
+ * stride >= 32, or >= 256 with targets.  Synchronous.  Errors: INVALID_ARG, DEVICE. */
+int ocean_mlp_encode(const double* a_dev, const double* b_dev, int n_seq, int stride, float* x_dev,
+                     float* t_dev);
+/* y [batch][448] = network(x [batch][64]); device arrays.  Synchronous. */
+int ocean_mlp_forward(ocean_mlp_t h, const float* x_dev, int batch, float* y_dev);
+/* Loss and gradient of the mean-squared error over the batch; loss (host) and grad (host,
+ * packed like the parameters) may each be NULL.  Synchronous. */
+int ocean_mlp_loss_grad(ocean_mlp_t h, const float* x_dev, const float* t_dev, int batch,
+                        double* loss, float* grad);
+/* One Adam step on the batch (forward, backward, update) with learning rate lr.  Returns
+ * the batch loss in *loss if not NULL (then synchronous; otherwise asynchronous). */
+int ocean_mlp_train_step(ocean_mlp_t h, const float* x_dev, const float* t_dev, int batch, float lr,
+                         double* loss);
+/* Extended coefficients for n_seq sequences (host a, b [n_seq][stride], stride >= 32):
+ * a_ext, b_ext [n_seq][256] hold the given first 32 pairs followed by the 224 predicted
+ * ones; valid[s] = 0 flags a sequence whose prediction is not finite or has b <= 0 (the
+ * caller then falls back to full-depth Haydock).  Synchronous. */
+int ocean_mlp_predict(ocean_mlp_t h, const double* a, const double* b, int n_seq, int stride,
+                      double* a_ext, double* b_ext, int* valid);
+
 /* Host helper: the L2,3-edge (2p core, d channel) matrices for ocean_bse_desc
  * from the spin-orbit parameter zeta and the Slater integrals F2 (screened
  * direct) and G1, G3 (bare exchange), all in Ha (section 2: H_h, V_D, V_X;

@@ -41,7 +41,12 @@ EXPORTED = [
     "ocean_spectrum", "ocean_multiplet_matrices", "ocean_dipole_amplitudes", "ocean_dipole_psi0",
     "ocean_bse_set_profiling", "ocean_bse_kernel_times", "ocean_bse_device_bytes",
     "ocean_last_error", "ocean_haydock_batch", "ocean_bse_autotune", "ocean_bse_get_tuning",
+    "ocean_mlp_param_count", "ocean_mlp_create", "ocean_mlp_destroy", "ocean_mlp_set_params",
+    "ocean_mlp_get_params", "ocean_mlp_encode", "ocean_mlp_forward", "ocean_mlp_loss_grad",
+    "ocean_mlp_train_step", "ocean_mlp_predict",
 ]
+MLP_BF16 = 0
+MLP_FP32 = 1
 
 
 class OceanError(RuntimeError):
@@ -105,6 +110,26 @@ def lib() -> ctypes.CDLL:
     L.ocean_bse_autotune.restype = ci
     L.ocean_bse_get_tuning.argtypes = [vp, vp, vp, vp]
     L.ocean_bse_get_tuning.restype = ci
+    L.ocean_mlp_param_count.argtypes = []
+    L.ocean_mlp_param_count.restype = ci
+    L.ocean_mlp_create.argtypes = [ci, ctypes.POINTER(vp)]
+    L.ocean_mlp_create.restype = ci
+    L.ocean_mlp_destroy.argtypes = [vp]
+    L.ocean_mlp_destroy.restype = None
+    L.ocean_mlp_set_params.argtypes = [vp, vp]
+    L.ocean_mlp_set_params.restype = ci
+    L.ocean_mlp_get_params.argtypes = [vp, vp]
+    L.ocean_mlp_get_params.restype = ci
+    L.ocean_mlp_encode.argtypes = [vp, vp, ci, ci, vp, vp]
+    L.ocean_mlp_encode.restype = ci
+    L.ocean_mlp_forward.argtypes = [vp, vp, ci, vp]
+    L.ocean_mlp_forward.restype = ci
+    L.ocean_mlp_loss_grad.argtypes = [vp, vp, vp, ci, vp, vp]
+    L.ocean_mlp_loss_grad.restype = ci
+    L.ocean_mlp_train_step.argtypes = [vp, vp, vp, ci, ctypes.c_float, vp]
+    L.ocean_mlp_train_step.restype = ci
+    L.ocean_mlp_predict.argtypes = [vp, vp, vp, ci, ci, vp, vp, vp]
+    L.ocean_mlp_predict.restype = ci
     L.ocean_last_error.argtypes = []
     L.ocean_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -358,3 +383,88 @@ class Bse:
     @property
     def device_bytes(self) -> int:
         return int(lib().ocean_bse_device_bytes(self._h))
+
+
+class Mlp:
+    """Learned terminator network (ocean_mlp_*).  Device arrays are torch.float32 tensors."""
+
+    def __init__(self, precision: str = "bf16"):
+        h = ctypes.c_void_p()
+        _check(lib().ocean_mlp_create(MLP_BF16 if precision == "bf16" else MLP_FP32, ctypes.byref(h)))
+        self._h = h
+        self.n_params = int(lib().ocean_mlp_param_count())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ocean_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _f32(t):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("expected a contiguous float32 CUDA tensor")
+        return t.data_ptr()
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.n_params:
+            raise ValueError("wrong parameter count")
+        _check(lib().ocean_mlp_set_params(self._h, _ptr(p)))
+
+    def get_params(self):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().ocean_mlp_get_params(self._h, _ptr(p)))
+        return p
+
+    @staticmethod
+    def encode(a_dev, b_dev, with_targets: bool = True):
+        """Features (and targets) from device FP64 coefficient arrays [n_seq, stride]."""
+        import torch
+        n, stride = a_dev.shape
+        for t in (a_dev, b_dev):
+            if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+                raise ValueError("expected contiguous float64 CUDA tensors")
+        x = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+        t = torch.empty((n, 448), dtype=torch.float32, device="cuda") if with_targets else None
+        _device_sync()
+        _check(lib().ocean_mlp_encode(a_dev.data_ptr(), b_dev.data_ptr(), n, stride, x.data_ptr(),
+                                      None if t is None else t.data_ptr()))
+        return x, t
+
+    def forward(self, x):
+        import torch
+        y = torch.empty((x.shape[0], 448), dtype=torch.float32, device="cuda")
+        _device_sync()
+        _check(lib().ocean_mlp_forward(self._h, self._f32(x), x.shape[0], self._f32(y)))
+        return y
+
+    def loss_grad(self, x, t):
+        loss = ctypes.c_double()
+        g = np.zeros(self.n_params, dtype=np.float32)
+        _device_sync()
+        _check(lib().ocean_mlp_loss_grad(self._h, self._f32(x), self._f32(t), x.shape[0], ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def train_step(self, x, t, lr: float, want_loss: bool = False):
+        loss = ctypes.c_double()
+        _check(lib().ocean_mlp_train_step(self._h, self._f32(x), self._f32(t), x.shape[0], float(lr),
+                                          ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def predict(self, a, b):
+        """Extended (a, b) [n, 256] from host arrays a, b [n, >=32]; valid flags [n]."""
+        a = _host_f64(np.atleast_2d(a))
+        b = _host_f64(np.atleast_2d(b))
+        n, stride = a.shape
+        ae = np.zeros((n, 256))
+        be = np.zeros((n, 256))
+        valid = np.zeros(n, dtype=np.int32)
+        _check(lib().ocean_mlp_predict(self._h, _ptr(a), _ptr(b), n, stride, _ptr(ae), _ptr(be), _ptr(valid)))
+        return ae, be, valid.astype(bool)

@@ -52,6 +52,7 @@ struct Workspace {
     int bwd_chunks = 0;
     void* phi = nullptr;        // [Nk][Nx][cols] complex (FP64 or FP32)
     double* part = nullptr;     // [S][Nk][Nb][cols] complex back-projection partials
+    double* w0 = nullptr;       // [Nk][Nb][cols] complex: the partials summed (W0 x)
     double* loc_part = nullptr; // [P][nv][Nc*Nmu] complex
     double* loc_b = nullptr;    // [nv][Nc*Nmu] complex
     size_t bytes = 0;
@@ -136,6 +137,8 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb);
 hipError_t launch_local_in(ocean_bse_s* h, const double* x, int nv);
 hipError_t launch_local_mat(ocean_bse_s* h, int nv);
 hipError_t launch_combine(ocean_bse_s* h, const double* x, double* y, int nv, double* dot_part);
+hipError_t launch_reduce_part(ocean_bse_s* h, int nv);
+hipError_t launch_w_gamma(ocean_bse_s* h, int cols);
 hipError_t launch_build_w(ocean_bse_s* h, const double* wr_dev, const double* wv_dev, int n_wr,
                           double h_r);
 hipError_t launch_to_fp32(ocean_bse_s* h, const double* src, float* dst, long long n);

@@ -409,7 +409,7 @@ void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks,
     const int bb = (h->Nb + 16 * W - 1) / (16 * W);
     const long long per_chunk = (long long)h->Nk * bb;
     long long s = (target_blocks + per_chunk - 1) / per_chunk;
-    const long long smax = (h->Nx + 63) / 64;
+    const long long smax = std::max(1, (h->Nx + 511) / 512);  // >= 512 points per chunk
     if (s < 1) s = 1;
     if (s > smax) s = smax;
     int c = (int)((h->Nx + s - 1) / s);

@@ -125,7 +125,8 @@ static void release_workspace(ocean_bse_s* h) {
     if (w.part) (void)hipFree(w.part);
     if (w.loc_part) (void)hipFree(w.loc_part);
     if (w.loc_b) (void)hipFree(w.loc_b);
-    w.part = w.loc_part = w.loc_b = nullptr;
+    if (w.w0) (void)hipFree(w.w0);
+    w.part = w.loc_part = w.loc_b = w.w0 = nullptr;
     h->device_bytes -= w.bytes;
     w.bytes = 0;
     w.cols = 0;
@@ -152,7 +153,8 @@ static int ensure_workspace(ocean_bse_s* h, int nv) {
     const int NP = std::max(1, h->Nc * h->Nmu);
     const size_t locp_b = (size_t)local_blocks(h) * nv * NP * 16;
     const size_t locb_b = (size_t)nv * NP * 16;
-    const size_t total = phi_b + part_b + locp_b + locb_b;
+    const size_t w0_b = (size_t)h->Nk * h->Nb * cols * 16;
+    const size_t total = phi_b + part_b + locp_b + locb_b + w0_b;
     if (h->device_bytes + total > max_device_bytes()) {
         set_error("device memory cap (OCEAN_MAX_DEVICE_BYTES) exceeded allocating the H*v workspace");
         return OCEAN_ERR_OUT_OF_MEMORY;
@@ -167,6 +169,8 @@ static int ensure_workspace(ocean_bse_s* h, int nv) {
     w.loc_part = static_cast<double*>(p);
     if (hipMalloc(&p, locb_b) != hipSuccess) goto oom;
     w.loc_b = static_cast<double*>(p);
+    if (hipMalloc(&p, w0_b) != hipSuccess) goto oom;
+    w.w0 = static_cast<double*>(p);
     w.bytes = total;
     h->device_bytes += total;
     w.cols = cols;
@@ -177,8 +181,9 @@ oom:
     if (w.phi) (void)hipFree(w.phi);
     if (w.part) (void)hipFree(w.part);
     if (w.loc_part) (void)hipFree(w.loc_part);
+    if (w.loc_b) (void)hipFree(w.loc_b);
     w.phi = nullptr;
-    w.part = w.loc_part = w.loc_b = nullptr;
+    w.part = w.loc_part = w.loc_b = w.w0 = nullptr;
     w.bytes = 0;
     w.cols = 0;
     set_error("hipMalloc failed for the H*v workspace (" + std::to_string(total) + " bytes)");
@@ -190,9 +195,13 @@ static int apply_pipeline(ocean_bse_s* h, const double* x, double* y, int nv, do
     const int cols = nv * h->Nc;
     for (int c0 = 0; c0 < cols; c0 += kColsPerPass)
         OCEAN_HIP(launch_proj_fwd(h, x, nv, c0, std::min(kColsPerPass, cols - c0)), "proj_fwd launch");
-    OCEAN_HIP(launch_fft_w(h, cols), "fft_w launch");
+    if (h->Nk == 1)
+        OCEAN_HIP(launch_w_gamma(h, cols), "w_gamma launch");
+    else
+        OCEAN_HIP(launch_fft_w(h, cols), "fft_w launch");
     for (int c0 = 0; c0 < cols; c0 += kColsPerPass)
         OCEAN_HIP(launch_proj_bwd(h, nv, c0, std::min(kColsPerPass, cols - c0)), "proj_bwd launch");
+    OCEAN_HIP(launch_reduce_part(h, nv), "reduce_part launch");
     if (h->Nmu > 0 && h->K != nullptr) {
         OCEAN_HIP(launch_local_in(h, x, nv), "local_in launch");
         OCEAN_HIP(launch_local_mat(h, nv), "local_mat launch");

@@ -481,6 +481,44 @@ __global__ __launch_bounds__(256) void dipole_kernel(const double2* __restrict__
     }
 }
 
+// w0[kn][col] = sum over chunks s of part[s][kn][col]: element e = blockIdx.x * 64 + (t % 64)
+// is summed by four threads over s = g, g + 4, ... (g = t / 64), then ((g0 + g1) + g2) + g3.
+__global__ __launch_bounds__(256) void reduce_part_kernel(const double2* __restrict__ part,
+                                                         double2* __restrict__ w0, int S,
+                                                         long long n_elem) {
+    __shared__ double2 sh[256];
+    const int t = threadIdx.x;
+    const int g = t >> 6;
+    const long long e = (long long)blockIdx.x * 64 + (t & 63);
+    double2 acc = make_double2(0.0, 0.0);
+    if (e < n_elem)
+        for (int s = g; s < S; s += 4) acc = cadd(acc, part[(size_t)s * n_elem + e]);
+    sh[t] = acc;
+    __syncthreads();
+    if (g == 0 && e < n_elem) {
+        double2 r = sh[t];
+        r = cadd(r, sh[t + 64]);
+        r = cadd(r, sh[t + 128]);
+        r = cadd(r, sh[t + 192]);
+        w0[e] = r;
+    }
+}
+
+// Gamma-point-only grids: the k-grid transform is the identity and W(x, R = 0) is diagonal
+// in x, so Algorithm 1 lines 3-5 reduce to phi[x][col] *= W[x].
+template <typename C2, typename T>
+__global__ __launch_bounds__(256) void w_gamma_kernel(C2* __restrict__ phi, const T* __restrict__ W,
+                                                     long long n_elem, int cols) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
+        const T w = W[e / cols];
+        C2 v = phi[e];
+        v.x *= w;
+        v.y *= w;
+        phi[e] = v;
+    }
+}
+
 inline long long per_block(long long dim) { return (dim + kRedBlocks - 1) / kRedBlocks; }
 
 }  // namespace
@@ -514,6 +552,28 @@ hipError_t launch_local_mat(ocean_bse_s* h, int nv) {
     return hipGetLastError();
 }
 
+hipError_t launch_reduce_part(ocean_bse_s* h, int nv) {
+    const long long n_elem = (long long)h->Nk * h->Nb * nv * h->Nc;
+    const int slot = prof_begin(h, "reduce_part");
+    reduce_part_kernel<<<(unsigned)((n_elem + 63) / 64), 256, 0, h->stream>>>(
+        reinterpret_cast<const double2*>(h->ws.part), reinterpret_cast<double2*>(h->ws.w0), h->ws.bwd_chunks,
+        n_elem);
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_w_gamma(ocean_bse_s* h, int cols) {
+    const long long n_elem = (long long)h->Nx * cols;
+    const unsigned nblk = (unsigned)std::min<long long>((n_elem + 255) / 256, 65536);
+    const int slot = prof_begin(h, "fft_w");
+    if (h->precision == OCEAN_PREC_FP64)
+        w_gamma_kernel<double2, double><<<nblk, 256, 0, h->stream>>>(static_cast<double2*>(h->ws.phi), h->W64, n_elem, cols);
+    else
+        w_gamma_kernel<float2, float><<<nblk, 256, 0, h->stream>>>(static_cast<float2*>(h->ws.phi), h->W32, n_elem, cols);
+    prof_end(h, slot);
+    return hipGetLastError();
+}
+
 hipError_t launch_combine(ocean_bse_s* h, const double* x, double* y, int nv, double* dot_part) {
     const long long NkNb = (long long)h->Nk * h->Nb;
     const long long per = (NkNb + kRedBlocks - 1) / kRedBlocks;
@@ -523,8 +583,8 @@ hipError_t launch_combine(ocean_bse_s* h, const double* x, double* y, int nv, do
     combine_kernel<<<grid, 256, 0, h->stream>>>(
         reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), h->E,
         reinterpret_cast<const double2*>(h->Hc), reinterpret_cast<const double2*>(h->A),
-        reinterpret_cast<const double2*>(h->ws.loc_b), reinterpret_cast<const double2*>(h->ws.part),
-        h->ws.bwd_chunks, nv, NkNb, h->Nc, h->Nmu, h->Hc != nullptr, has_w, dot_part, per);
+        reinterpret_cast<const double2*>(h->ws.loc_b), reinterpret_cast<const double2*>(h->ws.w0),
+        1, nv, NkNb, h->Nc, h->Nmu, h->Hc != nullptr, has_w, dot_part, per);
     prof_end(h, slot);
     return hipGetLastError();
 }

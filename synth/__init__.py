@@ -267,3 +267,14 @@ def molecule_sites(seed: int = 0, n_atoms: int = 52, n_sites: int = 40, box: flo
             u = gpu_orthonormal_u(1, grid ** 3, nb, seed=site_seed)
         sites.append((cr, u))
     return sites
+
+
+def terminator_system(seed: int, nk=(2, 2, 2), nx=(5, 5, 5), n_bands: int = 24,
+                      n_steps: int = 512) -> Crystal:
+    """One system of the learned-terminator dataset: the SrTiO3-shaped L2,3 edge in
+    miniature, with eps ~ U[2, 10] and band width ~ U[20, 60] eV drawn from the seed."""
+    rng = np.random.default_rng([seed, 7])
+    eps = float(rng.uniform(2.0, 10.0))
+    width = float(rng.uniform(20.0, 60.0))
+    return config2_shape(nk=nk, nx=nx, n_bands=n_bands, seed=seed, eps=eps, n_steps=n_steps,
+                         psi0="none", e_range_ev=width)
