@@ -64,12 +64,42 @@ template <> __device__ __forceinline__ float2 bload<float2>(Rsrc r, unsigned off
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
+// B operands are staged in LDS in MFMA order: value s (0..3) of lane l for sub-step ss and
+// column tile t sits at ((ss * NT + t) * 64 + l) * 4 + s, so a wave reads its operands with
+// one 4-wide LDS load per (ss, t).  Lane l = i + 16 kq of sub-step ss covers the
+// contraction slots (2 kq + s / 2, s % 2) of that 8-wide step and real column 16 t + i.
+
+template <typename T> struct Vec4;
+template <> struct Vec4<double> { typedef double4 t; };
+template <> struct Vec4<float> { typedef float4 t; };
+
+// Write the four B values of one complex input (re, im) at contraction point r8 (0..7 within
+// a sub-step) and local column cl into the MFMA-ordered buffer.  fwd = true gives
+// [[re, im], [-im, re]], false gives [[re, im], [im, -re]] (rows p, columns q).
+template <typename T, int NT>
+__device__ __forceinline__ void stage_pair(T* buf, int ss, int r8, int cl, double re, double im, bool fwd) {
+    const int kq = r8 >> 1, ns = r8 & 1;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int jr = 2 * cl + q;
+        const int t = jr >> 4, i = jr & 15;
+        if (t >= NT) continue;
+        T* dst = buf + ((size_t)(ss * NT + t) * 64 + i + 16 * kq) * 4 + 2 * ns;
+        if (fwd) {
+            dst[0] = (T)(q ? im : re);
+            dst[1] = (T)(q ? re : -im);
+        } else {
+            dst[0] = (T)(q ? im : re);
+            dst[1] = (T)(q ? -re : im);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Forward projection.  Block = 4 waves and one k; wave w owns rows
 // [xt*64*MS + w*16*MS, +16*MS) and every column tile.  The bands are walked in chunks of
-// KC: the chunk of psi (the B operand, shared by all waves) is staged in LDS, double
-// buffered, while each wave keeps the u values (A operand) of the next chunk in flight in
-// registers.
+// KC: the psi chunk (B operand, shared by all waves) is staged in LDS in MFMA order, double
+// buffered, while each wave keeps the u values (A operand) of the next chunk in flight.
 template <typename T, int MS, int NT, int KC>
 __global__ __launch_bounds__(256) void proj_fwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const double2* __restrict__ psi,
@@ -77,24 +107,17 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
     int ncb, int x_tiles) {
     typedef typename Cplx<T>::c2 C2;
     typedef typename Cplx<T>::acc ACC;
+    typedef typename Vec4<T>::t V4;
     constexpr int SS = KC / 8;                 // 8-band sub-steps per chunk
-    __shared__ double2 sP[2][KC * kColsPerPass];
+    constexpr int BUF = SS * NT * 64 * 4;      // T values per staged chunk
+    __shared__ __align__(16) T sB[2][BUF];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
     const int k = blockIdx.x / x_tiles;
     const int xt = blockIdx.x - k * x_tiles;
     const int rowbase = xt * (64 * MS) + wave * (16 * MS);
     const C2* Uk = U + (size_t)k * Nx * Nb;
-    const int q = i & 1;
 
-    int lcol[NT];
-    bool cval[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int cl = (16 * t + i) >> 1;
-        cval[t] = cl < ncb;
-        lcol[t] = cval[t] ? cl : 0;
-    }
     // u rows of this block: [xt*64*MS, min(Nx, (xt+1)*64*MS)), all bands
     const int brow0 = xt * (64 * MS);
     const int brows = min(Nx - brow0, 64 * MS);
@@ -108,7 +131,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
         rval[ms] = row < Nx;
         urow[ms] = (unsigned)((row - brow0) * Nb) * sizeof(C2);
     }
-    // cooperative psi chunk loads: element e = (n_local, c_local)
+    // cooperative psi chunk loads: element e = (n_local, c_local), c fastest
     constexpr int PER = (KC * kColsPerPass + 255) / 256;
     auto load_p = [&](int n0, double2 (&pv)[PER]) {
 #pragma unroll
@@ -127,7 +150,8 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 256 * j;
-            if (e < KC * kColsPerPass) sP[buf][e] = pv[j];
+            const int nl = e / kColsPerPass, cl = e - nl * kColsPerPass;
+            if (nl < KC && cl < ncb) stage_pair<T, NT>(sB[buf], nl >> 3, nl & 7, cl, pv[j].x, pv[j].y, true);
         }
     };
     auto load_a = [&](int n0, C2 (&aa)[MS][SS][2]) {
@@ -143,6 +167,9 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
             }
     };
 
+    // padding columns stay zero in both buffers
+    for (int e = threadIdx.x; e < 2 * BUF; e += 256) (&sB[0][0])[e] = (T)0;
+
     ACC acc[MS][NT];
 #pragma unroll
     for (int ms = 0; ms < MS; ++ms)
@@ -156,6 +183,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
     // Drain the prologue loads here: otherwise the wait-count analysis merges this path into
     // the loop header and waits for every in-flight prefetch before the first MFMA of a chunk.
     __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     store_p(0, pv);
     int buf = 0;
     for (int n0 = 0; n0 < Nb; n0 += KC) {
@@ -167,23 +195,20 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
-            T bv[NT][4];
+            V4 bv[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int ns = 0; ns < 2; ++ns) {
-                    const double2 p = sP[buf][(8 * ss + 2 * kq + ns) * kColsPerPass + lcol[t]];
-                    // B[(n, 0)][(c, q)] and B[(n, 1)][(c, q)]; zero for padding columns
-                    bv[t][2 * ns + 0] = cval[t] ? (T)(q ? p.y : p.x) : (T)0;
-                    bv[t][2 * ns + 1] = cval[t] ? (T)(q ? p.x : -p.y) : (T)0;
-                }
+                bv[t] = *reinterpret_cast<const V4*>(&sB[buf][((ss * NT + t) * 64 + lane) * 4]);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
 #pragma unroll
                 for (int ms = 0; ms < MS; ++ms) {
                     const T av = (s & 1) ? a[ms][ss][s >> 1].y : a[ms][ss][s >> 1].x;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) acc[ms][t] = mfma16(av, bv[t][s], acc[ms][t]);
+                    for (int t = 0; t < NT; ++t) {
+                        const T b = s == 0 ? bv[t].x : s == 1 ? bv[t].y : s == 2 ? bv[t].z : bv[t].w;
+                        acc[ms][t] = mfma16(av, b, acc[ms][t]);
+                    }
                 }
             }
         }
@@ -217,8 +242,8 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 // ---------------------------------------------------------------------------------------------
 // Backward projection with split-K over x.  Block = (k, band block of W x 16 bands,
 // x chunk); wave w owns the 16 bands [band block * 16 W + 16 w, +16).  The chunk is walked
-// in tiles of XT points: the phi' tile (B operand, shared by all waves) is staged in LDS,
-// double buffered, and every wave keeps the u values of the next tile in flight.
+// in tiles of XT points: the phi' tile (B operand, shared by all waves) is staged in LDS in
+// MFMA order, double buffered, and every wave keeps the u values of the next tile in flight.
 template <typename T, int NT, int XT, int W>
 __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const typename Cplx<T>::c2* __restrict__ phi,
@@ -226,8 +251,10 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     int band_blocks, int S, int chunk) {
     typedef typename Cplx<T>::c2 C2;
     typedef typename Cplx<T>::acc ACC;
+    typedef typename Vec4<T>::t V4;
     constexpr int SS = XT / 8;
-    __shared__ C2 sB[2][XT * kColsPerPass];
+    constexpr int BUF = SS * NT * 64 * 4;
+    __shared__ __align__(16) T sB[2][BUF];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
     int blk = blockIdx.x;
@@ -239,16 +266,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     const int x_begin = s * chunk;
     const int x_end = min(Nx, x_begin + chunk);
     const C2* Uk = U + (size_t)k * Nx * Nb;
-    const int q = i & 1;
 
-    int lcol[NT];
-    bool cval[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int cl = (16 * t + i) >> 1;
-        cval[t] = cl < ncb;
-        lcol[t] = cval[t] ? cl : 0;
-    }
     const int n = nbase + i;
     const bool nval = n < Nb;
     // u rows [x_begin, x_end) of this k, all bands; phi' x-blocks covering the chunk
@@ -273,7 +291,8 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 64 * W * j;
-            if (e < XT * kColsPerPass) sB[buf][e] = bv[j];
+            const int xl = e / kColsPerPass, cl = e - xl * kColsPerPass;
+            if (xl < XT && cl < ncb) stage_pair<T, NT>(sB[buf], xl >> 3, xl & 7, cl, bv[j].x, bv[j].y, false);
         }
     };
     auto load_a = [&](int x0, C2 (&aa)[SS][2]) {
@@ -287,6 +306,8 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
             }
     };
 
+    for (int e = threadIdx.x; e < 2 * BUF; e += 64 * W) (&sB[0][0])[e] = (T)0;
+
     ACC acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = ACC{0, 0, 0, 0};
@@ -296,6 +317,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     load_b(x_begin, bl);
     load_a(x_begin, a);
     __builtin_amdgcn_s_waitcnt(0);  // drain the prologue (see the forward kernel)
+    __syncthreads();
     store_b(0, bl);
     int buf = 0;
     for (int x0 = x_begin; x0 < x_end; x0 += XT) {
@@ -306,21 +328,18 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
-            T bv[NT][4];
+            V4 bv[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int xs = 0; xs < 2; ++xs) {
-                    const C2 p = sB[buf][(8 * ss + 2 * kq + xs) * kColsPerPass + lcol[t]];
-                    // B[(x, 0)][(c, q)] and B[(x, 1)][(c, q)]; zero for padding columns
-                    bv[t][2 * xs + 0] = cval[t] ? (q ? p.y : p.x) : (T)0;
-                    bv[t][2 * xs + 1] = cval[t] ? (q ? -p.x : p.y) : (T)0;
-                }
+                bv[t] = *reinterpret_cast<const V4*>(&sB[buf][((ss * NT + t) * 64 + lane) * 4]);
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const T av = (st & 1) ? a[ss][st >> 1].y : a[ss][st >> 1].x;
 #pragma unroll
-                for (int t = 0; t < NT; ++t) acc[t] = mfma16(av, bv[t][st], acc[t]);
+                for (int t = 0; t < NT; ++t) {
+                    const T b = st == 0 ? bv[t].x : st == 1 ? bv[t].y : st == 2 ? bv[t].z : bv[t].w;
+                    acc[t] = mfma16(av, b, acc[t]);
+                }
             }
         }
         store_b(buf ^ 1, bl);
