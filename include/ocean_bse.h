@@ -59,13 +59,17 @@ enum {
 enum {
     OCEAN_PREC_FP64 = 0,       /* u_nk in FP64, FP64 MFMA */
     OCEAN_PREC_FP32 = 1,       /* u_nk stored FP32, FP32 MFMA, FP32 accumulation */
-    OCEAN_PREC_SPLIT_BF16 = 2  /* u_nk stored as bf16 hi + lo, 3-product compensated bf16 MFMA, FP32 accumulation */
+    OCEAN_PREC_SPLIT_BF16 = 2, /* u_nk stored as bf16 hi + residual planes (8 B per complex), the vector split
+                                  into hi + residual when staged; 3 bf16 MFMA products, FP32 accumulation */
+    OCEAN_PREC_BF16 = 3        /* u_nk stored as one bf16 plane (4 B per complex), the vector split into hi +
+                                  residual; 2 bf16 MFMA products, FP32 accumulation.  The error is set by
+                                  the bf16 rounding of u_nk (relative 2^-9 per element). */
 };
 
 /* ocean_bse_desc.flags */
 #define OCEAN_FLAG_BORROW_DEVICE_U 0x1u  /* desc.u is a device pointer: in FP64 mode the handle uses it in
-                                            place (it must outlive the handle); in FP32 mode it is
-                                            only read during ocean_bse_create */
+                                            place (it must outlive the handle); in the FP32 and bf16
+                                            modes it is only read during ocean_bse_create */
 #define OCEAN_FLAG_CHECK_INPUTS    0x2u  /* scan inputs for NaN/Inf and check Hermiticity of the small matrices */
 
 /* ocean_haydock flags */

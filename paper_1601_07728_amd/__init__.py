@@ -28,7 +28,8 @@ ERR_UNSUPPORTED = -4
 PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_SPLIT_BF16 = 2
-PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16}
+PREC_BF16 = 3
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16, "bf16": PREC_BF16}
 
 FLAG_BORROW_DEVICE_U = 0x1
 FLAG_CHECK_INPUTS = 0x2

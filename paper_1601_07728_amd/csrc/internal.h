@@ -99,7 +99,7 @@ struct ocean_bse_s {
     const double* U64 = nullptr;    // [Nk][Nx][Nb] complex (owned or borrowed)
     double* U64_owned = nullptr;
     float* U32 = nullptr;           // [Nk][Nx][Nb] complex FP32 copy (FP32 mode)
-    uint16_t* Ubf = nullptr;        // [Nk][Nx][Nb][hi re, hi im, lo re, lo im] bf16 (split-BF16 mode)
+    uint16_t* Ubf = nullptr;        // bf16 modes: hi plane [Nk][Nx][Nb][re, im], then (split) the residual plane
     double* W64 = nullptr;          // [Nx][Nk] W(x, R)
     float* W32 = nullptr;
     double* phase = nullptr;        // per-axis e^{2 pi i a b / (n g)} tables, complex
@@ -142,7 +142,7 @@ hipError_t launch_w_gamma(ocean_bse_s* h, int cols);
 hipError_t launch_build_w(ocean_bse_s* h, const double* wr_dev, const double* wv_dev, int n_wr,
                           double h_r);
 hipError_t launch_to_fp32(ocean_bse_s* h, const double* src, float* dst, long long n);
-hipError_t launch_to_split_bf16(ocean_bse_s* h);
+hipError_t launch_to_bf16(ocean_bse_s* h, const double* src, uint16_t* hi, uint16_t* lo, long long n);
 hipError_t launch_dipole_psi0(ocean_bse_s* h, const double* d_dev, int n_pol, double* psi0);
 
 // Lanczos kernels

@@ -364,6 +364,318 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// bf16 matrix-core variants (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  u is stored as a
+// bf16 "hi" plane [k][x][n][re, im] and, in the split mode, a "lo" plane holding the
+// rounding residual u - hi.  The B operand (psi forward, phi' back) is split into hi + lo
+// when it is staged, and the products hi*hi + hi*lo (+ lo*hi in the split mode) are
+// accumulated, so the operand rounding of the dominant terms is compensated.
+// One MFMA contracts 16 complex points: lane l = i + 16 kq holds the 8 slots of points
+// 4 kq .. 4 kq + 3, slot 2 m + p = part p of point m.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+
+__device__ __forceinline__ v4f mfma_bf16(bf16x8 a, bf16x8 b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void split2(double v, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)(float)v;
+    lo = (__bf16)(float)(v - (double)(float)hi);
+}
+
+// Stage the B values of one complex input at contraction point r16 (0..15 within a
+// sub-step) and local column cl, as hi and lo bf16 planes in MFMA order.
+template <int NT>
+__device__ __forceinline__ void stage_pair_bf16(__bf16* bh, __bf16* bl, int ss, int r16, int cl, double re,
+                                                double im, bool fwd) {
+    const int kq = r16 >> 2, m = r16 & 3;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int jr = 2 * cl + q;
+        const int t = jr >> 4, i = jr & 15;
+        if (t >= NT) continue;
+        const size_t o = ((size_t)(ss * NT + t) * 64 + i + 16 * kq) * 8 + 2 * m;
+        const double v0 = q ? im : re;
+        const double v1 = fwd ? (q ? re : -im) : (q ? -re : im);
+        split2(v0, bh[o], bl[o]);
+        split2(v1, bh[o + 1], bl[o + 1]);
+    }
+}
+
+template <int MS, int NT, bool LO>
+__global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
+    const u16* __restrict__ Uh, const u16* __restrict__ Ul, const double2* __restrict__ psi,
+    float2* __restrict__ phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0, int ncb,
+    int x_tiles) {
+    constexpr int KC = 32, SS = KC / 16;
+    constexpr int BUF = SS * NT * 64 * 8;
+    __shared__ __align__(16) __bf16 sH[2][BUF];
+    __shared__ __align__(16) __bf16 sL[2][BUF];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+    const int k = blockIdx.x / x_tiles;
+    const int xt = blockIdx.x - k * x_tiles;
+    const int rowbase = xt * (64 * MS) + wave * (16 * MS);
+    const int brow0 = xt * (64 * MS);
+    const int brows = min(Nx - brow0, 64 * MS);
+    const size_t plane0 = ((size_t)k * Nx + brow0) * Nb * 2;
+    const Rsrc urh = make_rsrc(Uh + plane0, (size_t)brows * Nb * 4);
+    const Rsrc url = make_rsrc(LO ? Ul + plane0 : Uh + plane0, (size_t)brows * Nb * 4);
+    const Rsrc pr = make_rsrc(psi, (size_t)(col0 + ncb + Nc) / Nc * Nk * Nb * Nc * sizeof(double2));
+    bool rval[MS];
+    unsigned urow[MS];
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms) {
+        const int row = rowbase + 16 * ms + i;
+        rval[ms] = row < Nx;
+        urow[ms] = (unsigned)((row - brow0) * Nb) * 4u;
+    }
+    constexpr int PER = (KC * kColsPerPass + 255) / 256;
+    auto load_p = [&](int n0, double2 (&pv)[PER]) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            const int nl = e / kColsPerPass, cl = e - nl * kColsPerPass;
+            const int n = n0 + nl;
+            const bool ok = nl < KC && cl < ncb && n < Nb;
+            const int col = col0 + cl;
+            const int vv = col / Nc, c = col - vv * Nc;
+            const unsigned off = (unsigned)((((size_t)(vv * Nk + k) * Nb + n) * Nc + c) * sizeof(double2));
+            pv[j] = bload<double2>(pr, ok ? off : kOob);
+        }
+    };
+    auto store_p = [&](int buf, const double2 (&pv)[PER]) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            const int nl = e / kColsPerPass, cl = e - nl * kColsPerPass;
+            if (nl < KC && cl < ncb) stage_pair_bf16<NT>(sH[buf], sL[buf], nl >> 4, nl & 15, cl, pv[j].x, pv[j].y, true);
+        }
+    };
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    auto load_a = [&](int n0, u32x4 (&ah)[MS][SS], u32x4 (&al)[MS][SS]) {
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss) {
+            const int n = n0 + 16 * ss + 4 * kq;
+            const bool nok = n < Nb;
+#pragma unroll
+            for (int ms = 0; ms < MS; ++ms) {
+                const unsigned off = (nok && rval[ms]) ? urow[ms] + (unsigned)n * 4u : kOob;
+                ah[ms][ss] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(urh, (int)off, 0, 0));
+                if (LO) al[ms][ss] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(url, (int)off, 0, 0));
+            }
+        }
+    };
+
+    for (int e = threadIdx.x; e < 2 * BUF; e += 256) {
+        (&sH[0][0])[e] = (__bf16)0.f;
+        (&sL[0][0])[e] = (__bf16)0.f;
+    }
+    v4f acc[MS][NT];
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[ms][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    u32x4 ah[MS][SS], al[MS][SS], ahn[MS][SS], aln[MS][SS];
+    double2 pv[PER];
+    load_p(0, pv);
+    load_a(0, ah, al);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    store_p(0, pv);
+    int buf = 0;
+    for (int n0 = 0; n0 < Nb; n0 += KC) {
+        __syncthreads();
+        load_p(n0 + KC, pv);
+        load_a(n0 + KC, ahn, aln);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss) {
+            bf16x8 bh[NT], bl[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                bh[t] = *reinterpret_cast<const bf16x8*>(&sH[buf][((ss * NT + t) * 64 + lane) * 8]);
+                bl[t] = *reinterpret_cast<const bf16x8*>(&sL[buf][((ss * NT + t) * 64 + lane) * 8]);
+            }
+#pragma unroll
+            for (int ms = 0; ms < MS; ++ms) {
+                const bf16x8 a_h = __builtin_bit_cast(bf16x8, ah[ms][ss]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    acc[ms][t] = mfma_bf16(a_h, bh[t], acc[ms][t]);
+                    acc[ms][t] = mfma_bf16(a_h, bl[t], acc[ms][t]);
+                }
+                if (LO) {
+                    const bf16x8 a_l = __builtin_bit_cast(bf16x8, al[ms][ss]);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[ms][t] = mfma_bf16(a_l, bh[t], acc[ms][t]);
+                }
+            }
+        }
+        store_p(buf ^ 1, pv);
+#pragma unroll
+        for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+            for (int ss = 0; ss < SS; ++ss) {
+                ah[ms][ss] = ahn[ms][ss];
+                if (LO) al[ms][ss] = aln[ms][ss];
+            }
+        buf ^= 1;
+    }
+
+    float* out = reinterpret_cast<float*>(phi);
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int jr = 16 * t + i;
+            if ((jr >> 1) >= ncb) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rowbase + 16 * ms + 4 * kq + r;
+                if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = acc[ms][t][r];
+            }
+        }
+}
+
+template <int NT, int W, bool LO>
+__global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
+    const u16* __restrict__ Uh, const u16* __restrict__ Ul, const float2* __restrict__ phi,
+    double* __restrict__ part, int Nk, int Nx, int Nb, int cols, int col0, int ncb,
+    int band_blocks, int S, int chunk) {
+    constexpr int XT = 64, SS = XT / 16;
+    constexpr int BUF = SS * NT * 64 * 8;
+    __shared__ __align__(16) __bf16 sH[2][BUF];
+    __shared__ __align__(16) __bf16 sL[2][BUF];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+    int blk = blockIdx.x;
+    const int s = blk % S;
+    blk /= S;
+    const int bb = blk % band_blocks;
+    const int k = blk / band_blocks;
+    const int nbase = bb * 16 * W + 16 * wave;
+    const int x_begin = s * chunk;
+    const int x_end = min(Nx, x_begin + chunk);
+    const int n = nbase + i;
+    const bool nval = n < Nb;
+    const size_t plane0 = ((size_t)k * Nx + x_begin) * Nb * 2;
+    const Rsrc urh = make_rsrc(Uh + plane0, (size_t)(x_end - x_begin) * Nb * 4);
+    const Rsrc url = make_rsrc(LO ? Ul + plane0 : Uh + plane0, (size_t)(x_end - x_begin) * Nb * 4);
+    const int xb0 = x_begin / kXB;
+    const float2* pbase = phi + (size_t)xb0 * Nk * kXB * cols;
+    const Rsrc prs = make_rsrc(pbase, (size_t)((x_end - 1) / kXB - xb0 + 1) * Nk * kXB * cols * sizeof(float2));
+
+    constexpr int PER = (XT * kColsPerPass + 64 * W - 1) / (64 * W);
+    auto load_b = [&](int x0, float2 (&bv)[PER]) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + 64 * W * j;
+            const int xl = e / kColsPerPass, cl = e - xl * kColsPerPass;
+            const int x = x0 + xl;
+            const bool ok = xl < XT && cl < ncb && x < x_end;
+            const unsigned off = (unsigned)((phi_index_x(x, col0 + cl, k, Nk, cols) - (size_t)xb0 * Nk * kXB * cols) * sizeof(float2));
+            bv[j] = bload<float2>(prs, ok ? off : kOob);
+        }
+    };
+    auto store_b = [&](int buf, const float2 (&bv)[PER]) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + 64 * W * j;
+            const int xl = e / kColsPerPass, cl = e - xl * kColsPerPass;
+            if (xl < XT && cl < ncb) stage_pair_bf16<NT>(sH[buf], sL[buf], xl >> 4, xl & 15, cl, bv[j].x, bv[j].y, false);
+        }
+    };
+    // A: for point m of sub-step ss, the (re, im) bf16 pair of u[x][n] is one dword
+    auto load_a = [&](int x0, unsigned (&ah)[SS][4], unsigned (&al)[SS][4]) {
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int x = x0 + 16 * ss + 4 * kq + m;
+                const bool ok = nval && x < x_end;
+                const unsigned off = ok ? (unsigned)(((x - x_begin) * Nb + n) * 4) : kOob;
+                ah[ss][m] = __builtin_amdgcn_raw_buffer_load_b32(urh, (int)off, 0, 0);
+                if (LO) al[ss][m] = __builtin_amdgcn_raw_buffer_load_b32(url, (int)off, 0, 0);
+            }
+    };
+
+    for (int e = threadIdx.x; e < 2 * BUF; e += 64 * W) {
+        (&sH[0][0])[e] = (__bf16)0.f;
+        (&sL[0][0])[e] = (__bf16)0.f;
+    }
+    v4f acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    unsigned ah[SS][4], al[SS][4], ahn[SS][4], aln[SS][4];
+    float2 bl[PER];
+    load_b(x_begin, bl);
+    load_a(x_begin, ah, al);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    store_b(0, bl);
+    int buf = 0;
+    for (int x0 = x_begin; x0 < x_end; x0 += XT) {
+        __syncthreads();
+        load_b(x0 + XT, bl);
+        load_a(x0 + XT, ahn, aln);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss) {
+            const bf16x8 a_h = __builtin_bit_cast(bf16x8, u32x4{ah[ss][0], ah[ss][1], ah[ss][2], ah[ss][3]});
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bf16x8 b_h = *reinterpret_cast<const bf16x8*>(&sH[buf][((ss * NT + t) * 64 + lane) * 8]);
+                const bf16x8 b_l = *reinterpret_cast<const bf16x8*>(&sL[buf][((ss * NT + t) * 64 + lane) * 8]);
+                acc[t] = mfma_bf16(a_h, b_h, acc[t]);
+                acc[t] = mfma_bf16(a_h, b_l, acc[t]);
+                if (LO) {
+                    const bf16x8 a_l = __builtin_bit_cast(bf16x8, u32x4{al[ss][0], al[ss][1], al[ss][2], al[ss][3]});
+                    acc[t] = mfma_bf16(a_l, b_h, acc[t]);
+                }
+            }
+        }
+        store_b(buf ^ 1, bl);
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                ah[ss][m] = ahn[ss][m];
+                if (LO) al[ss][m] = aln[ss][m];
+            }
+        buf ^= 1;
+    }
+
+    double* out = part + ((size_t)s * Nk + k) * Nb * 2 * cols + 2 * col0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int jr = 16 * t + i;
+        if ((jr >> 1) >= ncb) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int nn = nbase + 4 * kq + r;
+            if (nn < Nb) out[(size_t)nn * 2 * cols + jr] = (double)acc[t][r];
+        }
+    }
+}
+
+// u (FP64 complex, device) -> bf16 hi plane and, if lo != nullptr, the residual plane
+__global__ __launch_bounds__(256) void to_bf16_kernel(const double* __restrict__ src, __bf16* __restrict__ hi,
+                                                     __bf16* __restrict__ lo, long long n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        __bf16 h, l;
+        split2(src[e], h, l);
+        hi[e] = h;
+        if (lo) lo[e] = l;
+    }
+}
+
 template <typename T> struct Tiles;
 template <> struct Tiles<double> { static constexpr int KC = 16, XT = 32; };
 template <> struct Tiles<float> { static constexpr int KC = 32, XT = 64; };
@@ -442,6 +754,48 @@ void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk) {
     bwd_geometry_for(h, h->bwd_target_blocks, band_blocks, S, chunk);
 }
 
+template <int MS, bool LO>
+hipError_t fwd_bf16_nt(int NT, dim3 grid, hipStream_t st, const u16* uh, const u16* ul, const double* x,
+                       void* phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0, int ncb, int x_tiles) {
+    const double2* ps = reinterpret_cast<const double2*>(x);
+    float2* p = static_cast<float2*>(phi);
+    switch (NT) {
+        case 1: proj_fwd_bf16_kernel<MS, 1, LO><<<grid, 256, 0, st>>>(uh, ul, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
+        case 2: proj_fwd_bf16_kernel<MS, 2, LO><<<grid, 256, 0, st>>>(uh, ul, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
+        default: proj_fwd_bf16_kernel<MS, 3, LO><<<grid, 256, 0, st>>>(uh, ul, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
+    }
+    return hipGetLastError();
+}
+
+template <int W, bool LO>
+hipError_t bwd_bf16_w(int NT, dim3 grid, hipStream_t st, const u16* uh, const u16* ul, const void* phi,
+                      double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int bb, int S, int chunk) {
+    const float2* p = static_cast<const float2*>(phi);
+    switch (NT) {
+        case 1: proj_bwd_bf16_kernel<1, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
+        case 2: proj_bwd_bf16_kernel<2, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
+        default: proj_bwd_bf16_kernel<3, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
+    }
+    return hipGetLastError();
+}
+
+template <bool LO>
+hipError_t bwd_bf16(int W, int NT, dim3 grid, hipStream_t st, const u16* uh, const u16* ul, const void* phi,
+                    double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int bb, int S, int chunk) {
+    switch (W) {
+#define OCEAN_BWD_BF(w) \
+        case w: return bwd_bf16_w<w, LO>(NT, grid, st, uh, ul, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
+        OCEAN_BWD_BF(1) OCEAN_BWD_BF(2) OCEAN_BWD_BF(3) OCEAN_BWD_BF(4) OCEAN_BWD_BF(5) OCEAN_BWD_BF(6)
+        OCEAN_BWD_BF(7)
+#undef OCEAN_BWD_BF
+        default: return bwd_bf16_w<8, LO>(NT, grid, st, uh, ul, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
+    }
+}
+
+bool is_bf16_mode(int precision) {
+    return precision == OCEAN_PREC_SPLIT_BF16 || precision == OCEAN_PREC_BF16;
+}
+
 hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, int ncb) {
     const int MS = h->fwd_ms == 1 ? 1 : 2;   // 16 * MS rows per wave, 64 * MS per block
     const int cols = nv * h->Nc;
@@ -450,7 +804,17 @@ hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, in
     dim3 grid((unsigned)(h->Nk * x_tiles));
     const int slot = prof_begin(h, "proj_fwd");
     hipError_t e;
-    if (h->precision == OCEAN_PREC_FP64)
+    if (is_bf16_mode(h->precision)) {
+        const u16* uh = reinterpret_cast<const u16*>(h->Ubf);
+        const u16* ul = uh + (size_t)2 * h->Nk * h->Nx * h->Nb;
+        const bool lo = h->precision == OCEAN_PREC_SPLIT_BF16;
+        if (MS == 1)
+            e = lo ? fwd_bf16_nt<1, true>(NT, grid, h->stream, uh, ul, x, h->ws.phi, h->Nk, h->Nx, h->Nb, h->Nc, cols, col0, ncb, x_tiles)
+                   : fwd_bf16_nt<1, false>(NT, grid, h->stream, uh, ul, x, h->ws.phi, h->Nk, h->Nx, h->Nb, h->Nc, cols, col0, ncb, x_tiles);
+        else
+            e = lo ? fwd_bf16_nt<2, true>(NT, grid, h->stream, uh, ul, x, h->ws.phi, h->Nk, h->Nx, h->Nb, h->Nc, cols, col0, ncb, x_tiles)
+                   : fwd_bf16_nt<2, false>(NT, grid, h->stream, uh, ul, x, h->ws.phi, h->Nk, h->Nx, h->Nb, h->Nc, cols, col0, ncb, x_tiles);
+    } else if (h->precision == OCEAN_PREC_FP64)
         e = MS == 1 ? fwd_dispatch_nt<double, 1>(NT, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
                                                  h->Nb, h->Nc, cols, col0, ncb, x_tiles)
                     : fwd_dispatch_nt<double, 2>(NT, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
@@ -473,7 +837,13 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     dim3 grid((unsigned)((long long)h->Nk * bb * S));
     const int slot = prof_begin(h, "proj_bwd");
     hipError_t e;
-    if (h->precision == OCEAN_PREC_FP64)
+    if (is_bf16_mode(h->precision)) {
+        const u16* uh = reinterpret_cast<const u16*>(h->Ubf);
+        const u16* ul = uh + (size_t)2 * h->Nk * h->Nx * h->Nb;
+        e = h->precision == OCEAN_PREC_SPLIT_BF16
+                ? bwd_bf16<true>(W, NT, grid, h->stream, uh, ul, h->ws.phi, h->ws.part, h->Nk, h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk)
+                : bwd_bf16<false>(W, NT, grid, h->stream, uh, ul, h->ws.phi, h->ws.part, h->Nk, h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
+    } else if (h->precision == OCEAN_PREC_FP64)
         e = bwd_dispatch<double>(W, NT, grid, h->stream, h->U64, h->ws.phi, h->ws.part, h->Nk,
                                  h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
     else
@@ -481,6 +851,11 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
                                 h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
     prof_end(h, slot);
     return e;
+}
+
+hipError_t launch_to_bf16(ocean_bse_s* h, const double* src, uint16_t* hi, uint16_t* lo, long long n) {
+    to_bf16_kernel<<<4096, 256, 0, h->stream>>>(src, reinterpret_cast<__bf16*>(hi), reinterpret_cast<__bf16*>(lo), n);
+    return hipGetLastError();
 }
 
 }  // namespace ocean

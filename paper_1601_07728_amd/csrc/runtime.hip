@@ -115,6 +115,13 @@ static int check_hip(hipError_t e, const char* what) {
 #define OCEAN_HIP(expr, what) OCEAN_TRY(check_hip((expr), (what)))
 
 static size_t u_elems(const ocean_bse_s* h) { return (size_t)h->Nk * h->Nx * h->Nb; }
+// bf16 planes: hi [Nk][Nx][Nb][re, im], then (split mode) the residual plane of the same shape,
+// then 64 bytes of padding: the forward projection reads four bands per 16-byte load, and a load
+// that starts at the last band of the last row may reach 12 bytes past the final plane (those
+// values meet zero operands and do not contribute)
+static size_t ubf_elems(const ocean_bse_s* h) {
+    return (h->precision == OCEAN_PREC_SPLIT_BF16 ? u_elems(h) * 4 : u_elems(h) * 2) + 32;
+}
 
 static void release_workspace(ocean_bse_s* h) {
     auto& w = h->ws;
@@ -301,7 +308,7 @@ static void destroy_handle(ocean_bse_s* h) {
     dfree(h, h->E, (size_t)h->Nk * h->Nb);
     dfree(h, h->U64_owned, ue * 2);
     dfree(h, h->U32, ue * 2);
-    dfree(h, h->Ubf, ue * 4);
+    dfree(h, h->Ubf, ubf_elems(h));
     dfree(h, h->W64, (size_t)h->Nx * h->Nk);
     dfree(h, h->W32, (size_t)h->Nx * h->Nk);
     if (h->phase) (void)hipFree(h->phase);
@@ -349,7 +356,7 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
         set_error("ocean_bse_create: n_local > 0 needs local_proj and local_mat");
         return OCEAN_ERR_INVALID_ARG;
     }
-    if (d->precision != OCEAN_PREC_FP64 && d->precision != OCEAN_PREC_FP32) {
+    if (d->precision < OCEAN_PREC_FP64 || d->precision > OCEAN_PREC_BF16) {
         set_error("ocean_bse_create: precision not supported by this build");
         return OCEAN_ERR_UNSUPPORTED;
     }
@@ -459,25 +466,40 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
         if ((rc = check_hip(hipMemcpyAsync(h->U64_owned, d->u, ue * 16, hipMemcpyHostToDevice, h->stream), "u upload")) != OCEAN_OK) return fail(rc);
         h->U64 = h->U64_owned;
     } else {
-        // FP32 copy converted on the device, staged through a bounded FP64 buffer
-        if ((rc = dalloc(h, &h->U32, ue * 2, "u (FP32)")) != OCEAN_OK) return fail(rc);
+        // reduced-precision copy converted on the device, from the borrowed FP64 array or
+        // staged from the host through a bounded FP64 buffer
+        const bool bf = h->precision != OCEAN_PREC_FP32;
+        uint16_t* lo_plane = nullptr;
+        if (bf) {
+            if ((rc = dalloc(h, &h->Ubf, ubf_elems(h), "u (bf16)")) != OCEAN_OK) return fail(rc);
+            if (h->precision == OCEAN_PREC_SPLIT_BF16) lo_plane = h->Ubf + 2 * ue;
+            const size_t planes = ubf_elems(h) - 32;
+            if ((rc = check_hip(hipMemsetAsync(h->Ubf + planes, 0, 64, h->stream), "u padding")) != OCEAN_OK) return fail(rc);
+        } else {
+            if ((rc = dalloc(h, &h->U32, ue * 2, "u (FP32)")) != OCEAN_OK) return fail(rc);
+        }
+        auto convert = [&](const double* src, size_t off, size_t n) {
+            if (bf)
+                return launch_to_bf16(h, src, h->Ubf + 2 * off, lo_plane ? lo_plane + 2 * off : nullptr, (long long)n * 2);
+            return launch_to_fp32(h, src, h->U32 + 2 * off, (long long)n * 2);
+        };
         if (d->flags & OCEAN_FLAG_BORROW_DEVICE_U) {
-            rc = check_hip(launch_to_fp32(h, d->u, h->U32, (long long)ue * 2), "u conversion");
+            rc = check_hip(convert(d->u, 0, ue), "u conversion");
             if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "u conversion");
             if (rc != OCEAN_OK) return fail(rc);
         } else {
-        const size_t slab = std::min<size_t>(ue, (size_t)1 << 26);
-        double* stage = nullptr;
-        if ((rc = dalloc(h, &stage, slab * 2, "u staging")) != OCEAN_OK) return fail(rc);
-        for (size_t off = 0; off < ue; off += slab) {
-            const size_t n = std::min(slab, ue - off);
-            rc = check_hip(hipMemcpyAsync(stage, d->u + 2 * off, n * 16, hipMemcpyHostToDevice, h->stream), "u upload");
-            if (rc == OCEAN_OK) rc = check_hip(launch_to_fp32(h, stage, h->U32 + 2 * off, (long long)n * 2), "u conversion");
-            if (rc != OCEAN_OK) break;
-        }
-        if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "u conversion");
-        dfree(h, stage, slab * 2);
-        if (rc != OCEAN_OK) return fail(rc);
+            const size_t slab = std::min<size_t>(ue, (size_t)1 << 26);
+            double* stage = nullptr;
+            if ((rc = dalloc(h, &stage, slab * 2, "u staging")) != OCEAN_OK) return fail(rc);
+            for (size_t off = 0; off < ue; off += slab) {
+                const size_t n = std::min(slab, ue - off);
+                rc = check_hip(hipMemcpyAsync(stage, d->u + 2 * off, n * 16, hipMemcpyHostToDevice, h->stream), "u upload");
+                if (rc == OCEAN_OK) rc = check_hip(convert(stage, off, n), "u conversion");
+                if (rc != OCEAN_OK) break;
+            }
+            if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "u conversion");
+            dfree(h, stage, slab * 2);
+            if (rc != OCEAN_OK) return fail(rc);
         }
     }
     // W(x, R) table
