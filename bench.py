@@ -10,8 +10,8 @@ device); there is no DFT data.
 A step is one Haydock step of all three polarisation vectors: three H*v
 (diagonal + core + long-range W0 + local terms) plus the FP64 recursion update.
 value = H*v per second (exciton-vector applications per second) of the FP64
-path; the mixed-precision (FP32 projection) path, spectra per second and the
-spectrum L1 between them are reported beside it.
+path; the mixed-precision paths (FP32, split-BF16 and BF16 projections), spectra
+per second and each path's spectrum L1 against FP64 are reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
 
 
 def log(msg):
@@ -46,13 +47,30 @@ def build_workload(seed: int = 0):
     return cr, u
 
 
-def proj_bytes(cr, cols, elem):
+MODES = ("fp64", "fp32", "split_bf16", "bf16")
+U_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "bf16": 4}     # per complex u element
+PHI_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "bf16": 8}   # per complex phi element
+
+
+def proj_bytes(cr, cols, u_elem, phi_elem):
     """Algorithmic HBM bytes of one projection launch: all of u once, the phi
     block once, and the small exciton-vector side once."""
-    u_b = cr.n_k * cr.n_x * cr.n_bands * elem
-    phi_b = cr.n_k * cr.n_x * cols * elem
+    u_b = cr.n_k * cr.n_x * cr.n_bands * u_elem
+    phi_b = cr.n_k * cr.n_x * cols * phi_elem
     vec_b = cr.n_k * cr.n_bands * cols * 16
     return u_b + phi_b + vec_b
+
+
+def proj_flops(cr, cols):
+    """Real flops of one projection as the MFMA computes it: a real GEMM of
+    M = Nx, K = 2 Nb, N = 2 cols per k point."""
+    return 2.0 * cr.n_k * cr.n_x * (2 * cr.n_bands) * (2 * cols)
+
+
+def fft_bytes(cr, cols, phi_elem):
+    """Algorithmic HBM bytes of the k-FFT / W-multiply pass: phi read and written once,
+    the real W(x, R) table read once."""
+    return 2 * cr.n_k * cr.n_x * cols * phi_elem + cr.n_k * cr.n_x * phi_elem // 2
 
 
 def timed_haydock(h, psi0, steps):
@@ -96,7 +114,7 @@ def bench_batched(ob, seed, steps=200):
         f"{max(c.n_bands for c, _ in sites)}, generated in {time.time() - t0:.1f} s")
     out = {}
     n_solves = sum(3 for _ in sites)
-    for prec in ("fp64", "fp32"):
+    for prec in MODES:
         hs = [ob.Bse.from_crystal(cr, precision=prec, u=u) for cr, u in sites]
         p0 = [torch.from_numpy(cr.psi0).to("cuda") if cr.psi0 is not None else hs[i].dipole_psi0(np.eye(3))
               for i, (cr, _) in enumerate(sites)]
@@ -113,11 +131,12 @@ def bench_batched(ob, seed, steps=200):
             f"{n_solves / dt:.1f} spectra/s, {n_solves * steps / dt:.0f} H*v/s")
         for h in hs:
             h.close()
-    num = sum(float(np.sum(np.abs(s32 - s64))) for s32, s64 in zip(out["fp32"]["sig"], out["fp64"]["sig"]))
     den = sum(float(np.sum(np.abs(s64))) for s64 in out["fp64"]["sig"])
-    for prec in out:
+    for prec in MODES[1:]:
+        num = sum(float(np.sum(np.abs(sm - s64))) for sm, s64 in zip(out[prec]["sig"], out["fp64"]["sig"]))
+        out[prec]["spectrum_l1_vs_fp64"] = num / den
+    for prec in MODES:
         out[prec].pop("sig")
-    out["fp32"]["spectrum_l1_vs_fp64"] = num / den
     out["workload"] = (f"molecule in a 30 bohr box, Gamma point, 48^3 grid, {len(sites)} sites "
                        f"(K and L2,3 edges), bands U{{200..800}}, 3 polarisations: {n_solves} solves x {steps} steps")
     return out
@@ -189,11 +208,12 @@ def bench_terminator(ob, seed, n_sys, n_held, n_steps=512, epochs=120, batch=256
                  "invalid_predictions": int((~valid).sum())}
 
 
-def spectra_gain(ob, cr, h64, h32, psi0, mlp, ref_steps=600, base_steps=300):
+def spectra_gain(ob, cr, hs, psi0, mlp, ref_steps=600, base_steps=300):
     """spectra/s of the plain FP64 recursion (base_steps) against the mixed path with fewer
     steps closed by a terminator, at spectrum L1 <= 1e-3 against the FP64 reference."""
     from paper_1601_07728_amd import terminator as term
     n_pol = psi0.shape[0]
+    h64 = hs["fp64"]
     _, (a, b, n2, sd, _) = timed_haydock(h64, psi0, ref_steps)
     ref = ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd)
     rows = []
@@ -205,7 +225,7 @@ def spectra_gain(ob, cr, h64, h32, psi0, mlp, ref_steps=600, base_steps=300):
             "l1": float(np.mean(term.l1(sig, ref)))}
     rows.append(base)
     for steps in (32, 64, 96, 128, 192):
-        for name, h in (("fp32", h32), ("fp64", h64)):
+        for name, h in hs.items():
             dt, (a, b, n2, sd, _) = timed_haydock(h, psi0, steps)
             for tname in ("sqrt", "mlp") if steps == 32 else ("sqrt",):
                 t0 = time.perf_counter()
@@ -246,19 +266,17 @@ def main():
 
     import torch
     import paper_1601_07728_amd as ob
-    from oracle import bse as orc_cf  # noqa: F401  (only for the cpu_baseline leg)
 
     torch.cuda.set_device(0)
     cr, u = build_workload(args.seed)
     n_pol = 3
     cols = n_pol * cr.n_core
-    log("creating FP64 and FP32 handles")
-    h64 = ob.Bse.from_crystal(cr, precision="fp64", u=u)
-    h32 = ob.Bse.from_crystal(cr, precision="fp32", u=u)
-    psi0 = h64.dipole_psi0(np.eye(3))
+    log("creating handles: " + ", ".join(MODES))
+    hs = {m: ob.Bse.from_crystal(cr, precision=m, u=u) for m in MODES}
+    psi0 = hs["fp64"].dipole_psi0(np.eye(3))
 
     results = {}
-    for name, h in (("fp64", h64), ("fp32", h32)):
+    for name, h in hs.items():
         timed_haydock(h, psi0, args.warmup)
         dt, _ = timed_haydock(h, psi0, args.steps)
         results[name] = {"ms_per_step": 1e3 * dt / args.steps,
@@ -267,45 +285,57 @@ def main():
 
     # full spectra: 3 polarisations x spectrum_steps each, then the continued fraction
     spec = {}
-    for name, h in (("fp64", h64), ("fp32", h32)):
+    for name, h in hs.items():
         dt, (a, b, n2, sd, rc) = timed_haydock(h, psi0, args.spectrum_steps)
         t0 = time.perf_counter()
         sig = ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd)
         dt += time.perf_counter() - t0
-        spec[name] = (sig, n_pol / dt)
+        spec[name] = sig
         results[name]["spectra_per_s"] = n_pol / dt
         log(f"{name}: {args.spectrum_steps}-step spectra: {n_pol / dt:.3f} spectra/s")
-    ref = spec["fp64"][0]
-    l1 = float(np.sum(np.abs(spec["fp32"][0] - ref)) / np.sum(np.abs(ref)))
-    results["fp32"]["spectrum_l1_vs_fp64"] = l1
-    log(f"fp32 vs fp64 spectrum L1 = {l1:.2e}")
+    ref = spec["fp64"]
+    for name in MODES[1:]:
+        l1 = float(np.sum(np.abs(spec[name] - ref)) / np.sum(np.abs(ref)))
+        results[name]["spectrum_l1_vs_fp64"] = l1
+        log(f"{name} vs fp64 spectrum L1 = {l1:.2e}")
 
     # per-kernel HIP-event timing over the same number of steps, each precision
     avgs = {}
-    for name, h in (("fp64", h64), ("fp32", h32)):
+    for name, h in hs.items():
         h.set_profiling(True)
         h.haydock(psi0, args.steps)
         kt = h.kernel_times()
         h.set_profiling(False)
         avgs[name] = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
         log(f"{name} kernel averages (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in sorted(avgs[name].items())))
+        results[name]["kernel_ms"] = {k: round(v, 4) for k, v in avgs[name].items()}
+        results[name]["achieved_GBs"] = {
+            "proj_fwd": proj_bytes(cr, cols, U_BYTES[name], PHI_BYTES[name]) / (avgs[name]["proj_fwd"] * 1e6),
+            "proj_bwd": proj_bytes(cr, cols, U_BYTES[name], PHI_BYTES[name]) / (avgs[name]["proj_bwd"] * 1e6),
+            "fft_w": fft_bytes(cr, cols, PHI_BYTES[name]) / (avgs[name]["fft_w"] * 1e6)}
     avg = avgs["fp64"]
     dom = max(("proj_fwd", "proj_bwd"), key=lambda k: avg.get(k, 0.0))
-    ach = proj_bytes(cr, cols, 16) / (avg[dom] * 1e-3) / 1e9
+    ach = proj_bytes(cr, cols, 16, 16) / (avg[dom] * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS, "traffic": None,
-                "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
-                "kernel_ms_fp32": {k: round(v, 4) for k, v in avgs["fp32"].items()}}
+                "mfma_fp64_tflops": proj_flops(cr, cols) / (avg[dom] * 1e-3) / 1e12,
+                "mfma_fp64_frac": proj_flops(cr, cols) / (avg[dom] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+    ok = [m for m in MODES[1:] if results[m]["spectrum_l1_vs_fp64"] <= 1e-3]
+    best = max(ok, key=lambda m: results[m]["hv_per_s"]) if ok else None
+    mixed_best = None if best is None else {
+        "path": best, "hv_per_s": results[best]["hv_per_s"],
+        "speedup_vs_fp64": results[best]["hv_per_s"] / results["fp64"]["hv_per_s"],
+        "spectrum_l1_vs_fp64": results[best]["spectrum_l1_vs_fp64"]}
 
     mlp, terminator = bench_terminator(ob, args.seed, args.term_systems, args.term_held_out,
                                        epochs=args.term_epochs)
-    gain = spectra_gain(ob, cr, h64, h32, psi0, mlp)
+    gain = spectra_gain(ob, cr, hs, psi0, mlp)
     terminator["srtio3_spectra_gain"] = gain
     mlp.close()
 
     batched = None
-    h64.close()
-    h32.close()
+    for h in hs.values():
+        h.close()
     if not args.no_batched:
         batched = bench_batched(ob, args.seed)
 
@@ -316,7 +346,7 @@ def main():
         log(f"cpu baseline {cpu['value']:.4f} H*v/s on {cpu['cores']} cores")
 
     line = {
-        "metric": "H*v/s (FP64 path; mixed FP32 path and spectra/s reported alongside)",
+        "metric": "H*v/s (FP64 path; mixed FP32 / split-BF16 / BF16 paths and spectra/s reported alongside)",
         "value": results["fp64"]["hv_per_s"],
         "unit": "H*v/s",
         "n_gpus": 1,
@@ -331,8 +361,8 @@ def main():
         "config": {"workload": "SrTiO3-shaped Ti L2,3 edge: 8^3 k, 96 bands, 20^3 x, 6 core states, "
                                "d-channel local term, H dim 294912, 3 polarisations per step",
                    "n_vec_per_step": n_pol, "spectrum_steps": args.spectrum_steps},
-        "fp64": results["fp64"],
-        "mixed_fp32": results["fp32"],
+        "paths": results,
+        "mixed_best_at_l1_1e-3": mixed_best,
         "batched": batched,
         "terminator": terminator,
         "roofline": roofline,

@@ -100,6 +100,10 @@ struct ocean_bse_s {
     double* U64_owned = nullptr;
     float* U32 = nullptr;           // [Nk][Nx][Nb] complex FP32 copy (FP32 mode)
     uint16_t* Ubf = nullptr;        // bf16 modes: hi plane [Nk][Nx][Nb][re, im], then (split) the residual plane
+    uint16_t* UbfT = nullptr;       // the same values transposed, [Nk][Nb][NxP][re, im] (+ residual plane),
+                                    // rows padded with zeros to NxP = Nx rounded up to 4; read by the
+                                    // back-projection so that 4 consecutive x are one 16-byte load
+    int NxP = 0;
     double* W64 = nullptr;          // [Nx][Nk] W(x, R)
     float* W32 = nullptr;
     double* phase = nullptr;        // per-axis e^{2 pi i a b / (n g)} tables, complex
@@ -143,6 +147,8 @@ hipError_t launch_build_w(ocean_bse_s* h, const double* wr_dev, const double* wv
                           double h_r);
 hipError_t launch_to_fp32(ocean_bse_s* h, const double* src, float* dst, long long n);
 hipError_t launch_to_bf16(ocean_bse_s* h, const double* src, uint16_t* hi, uint16_t* lo, long long n);
+hipError_t launch_to_bf16_t(ocean_bse_s* h, const double* src, long long g0, long long rows, uint16_t* hiT,
+                            uint16_t* loT);
 hipError_t launch_dipole_psi0(ocean_bse_s* h, const double* d_dev, int n_pol, double* psi0);
 
 // Lanczos kernels

@@ -543,8 +543,8 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
 
 template <int NT, int W, bool LO>
 __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
-    const u16* __restrict__ Uh, const u16* __restrict__ Ul, const float2* __restrict__ phi,
-    double* __restrict__ part, int Nk, int Nx, int Nb, int cols, int col0, int ncb,
+    const u16* __restrict__ UTh, const u16* __restrict__ UTl, const float2* __restrict__ phi,
+    double* __restrict__ part, int Nk, int Nx, int NxP, int Nb, int cols, int col0, int ncb,
     int band_blocks, int S, int chunk) {
     constexpr int XT = 64, SS = XT / 16;
     constexpr int BUF = SS * NT * 64 * 8;
@@ -562,9 +562,10 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
     const int x_end = min(Nx, x_begin + chunk);
     const int n = nbase + i;
     const bool nval = n < Nb;
-    const size_t plane0 = ((size_t)k * Nx + x_begin) * Nb * 2;
-    const Rsrc urh = make_rsrc(Uh + plane0, (size_t)(x_end - x_begin) * Nb * 4);
-    const Rsrc url = make_rsrc(LO ? Ul + plane0 : Uh + plane0, (size_t)(x_end - x_begin) * Nb * 4);
+    // transposed planes [k][n][NxP]: one k plane per resource
+    const size_t plane0 = (size_t)k * Nb * NxP * 2;
+    const Rsrc urh = make_rsrc(UTh + plane0, (size_t)Nb * NxP * 4);
+    const Rsrc url = make_rsrc(LO ? UTl + plane0 : UTh + plane0, (size_t)Nb * NxP * 4);
     const int xb0 = x_begin / kXB;
     const float2* pbase = phi + (size_t)xb0 * Nk * kXB * cols;
     const Rsrc prs = make_rsrc(pbase, (size_t)((x_end - 1) / kXB - xb0 + 1) * Nk * kXB * cols * sizeof(float2));
@@ -589,18 +590,19 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
             if (xl < XT && cl < ncb) stage_pair_bf16<NT>(sH[buf], sL[buf], xl >> 4, xl & 15, cl, bv[j].x, bv[j].y, false);
         }
     };
-    // A: for point m of sub-step ss, the (re, im) bf16 pair of u[x][n] is one dword
-    auto load_a = [&](int x0, unsigned (&ah)[SS][4], unsigned (&al)[SS][4]) {
+    // A: the four points 4 kq .. 4 kq + 3 of sub-step ss are consecutive x of row n of the
+    // transposed plane, one 16-byte load.  x_begin and chunk are multiples of 8, so a group
+    // never crosses a chunk end; past Nx it reads the zero row padding.
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    auto load_a = [&](int x0, u32x4 (&ah)[SS], u32x4 (&al)[SS]) {
 #pragma unroll
-        for (int ss = 0; ss < SS; ++ss)
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int x = x0 + 16 * ss + 4 * kq + m;
-                const bool ok = nval && x < x_end;
-                const unsigned off = ok ? (unsigned)(((x - x_begin) * Nb + n) * 4) : kOob;
-                ah[ss][m] = __builtin_amdgcn_raw_buffer_load_b32(urh, (int)off, 0, 0);
-                if (LO) al[ss][m] = __builtin_amdgcn_raw_buffer_load_b32(url, (int)off, 0, 0);
-            }
+        for (int ss = 0; ss < SS; ++ss) {
+            const int x = x0 + 16 * ss + 4 * kq;
+            const bool ok = nval && x < x_end;
+            const unsigned off = ok ? (unsigned)((n * NxP + x) * 4) : kOob;
+            ah[ss] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(urh, (int)off, 0, 0));
+            if (LO) al[ss] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(url, (int)off, 0, 0));
+        }
     };
 
     for (int e = threadIdx.x; e < 2 * BUF; e += 64 * W) {
@@ -611,8 +613,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-    unsigned ah[SS][4], al[SS][4], ahn[SS][4], aln[SS][4];
+    u32x4 ah[SS], al[SS], ahn[SS], aln[SS];
     float2 bl[PER];
     load_b(x_begin, bl);
     load_a(x_begin, ah, al);
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
-            const bf16x8 a_h = __builtin_bit_cast(bf16x8, u32x4{ah[ss][0], ah[ss][1], ah[ss][2], ah[ss][3]});
+            const bf16x8 a_h = __builtin_bit_cast(bf16x8, ah[ss]);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const bf16x8 b_h = *reinterpret_cast<const bf16x8*>(&sH[buf][((ss * NT + t) * 64 + lane) * 8]);
@@ -635,19 +636,17 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
                 acc[t] = mfma_bf16(a_h, b_h, acc[t]);
                 acc[t] = mfma_bf16(a_h, b_l, acc[t]);
                 if (LO) {
-                    const bf16x8 a_l = __builtin_bit_cast(bf16x8, u32x4{al[ss][0], al[ss][1], al[ss][2], al[ss][3]});
+                    const bf16x8 a_l = __builtin_bit_cast(bf16x8, al[ss]);
                     acc[t] = mfma_bf16(a_l, b_h, acc[t]);
                 }
             }
         }
         store_b(buf ^ 1, bl);
 #pragma unroll
-        for (int ss = 0; ss < SS; ++ss)
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                ah[ss][m] = ahn[ss][m];
-                if (LO) al[ss][m] = aln[ss][m];
-            }
+        for (int ss = 0; ss < SS; ++ss) {
+            ah[ss] = ahn[ss];
+            if (LO) al[ss] = aln[ss];
+        }
         buf ^= 1;
     }
 
@@ -673,6 +672,32 @@ __global__ __launch_bounds__(256) void to_bf16_kernel(const double* __restrict__
         split2(src[e], h, l);
         hi[e] = h;
         if (lo) lo[e] = l;
+    }
+}
+
+// rows g0 .. g0 + rows - 1 of u (row g = k Nx + x, Nb complex FP64 each, starting at src) ->
+// transposed bf16 planes [k][n][NxP]
+__global__ __launch_bounds__(256) void to_bf16_t_kernel(const double* __restrict__ src, long long g0, long long rows,
+                                                       int Nx, int Nb, int NxP, __bf16* __restrict__ hiT,
+                                                       __bf16* __restrict__ loT) {
+    const long long n_el = rows * Nb;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_el; e += stride) {
+        const long long r = e / Nb;
+        const int n = (int)(e - r * Nb);
+        const long long g = g0 + r;
+        const long long k = g / Nx;
+        const int x = (int)(g - k * Nx);
+        const size_t o = 2 * (((size_t)k * Nb + n) * NxP + x);
+        __bf16 h0, l0, h1, l1;
+        split2(src[2 * e], h0, l0);
+        split2(src[2 * e + 1], h1, l1);
+        hiT[o] = h0;
+        hiT[o + 1] = h1;
+        if (loT) {
+            loT[o] = l0;
+            loT[o + 1] = l1;
+        }
     }
 }
 
@@ -769,26 +794,28 @@ hipError_t fwd_bf16_nt(int NT, dim3 grid, hipStream_t st, const u16* uh, const u
 
 template <int W, bool LO>
 hipError_t bwd_bf16_w(int NT, dim3 grid, hipStream_t st, const u16* uh, const u16* ul, const void* phi,
-                      double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int bb, int S, int chunk) {
+                      double* part, int Nk, int Nx, int NxP, int Nb, int cols, int col0, int ncb, int bb, int S,
+                      int chunk) {
     const float2* p = static_cast<const float2*>(phi);
     switch (NT) {
-        case 1: proj_bwd_bf16_kernel<1, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
-        case 2: proj_bwd_bf16_kernel<2, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
-        default: proj_bwd_bf16_kernel<3, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
+        case 1: proj_bwd_bf16_kernel<1, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk); break;
+        case 2: proj_bwd_bf16_kernel<2, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk); break;
+        default: proj_bwd_bf16_kernel<3, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk); break;
     }
     return hipGetLastError();
 }
 
 template <bool LO>
 hipError_t bwd_bf16(int W, int NT, dim3 grid, hipStream_t st, const u16* uh, const u16* ul, const void* phi,
-                    double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int bb, int S, int chunk) {
+                    double* part, int Nk, int Nx, int NxP, int Nb, int cols, int col0, int ncb, int bb, int S,
+                    int chunk) {
     switch (W) {
 #define OCEAN_BWD_BF(w) \
-        case w: return bwd_bf16_w<w, LO>(NT, grid, st, uh, ul, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
+        case w: return bwd_bf16_w<w, LO>(NT, grid, st, uh, ul, phi, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk);
         OCEAN_BWD_BF(1) OCEAN_BWD_BF(2) OCEAN_BWD_BF(3) OCEAN_BWD_BF(4) OCEAN_BWD_BF(5) OCEAN_BWD_BF(6)
         OCEAN_BWD_BF(7)
 #undef OCEAN_BWD_BF
-        default: return bwd_bf16_w<8, LO>(NT, grid, st, uh, ul, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
+        default: return bwd_bf16_w<8, LO>(NT, grid, st, uh, ul, phi, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk);
     }
 }
 
@@ -838,11 +865,11 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     const int slot = prof_begin(h, "proj_bwd");
     hipError_t e;
     if (is_bf16_mode(h->precision)) {
-        const u16* uh = reinterpret_cast<const u16*>(h->Ubf);
-        const u16* ul = uh + (size_t)2 * h->Nk * h->Nx * h->Nb;
+        const u16* uh = reinterpret_cast<const u16*>(h->UbfT);
+        const u16* ul = uh + (size_t)2 * h->Nk * h->Nb * h->NxP;
         e = h->precision == OCEAN_PREC_SPLIT_BF16
-                ? bwd_bf16<true>(W, NT, grid, h->stream, uh, ul, h->ws.phi, h->ws.part, h->Nk, h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk)
-                : bwd_bf16<false>(W, NT, grid, h->stream, uh, ul, h->ws.phi, h->ws.part, h->Nk, h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
+                ? bwd_bf16<true>(W, NT, grid, h->stream, uh, ul, h->ws.phi, h->ws.part, h->Nk, h->Nx, h->NxP, h->Nb, cols, col0, ncb, bb, S, chunk)
+                : bwd_bf16<false>(W, NT, grid, h->stream, uh, ul, h->ws.phi, h->ws.part, h->Nk, h->Nx, h->NxP, h->Nb, cols, col0, ncb, bb, S, chunk);
     } else if (h->precision == OCEAN_PREC_FP64)
         e = bwd_dispatch<double>(W, NT, grid, h->stream, h->U64, h->ws.phi, h->ws.part, h->Nk,
                                  h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
@@ -851,6 +878,13 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
                                 h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
     prof_end(h, slot);
     return e;
+}
+
+hipError_t launch_to_bf16_t(ocean_bse_s* h, const double* src, long long g0, long long rows, uint16_t* hiT,
+                            uint16_t* loT) {
+    to_bf16_t_kernel<<<4096, 256, 0, h->stream>>>(src, g0, rows, h->Nx, h->Nb, h->NxP,
+                                                  reinterpret_cast<__bf16*>(hiT), reinterpret_cast<__bf16*>(loT));
+    return hipGetLastError();
 }
 
 hipError_t launch_to_bf16(ocean_bse_s* h, const double* src, uint16_t* hi, uint16_t* lo, long long n) {

@@ -122,6 +122,10 @@ static size_t u_elems(const ocean_bse_s* h) { return (size_t)h->Nk * h->Nx * h->
 static size_t ubf_elems(const ocean_bse_s* h) {
     return (h->precision == OCEAN_PREC_SPLIT_BF16 ? u_elems(h) * 4 : u_elems(h) * 2) + 32;
 }
+static size_t ubft_plane(const ocean_bse_s* h) { return (size_t)h->Nk * h->Nb * h->NxP * 2; }
+static size_t ubft_elems(const ocean_bse_s* h) {
+    return h->precision == OCEAN_PREC_SPLIT_BF16 ? 2 * ubft_plane(h) : ubft_plane(h);
+}
 
 static void release_workspace(ocean_bse_s* h) {
     auto& w = h->ws;
@@ -309,6 +313,7 @@ static void destroy_handle(ocean_bse_s* h) {
     dfree(h, h->U64_owned, ue * 2);
     dfree(h, h->U32, ue * 2);
     dfree(h, h->Ubf, ubf_elems(h));
+    dfree(h, h->UbfT, ubft_elems(h));
     dfree(h, h->W64, (size_t)h->Nx * h->Nk);
     dfree(h, h->W32, (size_t)h->Nx * h->Nk);
     if (h->phase) (void)hipFree(h->phase);
@@ -470,17 +475,33 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
         // staged from the host through a bounded FP64 buffer
         const bool bf = h->precision != OCEAN_PREC_FP32;
         uint16_t* lo_plane = nullptr;
+        uint16_t* lo_plane_t = nullptr;
         if (bf) {
+            h->NxP = (h->Nx + 3) / 4 * 4;
+            if ((long long)h->Nb * h->NxP * 4 >= (1LL << 31) || (long long)64 * 2 * h->Nb * 4 >= (1LL << 31)) {
+                set_error("ocean_bse_create: a k plane of u exceeds 2 GiB in the bf16 layouts");
+                return fail(OCEAN_ERR_UNSUPPORTED);
+            }
             if ((rc = dalloc(h, &h->Ubf, ubf_elems(h), "u (bf16)")) != OCEAN_OK) return fail(rc);
-            if (h->precision == OCEAN_PREC_SPLIT_BF16) lo_plane = h->Ubf + 2 * ue;
+            if ((rc = dalloc(h, &h->UbfT, ubft_elems(h), "u (bf16, transposed)")) != OCEAN_OK) return fail(rc);
+            if (h->precision == OCEAN_PREC_SPLIT_BF16) {
+                lo_plane = h->Ubf + 2 * ue;
+                lo_plane_t = h->UbfT + ubft_plane(h);
+            }
             const size_t planes = ubf_elems(h) - 32;
             if ((rc = check_hip(hipMemsetAsync(h->Ubf + planes, 0, 64, h->stream), "u padding")) != OCEAN_OK) return fail(rc);
+            // row padding x in [Nx, NxP) of the transposed copy stays zero
+            if ((rc = check_hip(hipMemsetAsync(h->UbfT, 0, ubft_elems(h) * 2, h->stream), "u padding")) != OCEAN_OK) return fail(rc);
         } else {
             if ((rc = dalloc(h, &h->U32, ue * 2, "u (FP32)")) != OCEAN_OK) return fail(rc);
         }
+        // src holds n complex elements starting at element off; off and n are whole rows of Nb
         auto convert = [&](const double* src, size_t off, size_t n) {
-            if (bf)
-                return launch_to_bf16(h, src, h->Ubf + 2 * off, lo_plane ? lo_plane + 2 * off : nullptr, (long long)n * 2);
+            if (bf) {
+                hipError_t e = launch_to_bf16(h, src, h->Ubf + 2 * off, lo_plane ? lo_plane + 2 * off : nullptr, (long long)n * 2);
+                if (e != hipSuccess) return e;
+                return launch_to_bf16_t(h, src, (long long)(off / h->Nb), (long long)(n / h->Nb), h->UbfT, lo_plane_t);
+            }
             return launch_to_fp32(h, src, h->U32 + 2 * off, (long long)n * 2);
         };
         if (d->flags & OCEAN_FLAG_BORROW_DEVICE_U) {
@@ -488,7 +509,8 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
             if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "u conversion");
             if (rc != OCEAN_OK) return fail(rc);
         } else {
-            const size_t slab = std::min<size_t>(ue, (size_t)1 << 26);
+            // whole rows of Nb bands per slab
+            const size_t slab = std::min<size_t>(ue, std::max<size_t>(1, ((size_t)1 << 26) / h->Nb) * h->Nb);
             double* stage = nullptr;
             if ((rc = dalloc(h, &stage, slab * 2, "u staging")) != OCEAN_OK) return fail(rc);
             for (size_t off = 0; off < ue; off += slab) {
