@@ -9,6 +9,7 @@
 // phi[k][x][col].  A block stages L consecutive lines (contiguous for every k)
 // in LDS as [k][line], runs the separable small DFTs along the three k axes in
 // LDS, multiplies by W and transforms back, then writes the lines in place.
+// W(x, R) is stored [x][R2 R3][R1] (R1 fastest), R = R1 n2 n3 + R2 n3 + R3.
 // The pass is HBM-bound: phi is read once and written once.
 #include "internal.h"
 
@@ -18,6 +19,9 @@ namespace {
 template <typename T> struct C2T;
 template <> struct C2T<double> { typedef double2 t; };
 template <> struct C2T<float> { typedef float2 t; };
+
+// N consecutive W values, aligned to their size so that they load as wide vectors
+template <typename T, int N> struct alignas(sizeof(T) * N) WVec { T v[N]; };
 
 template <typename C2> __device__ __forceinline__ C2 cmul(C2 a, C2 b) {
     C2 r;
@@ -129,7 +133,8 @@ __global__ __launch_bounds__(256) void fft_w_kernel(
         const long long line = line0 + l;
         if (line < total) {
             const int x = (int)(line / cols);
-            const T w = W[(size_t)x * Nk + r];
+            const int r23 = r % (n2 * n3), r1 = r / (n2 * n3);
+            const T w = W[(size_t)x * Nk + (size_t)r23 * n1 + r1];
             C2 v = buf[e];
             v.x *= w;
             v.y *= w;
@@ -278,9 +283,24 @@ __global__ __launch_bounds__(256) void fft_w_pow2_kernel(
     const int j3 = x % g3, j2 = (x / g3) % g2, j1 = x / (g2 * g3);
     const double2* ph1 = ph + po1 + j1;
     const double2* ph2 = ph + po2 + j2;
-    const double2* ph3 = ph + po3 + j3;
     const T* wrow = W + (size_t)x * Nk;
     C2* pl = phi + kbase + l;
+    // e^{ik.x} = p1(i1) p2(i2) p3(i3): the k3 factors are the same for every pencil of this
+    // thread's line, the (k1, k2) factor is one product per pencil
+    C2 q3[NMAX];
+#pragma unroll
+    for (int b = 0; b < NMAX; ++b) {
+        const double2 t = ph[po3 + (b < n3 ? b : 0) * g3 + j3];
+        q3[b].x = (T)t.x;
+        q3[b].y = (T)t.y;
+    }
+    auto pencil_phase = [&](int u) {
+        const double2 a = cmul(ph1[(u >> s2) * g1], ph2[(u & (n2 - 1)) * g2]);
+        C2 r;
+        r.x = (T)a.x;
+        r.y = (T)a.y;
+        return r;
+    };
 
     // P1: HBM -> registers, phase, FFT along k3 -> LDS.  Addresses are clamped instead of
     // branched on, so all loads of a pencil are in flight together (padding rows of the
@@ -295,15 +315,12 @@ __global__ __launch_bounds__(256) void fft_w_pow2_kernel(
                 const int bb = b < n3 ? b : 0;
                 v[b] = pl[(size_t)((u << s3) + bb) * xbc];
             }
+            const C2 a = pencil_phase(u);
 #pragma unroll
             for (int b = 0; b < NMAX; ++b) {
-                const int bb = b < n3 ? b : 0;
-                const int kk = (u << s3) + bb;
-                const int i1 = kk >> (s2 + s3), i2 = (kk >> s3) & (n2 - 1);
-                const double2 pp = cmul(cmul(ph1[i1 * g1], ph2[i2 * g2]), ph3[bb * g3]);
-                C2 pc;
-                pc.x = ok ? (T)pp.x : (T)0;
-                pc.y = ok ? (T)pp.y : (T)0;
+                C2 pc = cmul(a, q3[b]);
+                pc.x = ok ? pc.x : (T)0;
+                pc.y = ok ? pc.y : (T)0;
                 v[b] = cmul(v[b], pc);
             }
             fft_any<T, NMAX>(v, n3, false);
@@ -328,9 +345,16 @@ __global__ __launch_bounds__(256) void fft_w_pow2_kernel(
 #pragma unroll
             for (int b = 0; b < NMAX; ++b) v[b] = buf[(u + (b < n1 ? b : 0) * st) * L + l];
             fft_any<T, NMAX>(v, n1, false);
+            // W is stored [x][R2 R3][R1]: the n1 values of this pencil are contiguous
             T wv[NMAX];
+            if (n1 == NMAX) {
+                const WVec<T, NMAX> wl = reinterpret_cast<const WVec<T, NMAX>*>(wrow)[u];
 #pragma unroll
-            for (int b = 0; b < NMAX; ++b) wv[b] = wrow[u + (b < n1 ? b : 0) * st];
+                for (int b = 0; b < NMAX; ++b) wv[b] = wl.v[b];
+            } else {
+#pragma unroll
+                for (int b = 0; b < NMAX; ++b) wv[b] = wrow[u * n1 + (b < n1 ? b : 0)];
+            }
 #pragma unroll
             for (int b = 0; b < NMAX; ++b) {
                 const T w = ok ? wv[b] : (T)0;
@@ -359,16 +383,13 @@ __global__ __launch_bounds__(256) void fft_w_pow2_kernel(
 #pragma unroll
             for (int b = 0; b < NMAX; ++b) v[b] = buf[((u << s3) + (b < n3 ? b : 0)) * L + l];
             fft_any<T, NMAX>(v, n3, true);
+            const C2 a = pencil_phase(u);
             C2 o[NMAX];
 #pragma unroll
             for (int b = 0; b < NMAX; ++b) {
-                const int bb = b < n3 ? b : 0;
-                const int kk = (u << s3) + bb;
-                const int i1 = kk >> (s2 + s3), i2 = (kk >> s3) & (n2 - 1);
-                const double2 pp = cmul(cmul(ph1[i1 * g1], ph2[i2 * g2]), ph3[bb * g3]);
-                C2 pc;
-                pc.x = (T)pp.x * inv_nk;
-                pc.y = -(T)pp.y * inv_nk;
+                C2 pc = cmul(a, q3[b]);
+                pc.x = pc.x * inv_nk;
+                pc.y = -pc.y * inv_nk;
                 o[b] = cmul(v[b], pc);
             }
 #pragma unroll

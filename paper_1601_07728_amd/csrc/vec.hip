@@ -427,9 +427,12 @@ __global__ __launch_bounds__(256) void build_w_kernel(double* __restrict__ W64, 
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long Nx = (long long)g1 * g2 * g3;
     if (idx >= Nx * Nk) return;
-    const int x = (int)(idx / Nk), r = (int)(idx - (long long)x * Nk);
+    // layout [x][R2 R3][R1]: R1 fastest, so the k1 pass of the transform reads one pencil
+    // of W as a contiguous vector
+    const int x = (int)(idx / Nk), q = (int)(idx - (long long)x * Nk);
     const int j3 = x % g3, j2 = (x / g3) % g2, j1 = x / (g2 * g3);
-    const int r3 = r % n3, r2 = (r / n3) % n2, r1 = r / (n2 * n3);
+    const int r1 = q % n1, r23 = q / n1;
+    const int r3 = r23 % n3, r2 = r23 / n3;
     double d[3];
     d[0] = c1 * ((double)j1 / g1 + r1) - t1;
     d[1] = c2 * ((double)j2 / g2 + r2) - t2;
