@@ -116,6 +116,10 @@ def bench_batched(ob, seed, steps=200):
     n_solves = sum(3 for _ in sites)
     for prec in MODES:
         hs = [ob.Bse.from_crystal(cr, precision=prec, u=u) for cr, u in sites]
+        t0 = time.perf_counter()
+        for h in hs:
+            h.autotune(n_vec=3)
+        log(f"batched {prec}: {len(hs)} handles autotuned in {time.perf_counter() - t0:.1f} s")
         p0 = [torch.from_numpy(cr.psi0).to("cuda") if cr.psi0 is not None else hs[i].dipole_psi0(np.eye(3))
               for i, (cr, _) in enumerate(sites)]
         ob.haydock_batch(hs, p0, 2)
@@ -277,10 +281,15 @@ def main():
 
     results = {}
     for name, h in hs.items():
+        t0 = time.perf_counter()
+        tune = h.autotune(n_vec=n_pol)
+        log(f"{name}: autotuned {tune} in {time.perf_counter() - t0:.2f} s")
+        results[name] = {"tiles": tune}
+    for name, h in hs.items():
         timed_haydock(h, psi0, args.warmup)
         dt, _ = timed_haydock(h, psi0, args.steps)
-        results[name] = {"ms_per_step": 1e3 * dt / args.steps,
-                         "hv_per_s": n_pol * args.steps / dt}
+        results[name].update({"ms_per_step": 1e3 * dt / args.steps,
+                              "hv_per_s": n_pol * args.steps / dt})
         log(f"{name}: {results[name]['ms_per_step']:.3f} ms/step, {results[name]['hv_per_s']:.1f} H*v/s")
 
     # full spectra: 3 polarisations x spectrum_steps each, then the continued fraction

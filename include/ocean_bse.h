@@ -162,8 +162,9 @@ int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* p
                         double* norm2, int* steps_done);
 
 /* Tile autotuner: times the candidate tile shapes of the projection, back-projection
- * and k-grid transform kernels on this handle's shape with n_vec vectors (reps applies
- * per candidate, HIP events) and keeps the fastest.  If the environment variable
+ * and k-grid transform kernels on this handle's shape with n_vec vectors (mean of the
+ * tuned kernel's own HIP-event time over reps applies per candidate, after one untimed
+ * apply; reps < 1 means 5) and keeps the fastest.  If the environment variable
  * OCEAN_AUTOTUNE_CACHE names a file, a cached choice for the same shape is reused and new
  * choices are appended.  Results do not change numerics beyond summation order of the
  * split-K partials.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */

@@ -358,7 +358,7 @@ class Bse:
         _check(lib().ocean_dipole_psi0(self._h, _ptr(p), p.shape[0], _dev_ptr(out)))
         return out
 
-    def autotune(self, n_vec: int, reps: int = 3):
+    def autotune(self, n_vec: int, reps: int = 5):
         _device_sync()
         _check(lib().ocean_bse_autotune(self._h, int(n_vec), int(reps)))
         return self.tuning

@@ -98,13 +98,17 @@ struct ocean_bse_s {
     double* E = nullptr;            // [Nk][Nb]
     const double* U64 = nullptr;    // [Nk][Nx][Nb] complex (owned or borrowed)
     double* U64_owned = nullptr;
+    // true when the stored u (every owned copy: FP64, FP32, bf16) already carries the Bloch
+    // phase e^{ik.x}, so that the k-grid transform has no phase to apply; false for a
+    // borrowed FP64 array, which is used as given
+    bool u_phased = false;
     float* U32 = nullptr;           // [Nk][Nx][Nb] complex FP32 copy (FP32 mode)
     uint16_t* Ubf = nullptr;        // bf16 modes: hi plane [Nk][Nx][Nb][re, im], then (split) the residual plane
     uint16_t* UbfT = nullptr;       // the same values transposed, [Nk][Nb][NxP][re, im] (+ residual plane),
                                     // rows padded with zeros to NxP = Nx rounded up to 4; read by the
                                     // back-projection so that 4 consecutive x are one 16-byte load
     int NxP = 0;
-    double* W64 = nullptr;          // [Nx][Nk] W(x, R)
+    double* W64 = nullptr;          // [Nx][R2 R3][R1] W(x, R) / Nk
     float* W32 = nullptr;
     double* phase = nullptr;        // per-axis e^{2 pi i a b / (n g)} tables, complex
     double* twiddle = nullptr;      // per-axis e^{2 pi i m / n} tables, complex
@@ -131,6 +135,49 @@ struct ocean_bse_s {
 
 namespace ocean {
 
+// Raw buffer access: loads at offsets beyond the descriptor extent return zero and stores
+// there are dropped, which replaces bounds branches in the streaming kernels.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr unsigned kOob = 0xFFFFFFF0u;  // an offset beyond every descriptor extent
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, size_t bytes) {
+    const unsigned n = bytes >= 0xFFFFFFF0ull ? 0xFFFFFFF0u : (unsigned)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, 0x00020000);
+}
+template <typename C2> __device__ __forceinline__ C2 bload(Rsrc r, unsigned off);
+template <> __device__ __forceinline__ double2 bload<double2>(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ float2 bload<float2>(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <typename C2> __device__ __forceinline__ void bstore(C2 v, Rsrc r, unsigned off);
+template <> __device__ __forceinline__ void bstore<double2>(double2 v, Rsrc r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r, (int)off, 0, 0);
+}
+template <> __device__ __forceinline__ void bstore<float2>(float2 v, Rsrc r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, (int)off, 0, 0);
+}
+
+// Bloch phase e^{ik.x} of row g = k Nx + x of u, from the per-axis tables
+// ph[po[a] + i n_x[a]... ] = e^{2 pi i i_a j_a / (n_k[a] n_x[a])}.
+struct PhaseArgs {
+    const double* ph;
+    int po[3], nk[3], nx[3];
+    long long Nx;
+};
+
+__device__ inline double2 bloch_phase(const PhaseArgs& p, long long g) {
+    const long long k = g / p.Nx;
+    const long long x = g - k * p.Nx;
+    const int i3 = (int)(k % p.nk[2]), i2 = (int)((k / p.nk[2]) % p.nk[1]), i1 = (int)(k / ((long long)p.nk[1] * p.nk[2]));
+    const int j3 = (int)(x % p.nx[2]), j2 = (int)((x / p.nx[2]) % p.nx[1]), j1 = (int)(x / ((long long)p.nx[1] * p.nx[2]));
+    const double2* t = reinterpret_cast<const double2*>(p.ph);
+    const double2 a = t[p.po[0] + i1 * p.nx[0] + j1], b = t[p.po[1] + i2 * p.nx[1] + j2], c = t[p.po[2] + i3 * p.nx[2] + j3];
+    const double2 ab = make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_double2(ab.x * c.x - ab.y * c.y, ab.x * c.y + ab.y * c.x);
+}
+
 void set_error(const std::string& msg);
 size_t max_device_bytes();
 
@@ -145,10 +192,12 @@ hipError_t launch_reduce_part(ocean_bse_s* h, int nv);
 hipError_t launch_w_gamma(ocean_bse_s* h, int cols);
 hipError_t launch_build_w(ocean_bse_s* h, const double* wr_dev, const double* wv_dev, int n_wr,
                           double h_r);
-hipError_t launch_to_fp32(ocean_bse_s* h, const double* src, float* dst, long long n);
-hipError_t launch_to_bf16(ocean_bse_s* h, const double* src, uint16_t* hi, uint16_t* lo, long long n);
-hipError_t launch_to_bf16_t(ocean_bse_s* h, const double* src, long long g0, long long rows, uint16_t* hiT,
-                            uint16_t* loT);
+// u rows g0 .. g0 + rows - 1 (FP64, at src) times their Bloch phase, stored in the handle's
+// precision: FP64 in place (src may equal dst), FP32, or the bf16 planes of both layouts
+PhaseArgs phase_args(const ocean_bse_s* h);
+hipError_t launch_u_phase_fp64(ocean_bse_s* h, const double* src, long long g0, long long rows, double* dst);
+hipError_t launch_u_to_fp32(ocean_bse_s* h, const double* src, long long g0, long long rows, float* dst);
+hipError_t launch_u_to_bf16(ocean_bse_s* h, const double* src, long long g0, long long rows);
 hipError_t launch_dipole_psi0(ocean_bse_s* h, const double* d_dev, int n_pol, double* psi0);
 
 // Lanczos kernels

@@ -49,20 +49,6 @@ template <> __device__ __forceinline__ int acc_row<float>(int kq, int r) { retur
 // Raw buffer loads: the hardware returns zero for byte offsets at or beyond the
 // descriptor's extent, so masked elements are loaded from an out-of-range offset
 // instead of behind a branch (which would serialise the loads).
-typedef __amdgpu_buffer_rsrc_t Rsrc;
-constexpr unsigned kOob = 0xFFFFFFF0u;  // an offset beyond every descriptor extent
-
-__device__ __forceinline__ Rsrc make_rsrc(const void* base, size_t bytes) {
-    const unsigned n = bytes >= 0xFFFFFFF0ull ? 0xFFFFFFF0u : (unsigned)bytes;
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, 0x00020000);
-}
-template <typename C2> __device__ __forceinline__ C2 bload(Rsrc r, unsigned off);
-template <> __device__ __forceinline__ double2 bload<double2>(Rsrc r, unsigned off) {
-    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
-}
-template <> __device__ __forceinline__ float2 bload<float2>(Rsrc r, unsigned off) {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-}
 
 // B operands are staged in LDS in MFMA order: value s (0..3) of lane l for sub-step ss and
 // column tile t sits at ((ss * NT + t) * 64 + l) * 4 + s, so a wave reads its operands with
@@ -663,40 +649,38 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
     }
 }
 
-// u (FP64 complex, device) -> bf16 hi plane and, if lo != nullptr, the residual plane
-__global__ __launch_bounds__(256) void to_bf16_kernel(const double* __restrict__ src, __bf16* __restrict__ hi,
-                                                     __bf16* __restrict__ lo, long long n) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        __bf16 h, l;
-        split2(src[e], h, l);
-        hi[e] = h;
-        if (lo) lo[e] = l;
-    }
-}
-
-// rows g0 .. g0 + rows - 1 of u (row g = k Nx + x, Nb complex FP64 each, starting at src) ->
-// transposed bf16 planes [k][n][NxP]
-__global__ __launch_bounds__(256) void to_bf16_t_kernel(const double* __restrict__ src, long long g0, long long rows,
-                                                       int Nx, int Nb, int NxP, __bf16* __restrict__ hiT,
-                                                       __bf16* __restrict__ loT) {
+// rows g0 .. g0 + rows - 1 of u (row g = k Nx + x, Nb complex FP64 each, starting at src),
+// times their Bloch phase, -> bf16 hi (and residual) planes in both layouts: [k][x][n] and
+// the transposed [k][n][NxP]
+__global__ __launch_bounds__(256) void u_to_bf16_kernel(const double* __restrict__ src, long long g0, long long rows,
+                                                       int Nx, int Nb, int NxP, PhaseArgs pa,
+                                                       __bf16* __restrict__ hi, __bf16* __restrict__ lo,
+                                                       __bf16* __restrict__ hiT, __bf16* __restrict__ loT) {
     const long long n_el = rows * Nb;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_el; e += stride) {
         const long long r = e / Nb;
         const int n = (int)(e - r * Nb);
         const long long g = g0 + r;
+        const double2 ph = bloch_phase(pa, g);
+        const double re = src[2 * e], im = src[2 * e + 1];
+        const double vr = re * ph.x - im * ph.y, vi = re * ph.y + im * ph.x;
+        __bf16 h0, l0, h1, l1;
+        split2(vr, h0, l0);
+        split2(vi, h1, l1);
+        const size_t o = 2 * ((size_t)g * Nb + n);
         const long long k = g / Nx;
         const int x = (int)(g - k * Nx);
-        const size_t o = 2 * (((size_t)k * Nb + n) * NxP + x);
-        __bf16 h0, l0, h1, l1;
-        split2(src[2 * e], h0, l0);
-        split2(src[2 * e + 1], h1, l1);
-        hiT[o] = h0;
-        hiT[o + 1] = h1;
-        if (loT) {
-            loT[o] = l0;
-            loT[o + 1] = l1;
+        const size_t ot = 2 * (((size_t)k * Nb + n) * NxP + x);
+        hi[o] = h0;
+        hi[o + 1] = h1;
+        hiT[ot] = h0;
+        hiT[ot + 1] = h1;
+        if (lo) {
+            lo[o] = l0;
+            lo[o + 1] = l1;
+            loT[ot] = l0;
+            loT[ot + 1] = l1;
         }
     }
 }
@@ -880,15 +864,13 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     return e;
 }
 
-hipError_t launch_to_bf16_t(ocean_bse_s* h, const double* src, long long g0, long long rows, uint16_t* hiT,
-                            uint16_t* loT) {
-    to_bf16_t_kernel<<<4096, 256, 0, h->stream>>>(src, g0, rows, h->Nx, h->Nb, h->NxP,
-                                                  reinterpret_cast<__bf16*>(hiT), reinterpret_cast<__bf16*>(loT));
-    return hipGetLastError();
-}
-
-hipError_t launch_to_bf16(ocean_bse_s* h, const double* src, uint16_t* hi, uint16_t* lo, long long n) {
-    to_bf16_kernel<<<4096, 256, 0, h->stream>>>(src, reinterpret_cast<__bf16*>(hi), reinterpret_cast<__bf16*>(lo), n);
+hipError_t launch_u_to_bf16(ocean_bse_s* h, const double* src, long long g0, long long rows) {
+    const bool split = h->precision == OCEAN_PREC_SPLIT_BF16;
+    __bf16* hi = reinterpret_cast<__bf16*>(h->Ubf);
+    __bf16* hiT = reinterpret_cast<__bf16*>(h->UbfT);
+    __bf16* lo = split ? hi + (size_t)2 * h->Nk * h->Nx * h->Nb : nullptr;
+    __bf16* loT = split ? hiT + (size_t)2 * h->Nk * h->Nb * h->NxP : nullptr;
+    u_to_bf16_kernel<<<4096, 256, 0, h->stream>>>(src, g0, rows, h->Nx, h->Nb, h->NxP, phase_args(h), hi, lo, hiT, loT);
     return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 // the Haydock driver (optionally replayed from a captured HIP graph), spectra,
 // profiling and error reporting.
 #include <algorithm>
+#include <initializer_list>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -463,19 +464,55 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
     // energies
     if ((rc = dalloc(h, &h->E, (size_t)Nk * h->Nb, "energies")) != OCEAN_OK) return fail(rc);
     if ((rc = check_hip(hipMemcpyAsync(h->E, d->energies, (size_t)Nk * h->Nb * 8, hipMemcpyHostToDevice, h->stream), "energies upload")) != OCEAN_OK) return fail(rc);
+    // phase tables e^{2 pi i a b / (n g)} per axis and DFT twiddles e^{2 pi i m / n}
+    {
+        std::vector<double> ph, tw;
+        for (int a = 0; a < 3; ++a) {
+            h->phase_off[a] = (int)(ph.size() / 2);
+            const long long ng = (long long)h->nk[a] * h->nx[a];
+            for (int i = 0; i < h->nk[a]; ++i)
+                for (int j = 0; j < h->nx[a]; ++j) {
+                    const long long m = ((long long)i * j) % ng;
+                    const double ang = 2.0 * M_PI * (double)m / (double)ng;
+                    ph.push_back(std::cos(ang));
+                    ph.push_back(std::sin(ang));
+                }
+            h->tw_off[a] = (int)(tw.size() / 2);
+            for (int m = 0; m < h->nk[a]; ++m) {
+                const double ang = 2.0 * M_PI * (double)m / (double)h->nk[a];
+                tw.push_back(std::cos(ang));
+                tw.push_back(std::sin(ang));
+            }
+        }
+        if (hipMalloc((void**)&h->phase, ph.size() * 8) != hipSuccess ||
+            hipMalloc((void**)&h->twiddle, tw.size() * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("ocean_bse_create: hipMalloc failed for phase tables");
+            return fail(OCEAN_ERR_OUT_OF_MEMORY);
+        }
+        h->device_bytes += (ph.size() + tw.size()) * 8;
+        if ((rc = check_hip(hipMemcpy(h->phase, ph.data(), ph.size() * 8, hipMemcpyHostToDevice), "phase upload")) != OCEAN_OK) return fail(rc);
+        if ((rc = check_hip(hipMemcpy(h->twiddle, tw.data(), tw.size() * 8, hipMemcpyHostToDevice), "twiddle upload")) != OCEAN_OK) return fail(rc);
+    }
     // u
+    // Owned copies store e^{ik.x} u_nk(x), so the projections deliver phased lines and the
+    // k-grid transform applies no phase; a borrowed FP64 array is used as given.
     if ((d->flags & OCEAN_FLAG_BORROW_DEVICE_U) && h->precision == OCEAN_PREC_FP64) {
         h->U64 = d->u;
+        h->u_phased = false;
     } else if (h->precision == OCEAN_PREC_FP64) {
         if ((rc = dalloc(h, &h->U64_owned, ue * 2, "u (FP64)")) != OCEAN_OK) return fail(rc);
         if ((rc = check_hip(hipMemcpyAsync(h->U64_owned, d->u, ue * 16, hipMemcpyHostToDevice, h->stream), "u upload")) != OCEAN_OK) return fail(rc);
+        rc = check_hip(launch_u_phase_fp64(h, h->U64_owned, 0, (long long)Nk * Nx, h->U64_owned), "u phase");
+        if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "u phase");
+        if (rc != OCEAN_OK) return fail(rc);
         h->U64 = h->U64_owned;
+        h->u_phased = true;
     } else {
+        h->u_phased = true;
         // reduced-precision copy converted on the device, from the borrowed FP64 array or
         // staged from the host through a bounded FP64 buffer
         const bool bf = h->precision != OCEAN_PREC_FP32;
-        uint16_t* lo_plane = nullptr;
-        uint16_t* lo_plane_t = nullptr;
         if (bf) {
             h->NxP = (h->Nx + 3) / 4 * 4;
             if ((long long)h->Nb * h->NxP * 4 >= (1LL << 31) || (long long)64 * 2 * h->Nb * 4 >= (1LL << 31)) {
@@ -484,10 +521,6 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
             }
             if ((rc = dalloc(h, &h->Ubf, ubf_elems(h), "u (bf16)")) != OCEAN_OK) return fail(rc);
             if ((rc = dalloc(h, &h->UbfT, ubft_elems(h), "u (bf16, transposed)")) != OCEAN_OK) return fail(rc);
-            if (h->precision == OCEAN_PREC_SPLIT_BF16) {
-                lo_plane = h->Ubf + 2 * ue;
-                lo_plane_t = h->UbfT + ubft_plane(h);
-            }
             const size_t planes = ubf_elems(h) - 32;
             if ((rc = check_hip(hipMemsetAsync(h->Ubf + planes, 0, 64, h->stream), "u padding")) != OCEAN_OK) return fail(rc);
             // row padding x in [Nx, NxP) of the transposed copy stays zero
@@ -497,12 +530,9 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
         }
         // src holds n complex elements starting at element off; off and n are whole rows of Nb
         auto convert = [&](const double* src, size_t off, size_t n) {
-            if (bf) {
-                hipError_t e = launch_to_bf16(h, src, h->Ubf + 2 * off, lo_plane ? lo_plane + 2 * off : nullptr, (long long)n * 2);
-                if (e != hipSuccess) return e;
-                return launch_to_bf16_t(h, src, (long long)(off / h->Nb), (long long)(n / h->Nb), h->UbfT, lo_plane_t);
-            }
-            return launch_to_fp32(h, src, h->U32 + 2 * off, (long long)n * 2);
+            const long long g0 = (long long)(off / h->Nb), rows = (long long)(n / h->Nb);
+            if (bf) return launch_u_to_bf16(h, src, g0, rows);
+            return launch_u_to_fp32(h, src, g0, rows, h->U32);
         };
         if (d->flags & OCEAN_FLAG_BORROW_DEVICE_U) {
             rc = check_hip(convert(d->u, 0, ue), "u conversion");
@@ -545,36 +575,6 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
         dfree(h, wr, d->n_wr);
         dfree(h, wv, d->n_wr);
         if (rc != OCEAN_OK) return fail(rc);
-    }
-    // phase tables e^{2 pi i a b / (n g)} per axis and DFT twiddles e^{2 pi i m / n}
-    {
-        std::vector<double> ph, tw;
-        for (int a = 0; a < 3; ++a) {
-            h->phase_off[a] = (int)(ph.size() / 2);
-            const long long ng = (long long)h->nk[a] * h->nx[a];
-            for (int i = 0; i < h->nk[a]; ++i)
-                for (int j = 0; j < h->nx[a]; ++j) {
-                    const long long m = ((long long)i * j) % ng;
-                    const double ang = 2.0 * M_PI * (double)m / (double)ng;
-                    ph.push_back(std::cos(ang));
-                    ph.push_back(std::sin(ang));
-                }
-            h->tw_off[a] = (int)(tw.size() / 2);
-            for (int m = 0; m < h->nk[a]; ++m) {
-                const double ang = 2.0 * M_PI * (double)m / (double)h->nk[a];
-                tw.push_back(std::cos(ang));
-                tw.push_back(std::sin(ang));
-            }
-        }
-        if (hipMalloc((void**)&h->phase, ph.size() * 8) != hipSuccess ||
-            hipMalloc((void**)&h->twiddle, tw.size() * 8) != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("ocean_bse_create: hipMalloc failed for phase tables");
-            return fail(OCEAN_ERR_OUT_OF_MEMORY);
-        }
-        h->device_bytes += (ph.size() + tw.size()) * 8;
-        if ((rc = check_hip(hipMemcpy(h->phase, ph.data(), ph.size() * 8, hipMemcpyHostToDevice), "phase upload")) != OCEAN_OK) return fail(rc);
-        if ((rc = check_hip(hipMemcpy(h->twiddle, tw.data(), tw.size() * 8, hipMemcpyHostToDevice), "twiddle upload")) != OCEAN_OK) return fail(rc);
     }
     // small matrices and the local projectors
     auto upload = [&](double** dst, const double* src, size_t ndouble, const char* what) -> int {
@@ -858,7 +858,7 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
         set_error("ocean_bse_autotune: NULL handle or n_vec < 1");
         return OCEAN_ERR_INVALID_ARG;
     }
-    if (reps < 1) reps = 3;
+    if (reps < 1) reps = 5;
     (void)hipSetDevice(h->device);
     char key[160];
     std::snprintf(key, sizeof key, "nk=%d,%d,%d nx=%d,%d,%d nb=%d nc=%d nmu=%d prec=%d cols=%d", h->nk[0],
@@ -893,22 +893,28 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
         set_error("ocean_bse_autotune: hipMalloc failed");
         return OCEAN_ERR_OUT_OF_MEMORY;
     }
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
     const bool saved_prof = h->profiling;
     h->profiling = false;
-    auto time_apply = [&](float* ms) -> int {
+    // mean time of the named kernels over `reps` applies (one untimed apply first), read from
+    // the per-kernel events; the handle's own kernel statistics are kept aside meanwhile
+    const std::vector<KernelStat> saved_stats = h->stats;
+    auto time_kernels = [&](std::initializer_list<const char*> names, float* ms) -> int {
         (void)hipMemsetAsync(x, 0, vb, h->stream);
+        h->profiling = false;
         int rc = apply_pipeline(h, x, y, n_vec, nullptr);
         if (rc != OCEAN_OK) return rc;
-        (void)hipEventRecord(e0, h->stream);
+        h->stats.clear();
+        h->profiling = true;
         for (int r = 0; r < reps && rc == OCEAN_OK; ++r) rc = apply_pipeline(h, x, y, n_vec, nullptr);
-        (void)hipEventRecord(e1, h->stream);
+        prof_collect(h);
+        h->profiling = false;
         if (rc != OCEAN_OK) return rc;
-        rc = check_hip(hipEventSynchronize(e1), "autotune");
-        if (rc == OCEAN_OK) rc = check_hip(hipEventElapsedTime(ms, e0, e1), "autotune");
-        return rc;
+        double t = 0.0;
+        for (const char* nm : names)
+            for (const auto& st : h->stats)
+                if (std::strcmp(st.name, nm) == 0 && st.count > 0) t += st.ms / (double)st.count;
+        *ms = (float)t;
+        return OCEAN_OK;
     };
     int rc = OCEAN_OK;
     // one knob at a time, the others held at their current values
@@ -918,7 +924,7 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
         for (int ms : {1, 2}) {
             h->fwd_ms = ms;
             float t;
-            if ((rc = time_apply(&t)) != OCEAN_OK) break;
+            if ((rc = time_kernels({"proj_fwd"}, &t)) != OCEAN_OK) break;
             if (t < best_ms) { best_ms = t; best = ms; }
         }
         h->fwd_ms = best;
@@ -932,7 +938,7 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
             bwd_geometry(h, &bb, &S, &ch);
             h->ws.bwd_chunks = S;
             float t;
-            if ((rc = time_apply(&t)) != OCEAN_OK) break;
+            if ((rc = time_kernels({"proj_bwd", "reduce_part", "combine"}, &t)) != OCEAN_OK) break;
             if (t < best_ms) { best_ms = t; best = bt; }
         }
         h->bwd_target_blocks = best;
@@ -940,22 +946,21 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
         bwd_geometry(h, &bb, &S, &ch);
         h->ws.bwd_chunks = S;
     }
-    if (rc == OCEAN_OK) {
+    if (rc == OCEAN_OK && h->Nk > 1) {
         int best = h->fft_lines;
         float best_ms = 1e30f;
         for (int L : {4, 8, 16, 32, 64}) {
             if (fft_lds_bytes(h, L) > 160 * 1024) continue;
             h->fft_lines = L;
             float t;
-            if ((rc = time_apply(&t)) != OCEAN_OK) break;
+            if ((rc = time_kernels({"fft_w"}, &t)) != OCEAN_OK) break;
             if (t < best_ms) { best_ms = t; best = L; }
         }
         h->fft_lines = best;
     }
+    h->stats = saved_stats;
     h->profiling = saved_prof;
     (void)hipStreamSynchronize(h->stream);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     (void)hipFree(x);
     (void)hipFree(y);
     if (rc != OCEAN_OK) return rc;

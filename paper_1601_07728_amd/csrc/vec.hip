@@ -455,15 +455,25 @@ __global__ __launch_bounds__(256) void build_w_kernel(double* __restrict__ W64, 
         const double t = s - j;
         val = (1.0 - t) * wv[j] + t * wv[j + 1];
     }
+    // the 1/Nk of the unitary k <-> R pair is folded into the table
+    val /= (double)Nk;
     if (W64) W64[idx] = val;
     if (W32) W32[idx] = (float)val;
 }
 
-__global__ __launch_bounds__(256) void to_fp32_kernel(const double* __restrict__ src,
-                                                      float* __restrict__ dst, long long n) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// rows g0 .. g0 + rows - 1 of u (row g = k Nx + x, Nb complex FP64 each) times their Bloch
+// phase, stored as T (FP64 in place is allowed: each element is read before it is written)
+template <typename T>
+__global__ __launch_bounds__(256) void u_phase_kernel(const double* __restrict__ src, long long g0, long long rows,
+                                                     int Nb, PhaseArgs pa, T* dst) {
+    const long long n_el = rows * Nb;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long e = i; e < n; e += stride) dst[e] = (float)src[e];
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_el; e += stride) {
+        const double2 ph = bloch_phase(pa, g0 + e / Nb);
+        const double re = src[2 * e], im = src[2 * e + 1];
+        dst[2 * e] = (T)(re * ph.x - im * ph.y);
+        dst[2 * e + 1] = (T)(re * ph.y + im * ph.x);
+    }
 }
 
 // psi0[p][kn][(mc, s)] = sum_m conj(A[kn][m]) d_p[m][mc]
@@ -710,8 +720,25 @@ hipError_t launch_build_w(ocean_bse_s* h, const double* wr_dev, const double* wv
     return hipGetLastError();
 }
 
-hipError_t launch_to_fp32(ocean_bse_s* h, const double* src, float* dst, long long n) {
-    to_fp32_kernel<<<4096, 256, 0, h->stream>>>(src, dst, n);
+PhaseArgs phase_args(const ocean_bse_s* h) {
+    PhaseArgs p;
+    p.ph = h->phase;
+    for (int a = 0; a < 3; ++a) {
+        p.po[a] = h->phase_off[a];
+        p.nk[a] = h->nk[a];
+        p.nx[a] = h->nx[a];
+    }
+    p.Nx = h->Nx;
+    return p;
+}
+
+hipError_t launch_u_phase_fp64(ocean_bse_s* h, const double* src, long long g0, long long rows, double* dst) {
+    u_phase_kernel<double><<<4096, 256, 0, h->stream>>>(src, g0, rows, h->Nb, phase_args(h), dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_u_to_fp32(ocean_bse_s* h, const double* src, long long g0, long long rows, float* dst) {
+    u_phase_kernel<float><<<4096, 256, 0, h->stream>>>(src, g0, rows, h->Nb, phase_args(h), dst + 2 * g0 * h->Nb);
     return hipGetLastError();
 }
 

@@ -54,6 +54,8 @@ HV_CASES = {
     "l_tiles": lambda: synth.small_l_edge(seed=4, nk=(4, 2, 2), nx=(10, 9, 11), n_bands=37),
     "gamma": lambda: synth.small_l_edge(seed=5, nk=(1, 1, 1), nx=(12, 12, 12), n_bands=53),
     "k8_axis": lambda: synth.small_l_edge(seed=6, nk=(8, 1, 3), nx=(3, 4, 5), n_bands=19),
+    "cube4": lambda: synth.small_l_edge(seed=8, nk=(4, 4, 4), nx=(5, 4, 3), n_bands=9),
+    "cube8": lambda: synth.small_l_edge(seed=9, nk=(8, 8, 8), nx=(3, 2, 2), n_bands=5),
 }
 
 
@@ -72,6 +74,25 @@ def test_apply_fp64_matches_oracle(case, n_vec):
     ut = orc.folded_u(cr)
     w = orc.w_supercell(cr)
     for v in range(n_vec):
+        ref = orc.apply_h(cr, x[v], hc, kl, ut=ut, w=w, f=f)
+        assert _rel(y[v], ref) <= 1e-13, (case, v, _rel(y[v], ref))
+    h.close()
+
+
+@pytest.mark.parametrize("case", ["c1", "l_tiles", "k8_axis", "cube4", "cube8"])
+def test_apply_borrowed_fp64_matches_oracle(case):
+    """A borrowed FP64 u is used as given, so the k-grid transform applies the Bloch phase
+    itself (owned copies carry it): both routes against the oracle."""
+    ob = _ob()
+    cr = HV_CASES[case]()
+    _say(f"[apply fp64 borrowed] case={case} nk={cr.nk} nx={cr.nx} nb={cr.n_bands}")
+    u_dev = _to_dev(cr.u)
+    h = ob.Bse.from_crystal(cr, precision="fp64", u=u_dev)
+    hc, kl = _oracle_mats(cr)
+    x = synth.complex_gaussian(np.random.default_rng(77), (3, cr.n_k, cr.n_bands, cr.n_core))
+    y = h.apply(_to_dev(x)).cpu().numpy()
+    f, ut, w = orc.dft_matrix(cr), orc.folded_u(cr), orc.w_supercell(cr)
+    for v in range(3):
         ref = orc.apply_h(cr, x[v], hc, kl, ut=ut, w=w, f=f)
         assert _rel(y[v], ref) <= 1e-13, (case, v, _rel(y[v], ref))
     h.close()
