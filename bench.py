@@ -68,7 +68,28 @@ def proj_bytes(cr, cols, u_elem, phi_elem):
 # reading for the 1 GiB calibration kernel (FETCH_SIZE reads 0.5 GiB for 1 GiB read,
 # WRITE_SIZE 1.0 GiB for 1 GiB written).  A figure holds only for the kernel source it was
 # taken with (sha256 of the .hip file); for any other source the traffic is reported null.
-TRAFFIC = {}
+TRAFFIC = {
+    ("fp64", "proj_bwd"): {"bytes": 7535475292, "src": "proj.hip",
+        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
+    ("fp64", "proj_fwd"): {"bytes": 7589273278, "src": "proj.hip",
+        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
+    ("fp32", "proj_bwd"): {"bytes": 3796823115, "src": "proj.hip",
+        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
+    ("fp32", "proj_fwd"): {"bytes": 3849083002, "src": "proj.hip",
+        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
+    ("split_bf16", "proj_bwd"): {"bytes": 3931744257, "src": "proj.hip",
+        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
+    ("split_bf16", "proj_fwd"): {"bytes": 3849136248, "src": "proj.hip",
+        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
+    ("bf16", "proj_bwd"): {"bytes": 2260313423, "src": "proj.hip",
+        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
+    ("bf16", "proj_fwd"): {"bytes": 2333645932, "src": "proj.hip",
+        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
+    ("fp64", "fft_w"): {"bytes": 2392631539, "src": "fftw.hip",
+        "sha256": "f00fa72c15c460b1e922810cd0d049cec425aff65b64428b192d46ce5979f90d"},
+    ("fp32", "fft_w"): {"bytes": 1224824029, "src": "fftw.hip",
+        "sha256": "f00fa72c15c460b1e922810cd0d049cec425aff65b64428b192d46ce5979f90d"},
+}
 
 
 def kernel_traffic(mode, kernel):
@@ -356,6 +377,10 @@ def main():
             "proj_fwd": proj_bytes(cr, cols, U_BYTES[name], PHI_BYTES[name]) / (avgs[name]["proj_fwd"] * 1e6),
             "proj_bwd": proj_bytes(cr, cols, U_BYTES[name], PHI_BYTES[name]) / (avgs[name]["proj_bwd"] * 1e6),
             "fft_w": fft_bytes(cr, cols, PHI_BYTES[name]) / (avgs[name]["fft_w"] * 1e6)}
+        fft_mode = "fp64" if name == "fp64" else "fp32"   # every mixed mode runs the FP32 transform
+        results[name]["traffic_bytes"] = {"proj_fwd": kernel_traffic(name, "proj_fwd"),
+                                          "proj_bwd": kernel_traffic(name, "proj_bwd"),
+                                          "fft_w": kernel_traffic(fft_mode, "fft_w")}
     avg = avgs["fp64"]
     dom = max(("proj_fwd", "proj_bwd"), key=lambda k: avg.get(k, 0.0))
     ach = proj_bytes(cr, cols, 16, 16) / (avg[dom] * 1e-3) / 1e9
