@@ -53,3 +53,49 @@ def test_encode_decode_round_trip():
     assert np.allclose(ae, a[:, :256], rtol=0, atol=1e-14)
     assert np.allclose(be, b[:, :256], rtol=1e-14, atol=0)
     assert np.allclose(c, a[:, 16:32].mean(axis=1)) and np.allclose(s, b[:, 16:32].mean(axis=1))
+
+
+def _fd_mismatch(p, x, t, g, idx):
+    """Largest |finite difference - g| / max(|g|, 1e-3) over the parameters idx."""
+    worst = 0.0
+    for i in idx:
+        h = 1e-6 * max(1.0, abs(p[i]))
+        pp = p.copy()
+        pp[i] += h
+        lp = mlp.loss_and_grad(pp, x, t)[0]
+        pp[i] -= 2 * h
+        lm = mlp.loss_and_grad(pp, x, t)[0]
+        worst = max(worst, abs((lp - lm) / (2 * h) - g[i]) / max(abs(g[i]), 1e-3))
+    return worst
+
+
+def test_planted_gradient_mistakes_are_caught():
+    """The finite-difference pin must reject plausible backward-pass mistakes, planted here in
+    a copy of the oracle's gradient: a sign flip in one layer's weights and a dropped bias
+    gradient."""
+    rng, p, x, t = _data(2)
+    _, g = mlp.loss_and_grad(p, x, t)
+    w2 = slice(64 * 256 + 256, 64 * 256 + 256 + 256 * 256)
+    idx_w2 = rng.choice(np.arange(w2.start, w2.stop), 8, replace=False)
+    assert _fd_mismatch(p, x, t, g, idx_w2) <= 1e-6
+    bad = g.copy()
+    bad[w2] *= -1.0
+    assert _fd_mismatch(p, x, t, bad, idx_w2) > 0.5
+    b4 = slice(p.size - 448, p.size)
+    bad = g.copy()
+    bad[b4] = 0.0
+    assert _fd_mismatch(p, x, t, bad, np.arange(b4.start, b4.start + 8)) > 0.5
+
+
+def test_zero_network_extends_with_the_constant_chain():
+    """With every parameter zero the network outputs 0, which decodes to a_n = c and
+    b_n = s for n >= 32: the constant chain the square-root terminator assumes."""
+    rng = np.random.default_rng(5)
+    a = rng.uniform(0.2, 1.4, (3, 32))
+    b = rng.uniform(0.05, 0.3, (3, 32))
+    x, _, c, s = mlp.encode(a, b)
+    y, _ = mlp.forward(np.zeros(mlp.n_params()), x)
+    ae, be = mlp.decode(y, a, b, c, s)
+    assert np.array_equal(ae[:, :32], a) and np.array_equal(be[:, :32], b)
+    assert np.allclose(ae[:, 32:], c[:, None], rtol=0, atol=1e-15)
+    assert np.allclose(be[:, 32:], s[:, None], rtol=1e-15, atol=0)
