@@ -53,7 +53,7 @@ enum {
 };
 
 /* Storage / arithmetic precision of the two band-projection contractions
- * (Algorithm 1 lines 2 and 6).  Everything else -- the diagonal, core and local
+ * (the band-to-real-space and real-space-to-band steps of Algorithm 1).  Everything else -- the diagonal, core and local
  * terms, the Lanczos inner products, norms, coefficients and the continued
  * fraction -- is FP64 in every mode. */
 enum {

@@ -16,7 +16,7 @@ equation calculations", section 2 and section 3.2):
 
 Readings where the paper is silent (each is listed in the design doc):
 
-* Fourier pair of Algorithm 1 lines 3 and 5: unitary, e^{+ik.R} forward and
+* Fourier pair of Algorithm 1 (k -> R and back): unitary, e^{+ik.R} forward and
   e^{-ik.R} back, with Nk^{-1/2} each way.
 * W(x, R) = W_rad(|x + R - tau|) with the minimum image in the Born-von-Karman
   supercell (the k grid fixes the range of W, section 3.2.1); W_rad is the
@@ -94,7 +94,7 @@ def w_supercell(cr):
 
 
 def folded_u(cr):
-    """e^{ik.x} u_nk(x): the phase factor of Algorithm 1 line 2 folded into u."""
+    """e^{ik.x} u_nk(x): the phase factor of Algorithm 1's band-to-real-space step folded into u."""
     k = kpoints(cr)
     x = xpoints(cr)
     phase = np.exp(1j * (k @ x.T))            # [k, x]
@@ -102,7 +102,7 @@ def folded_u(cr):
 
 
 def dft_matrix(cr):
-    """F[R, k] = Nk^{-1/2} e^{+ik.R} (Algorithm 1 line 3); its conjugate transpose is line 5."""
+    """F[R, k] = Nk^{-1/2} e^{+ik.R} (Algorithm 1, k -> R); its conjugate transpose is R -> k."""
     return np.exp(1j * (lattice_vectors(cr) @ kpoints(cr).T)) / math.sqrt(cr.n_k)
 
 
@@ -116,15 +116,15 @@ def apply_w0(cr, psi, ut=None, w=None, f=None):
     f = dft_matrix(cr) if f is None else f
     out = np.zeros_like(psi)
     for alpha in range(psi.shape[2]):
-        # line 2: phi(k) = sum_n psi_{n,k,alpha} e^{ik.x} u_nk(x), for every x at once
+        # band -> real space: phi(k) = sum_n psi_{n,k,alpha} e^{ik.x} u_nk(x), for every x at once
         phi_k = np.einsum("kxn,kn->kx", ut, psi[:, :, alpha])
-        # line 3: phi(R) = F_{k->R}[phi(k)]
+        # k -> R: phi(R) = F_{k->R}[phi(k)]
         phi_r = f @ phi_k
-        # line 4: phi(R) = W(x, R) phi(R)
+        # screened potential: phi(R) = W(x, R) phi(R)
         phi_r = w.T * phi_r
-        # line 5: phi(k) = F_{R->k}[phi(R)]
+        # R -> k: phi(k) = F_{R->k}[phi(R)]
         phi_k = f.conj().T @ phi_r
-        # line 6: psi'_{n,k,alpha} += phi(k) e^{-ik.x} u*_nk(x), summed over x
+        # real space -> band: psi'_{n,k,alpha} += phi(k) e^{-ik.x} u*_nk(x), summed over x
         out[:, :, alpha] += np.einsum("kx,kxn->kn", phi_k, ut.conj())
     return out
 

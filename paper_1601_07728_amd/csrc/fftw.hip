@@ -1,16 +1,17 @@
-// k-grid transform and screened-potential multiply of Algorithm 1 lines 3-5
-// (section 3.2.1), with the e^{+-ik.x} phases of lines 2 and 6 folded in:
+// k-grid transform and screened-potential multiply of Algorithm 1 (section 3.2.1):
 //
-//   phi(x, R)  = Nk^{-1/2} sum_k e^{+ik.R} e^{+ik.x} phi(x, k)      (line 3)
-//   phi(x, R) *= W(x, R)                                            (line 4)
-//   phi'(x, k) = Nk^{-1/2} e^{-ik.x} sum_R e^{-ik.R} phi(x, R)       (line 5)
+//   phi(x, R)  = Nk^{-1/2} sum_k e^{+ik.R} phi(x, k)      (k -> R)
+//   phi(x, R) *= W(x, R)                                  (screened potential, diagonal in x)
+//   phi'(x, k) = Nk^{-1/2} sum_R e^{-ik.R} phi(x, R)       (R -> k)
 //
-// A line is one (x, column) pair; its Nk values sit at stride Nx*cols in
-// phi[k][x][col].  A block stages L consecutive lines (contiguous for every k)
-// in LDS as [k][line], runs the separable small DFTs along the three k axes in
-// LDS, multiplies by W and transforms back, then writes the lines in place.
-// W(x, R) is stored [x][R2 R3][R1] (R1 fastest), R = R1 n2 n3 + R2 n3 + R3.
-// The pass is HBM-bound: phi is read once and written once.
+// The Bloch phase e^{+-ik.x} of the band projections is normally carried by the stored u;
+// for a borrowed FP64 u the kernels apply it here on the way in and out.  The product of
+// the two Nk^{-1/2} is folded into the W table.
+//
+// A line is one (x, column) pair; its Nk values sit in the x-blocked phi layout.  A block
+// stages L lines in LDS as [k][line], runs the separable small DFTs along the three k axes,
+// multiplies by W and transforms back, then writes the lines in place.  The pass is
+// HBM-bound: phi is read once and written once.
 #include <type_traits>
 
 #include "internal.h"
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(256) void fft_w_kernel(
         }
         tw_lds[threadIdx.x] = v;
     }
-    // load, with the e^{+ik.x} phase of line 2 unless u carries it
+    // load, with the e^{+ik.x} phase unless u carries it
     for (int e = threadIdx.x; e < Nk * L; e += blockDim.x) {
         const int kk = e / L, l = e - kk * L;
         const long long line = line0 + l;
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(256) void fft_w_kernel(
     __syncthreads();
     dft3<T, NMAX>(buf, tw_lds, n1, n2, n3, L, false);
 
-    // line 4: multiply by W(x, R)
+    // screened potential: multiply by W(x, R)
     for (int e = threadIdx.x; e < Nk * L; e += blockDim.x) {
         const int r = e / L, l = e - r * L;
         const long long line = line0 + l;
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(256) void fft_w_kernel(
     __syncthreads();
     dft3<T, NMAX>(buf, tw_lds, n1, n2, n3, L, true);
 
-    // store, with the e^{-ik.x} phase of line 6 unless u carries it (the 1/Nk of the
+    // store, with the e^{-ik.x} phase unless u carries it (the 1/Nk of the
     // unitary pair is in W)
     for (int e = threadIdx.x; e < Nk * L; e += blockDim.x) {
         const int kk = e / L, l = e - kk * L;

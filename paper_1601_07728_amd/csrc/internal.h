@@ -20,6 +20,7 @@ constexpr int kMaxDft = 16;     // largest k-grid extent per axis
 constexpr int kColsPerPass = 24;  // exciton columns per projection launch (3 MFMA column tiles)
 constexpr int kRedBlocks = 240;   // blocks per vector in the Lanczos reductions
 constexpr int kXB = 16;           // x-block of the phi work array (a power of two: phi_index_x)
+constexpr int kStageTile = 4096;  // bytes of one staged B chunk per 16-wide column tile
 
 // phi work array layout: [x / kXB][k][x % kXB][col] (complex).  A "line" is
 // line = x * cols + col; for a fixed k the lines of one x-block are contiguous,
@@ -55,6 +56,8 @@ struct Workspace {
     double* w0 = nullptr;       // [Nk][Nb][cols] complex: the partials summed (W0 x)
     double* loc_part = nullptr; // [P][nv][Nc*Nmu] complex
     double* loc_b = nullptr;    // [nv][Nc*Nmu] complex
+    unsigned char* bst = nullptr;  // bf16 modes: forward B operand of one projection pass,
+                                   // staged per (k, band chunk) in the kernel's LDS order
     size_t bytes = 0;
 };
 
@@ -183,6 +186,7 @@ size_t max_device_bytes();
 
 // Kernel launchers (each enqueues on h->stream).  Return hipSuccess or the launch error.
 hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, int ncb);
+int fwd_band_chunk(const ocean_bse_s* h);  // bands per staged forward chunk, 0 if not staged
 hipError_t launch_fft_w(ocean_bse_s* h, int cols);
 hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb);
 hipError_t launch_local_in(ocean_bse_s* h, const double* x, int nv);

@@ -1,24 +1,24 @@
 // Band projections of Algorithm 1 (section 3.2.1) on the gfx950 matrix cores.
 //
-//   forward (line 2):  phi[k][x][col]  = sum_n u[k][x][n] psi[k][n][col]
-//   backward (line 6): part[s][k][n][col] = sum_{x in chunk s} conj(u[k][x][n]) phi'[k][x][col]
+//   band -> real space:  phi[k][x][col]      = sum_n u~[k][x][n] psi[k][n][col]
+//   real space -> band:  part[s][k][n][col]  = sum_{x in chunk s} conj(u~[k][x][n]) phi'[k][x][col]
 //
-// The e^{+-ik.x} phases of lines 2 and 6 are applied by the k-grid transform
-// kernel, so u is used exactly as stored.  Both contractions are written as
-// real GEMMs on the interleaved (re, im) storage of u: the contraction index is
-// (band or point, re/im part) and the real output columns are (column, re/im),
-// so one 16x16x4 MFMA tile consumes the complex data in place:
+// u~ = e^{ik.x} u is the stored copy (a borrowed FP64 u is used as given and the k-grid
+// transform applies the phase).  Both contractions are written as real GEMMs on the
+// interleaved (re, im) storage: the contraction index is (band or point, re/im part) and
+// the real output columns are (column, re/im), so the MFMA tiles consume the data in place:
 //
 //   forward  C[(x)][(c,q)] = sum_{(n,p)} U_p[x][n] B[(n,p)][(c,q)]
 //            B = [[re psi, im psi], [-im psi, re psi]]        (rows p = 0, 1; columns q = 0, 1)
 //   backward Z[(n)][(c,q)] = sum_{(x,p)} U_p[x][n] B[(x,p)][(c,q)]
 //            B = [[re phi, im phi], [im phi, -re phi]]
 //
-// MFMA operand layout (v_mfma_{f64,f32}_16x16x4): lane l = i + 16 kq holds
-// A[i][kq] and B[kq][i]; result register r of lane l holds column i of row
-// 4 r + kq (f64) or 4 kq + r (f32), as measured on gfx950.  Inside one 16x16x4 step the four K slots kq map to the contraction
-// index ((2 kq + s/2), s%2) for step s = 0..3, so every lane reads two adjacent
-// complex values of u (32 contiguous bytes in FP64).
+// 16x16x4 FP64/FP32 MFMA: lane l = i + 16 kq holds A[i][kq] and B[kq][i]; result register r
+// holds column i of row 4 r + kq (f64) or 4 kq + r (f32), as measured on gfx950.  A
+// sub-step covers 8 contraction points: lane group kq holds points 2 kq and 2 kq + 1, and
+// MFMA s = 0..3 of the sub-step contracts (point 2 kq + s / 2, part s % 2).
+// 16x16x32 bf16 MFMA: a sub-step covers 16 points, lane group kq holds points 4 kq .. 4 kq + 3,
+// slot 2 m + p = part p of point m; the result layout is that of the f32 form.
 #include "internal.h"
 
 namespace ocean {
@@ -26,6 +26,9 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
 
 __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -33,12 +36,13 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
 __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ v4f mfma_bf16(bf16x8 a, bf16x8 b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 template <typename T> struct Cplx;
 template <> struct Cplx<double> { typedef double2 c2; typedef v4d acc; };
 template <> struct Cplx<float> { typedef float2 c2; typedef v4f acc; };
-
-template <typename C2> __device__ __forceinline__ C2 czero() { C2 z; z.x = 0; z.y = 0; return z; }
 
 // Row of the 16x16 result held in accumulator register r of a lane in group kq
 // (column = lane % 16).  The f64 and f32 16x16x4 instructions differ here.
@@ -46,9 +50,46 @@ template <typename T> __device__ __forceinline__ int acc_row(int kq, int r);
 template <> __device__ __forceinline__ int acc_row<double>(int kq, int r) { return 4 * r + kq; }
 template <> __device__ __forceinline__ int acc_row<float>(int kq, int r) { return 4 * kq + r; }
 
-// Raw buffer loads: the hardware returns zero for byte offsets at or beyond the
-// descriptor's extent, so masked elements are loaded from an out-of-range offset
-// instead of behind a branch (which would serialise the loads).
+// v = hi + lo with hi = v rounded to bf16 and lo the rounded residual
+__device__ __forceinline__ void split_d(double v, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)(float)v;
+    lo = (__bf16)(float)(v - (double)(float)hi);
+}
+__device__ __forceinline__ void split_f(float v, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)v;
+    lo = (__bf16)(v - (float)hi);  // exact in FP32
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; this renumbering gives each XCD a
+// contiguous run of blocks, so the blocks that share a k (and its staged B operand) meet in
+// one L2.
+__device__ __forceinline__ int xcd_block() {
+    const unsigned nblk = gridDim.x, q8 = nblk / 8, r8 = nblk % 8;
+    const unsigned xcd = blockIdx.x % 8, pos = blockIdx.x / 8;
+    return (int)(xcd * q8 + (xcd < r8 ? xcd : r8) + pos);
+}
+
+// Wait until at most N vector-memory loads of this wave are outstanding (vmcnt counts loads
+// in issue order); expcnt and lgkmcnt are left alone.
+template <int N> __device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Copy staged chunk ch (CB = NT * 4 KiB bytes) straight from memory into an LDS buffer:
+// buffer_load ... lds writes lane l's 16 bytes at the wave's LDS base + 16 l, so the 256
+// threads move the chunk in NT rounds of 4 KiB with no registers in between.  Offsets past
+// the last chunk are outside the descriptor and read zero.
+template <int NT>
+__device__ __forceinline__ void copy_chunk_lds(Rsrc br, void* lds_buf, int ch) {
+    constexpr int CB = NT * kStageTile;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            br, (__attribute__((address_space(3))) void*)(static_cast<unsigned char*>(lds_buf) + (j * 256 + 64 * wave) * 16),
+            16, (int)((unsigned)ch * CB + (j * 256 + threadIdx.x) * 16u), 0, 0, 0);
+}
 
 // B operands are staged in LDS in MFMA order: value s (0..3) of lane l for sub-step ss and
 // column tile t sits at ((ss * NT + t) * 64 + l) * 4 + s, so a wave reads its operands with
@@ -78,6 +119,58 @@ __device__ __forceinline__ void stage_pair(T* buf, int ss, int r8, int cl, doubl
             dst[0] = (T)(q ? im : re);
             dst[1] = (T)(q ? -re : im);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Forward B operand of the bf16 kernels, staged once per apply.  Every x tile of a k uses the
+// same psi chunk, so the chunk is split into bf16 hi + residual and laid out here, in exactly
+// the byte order of the kernel's LDS buffer, for all (k, band chunk): the projection kernel
+// then only copies 16-byte pieces.  One item = one (k, chunk, sub-step, column tile, lane);
+// padding columns and bands are zero.
+// chunk = [hi plane][lo plane], each [ss][t][lane][8] with 16-point sub-steps
+__global__ __launch_bounds__(256) void prep_fwd_b_bf16_kernel(const double2* __restrict__ psi,
+                                                             unsigned char* __restrict__ out, int Nk, int Nb,
+                                                             int Nc, int col0, int ncb, int NT, int nchunks) {
+    constexpr int KC = 32, SS = KC / 16;
+    const int BUF = SS * NT * 64 * 8;  // bf16 values per plane
+    const long long total = (long long)Nk * nchunks * SS * NT * 64;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int lane = (int)(e & 63);
+        long long r = e >> 6;
+        const int t = (int)(r % NT);
+        r /= NT;
+        const int ss = (int)(r % SS);
+        r /= SS;
+        const int ch = (int)(r % nchunks);
+        const int k = (int)(r / nchunks);
+        const int i = lane & 15, kq = lane >> 4;
+        const int jr = 16 * t + i, cl = jr >> 1, q = jr & 1;
+        bf16x8 hv, lv;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) hv[j] = lv[j] = (__bf16)0.f;
+        if (cl < ncb) {
+            const int col = col0 + cl, vv = col / Nc, c = col - vv * Nc;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int n = ch * KC + 16 * ss + 4 * kq + m;
+                if (n < Nb) {
+                    const double2 z = psi[(((size_t)vv * Nk + k) * Nb + n) * Nc + c];
+                    __bf16 h0, l0, h1, l1;
+                    split_d(q ? z.y : z.x, h0, l0);
+                    split_d(q ? z.x : -z.y, h1, l1);
+                    hv[2 * m] = h0;
+                    lv[2 * m] = l0;
+                    hv[2 * m + 1] = h1;
+                    lv[2 * m + 1] = l1;
+                }
+            }
+        }
+        __bf16* dst = reinterpret_cast<__bf16*>(out + ((size_t)k * nchunks + ch) * NT * kStageTile);
+        const int o = ((ss * NT + t) * 64 + lane) * 8;
+        *reinterpret_cast<bf16x8*>(dst + o) = hv;
+        *reinterpret_cast<bf16x8*>(dst + BUF + o) = lv;
     }
 }
 
@@ -351,65 +444,33 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
 }
 
 // ---------------------------------------------------------------------------------------------
-// bf16 matrix-core variants (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  u is stored as a
-// bf16 "hi" plane [k][x][n][re, im] and, in the split mode, a "lo" plane holding the
-// rounding residual u - hi.  The B operand (psi forward, phi' back) is split into hi + lo
-// when it is staged, and the products hi*hi + hi*lo (+ lo*hi in the split mode) are
-// accumulated, so the operand rounding of the dominant terms is compensated.
-// One MFMA contracts 16 complex points: lane l = i + 16 kq holds the 8 slots of points
-// 4 kq .. 4 kq + 3, slot 2 m + p = part p of point m.
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16;
-
-__device__ __forceinline__ v4f mfma_bf16(bf16x8 a, bf16x8 b, v4f c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ void split2(double v, __bf16& hi, __bf16& lo) {
-    hi = (__bf16)(float)v;
-    lo = (__bf16)(float)(v - (double)(float)hi);
-}
-
-// Stage the B values of one complex input at contraction point r16 (0..15 within a
-// sub-step) and local column cl, as hi and lo bf16 planes in MFMA order.
-template <int NT>
-__device__ __forceinline__ void stage_pair_bf16(__bf16* bh, __bf16* bl, int ss, int r16, int cl, double re,
-                                                double im, bool fwd) {
-    const int kq = r16 >> 2, m = r16 & 3;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int jr = 2 * cl + q;
-        const int t = jr >> 4, i = jr & 15;
-        if (t >= NT) continue;
-        const size_t o = ((size_t)(ss * NT + t) * 64 + i + 16 * kq) * 8 + 2 * m;
-        const double v0 = q ? im : re;
-        const double v1 = fwd ? (q ? re : -im) : (q ? -re : im);
-        split2(v0, bh[o], bl[o]);
-        split2(v1, bh[o + 1], bl[o + 1]);
-    }
-}
+// bf16 matrix-core variants (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  u~ is stored as
+// a bf16 hi plane and, in the split mode, a plane holding the rounding residual; the B
+// operand (psi forward, phi' back) is split into hi + residual when it is staged, and the
+// products hi*hi + hi*lo (+ lo*hi in the split mode) are accumulated, so the operand
+// rounding of the dominant terms is compensated.
 
 template <int MS, int NT, bool LO>
 __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
-    const u16* __restrict__ Uh, const u16* __restrict__ Ul, const double2* __restrict__ psi,
-    float2* __restrict__ phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0, int ncb,
-    int x_tiles) {
+    const u16* __restrict__ Uh, const u16* __restrict__ Ul, const unsigned char* __restrict__ bst,
+    float2* __restrict__ phi, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int x_tiles, int nchunks) {
     constexpr int KC = 32, SS = KC / 16;
-    constexpr int BUF = SS * NT * 64 * 8;
-    __shared__ __align__(16) __bf16 sH[2][BUF];
-    __shared__ __align__(16) __bf16 sL[2][BUF];
+    constexpr int BUF = SS * NT * 64 * 8;      // bf16 values per plane
+    constexpr int CB = NT * kStageTile;
+    static_assert(2 * BUF * 2 == CB, "chunk layout");
+    __shared__ __align__(16) __bf16 sB[2][2 * BUF];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
-    const int k = blockIdx.x / x_tiles;
-    const int xt = blockIdx.x - k * x_tiles;
+    const int lblk = xcd_block();
+    const int k = lblk / x_tiles;
+    const int xt = lblk - k * x_tiles;
     const int rowbase = xt * (64 * MS) + wave * (16 * MS);
     const int brow0 = xt * (64 * MS);
     const int brows = min(Nx - brow0, 64 * MS);
     const size_t plane0 = ((size_t)k * Nx + brow0) * Nb * 2;
     const Rsrc urh = make_rsrc(Uh + plane0, (size_t)brows * Nb * 4);
     const Rsrc url = make_rsrc(LO ? Ul + plane0 : Uh + plane0, (size_t)brows * Nb * 4);
-    const Rsrc pr = make_rsrc(psi, (size_t)(col0 + ncb + Nc) / Nc * Nk * Nb * Nc * sizeof(double2));
+    const Rsrc br = make_rsrc(bst + (size_t)k * nchunks * CB, (size_t)nchunks * CB);
     bool rval[MS];
     unsigned urow[MS];
 #pragma unroll
@@ -418,29 +479,9 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
         rval[ms] = row < Nx;
         urow[ms] = (unsigned)((row - brow0) * Nb) * 4u;
     }
-    constexpr int PER = (KC * kColsPerPass + 255) / 256;
-    auto load_p = [&](int n0, double2 (&pv)[PER]) {
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int e = threadIdx.x + 256 * j;
-            const int nl = e / kColsPerPass, cl = e - nl * kColsPerPass;
-            const int n = n0 + nl;
-            const bool ok = nl < KC && cl < ncb && n < Nb;
-            const int col = col0 + cl;
-            const int vv = col / Nc, c = col - vv * Nc;
-            const unsigned off = (unsigned)((((size_t)(vv * Nk + k) * Nb + n) * Nc + c) * sizeof(double2));
-            pv[j] = bload<double2>(pr, ok ? off : kOob);
-        }
-    };
-    auto store_p = [&](int buf, const double2 (&pv)[PER]) {
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int e = threadIdx.x + 256 * j;
-            const int nl = e / kColsPerPass, cl = e - nl * kColsPerPass;
-            if (nl < KC && cl < ncb) stage_pair_bf16<NT>(sH[buf], sL[buf], nl >> 4, nl & 15, cl, pv[j].x, pv[j].y, true);
-        }
-    };
-    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    // A: the four points 4 kq .. 4 kq + 3 of a sub-step are four consecutive bands of row i,
+    // one 16-byte load per plane.  A group that straddles Nb reads into the next row (or the
+    // zeroed padding after the last plane); those values meet zero B entries.
     auto load_a = [&](int n0, u32x4 (&ah)[MS][SS], u32x4 (&al)[MS][SS]) {
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
@@ -455,10 +496,6 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
         }
     };
 
-    for (int e = threadIdx.x; e < 2 * BUF; e += 256) {
-        (&sH[0][0])[e] = (__bf16)0.f;
-        (&sL[0][0])[e] = (__bf16)0.f;
-    }
     v4f acc[MS][NT];
 #pragma unroll
     for (int ms = 0; ms < MS; ++ms)
@@ -466,42 +503,43 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
         for (int t = 0; t < NT; ++t) acc[ms][t] = v4f{0.f, 0.f, 0.f, 0.f};
 
     u32x4 ah[MS][SS], al[MS][SS], ahn[MS][SS], aln[MS][SS];
-    double2 pv[PER];
-    load_p(0, pv);
+    copy_chunk_lds<NT>(br, sB[0], 0);
     load_a(0, ah, al);
     __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    store_p(0, pv);
     int buf = 0;
-    for (int n0 = 0; n0 < Nb; n0 += KC) {
+    for (int n0 = 0, ch = 0; n0 < Nb; n0 += KC, ++ch) {
         __syncthreads();
-        load_p(n0 + KC, pv);
+        // B of the current chunk into registers before the copy into the other buffer
+        bf16x8 bh[SS][NT], bl[SS][NT];
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                bh[ss][t] = *reinterpret_cast<const bf16x8*>(&sB[buf][((ss * NT + t) * 64 + lane) * 8]);
+                bl[ss][t] = *reinterpret_cast<const bf16x8*>(&sB[buf][BUF + ((ss * NT + t) * 64 + lane) * 8]);
+            }
+        copy_chunk_lds<NT>(br, sB[buf ^ 1], ch + 1);
+        __builtin_amdgcn_sched_barrier(0);
         load_a(n0 + KC, ahn, aln);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
-            bf16x8 bh[NT], bl[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                bh[t] = *reinterpret_cast<const bf16x8*>(&sH[buf][((ss * NT + t) * 64 + lane) * 8]);
-                bl[t] = *reinterpret_cast<const bf16x8*>(&sL[buf][((ss * NT + t) * 64 + lane) * 8]);
-            }
 #pragma unroll
             for (int ms = 0; ms < MS; ++ms) {
                 const bf16x8 a_h = __builtin_bit_cast(bf16x8, ah[ms][ss]);
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    acc[ms][t] = mfma_bf16(a_h, bh[t], acc[ms][t]);
-                    acc[ms][t] = mfma_bf16(a_h, bl[t], acc[ms][t]);
+                    acc[ms][t] = mfma_bf16(a_h, bh[ss][t], acc[ms][t]);
+                    acc[ms][t] = mfma_bf16(a_h, bl[ss][t], acc[ms][t]);
                 }
                 if (LO) {
                     const bf16x8 a_l = __builtin_bit_cast(bf16x8, al[ms][ss]);
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) acc[ms][t] = mfma_bf16(a_l, bh[t], acc[ms][t]);
+                    for (int t = 0; t < NT; ++t) acc[ms][t] = mfma_bf16(a_l, bh[ss][t], acc[ms][t]);
                 }
             }
         }
-        store_p(buf ^ 1, pv);
+        wait_vmcnt<MS * SS * (LO ? 2 : 1)>();
 #pragma unroll
         for (int ms = 0; ms < MS; ++ms)
 #pragma unroll
@@ -527,6 +565,9 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
         }
 }
 
+// Staging item = (column cl, lane group kq, sub-step ss): the four points of that lane group
+// are loaded once, split into bf16 hi + residual, and written as the 16-byte slots of lanes
+// 2 cl and 2 cl + 1 in both planes.
 template <int NT, int W, bool LO>
 __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
     const u16* __restrict__ UTh, const u16* __restrict__ UTl, const float2* __restrict__ phi,
@@ -534,8 +575,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
     int band_blocks, int S, int chunk) {
     constexpr int XT = 64, SS = XT / 16;
     constexpr int BUF = SS * NT * 64 * 8;
-    __shared__ __align__(16) __bf16 sH[2][BUF];
-    __shared__ __align__(16) __bf16 sL[2][BUF];
+    __shared__ __align__(16) __bf16 sB[2][2 * BUF];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
     int blk = blockIdx.x;
@@ -553,54 +593,76 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
     const Rsrc urh = make_rsrc(UTh + plane0, (size_t)Nb * NxP * 4);
     const Rsrc url = make_rsrc(LO ? UTl + plane0 : UTh + plane0, (size_t)Nb * NxP * 4);
     const int xb0 = x_begin / kXB;
-    const float2* pbase = phi + (size_t)xb0 * Nk * kXB * cols;
-    const Rsrc prs = make_rsrc(pbase, (size_t)((x_end - 1) / kXB - xb0 + 1) * Nk * kXB * cols * sizeof(float2));
+    const size_t pbase_i = (size_t)xb0 * Nk * kXB * cols;
+    const Rsrc prs = make_rsrc(phi + pbase_i, (size_t)((x_end - 1) / kXB - xb0 + 1) * Nk * kXB * cols * sizeof(float2));
 
-    constexpr int PER = (XT * kColsPerPass + 64 * W - 1) / (64 * W);
-    auto load_b = [&](int x0, float2 (&bv)[PER]) {
+    constexpr int NITEM = kColsPerPass * 4 * SS;
+    constexpr int PER = (NITEM + 64 * W - 1) / (64 * W);
+    auto load_b = [&](int x0, float2 (&bv)[PER][4]) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 64 * W * j;
-            const int xl = e / kColsPerPass, cl = e - xl * kColsPerPass;
-            const int x = x0 + xl;
-            const bool ok = xl < XT && cl < ncb && x < x_end;
-            const unsigned off = (unsigned)((phi_index_x(x, col0 + cl, k, Nk, cols) - (size_t)xb0 * Nk * kXB * cols) * sizeof(float2));
-            bv[j] = bload<float2>(prs, ok ? off : kOob);
+            const int cl = e % kColsPerPass, rest = e / kColsPerPass;
+            const int iq = rest & 3, ss = rest >> 2;
+            const bool item = e < NITEM && cl < ncb;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int x = x0 + 16 * ss + 4 * iq + m;
+                const bool ok = item && x < x_end;
+                const unsigned off = (unsigned)((phi_index_x(x, col0 + cl, k, Nk, cols) - pbase_i) * sizeof(float2));
+                bv[j][m] = bload<float2>(prs, ok ? off : kOob);
+            }
         }
     };
-    auto store_b = [&](int buf, const float2 (&bv)[PER]) {
+    auto store_b = [&](int buf, const float2 (&bv)[PER][4]) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 64 * W * j;
-            const int xl = e / kColsPerPass, cl = e - xl * kColsPerPass;
-            if (xl < XT && cl < ncb) stage_pair_bf16<NT>(sH[buf], sL[buf], xl >> 4, xl & 15, cl, bv[j].x, bv[j].y, false);
+            const int cl = e % kColsPerPass, rest = e / kColsPerPass;
+            const int iq = rest & 3, ss = rest >> 2;
+            if (e >= NITEM || cl >= ncb) continue;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int jr = 2 * cl + q, t = jr >> 4;
+                if (t >= NT) continue;
+                bf16x8 hv, lv;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    __bf16 h0, l0, h1, l1;
+                    split_f(q ? bv[j][m].y : bv[j][m].x, h0, l0);
+                    split_f(q ? -bv[j][m].x : bv[j][m].y, h1, l1);
+                    hv[2 * m] = h0;
+                    lv[2 * m] = l0;
+                    hv[2 * m + 1] = h1;
+                    lv[2 * m + 1] = l1;
+                }
+                const int o = ((ss * NT + t) * 64 + (jr & 15) + 16 * iq) * 8;
+                *reinterpret_cast<bf16x8*>(&sB[buf][o]) = hv;
+                *reinterpret_cast<bf16x8*>(&sB[buf][BUF + o]) = lv;
+            }
         }
     };
     // A: the four points 4 kq .. 4 kq + 3 of sub-step ss are consecutive x of row n of the
     // transposed plane, one 16-byte load.  x_begin and chunk are multiples of 8, so a group
     // never crosses a chunk end; past Nx it reads the zero row padding.
-    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
     auto load_a = [&](int x0, u32x4 (&ah)[SS], u32x4 (&al)[SS]) {
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
             const int x = x0 + 16 * ss + 4 * kq;
             const bool ok = nval && x < x_end;
-            const unsigned off = ok ? (unsigned)((n * NxP + x) * 4) : kOob;
+            const unsigned off = ok ? ((unsigned)n * (unsigned)NxP + (unsigned)x) * 4u : kOob;
             ah[ss] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(urh, (int)off, 0, 0));
             if (LO) al[ss] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(url, (int)off, 0, 0));
         }
     };
 
-    for (int e = threadIdx.x; e < 2 * BUF; e += 64 * W) {
-        (&sH[0][0])[e] = (__bf16)0.f;
-        (&sL[0][0])[e] = (__bf16)0.f;
-    }
+    for (int e = threadIdx.x; e < 4 * BUF; e += 64 * W) (&sB[0][0])[e] = (__bf16)0.f;
     v4f acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
 
     u32x4 ah[SS], al[SS], ahn[SS], aln[SS];
-    float2 bl[PER];
+    float2 bl[PER][4];
     load_b(x_begin, bl);
     load_a(x_begin, ah, al);
     __builtin_amdgcn_s_waitcnt(0);
@@ -617,14 +679,11 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
             const bf16x8 a_h = __builtin_bit_cast(bf16x8, ah[ss]);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const bf16x8 b_h = *reinterpret_cast<const bf16x8*>(&sH[buf][((ss * NT + t) * 64 + lane) * 8]);
-                const bf16x8 b_l = *reinterpret_cast<const bf16x8*>(&sL[buf][((ss * NT + t) * 64 + lane) * 8]);
+                const bf16x8 b_h = *reinterpret_cast<const bf16x8*>(&sB[buf][((ss * NT + t) * 64 + lane) * 8]);
+                const bf16x8 b_l = *reinterpret_cast<const bf16x8*>(&sB[buf][BUF + ((ss * NT + t) * 64 + lane) * 8]);
                 acc[t] = mfma_bf16(a_h, b_h, acc[t]);
                 acc[t] = mfma_bf16(a_h, b_l, acc[t]);
-                if (LO) {
-                    const bf16x8 a_l = __builtin_bit_cast(bf16x8, al[ss]);
-                    acc[t] = mfma_bf16(a_l, b_h, acc[t]);
-                }
+                if (LO) acc[t] = mfma_bf16(__builtin_bit_cast(bf16x8, al[ss]), b_h, acc[t]);
             }
         }
         store_b(buf ^ 1, bl);
@@ -666,8 +725,8 @@ __global__ __launch_bounds__(256) void u_to_bf16_kernel(const double* __restrict
         const double re = src[2 * e], im = src[2 * e + 1];
         const double vr = re * ph.x - im * ph.y, vi = re * ph.y + im * ph.x;
         __bf16 h0, l0, h1, l1;
-        split2(vr, h0, l0);
-        split2(vi, h1, l1);
+        split_d(vr, h0, l0);
+        split_d(vi, h1, l1);
         const size_t o = 2 * ((size_t)g * Nb + n);
         const long long k = g / Nx;
         const int x = (int)(g - k * Nx);
@@ -764,14 +823,13 @@ void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk) {
 }
 
 template <int MS, bool LO>
-hipError_t fwd_bf16_nt(int NT, dim3 grid, hipStream_t st, const u16* uh, const u16* ul, const double* x,
-                       void* phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0, int ncb, int x_tiles) {
-    const double2* ps = reinterpret_cast<const double2*>(x);
+hipError_t fwd_bf16_nt(int NT, dim3 grid, hipStream_t st, const u16* uh, const u16* ul, const unsigned char* bst,
+                       void* phi, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int x_tiles, int nchunks) {
     float2* p = static_cast<float2*>(phi);
     switch (NT) {
-        case 1: proj_fwd_bf16_kernel<MS, 1, LO><<<grid, 256, 0, st>>>(uh, ul, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
-        case 2: proj_fwd_bf16_kernel<MS, 2, LO><<<grid, 256, 0, st>>>(uh, ul, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
-        default: proj_fwd_bf16_kernel<MS, 3, LO><<<grid, 256, 0, st>>>(uh, ul, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
+        case 1: proj_fwd_bf16_kernel<MS, 1, LO><<<grid, 256, 0, st>>>(uh, ul, bst, p, Nk, Nx, Nb, cols, col0, ncb, x_tiles, nchunks); break;
+        case 2: proj_fwd_bf16_kernel<MS, 2, LO><<<grid, 256, 0, st>>>(uh, ul, bst, p, Nk, Nx, Nb, cols, col0, ncb, x_tiles, nchunks); break;
+        default: proj_fwd_bf16_kernel<MS, 3, LO><<<grid, 256, 0, st>>>(uh, ul, bst, p, Nk, Nx, Nb, cols, col0, ncb, x_tiles, nchunks); break;
     }
     return hipGetLastError();
 }
@@ -807,25 +865,43 @@ bool is_bf16_mode(int precision) {
     return precision == OCEAN_PREC_SPLIT_BF16 || precision == OCEAN_PREC_BF16;
 }
 
+int fwd_band_chunk(const ocean_bse_s* h) { return is_bf16_mode(h->precision) ? 32 : 0; }
+
 hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, int ncb) {
     const int MS = h->fwd_ms == 1 ? 1 : 2;   // 16 * MS rows per wave, 64 * MS per block
     const int cols = nv * h->Nc;
     const int NT = (2 * ncb + 15) / 16;
     const int x_tiles = (h->Nx + 64 * MS - 1) / (64 * MS);
     dim3 grid((unsigned)(h->Nk * x_tiles));
-    const int slot = prof_begin(h, "proj_fwd");
     hipError_t e;
     if (is_bf16_mode(h->precision)) {
+        // stage the B operand of this pass once for all (k, band chunk)
+        const int KC = fwd_band_chunk(h);
+        const int nchunks = (h->Nb + KC - 1) / KC;
+        int slot = prof_begin(h, "prep_b");
+        const long long items = (long long)h->Nk * nchunks * (KC / 16) * NT * 64;
+        const unsigned nblk = (unsigned)std::min<long long>((items + 255) / 256, 16384);
+        prep_fwd_b_bf16_kernel<<<nblk, 256, 0, h->stream>>>(reinterpret_cast<const double2*>(x), h->ws.bst, h->Nk,
+                                                            h->Nb, h->Nc, col0, ncb, NT, nchunks);
+        e = hipGetLastError();
+        prof_end(h, slot);
+        if (e != hipSuccess) return e;
+        slot = prof_begin(h, "proj_fwd");
         const u16* uh = reinterpret_cast<const u16*>(h->Ubf);
         const u16* ul = uh + (size_t)2 * h->Nk * h->Nx * h->Nb;
+        const unsigned char* bst = h->ws.bst;
         const bool lo = h->precision == OCEAN_PREC_SPLIT_BF16;
         if (MS == 1)
-            e = lo ? fwd_bf16_nt<1, true>(NT, grid, h->stream, uh, ul, x, h->ws.phi, h->Nk, h->Nx, h->Nb, h->Nc, cols, col0, ncb, x_tiles)
-                   : fwd_bf16_nt<1, false>(NT, grid, h->stream, uh, ul, x, h->ws.phi, h->Nk, h->Nx, h->Nb, h->Nc, cols, col0, ncb, x_tiles);
+            e = lo ? fwd_bf16_nt<1, true>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks)
+                   : fwd_bf16_nt<1, false>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks);
         else
-            e = lo ? fwd_bf16_nt<2, true>(NT, grid, h->stream, uh, ul, x, h->ws.phi, h->Nk, h->Nx, h->Nb, h->Nc, cols, col0, ncb, x_tiles)
-                   : fwd_bf16_nt<2, false>(NT, grid, h->stream, uh, ul, x, h->ws.phi, h->Nk, h->Nx, h->Nb, h->Nc, cols, col0, ncb, x_tiles);
-    } else if (h->precision == OCEAN_PREC_FP64)
+            e = lo ? fwd_bf16_nt<2, true>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks)
+                   : fwd_bf16_nt<2, false>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks);
+        prof_end(h, slot);
+        return e;
+    }
+    const int slot = prof_begin(h, "proj_fwd");
+    if (h->precision == OCEAN_PREC_FP64)
         e = MS == 1 ? fwd_dispatch_nt<double, 1>(NT, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
                                                  h->Nb, h->Nc, cols, col0, ncb, x_tiles)
                     : fwd_dispatch_nt<double, 2>(NT, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,

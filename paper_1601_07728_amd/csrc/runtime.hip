@@ -138,7 +138,9 @@ static void release_workspace(ocean_bse_s* h) {
     if (w.loc_part) (void)hipFree(w.loc_part);
     if (w.loc_b) (void)hipFree(w.loc_b);
     if (w.w0) (void)hipFree(w.w0);
+    if (w.bst) (void)hipFree(w.bst);
     w.part = w.loc_part = w.loc_b = w.w0 = nullptr;
+    w.bst = nullptr;
     h->device_bytes -= w.bytes;
     w.bytes = 0;
     w.cols = 0;
@@ -166,7 +168,9 @@ static int ensure_workspace(ocean_bse_s* h, int nv) {
     const size_t locp_b = (size_t)local_blocks(h) * nv * NP * 16;
     const size_t locb_b = (size_t)nv * NP * 16;
     const size_t w0_b = (size_t)h->Nk * h->Nb * cols * 16;
-    const size_t total = phi_b + part_b + locp_b + locb_b + w0_b;
+    const int kc = fwd_band_chunk(h);  // 0: this precision stages its B operand in-kernel
+    const size_t bst_b = kc > 0 ? (size_t)h->Nk * ((h->Nb + kc - 1) / kc) * 3 * kStageTile : 0;
+    const size_t total = phi_b + part_b + locp_b + locb_b + w0_b + bst_b;
     if (h->device_bytes + total > max_device_bytes()) {
         set_error("device memory cap (OCEAN_MAX_DEVICE_BYTES) exceeded allocating the H*v workspace");
         return OCEAN_ERR_OUT_OF_MEMORY;
@@ -183,6 +187,10 @@ static int ensure_workspace(ocean_bse_s* h, int nv) {
     w.loc_b = static_cast<double*>(p);
     if (hipMalloc(&p, w0_b) != hipSuccess) goto oom;
     w.w0 = static_cast<double*>(p);
+    if (bst_b > 0) {
+        if (hipMalloc(&p, bst_b) != hipSuccess) goto oom;
+        w.bst = static_cast<unsigned char*>(p);
+    }
     w.bytes = total;
     h->device_bytes += total;
     w.cols = cols;
@@ -194,8 +202,10 @@ oom:
     if (w.part) (void)hipFree(w.part);
     if (w.loc_part) (void)hipFree(w.loc_part);
     if (w.loc_b) (void)hipFree(w.loc_b);
+    if (w.w0) (void)hipFree(w.w0);
     w.phi = nullptr;
     w.part = w.loc_part = w.loc_b = w.w0 = nullptr;
+    w.bst = nullptr;
     w.bytes = 0;
     w.cols = 0;
     set_error("hipMalloc failed for the H*v workspace (" + std::to_string(total) + " bytes)");

@@ -518,7 +518,7 @@ __global__ __launch_bounds__(256) void reduce_part_kernel(const double2* __restr
 }
 
 // Gamma-point-only grids: the k-grid transform is the identity and W(x, R = 0) is diagonal
-// in x, so Algorithm 1 lines 3-5 reduce to phi[x][col] *= W[x].
+// in x, so the transform and W steps of Algorithm 1 reduce to phi[x][col] *= W[x].
 template <typename C2, typename T>
 __global__ __launch_bounds__(256) void w_gamma_kernel(C2* __restrict__ phi, const T* __restrict__ W,
                                                      long long n_elem, int cols) {
