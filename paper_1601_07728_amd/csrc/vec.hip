@@ -40,56 +40,84 @@ __device__ double2 block_sum2(double2 v, double* sh) {
 }
 
 // ---- local term --------------------------------------------------------------------------------
-// part[b][v][c*Nmu+mu] = sum_{kn in block b} A[kn][mu] x[v][kn][c]
+// part[blk][v][c*Nmu+mu] = sum_{kn in rows of blk} A[kn][mu] x[v][kn][c].  A block takes
+// kLocRows consecutive (k, n) rows: the A rows and, per vector, the x rows go to LDS with
+// coalesced loads, then thread (pair, g) sums the rows r = g, g + G, ... of its (c, mu) pair
+// and the G partial sums are added in a fixed order.
+constexpr int kLocRows = 128;
+
 __global__ __launch_bounds__(256) void local_in_kernel(const double2* __restrict__ x,
                                                        const double2* __restrict__ A,
                                                        double2* __restrict__ part, int nv,
-                                                       long long NkNb, int Nc, int Nmu,
-                                                       long long chunk) {
+                                                       long long NkNb, int Nc, int Nmu) {
+    __shared__ double2 sA[kLocRows * kMaxLocal];
+    __shared__ double2 sX[kLocRows * kMaxCore];
     __shared__ double2 red[256];
     const int NP = Nc * Nmu;
     const int G = 256 / NP;
     const int t = threadIdx.x;
     const int pair = t % NP, g = t / NP;
     const int c = pair / Nmu, mu = pair - c * Nmu;
-    const long long kn0 = (long long)blockIdx.x * chunk;
-    const long long kn1 = min(NkNb, kn0 + chunk);
+    const long long r0 = (long long)blockIdx.x * kLocRows;
+    const int rows = (int)min((long long)kLocRows, NkNb - r0);
+    for (int e = t; e < kLocRows * Nmu; e += 256)
+        sA[e] = e < rows * Nmu ? A[r0 * Nmu + e] : make_double2(0.0, 0.0);
     for (int v = 0; v < nv; ++v) {
+        const double2* xv = x + ((size_t)v * NkNb + r0) * Nc;
+        for (int e = t; e < kLocRows * Nc; e += 256) sX[e] = e < rows * Nc ? xv[e] : make_double2(0.0, 0.0);
+        __syncthreads();
         double2 acc = make_double2(0.0, 0.0);
-        if (g < G) {
-            const double2* xv = x + (size_t)v * NkNb * Nc;
-            for (long long kn = kn0 + g; kn < kn1; kn += G)
-                acc = cadd(acc, cmul(A[kn * Nmu + mu], xv[kn * Nc + c]));
-        }
+        if (g < G)
+            for (int r = g; r < rows; r += G) acc = cadd(acc, cmul(sA[r * Nmu + mu], sX[r * Nc + c]));
         red[t] = acc;
         __syncthreads();
         if (t < NP) {
-            double2 s = red[t];
-            for (int gg = 1; gg < G; ++gg) s = cadd(s, red[gg * NP + t]);
-            part[((size_t)blockIdx.x * nv + v) * NP + t] = s;
+            double2 sum = red[t];
+            for (int gg = 1; gg < G; ++gg) sum = cadd(sum, red[gg * NP + t]);
+            part[((size_t)blockIdx.x * nv + v) * NP + t] = sum;
         }
         __syncthreads();
     }
 }
 
-// b = sum over blocks; b' = K b
-__global__ __launch_bounds__(128) void local_mat_kernel(const double2* __restrict__ part,
-                                                        const double2* __restrict__ K,
-                                                        double2* __restrict__ bprime, int nv,
-                                                        int NP, int nblk) {
+// b = sum over blocks (group g of pair p adds blocks g, g + G, ... in that order, eight loads
+// in flight at a time; then the groups in order); b' = K b
+__global__ __launch_bounds__(1024) void local_mat_kernel(const double2* __restrict__ part,
+                                                         const double2* __restrict__ K,
+                                                         double2* __restrict__ bprime, int nv,
+                                                         int NP, int nblk) {
+    __shared__ double2 red[1024];
     __shared__ double2 bsh[kMaxPairs];
     const int v = blockIdx.x;
     const int t = threadIdx.x;
+    const int G = 1024 / NP;
+    const int p = t % NP, g = t / NP;
+    double2 s = make_double2(0.0, 0.0);
+    if (g < G) {
+        for (int b0 = g; b0 < nblk; b0 += 8 * G) {
+            double2 q[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + u * G;
+                q[u] = b < nblk ? part[((size_t)b * nv + v) * NP + p] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (b0 + u * G < nblk) s = cadd(s, q[u]);
+        }
+    }
+    red[t] = s;
+    __syncthreads();
     if (t < NP) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int b = 0; b < nblk; ++b) s = cadd(s, part[((size_t)b * nv + v) * NP + t]);
-        bsh[t] = s;
+        double2 sum = red[t];
+        for (int gg = 1; gg < G; ++gg) sum = cadd(sum, red[gg * NP + t]);
+        bsh[t] = sum;
     }
     __syncthreads();
     if (t < NP) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int p = 0; p < NP; ++p) s = cadd(s, cmul(K[(size_t)t * NP + p], bsh[p]));
-        bprime[(size_t)v * NP + t] = s;
+        double2 o = make_double2(0.0, 0.0);
+        for (int qq = 0; qq < NP; ++qq) o = cadd(o, cmul(K[(size_t)t * NP + qq], bsh[qq]));
+        bprime[(size_t)v * NP + t] = o;
     }
 }
 
@@ -176,9 +204,18 @@ __global__ __launch_bounds__(256) void lz_dot_partial_kernel(const double2* __re
     if (threadIdx.x == 0) part[(size_t)v * gridDim.x + blockIdx.x] = s;
 }
 
+// Sum of nblk <= 256 block partials, computed by every lane of the calling wave (all 64 lanes
+// must be active): lane l adds part[l], part[l + 64], ... in order, then a fixed xor-shuffle
+// tree combines the lanes.  Every wave and every run gets the same bits.
+static_assert(kRedBlocks <= 256, "sum_parts reads at most 256 partials");
 __device__ __forceinline__ double sum_parts(const double* part, int nblk) {
+    const int l = threadIdx.x & 63;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[b];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (l + 64 * u < nblk) s += part[l + 64 * u];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     return s;
 }
 
@@ -322,11 +359,12 @@ __global__ __launch_bounds__(64) void lz_finalize_kernel(const double* __restric
                                                          const int* __restrict__ step, int n_steps,
                                                          int nblk) {
     const int v = blockIdx.x;
+    const double b2 = sum_parts(part_n + (size_t)v * nblk, nblk);  // the whole wave
     if (threadIdx.x != 0) return;
     LzState s = st[v];
     if (s.done) return;
     const int i = *step;
-    const double b = sqrt(sum_parts(part_n + (size_t)v * nblk, nblk));
+    const double b = sqrt(b2);
     s.scale = fmax(s.scale, fmax(fabs(s.a_cur), s.b_cur));
     b_out[(size_t)v * n_steps + i] = b;
     s.steps = i + 1;
@@ -539,25 +577,23 @@ inline long long per_block(long long dim) { return (dim + kRedBlocks - 1) / kRed
 // ---- launchers ---------------------------------------------------------------------------------------------
 long long local_blocks(const ocean_bse_s* h) {
     const long long NkNb = (long long)h->Nk * h->Nb;
-    long long nb = (NkNb + 255) / 256;
-    return nb < 120 ? nb : 120;
+    return (NkNb + kLocRows - 1) / kLocRows;
 }
 
 hipError_t launch_local_in(ocean_bse_s* h, const double* x, int nv) {
     const long long NkNb = (long long)h->Nk * h->Nb;
     const long long nblk = local_blocks(h);
-    const long long chunk = (NkNb + nblk - 1) / nblk;
     const int slot = prof_begin(h, "local_in");
     local_in_kernel<<<(unsigned)nblk, 256, 0, h->stream>>>(
         reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(h->A),
-        reinterpret_cast<double2*>(h->ws.loc_part), nv, NkNb, h->Nc, h->Nmu, chunk);
+        reinterpret_cast<double2*>(h->ws.loc_part), nv, NkNb, h->Nc, h->Nmu);
     prof_end(h, slot);
     return hipGetLastError();
 }
 
 hipError_t launch_local_mat(ocean_bse_s* h, int nv) {
     const int slot = prof_begin(h, "local_mat");
-    local_mat_kernel<<<nv, 128, 0, h->stream>>>(reinterpret_cast<const double2*>(h->ws.loc_part),
+    local_mat_kernel<<<nv, 1024, 0, h->stream>>>(reinterpret_cast<const double2*>(h->ws.loc_part),
                                                 reinterpret_cast<const double2*>(h->K),
                                                 reinterpret_cast<double2*>(h->ws.loc_b), nv,
                                                 h->Nc * h->Nmu, (int)local_blocks(h));
