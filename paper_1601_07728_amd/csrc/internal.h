@@ -20,7 +20,9 @@ constexpr int kMaxDft = 16;     // largest k-grid extent per axis
 constexpr int kColsPerPass = 24;  // exciton columns per projection launch (3 MFMA column tiles)
 constexpr int kRedBlocks = 240;   // blocks per vector in the Lanczos reductions
 constexpr int kXB = 16;           // x-block of the phi work array (a power of two: phi_index_x)
-constexpr int kStageTile = 4096;  // bytes of one staged B chunk per 16-wide column tile
+constexpr int kStageTile = 4096;
+constexpr int kCombineDirectChunks = 4;  // up to this many x chunks the combine pass sums the
+                                          // back-projection partials itself  // bytes of one staged B chunk per 16-wide column tile
 
 // phi work array layout: [x / kXB][k][x % kXB][col] (complex).  A "line" is
 // line = x * cols + col; for a fixed k the lines of one x-block are contiguous,

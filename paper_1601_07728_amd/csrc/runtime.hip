@@ -223,7 +223,7 @@ static int apply_pipeline(ocean_bse_s* h, const double* x, double* y, int nv, do
         OCEAN_HIP(launch_fft_w(h, cols), "fft_w launch");
     for (int c0 = 0; c0 < cols; c0 += kColsPerPass)
         OCEAN_HIP(launch_proj_bwd(h, nv, c0, std::min(kColsPerPass, cols - c0)), "proj_bwd launch");
-    OCEAN_HIP(launch_reduce_part(h, nv), "reduce_part launch");
+    if (h->ws.bwd_chunks > kCombineDirectChunks) OCEAN_HIP(launch_reduce_part(h, nv), "reduce_part launch");
     if (h->Nmu > 0 && h->K != nullptr) {
         OCEAN_HIP(launch_local_in(h, x, nv), "local_in launch");
         OCEAN_HIP(launch_local_mat(h, nv), "local_mat launch");

@@ -122,51 +122,46 @@ __global__ __launch_bounds__(1024) void local_mat_kernel(const double2* __restri
 }
 
 // ---- combine: y = E x + Hc x + conj(A) b' - sum_s part[s] -----------------------------------------
-// One thread per (v, k, n).  Optionally also the per-block partial of Re<x|y> for Lanczos.
+// One thread per element (k, n, c) of vector v = blockIdx.y; block b covers elements
+// [b per, (b + 1) per) of that vector, so each vector's dot partials are contiguous.  The
+// back-projection partials of the S x chunks are added in chunk order.  Optionally also the
+// block partial of Re<x|y> for Lanczos.
 __global__ __launch_bounds__(256) void combine_kernel(
     const double2* __restrict__ x, double2* __restrict__ y, const double* __restrict__ E,
     const double2* __restrict__ Hc, const double2* __restrict__ A, const double2* __restrict__ bprime,
     const double2* __restrict__ part, int S, int nv, long long NkNb, int Nc, int Nmu, int has_core,
-    int has_w, double* __restrict__ dot_part, long long per_block) {
+    double* __restrict__ dot_part, long long per_block) {
     __shared__ double sh[256];
-    const long long total = (long long)nv * NkNb;
+    __shared__ double2 sHc[kMaxCore * kMaxCore];
+    __shared__ double2 sB[kMaxPairs];
     const int cols = nv * Nc;
-    double dot = 0.0;
-    // blocks are laid out [v][block-in-vector] so each vector's dot partials are contiguous
     const int v = blockIdx.y;
+    for (int e = threadIdx.x; e < Nc * Nc; e += blockDim.x) sHc[e] = has_core ? Hc[e] : make_double2(0.0, 0.0);
+    for (int e = threadIdx.x; e < Nc * Nmu; e += blockDim.x) sB[e] = bprime[(size_t)v * Nc * Nmu + e];
+    __syncthreads();
+    const long long n_el = NkNb * Nc;
     const long long start = (long long)blockIdx.x * per_block;
-    const long long stop = min(NkNb, start + per_block);
-    for (long long kn = start + threadIdx.x; kn < stop; kn += blockDim.x) {
-        const size_t base = ((size_t)v * NkNb + kn) * Nc;
-        double2 xv[kMaxCore];
-#pragma unroll
-        for (int c = 0; c < kMaxCore; ++c)
-            if (c < Nc) xv[c] = x[base + c];
-        const double e = E[kn];
-#pragma unroll
-        for (int c = 0; c < kMaxCore; ++c) {
-            if (c >= Nc) break;
-            double2 acc = make_double2(e * xv[c].x, e * xv[c].y);
-            if (has_core) {
-#pragma unroll
-                for (int d = 0; d < kMaxCore; ++d)
-                    if (d < Nc) acc = cadd(acc, cmul(Hc[c * Nc + d], xv[d]));
-            }
-            if (Nmu > 0) {
-                const double2* bp = bprime + ((size_t)v * Nc + c) * Nmu;
-                for (int mu = 0; mu < Nmu; ++mu) acc = cadd(acc, cmulc(A[kn * Nmu + mu], bp[mu]));
-            }
-            if (has_w) {
-                double2 w0 = make_double2(0.0, 0.0);
-                for (int s = 0; s < S; ++s) w0 = cadd(w0, part[((size_t)s * NkNb + kn) * cols + v * Nc + c]);
-                acc.x -= w0.x;
-                acc.y -= w0.y;
-            }
-            y[base + c] = acc;
-            dot += xv[c].x * acc.x + xv[c].y * acc.y;
+    const long long stop = min(n_el, start + per_block);
+    const double2* xv = x + (size_t)v * n_el;
+    double dot = 0.0;
+    for (long long e = start + threadIdx.x; e < stop; e += blockDim.x) {
+        const long long kn = e / Nc;
+        const int c = (int)(e - kn * Nc);
+        const double2 xe = xv[e];
+        const double en = E[kn];
+        double2 acc = make_double2(en * xe.x, en * xe.y);
+        if (has_core) {
+            const double2* xrow = xv + kn * Nc;
+            for (int d = 0; d < Nc; ++d) acc = cadd(acc, cmul(sHc[c * Nc + d], xrow[d]));
         }
+        for (int mu = 0; mu < Nmu; ++mu) acc = cadd(acc, cmulc(A[kn * Nmu + mu], sB[c * Nmu + mu]));
+        double2 w0 = make_double2(0.0, 0.0);
+        for (int sc = 0; sc < S; ++sc) w0 = cadd(w0, part[((size_t)sc * NkNb + kn) * cols + v * Nc + c]);
+        acc.x -= w0.x;
+        acc.y -= w0.y;
+        y[(size_t)v * n_el + e] = acc;
+        dot += xe.x * acc.x + xe.y * acc.y;
     }
-    (void)total;
     if (dot_part != nullptr) {
         const double s = block_sum(dot, sh);
         if (threadIdx.x == 0) dot_part[(size_t)v * gridDim.x + blockIdx.x] = s;
@@ -624,16 +619,18 @@ hipError_t launch_w_gamma(ocean_bse_s* h, int cols) {
 }
 
 hipError_t launch_combine(ocean_bse_s* h, const double* x, double* y, int nv, double* dot_part) {
-    const long long NkNb = (long long)h->Nk * h->Nb;
-    const long long per = (NkNb + kRedBlocks - 1) / kRedBlocks;
+    const long long n_el = (long long)h->Nk * h->Nb * h->Nc;
+    const long long per = (n_el + kRedBlocks - 1) / kRedBlocks;
     dim3 grid(kRedBlocks, nv);
-    const int has_w = 1;
+    // few x chunks: read the back-projection partials here; many: from their sum
+    const bool direct = h->ws.bwd_chunks <= kCombineDirectChunks;
     const int slot = prof_begin(h, "combine");
     combine_kernel<<<grid, 256, 0, h->stream>>>(
         reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), h->E,
         reinterpret_cast<const double2*>(h->Hc), reinterpret_cast<const double2*>(h->A),
-        reinterpret_cast<const double2*>(h->ws.loc_b), reinterpret_cast<const double2*>(h->ws.w0),
-        1, nv, NkNb, h->Nc, h->Nmu, h->Hc != nullptr, has_w, dot_part, per);
+        reinterpret_cast<const double2*>(h->ws.loc_b),
+        reinterpret_cast<const double2*>(direct ? h->ws.part : h->ws.w0), direct ? h->ws.bwd_chunks : 1, nv,
+        (long long)h->Nk * h->Nb, h->Nc, h->Nmu > 0 && h->K != nullptr ? h->Nmu : 0, h->Hc != nullptr, dot_part, per);
     prof_end(h, slot);
     return hipGetLastError();
 }
