@@ -69,26 +69,26 @@ def proj_bytes(cr, cols, u_elem, phi_elem):
 # WRITE_SIZE 1.0 GiB for 1 GiB written).  A figure holds only for the kernel source it was
 # taken with (sha256 of the .hip file); for any other source the traffic is reported null.
 TRAFFIC = {
-    ("fp64", "proj_bwd"): {"bytes": 7535475292, "src": "proj.hip",
-        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
-    ("fp64", "proj_fwd"): {"bytes": 7589273278, "src": "proj.hip",
-        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
-    ("fp32", "proj_bwd"): {"bytes": 3796823115, "src": "proj.hip",
-        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
-    ("fp32", "proj_fwd"): {"bytes": 3849083002, "src": "proj.hip",
-        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
-    ("split_bf16", "proj_bwd"): {"bytes": 3931744257, "src": "proj.hip",
-        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
-    ("split_bf16", "proj_fwd"): {"bytes": 3849136248, "src": "proj.hip",
-        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
-    ("bf16", "proj_bwd"): {"bytes": 2260313423, "src": "proj.hip",
-        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
-    ("bf16", "proj_fwd"): {"bytes": 2333645932, "src": "proj.hip",
-        "sha256": "806e7ebac28c6a075b1f986498b7e46950a039a0a3772fa79a9ebbd0778c6cf3"},
-    ("fp64", "fft_w"): {"bytes": 2392631539, "src": "fftw.hip",
-        "sha256": "f00fa72c15c460b1e922810cd0d049cec425aff65b64428b192d46ce5979f90d"},
-    ("fp32", "fft_w"): {"bytes": 1224824029, "src": "fftw.hip",
-        "sha256": "f00fa72c15c460b1e922810cd0d049cec425aff65b64428b192d46ce5979f90d"},
+    ("fp64", "proj_fwd"): {"bytes": 7589081753, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 3, 16>
+        "sha256": "baaa90afaf9e5e18a261018ca03bc0b13c98a368c905df6009b7d46cbd3ab2af"},
+    ("fp64", "proj_bwd"): {"bytes": 7535490156, "src": "proj.hip",  # proj_bwd_kernel<double, 3, 32, 6>
+        "sha256": "baaa90afaf9e5e18a261018ca03bc0b13c98a368c905df6009b7d46cbd3ab2af"},
+    ("fp32", "proj_fwd"): {"bytes": 3849091773, "src": "proj.hip",  # proj_fwd_kernel<float, 1, 3, 32>
+        "sha256": "baaa90afaf9e5e18a261018ca03bc0b13c98a368c905df6009b7d46cbd3ab2af"},
+    ("fp32", "proj_bwd"): {"bytes": 3796830825, "src": "proj.hip",  # proj_bwd_kernel<float, 3, 64, 6>
+        "sha256": "baaa90afaf9e5e18a261018ca03bc0b13c98a368c905df6009b7d46cbd3ab2af"},
+    ("split_bf16", "proj_fwd"): {"bytes": 3755327983, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<1, 3, true>
+        "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
+    ("split_bf16", "proj_bwd"): {"bytes": 3927675907, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
+        "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
+    ("bf16", "proj_fwd"): {"bytes": 2184760631, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<2, 3, false>
+        "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
+    ("bf16", "proj_bwd"): {"bytes": 2245180462, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
+        "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
+    ("fp64", "fft_w"): {"bytes": 2392643054, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
+        "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
+    ("fp32", "fft_w"): {"bytes": 1196251897, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
+        "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
 }
 
 

@@ -189,6 +189,9 @@ size_t max_device_bytes();
 // Kernel launchers (each enqueues on h->stream).  Return hipSuccess or the launch error.
 hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, int ncb);
 int fwd_band_chunk(const ocean_bse_s* h);  // bands per staged forward chunk, 0 if not staged
+bool is_bf16_mode(int precision);
+hipError_t launch_proj_fwd_bf16(ocean_bse_s* h, const double* x, int nv, int col0, int ncb);
+hipError_t launch_proj_bwd_bf16(ocean_bse_s* h, int nv, int col0, int ncb);
 hipError_t launch_fft_w(ocean_bse_s* h, int cols);
 hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb);
 hipError_t launch_local_in(ocean_bse_s* h, const double* x, int nv);
