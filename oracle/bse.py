@@ -109,24 +109,23 @@ def dft_matrix(cr):
 # --- Hamiltonian pieces ----------------------------------------------------------------------
 
 def apply_w0(cr, psi, ut=None, w=None, f=None):
-    """W0 psi by Algorithm 1, one core index alpha at a time (the long-range
-    direct term does not mix spin or angular momentum).  psi is [k, n, c]."""
+    """W0 psi by Algorithm 1, every core index alpha at once (the long-range direct term
+    does not mix spin or angular momentum, so alpha is a spectator column).  psi is
+    [k, n, c].  The band sums are matrix products per k."""
     ut = folded_u(cr) if ut is None else ut
     w = w_supercell(cr) if w is None else w
     f = dft_matrix(cr) if f is None else f
-    out = np.zeros_like(psi)
-    for alpha in range(psi.shape[2]):
-        # band -> real space: phi(k) = sum_n psi_{n,k,alpha} e^{ik.x} u_nk(x), for every x at once
-        phi_k = np.einsum("kxn,kn->kx", ut, psi[:, :, alpha])
-        # k -> R: phi(R) = F_{k->R}[phi(k)]
-        phi_r = f @ phi_k
-        # screened potential: phi(R) = W(x, R) phi(R)
-        phi_r = w.T * phi_r
-        # R -> k: phi(k) = F_{R->k}[phi(R)]
-        phi_k = f.conj().T @ phi_r
-        # real space -> band: psi'_{n,k,alpha} += phi(k) e^{-ik.x} u*_nk(x), summed over x
-        out[:, :, alpha] += np.einsum("kx,kxn->kn", phi_k, ut.conj())
-    return out
+    nk = psi.shape[0]
+    # band -> real space: phi(k, x, alpha) = sum_n psi_{n,k,alpha} e^{ik.x} u_nk(x)
+    phi_k = np.stack([ut[k] @ psi[k] for k in range(nk)])            # [k, x, c]
+    # k -> R: phi(R) = F_{k->R}[phi(k)]
+    phi_r = np.einsum("rk,kxc->rxc", f, phi_k)
+    # screened potential: phi(R) = W(x, R) phi(R)
+    phi_r = w.T[:, :, None] * phi_r
+    # R -> k: phi(k) = F_{R->k}[phi(R)]
+    phi_k = np.einsum("kr,rxc->kxc", f.conj().T, phi_r)
+    # real space -> band: psi'_{n,k,alpha} = sum_x conj(e^{ik.x} u_nk(x)) phi(k, x, alpha)
+    return np.stack([(ut[k].T @ phi_k[k].conj()).conj() for k in range(nk)])
 
 
 def apply_local(psi, local_proj, local_mat):

@@ -189,6 +189,19 @@ def config2_shape(nk=(8, 8, 8), nx=(20, 20, 20), n_bands=96, seed: int = 0,
                         omega_ev=(-25.0, 55.0), u_override=u_override)
 
 
+def config3_shape(seed: int = 0, n_steps: int = 300, psi0: str = "none", u_override="skip",
+                  nk=(2, 2, 2), nx=(64, 64, 64), n_bands: int = 1200) -> Crystal:
+    """Ti L2,3 edge at one site of a 4x4x4 supercell of the SrTiO3-shaped cell (320 atoms,
+    a_s = 4 a, the site at the first Ti, (1/2,1/2,1/2) a): 2^3 k, 1200 bands in [0, 40] eV,
+    64^3 x, the c2 screening and multiplet parameters.  u (40 GB in FP64) is meant to be
+    drawn on the device (gpu_orthonormal_u)."""
+    return make_crystal("c3", a=4.0 * SRTIO3_A, tau=(0.5 * SRTIO3_A,) * 3, nk=nk, nx=nx,
+                        n_bands=n_bands, n_core=6, e_range_ev=40.0, eps=6.0, seed=seed,
+                        n_local=5, multiplet_ev=dict(L_EDGE_MULTIPLET_EV), psi0=psi0,
+                        polarisations=XYZ_POLARISATIONS, n_steps=n_steps,
+                        omega_ev=(-25.0, 55.0), u_override=u_override)
+
+
 def small_l_edge(seed: int = 1, nk=(2, 2, 2), nx=(6, 6, 6), n_bands=12, **kw) -> Crystal:
     """A tiny L-edge crystal (dense H feasible) for parity and pin tests."""
     return config2_shape(nk=nk, nx=nx, n_bands=n_bands, seed=seed, **kw)

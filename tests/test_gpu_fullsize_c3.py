@@ -1,0 +1,90 @@
+"""Parity at the full size of the supercell workload: one Ti L2,3 site of a 4x4x4
+SrTiO3-shaped supercell, 2^3 k, 1200 bands, 64^3 x, 6 core states (H dimension 57600; u is
+40 GB in FP64 and is drawn on the device).  Three polarisation vectors per call, as the
+solver runs them.  The oracle computes the complete H*v of the first vector (every
+output element) from a host copy of the same u; it needs about 130 GB of host memory and
+a minute of host time."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bse as orc
+from oracle import multiplet as omp
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import torch
+
+    import paper_1601_07728_amd as ob
+    t0 = time.time()
+    cr = synth.config3_shape(seed=0)
+    u = synth.gpu_orthonormal_u(cr.n_k, cr.n_x, cr.n_bands, seed=3000)
+    torch.cuda.synchronize()
+    _say(f"[c3] u on the device ({u.numel() * 16 / 1e9:.1f} GB) in {time.time() - t0:.1f} s")
+    out = {}
+    h64 = ob.Bse.from_crystal(cr, precision="fp64", u=u)
+    psi0 = h64.dipole_psi0(np.eye(3))
+    out["fp64"] = h64.apply(psi0)[0].cpu().numpy()
+    a, b, n2, sd, _ = h64.haydock(psi0, 2)
+    out["hay"] = (a, b, n2)
+    h64.close()
+    for prec in ("bf16",):
+        h = ob.Bse.from_crystal(cr, precision=prec, u=u)
+        out[prec] = h.apply(psi0)[0].cpu().numpy()
+        h.close()
+    p0 = psi0.cpu().numpy()
+    _say(f"[c3] GPU applies done at {time.time() - t0:.1f} s; copying u to the host")
+    cr.u = u.cpu().numpy()
+    del u, psi0
+    torch.cuda.empty_cache()
+    hc, kl = omp.core_matrix(cr.multiplet), omp.local_matrix(cr.multiplet)
+    ut = orc.folded_u(cr)
+    cr.u = None
+    w, f = orc.w_supercell(cr), orc.dft_matrix(cr)
+    _say(f"[c3] oracle H*v of vector 0 from {time.time() - t0:.1f} s")
+    ref = orc.apply_h(cr, p0[0], hc, kl, ut=ut, w=w, f=f)
+    _say(f"[c3] oracle done at {time.time() - t0:.1f} s")
+    # the first Haydock coefficients follow from this one H*v
+    n2 = float(np.vdot(p0[0], p0[0]).real)
+    v0 = p0[0] / np.sqrt(n2)
+    wv = ref / np.sqrt(n2)
+    a0 = float(np.vdot(v0, wv).real)
+    b1 = float(np.linalg.norm(wv - a0 * v0))
+    del ut
+    out.update(ref=ref, n2=n2, a0=a0, b1=b1)
+    return out
+
+
+def _rel(y, ref):
+    return float(np.abs(y - ref).max() / np.abs(ref).max())
+
+
+def test_c3_fullsize_apply_fp64(c3):
+    err = _rel(c3["fp64"], c3["ref"])
+    _say(f"[c3] fp64 H*v rel err {err:.2e}")
+    assert err <= 1e-13
+
+
+def test_c3_fullsize_apply_bf16(c3):
+    err = _rel(c3["bf16"], c3["ref"])
+    _say(f"[c3] bf16 H*v rel err {err:.2e}")
+    assert err <= 1e-2
+
+
+def test_c3_fullsize_first_haydock_coefficients(c3):
+    a, b, n2 = c3["hay"]
+    scale = abs(c3["a0"]) + 2 * c3["b1"]
+    assert abs(n2[0] - c3["n2"]) <= 1e-13 * c3["n2"]
+    assert abs(a[0, 0] - c3["a0"]) <= 1e-12 * scale
+    assert abs(b[0, 0] - c3["b1"]) <= 1e-12 * scale
