@@ -80,3 +80,24 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     assert (tmp_path / "tune.txt").read_text().count("|") == 1
     h.close()
     h2.close()
+
+
+def test_terminator_systems_fullsize_prefix():
+    """Learned-terminator data at its generation shape and step count (two seeded systems,
+    512 steps, batched as the dataset is generated): the first 30 coefficients against the
+    oracle's plain recursion (before orthogonality is lost either side)."""
+    import paper_1601_07728_amd as ob
+    crs = [synth.terminator_system(sd, nk=(4, 4, 4), nx=(5, 5, 5), n_bands=24) for sd in (1, 4096)]
+    hs = [ob.Bse.from_crystal(cr) for cr in crs]
+    p0 = [h.dipole_psi0([0.0, 0.0, 1.0]) for h in hs]
+    out, _ = ob.haydock_batch(hs, p0, 512)
+    for cr, h, q, (a, b, n2, sd) in zip(crs, hs, p0, out):
+        hc, kl = omp.core_matrix(cr.multiplet), omp.local_matrix(cr.multiplet)
+        ra, rb, rn2, rs, _ = orc.haydock(lambda v: orc.apply_h(cr, v, hc, kl), q.cpu().numpy()[0], 30)
+        S = np.abs(ra).max() + 2 * rb.max()
+        _say(f"[terminator system {cr.name}] steps {sd[0]}, max|da| {np.abs(a[0, :30] - ra).max():.2e}")
+        assert sd[0] == 512
+        assert np.abs(a[0, :30] - ra).max() <= 1e-10 * S
+        assert np.abs(b[0, :30] - rb).max() <= 1e-10 * S
+        assert abs(n2[0] - rn2) <= 1e-13 * rn2
+        h.close()
