@@ -212,6 +212,15 @@ void ocean_mlp_destroy(ocean_mlp_t h);
 /* Copy parameters in (host, resets the Adam moments and step count) or out (host). */
 int ocean_mlp_set_params(ocean_mlp_t h, const float* params);
 int ocean_mlp_get_params(ocean_mlp_t h, float* params);
+/* Checkpoint: write the parameters, the Adam moments and step count to the file at path
+ * (binary, little-endian: the 8 bytes "OCEANMLP", int32 version 1, int32 precision,
+ * int32 Adam step, int32 parameter count, then three float32 arrays of that count:
+ * parameters, first moments, second moments), or restore them from such a file so that
+ * training resumes exactly where it stopped.  The precision stored must match the
+ * handle's.  Synchronous.  Errors: INVALID_ARG (NULL argument, unreadable or unwritable
+ * file, wrong format, count or precision), DEVICE. */
+int ocean_mlp_save(ocean_mlp_t h, const char* path);
+int ocean_mlp_load(ocean_mlp_t h, const char* path);
 /* Features x [n_seq][64] and, when t_dev is not NULL, targets t [n_seq][448] (device,
  * FP32) from coefficient sequences a, b [n_seq][stride] (device, FP64, b[j] = b_{j+1});
  * stride >= 32, or >= 256 with targets.  Synchronous.  Errors: INVALID_ARG, DEVICE. */

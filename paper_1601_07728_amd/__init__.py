@@ -44,7 +44,7 @@ EXPORTED = [
     "ocean_last_error", "ocean_haydock_batch", "ocean_bse_autotune", "ocean_bse_get_tuning",
     "ocean_mlp_param_count", "ocean_mlp_create", "ocean_mlp_destroy", "ocean_mlp_set_params",
     "ocean_mlp_get_params", "ocean_mlp_encode", "ocean_mlp_forward", "ocean_mlp_loss_grad",
-    "ocean_mlp_train_step", "ocean_mlp_predict",
+    "ocean_mlp_train_step", "ocean_mlp_predict", "ocean_mlp_save", "ocean_mlp_load",
 ]
 MLP_BF16 = 0
 MLP_FP32 = 1
@@ -131,6 +131,10 @@ def lib() -> ctypes.CDLL:
     L.ocean_mlp_train_step.restype = ci
     L.ocean_mlp_predict.argtypes = [vp, vp, vp, ci, ci, vp, vp, vp]
     L.ocean_mlp_predict.restype = ci
+    L.ocean_mlp_save.argtypes = [vp, ctypes.c_char_p]
+    L.ocean_mlp_save.restype = ci
+    L.ocean_mlp_load.argtypes = [vp, ctypes.c_char_p]
+    L.ocean_mlp_load.restype = ci
     L.ocean_last_error.argtypes = []
     L.ocean_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -423,6 +427,14 @@ class Mlp:
         p = np.zeros(self.n_params, dtype=np.float32)
         _check(lib().ocean_mlp_get_params(self._h, _ptr(p)))
         return p
+
+    def save(self, path):
+        """Checkpoint parameters, Adam moments and step count (ocean_mlp_save)."""
+        _check(lib().ocean_mlp_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        """Restore a checkpoint written by save (ocean_mlp_load)."""
+        _check(lib().ocean_mlp_load(self._h, os.fsencode(path)))
 
     @staticmethod
     def encode(a_dev, b_dev, with_targets: bool = True):

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include <cstdio>
 #include "internal.h"
 
 namespace ocean {
@@ -359,6 +360,49 @@ int ocean_mlp_get_params(ocean_mlp_t h, float* params) {
     if (!h || !params) return mlp_fail("ocean_mlp_get_params: invalid argument", OCEAN_ERR_INVALID_ARG);
     int rc = mlp_hip(hipMemcpyAsync(params, h->p, (size_t)kParams * sizeof(float), hipMemcpyDeviceToHost, h->stream), "download");
     if (rc == OCEAN_OK) rc = mlp_hip(hipStreamSynchronize(h->stream), "get_params");
+    return rc;
+}
+
+int ocean_mlp_save(ocean_mlp_t h, const char* path) {
+    if (!h || !path) return mlp_fail("ocean_mlp_save: invalid argument", OCEAN_ERR_INVALID_ARG);
+    std::vector<float> buf((size_t)3 * kParams);
+    const size_t pb = (size_t)kParams * sizeof(float);
+    int rc = mlp_hip(hipMemcpyAsync(buf.data(), h->p, pb, hipMemcpyDeviceToHost, h->stream), "download");
+    if (rc == OCEAN_OK) rc = mlp_hip(hipMemcpyAsync(buf.data() + kParams, h->m, pb, hipMemcpyDeviceToHost, h->stream), "download");
+    if (rc == OCEAN_OK) rc = mlp_hip(hipMemcpyAsync(buf.data() + 2 * (size_t)kParams, h->v, pb, hipMemcpyDeviceToHost, h->stream), "download");
+    if (rc == OCEAN_OK) rc = mlp_hip(hipStreamSynchronize(h->stream), "save");
+    if (rc != OCEAN_OK) return rc;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return mlp_fail(std::string("ocean_mlp_save: cannot open ") + path, OCEAN_ERR_INVALID_ARG);
+    const int32_t head[4] = {1, h->precision, h->t, kParams};
+    bool ok = std::fwrite("OCEANMLP", 1, 8, f) == 8 && std::fwrite(head, sizeof(int32_t), 4, f) == 4 &&
+              std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return mlp_fail(std::string("ocean_mlp_save: write failed for ") + path, OCEAN_ERR_INVALID_ARG);
+    return OCEAN_OK;
+}
+
+int ocean_mlp_load(ocean_mlp_t h, const char* path) {
+    if (!h || !path) return mlp_fail("ocean_mlp_load: invalid argument", OCEAN_ERR_INVALID_ARG);
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return mlp_fail(std::string("ocean_mlp_load: cannot open ") + path, OCEAN_ERR_INVALID_ARG);
+    char magic[8];
+    int32_t head[4];
+    std::vector<float> buf((size_t)3 * kParams);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "OCEANMLP", 8) == 0 &&
+              std::fread(head, sizeof(int32_t), 4, f) == 4 && head[0] == 1 && head[3] == kParams &&
+              head[1] == h->precision && head[2] >= 0 &&
+              std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok)
+        return mlp_fail(std::string("ocean_mlp_load: not a checkpoint of this network and precision: ") + path,
+                        OCEAN_ERR_INVALID_ARG);
+    const size_t pb = (size_t)kParams * sizeof(float);
+    int rc = mlp_hip(hipMemcpyAsync(h->p, buf.data(), pb, hipMemcpyHostToDevice, h->stream), "upload");
+    if (rc == OCEAN_OK) rc = mlp_hip(hipMemcpyAsync(h->m, buf.data() + kParams, pb, hipMemcpyHostToDevice, h->stream), "upload");
+    if (rc == OCEAN_OK) rc = mlp_hip(hipMemcpyAsync(h->v, buf.data() + 2 * (size_t)kParams, pb, hipMemcpyHostToDevice, h->stream), "upload");
+    if (rc == OCEAN_OK) rc = mlp_hip(hipStreamSynchronize(h->stream), "load");
+    if (rc == OCEAN_OK) h->t = head[2];
     return rc;
 }
 

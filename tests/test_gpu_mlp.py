@@ -139,3 +139,32 @@ def test_learned_terminator_gains_on_held_out_systems():
     assert l1["mlp"] < 0.5 * l1["truncated"]
     assert valid.all()
     m.close()
+
+
+def test_checkpoint_resume_is_exact(tmp_path):
+    """Save after a few Adam steps, load into a fresh handle, and continue both: the
+    parameters stay bitwise equal (the moments and the step count are restored)."""
+    import torch
+
+    import paper_1601_07728_amd as ob
+    rng = np.random.default_rng(11)
+    x = torch.from_numpy(rng.standard_normal((64, 64)).astype(np.float32)).to("cuda")
+    t = torch.from_numpy((0.1 * rng.standard_normal((64, 448))).astype(np.float32)).to("cuda")
+    m1 = ob.Mlp("bf16")
+    m1.set_params((0.05 * rng.standard_normal(m1.n_params)).astype(np.float32))
+    for _ in range(3):
+        m1.train_step(x, t, 1e-3)
+    path = str(tmp_path / "mlp.ckpt")
+    m1.save(path)
+    m2 = ob.Mlp("bf16")
+    m2.load(path)
+    assert np.array_equal(m1.get_params(), m2.get_params())
+    for _ in range(2):
+        m1.train_step(x, t, 1e-3)
+        m2.train_step(x, t, 1e-3)
+    assert np.array_equal(m1.get_params(), m2.get_params())
+    m3 = ob.Mlp("fp32")
+    with pytest.raises(ob.OceanError):
+        m3.load(path)           # a bf16 checkpoint does not load into an FP32 handle
+    for m in (m1, m2, m3):
+        m.close()
