@@ -16,8 +16,12 @@
 //
 // 16x16x4 MFMA: lane l = i + 16 kq holds A[i][kq] and B[kq][i]; result register r holds
 // column i of row 4 r + kq (f64) or 4 kq + r (f32), as measured on gfx950.  A sub-step covers
-// 8 contraction points: lane group kq holds points 2 kq and 2 kq + 1, and MFMA s = 0..3 of the
-// sub-step contracts (point 2 kq + s / 2, part s % 2).
+// 8 contraction points, two per lane group, and each point feeds two MFMAs (re and im part);
+// which two points a lane group holds is chosen per kernel so that its loads coalesce.
+//
+// On gfx950 an FP64 16x16x4 MFMA takes the issue slots of 16 wave-wide FP64 FMAs, so in FP64
+// a pass whose columns leave at most 2 complex columns after whole 16-wide tiles contracts
+// those with plain FMAs instead of a mostly empty tile.
 #include "internal.h"
 
 namespace ocean {
@@ -43,34 +47,33 @@ template <typename T> __device__ __forceinline__ int acc_row(int kq, int r);
 template <> __device__ __forceinline__ int acc_row<double>(int kq, int r) { return 4 * r + kq; }
 template <> __device__ __forceinline__ int acc_row<float>(int kq, int r) { return 4 * kq + r; }
 
-// B operands are staged in LDS in MFMA order: value s (0..3) of lane l for sub-step ss and
-// column tile t sits at ((ss * NT + t) * 64 + l) * 4 + s, so a wave reads its operands with
-// one 4-wide LDS load per (ss, t).  Lane l = i + 16 kq of sub-step ss covers the
-// contraction slots (2 kq + s / 2, s % 2) of that 8-wide step and real column 16 t + i.
+// Forward projection: B operands are staged in LDS in MFMA order: value s (0..3) of lane l
+// for sub-step ss and column tile t sits at ((ss * NT + t) * 64 + l) * 4 + s, so a wave reads
+// its operands with one 4-wide LDS load per (ss, t).  Lane l = i + 16 kq of sub-step ss
+// covers the bands fwd_band(kq, s / 2) of that 8-band step (parts s % 2) and real column
+// 16 t + i.  FP64: the four lane groups take four consecutive bands (kq + 4 ns), so the 16-byte
+// u loads of one row form one aligned 64-byte piece; FP32: a lane takes two consecutive bands
+// (2 kq + ns) and loads both with one 16-byte load.
+template <typename T> __device__ __forceinline__ int fwd_band(int kq, int ns) {
+    return sizeof(T) == 8 ? kq + 4 * ns : 2 * kq + ns;
+}
 
 template <typename T> struct Vec4;
 template <> struct Vec4<double> { typedef double4 t; };
 template <> struct Vec4<float> { typedef float4 t; };
 
-// Write the four B values of one complex input (re, im) at contraction point r8 (0..7 within
-// a sub-step) and local column cl into the MFMA-ordered buffer.  fwd = true gives
-// [[re, im], [-im, re]], false gives [[re, im], [im, -re]] (rows p, columns q).
+// Write the four B values [[re, im], [-im, re]] (rows p, columns q) of one complex psi value
+// of band slot (kq, ns) of sub-step ss and local column cl into the MFMA-ordered buffer.
 template <typename T, int NT>
-__device__ __forceinline__ void stage_pair(T* buf, int ss, int r8, int cl, double re, double im, bool fwd) {
-    const int kq = r8 >> 1, ns = r8 & 1;
+__device__ __forceinline__ void stage_pair(T* buf, int ss, int kq, int ns, int cl, double re, double im) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int jr = 2 * cl + q;
         const int t = jr >> 4, i = jr & 15;
         if (t >= NT) continue;
         T* dst = buf + ((size_t)(ss * NT + t) * 64 + i + 16 * kq) * 4 + 2 * ns;
-        if (fwd) {
-            dst[0] = (T)(q ? im : re);
-            dst[1] = (T)(q ? re : -im);
-        } else {
-            dst[0] = (T)(q ? im : re);
-            dst[1] = (T)(q ? -re : im);
-        }
+        dst[0] = (T)(q ? im : re);
+        dst[1] = (T)(q ? re : -im);
     }
 }
 
@@ -79,7 +82,7 @@ __device__ __forceinline__ void stage_pair(T* buf, int ss, int r8, int cl, doubl
 // [xt*64*MS + w*16*MS, +16*MS) and every column tile.  The bands are walked in chunks of
 // KC: the psi chunk (B operand, shared by all waves) is staged in LDS in MFMA order, double
 // buffered, while each wave keeps the u values (A operand) of the next chunk in flight.
-template <typename T, int MS, int NT, int KC>
+template <typename T, int MS, int NT, int TC, int KC>
 __global__ __launch_bounds__(256) void proj_fwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const double2* __restrict__ psi,
     typename Cplx<T>::c2* __restrict__ phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0,
@@ -90,6 +93,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
     constexpr int SS = KC / 8;                 // 8-band sub-steps per chunk
     constexpr int BUF = SS * NT * 64 * 4;      // T values per staged chunk
     __shared__ __align__(16) T sB[2][BUF];
+    __shared__ __align__(16) C2 sT[2][KC][TC > 0 ? TC : 1];   // FMA tail columns, (re, im)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
     const int k = blockIdx.x / x_tiles;
@@ -130,20 +134,47 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 256 * j;
             const int nl = e / kColsPerPass, cl = e - nl * kColsPerPass;
-            if (nl < KC && cl < ncb) stage_pair<T, NT>(sB[buf], nl >> 3, nl & 7, cl, pv[j].x, pv[j].y, true);
+            if (nl < KC && cl < ncb) {
+                const int r8 = nl & 7;
+                const int kq8 = sizeof(T) == 8 ? (r8 & 3) : (r8 >> 1), ns8 = sizeof(T) == 8 ? (r8 >> 2) : (r8 & 1);
+                if (cl < 8 * NT) stage_pair<T, NT>(sB[buf], nl >> 3, kq8, ns8, cl, pv[j].x, pv[j].y);
+                else if (TC > 0) sT[buf][nl][cl - 8 * NT] = C2{(T)pv[j].x, (T)pv[j].y};
+            }
         }
     };
     auto load_a = [&](int n0, C2 (&aa)[MS][SS][2]) {
 #pragma unroll
-        for (int ss = 0; ss < SS; ++ss)
+        for (int ss = 0; ss < SS; ++ss) {
+            if constexpr (sizeof(T) == 8) {
 #pragma unroll
-            for (int ns = 0; ns < 2; ++ns) {
-                const int n = n0 + 8 * ss + 2 * kq + ns;
-                const bool nok = n < Nb;
+                for (int ns = 0; ns < 2; ++ns) {
+                    const int n = n0 + 8 * ss + fwd_band<T>(kq, ns);
+                    const bool nok = n < Nb;
 #pragma unroll
-                for (int ms = 0; ms < MS; ++ms)
-                    aa[ms][ss][ns] = bload<C2>(ur, (nok && rval[ms]) ? urow[ms] + (unsigned)(n * sizeof(C2)) : kOob);
+                    for (int ms = 0; ms < MS; ++ms)
+                        aa[ms][ss][ns] = bload<C2>(ur, (nok && rval[ms]) ? urow[ms] + (unsigned)(n * sizeof(C2)) : kOob);
+                }
+            } else {
+                // bands 2 kq and 2 kq + 1 in one 16-byte load (Nb even; else two 8-byte loads)
+                const int n = n0 + 8 * ss + 2 * kq;
+#pragma unroll
+                for (int ms = 0; ms < MS; ++ms) {
+                    if ((Nb & 1) == 0) {
+                        const bool ok = n < Nb && rval[ms];
+                        const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                            ur, (int)(ok ? urow[ms] + (unsigned)(n * sizeof(C2)) : kOob), 0, 0));
+                        aa[ms][ss][0] = C2{(T)v.x, (T)v.y};
+                        aa[ms][ss][1] = C2{(T)v.z, (T)v.w};
+                    } else {
+#pragma unroll
+                        for (int ns = 0; ns < 2; ++ns) {
+                            const bool ok = n + ns < Nb && rval[ms];
+                            aa[ms][ss][ns] = bload<C2>(ur, ok ? urow[ms] + (unsigned)((n + ns) * sizeof(C2)) : kOob);
+                        }
+                    }
+                }
             }
+        }
     };
 
     // padding columns stay zero in both buffers
@@ -154,6 +185,12 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
     for (int ms = 0; ms < MS; ++ms)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[ms][t] = ACC{0, 0, 0, 0};
+    // FMA tail: lane (i, kq) sums its own bands for row i; the lane groups are added at the end
+    T tre[MS][TC > 0 ? TC : 1], tim[MS][TC > 0 ? TC : 1];
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+        for (int c = 0; c < TC; ++c) tre[ms][c] = tim[ms][c] = (T)0;
 
     C2 a[MS][SS][2], an[MS][SS][2];
     double2 pv[PER];
@@ -190,7 +227,24 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
                     }
                 }
             }
+#pragma unroll
+            for (int c = 0; c < TC; ++c)
+#pragma unroll
+                for (int ns = 0; ns < 2; ++ns) {
+                    const C2 f = sT[buf][8 * ss + fwd_band<T>(kq, ns)][c];   // same address for the 16 lanes
+#pragma unroll
+                    for (int ms = 0; ms < MS; ++ms) {
+                        const C2 v = a[ms][ss][ns];
+                        tre[ms][c] = __builtin_fma(v.x, f.x, __builtin_fma(-v.y, f.y, tre[ms][c]));
+                        tim[ms][c] = __builtin_fma(v.x, f.y, __builtin_fma(v.y, f.x, tim[ms][c]));
+                    }
+                }
         }
+        // keep this chunk's tail sums here (sunk later they would pin the u registers)
+#pragma unroll
+        for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+            for (int c = 0; c < TC; ++c) asm volatile("" : "+v"(tre[ms][c]), "+v"(tim[ms][c]));
         store_p(buf ^ 1, pv);
 #pragma unroll
         for (int ms = 0; ms < MS; ++ms)
@@ -216,24 +270,52 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
                     out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = acc[ms][t][r];
             }
         }
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+        for (int c = 0; c < TC; ++c) {
+            T re = tre[ms][c], im = tim[ms][c];
+            re += __shfl_xor(re, 16);
+            im += __shfl_xor(im, 16);
+            re += __shfl_xor(re, 32);
+            im += __shfl_xor(im, 32);
+            const int row = rowbase + 16 * ms + i;
+            if (kq == 0 && row < Nx) {
+                out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c)] = re;
+                out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c) + 1] = im;
+            }
+        }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Backward projection with split-K over x.  Block = (k, band block of W x 16 bands,
 // x chunk); wave w owns the 16 bands [band block * 16 W + 16 w, +16).  The chunk is walked
-// in tiles of XT points: the phi' tile (B operand, shared by all waves) is staged in LDS in
-// MFMA order, double buffered, and every wave keeps the u values of the next tile in flight.
-template <typename T, int NT, int XT, int W>
+// in tiles of XT points through a ring of R slots: while tile t is contracted, the u values
+// and the phi' values of tiles up to t + R - 1 are in flight (R = 3 for FP64, whose 16-byte
+// loads make short tiles; R = 2 with tiles twice as long for FP32).  phi' tiles (shared by all waves) sit in
+// LDS as [sub-step][lane group kq][column][q][point pair] complex pairs, q = 0 holding
+// (re, im) and q = 1 holding (im, -re): the B operands of real column (column, q) are then
+// the two halves of one pair, and a lane picks its orientation by address, with no per-lane
+// select.
+//
+// Columns [0, 8 NT) go through NT MFMA column tiles.  The last TC (0..2) columns, which
+// would fill at most a quarter of one more tile, are contracted with plain FMAs instead: a
+// 16x16x4 FP64 MFMA costs the issue slots of 16 wave-wide FMAs, so a tile holding 4 real
+// columns of 16 wastes three quarters of them.  Lane (i, kq) sums its own points for band
+// i, and the four lane groups are added at the end.
+template <typename T, int NT, int TC, int XT, int R, int W>
 __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const typename Cplx<T>::c2* __restrict__ phi,
     double* __restrict__ part, int Nk, int Nx, int Nb, int cols, int col0, int ncb,
     int band_blocks, int S, int chunk) {
     typedef typename Cplx<T>::c2 C2;
     typedef typename Cplx<T>::acc ACC;
-    typedef typename Vec4<T>::t V4;
     constexpr int SS = XT / 8;
-    constexpr int BUF = SS * NT * 64 * 4;
-    __shared__ __align__(16) T sB[2][BUF];
+    constexpr int TILE = 2 * XT * kColsPerPass;          // complex pairs of one phi' tile
+    constexpr int PER = (XT * kColsPerPass + 64 * W - 1) / (64 * W);
+    static_assert(8 * NT + TC <= kColsPerPass, "columns per pass");
+    static_assert(R == 2 || R == 3, "ring depth");
+    __shared__ __align__(16) C2 sP[R][TILE];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
     int blk = blockIdx.x;
@@ -254,8 +336,8 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     const C2* pbase = phi + (size_t)xb0 * Nk * kXB * cols;
     const Rsrc prs = make_rsrc(pbase, (size_t)((x_end - 1) / kXB - xb0 + 1) * Nk * kXB * cols * sizeof(C2));
 
-    constexpr int PER = (XT * kColsPerPass + 64 * W - 1) / (64 * W);
-    auto load_b = [&](int x0, C2 (&bv)[PER]) {
+    // tile loads (masked to zero past the chunk end)
+    auto issue = [&](int x0, C2 (&pp)[PER], C2 (&uu)[SS][2]) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 64 * W * j;
@@ -263,72 +345,107 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
             const int x = x0 + xl;
             const bool ok = xl < XT && cl < ncb && x < x_end;
             const unsigned off = (unsigned)((phi_index_x(x, col0 + cl, k, Nk, cols) - (size_t)xb0 * Nk * kXB * cols) * sizeof(C2));
-            bv[j] = bload<C2>(prs, ok ? off : kOob);
+            pp[j] = bload<C2>(prs, ok ? off : kOob);
         }
-    };
-    auto store_b = [&](int buf, const C2 (&bv)[PER]) {
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int e = threadIdx.x + 64 * W * j;
-            const int xl = e / kColsPerPass, cl = e - xl * kColsPerPass;
-            if (xl < XT && cl < ncb) stage_pair<T, NT>(sB[buf], xl >> 3, xl & 7, cl, bv[j].x, bv[j].y, false);
-        }
-    };
-    auto load_a = [&](int x0, C2 (&aa)[SS][2]) {
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss)
 #pragma unroll
             for (int xs = 0; xs < 2; ++xs) {
                 const int x = x0 + 8 * ss + 2 * kq + xs;
                 const bool ok = nval && x < x_end;
-                aa[ss][xs] = bload<C2>(ur, ok ? (unsigned)(((x - x_begin) * Nb + n) * sizeof(C2)) : kOob);
+                uu[ss][xs] = bload<C2>(ur, ok ? (unsigned)(((x - x_begin) * Nb + n) * sizeof(C2)) : kOob);
             }
     };
-
-    for (int e = threadIdx.x; e < 2 * BUF; e += 64 * W) (&sB[0][0])[e] = (T)0;
-
+    // point xl of the tile = (sub-step xl / 8, lane group (xl % 8) / 2, pair slot xl % 2)
+    auto stage = [&](C2* dst, const C2 (&pp)[PER]) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + 64 * W * j;
+            const int xl = e / kColsPerPass, cl = e - xl * kColsPerPass;
+            if (xl < XT && cl < ncb) {
+                C2* d = dst + ((((xl >> 3) * 4 + ((xl & 7) >> 1)) * kColsPerPass + cl) * 2) * 2 + (xl & 1);
+                d[0] = pp[j];
+                d[2] = C2{pp[j].y, -pp[j].x};
+            }
+        }
+    };
     ACC acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = ACC{0, 0, 0, 0};
-
-    C2 a[SS][2], an[SS][2];
-    C2 bl[PER];
-    load_b(x_begin, bl);
-    load_a(x_begin, a);
-    __builtin_amdgcn_s_waitcnt(0);  // drain the prologue (see the forward kernel)
-    __syncthreads();
-    store_b(0, bl);
-    int buf = 0;
-    for (int x0 = x_begin; x0 < x_end; x0 += XT) {
-        __syncthreads();
-        // next tile (masked to zero past the chunk end), kept ahead of the MFMAs
-        load_b(x0 + XT, bl);
-        load_a(x0 + XT, an);
-        __builtin_amdgcn_sched_barrier(0);
+    T tre[TC > 0 ? TC : 1], tim[TC > 0 ? TC : 1];
+#pragma unroll
+    for (int c = 0; c < TC; ++c) tre[c] = tim[c] = (T)0;
+    auto contract = [&](const C2* src, const C2 (&uu)[SS][2]) {
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
-            V4 bv[NT];
+            const C2* row = src + (ss * 4 + kq) * kColsPerPass * 4;
+            // lane (i, kq): real column (8 t + i / 2, q = i % 2) -> pair (column, q)
+            const C2* mine = row + (i >> 1) * 4 + (i & 1) * 2;
+            C2 b[NT][2];
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-                bv[t] = *reinterpret_cast<const V4*>(&sB[buf][((ss * NT + t) * 64 + lane) * 4]);
-#pragma unroll
-            for (int st = 0; st < 4; ++st) {
-                const T av = (st & 1) ? a[ss][st >> 1].y : a[ss][st >> 1].x;
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const T b = st == 0 ? bv[t].x : st == 1 ? bv[t].y : st == 2 ? bv[t].z : bv[t].w;
-                    acc[t] = mfma16(av, b, acc[t]);
-                }
+            for (int t = 0; t < NT; ++t) {
+                b[t][0] = mine[32 * t];
+                b[t][1] = mine[32 * t + 1];
             }
-        }
-        store_b(buf ^ 1, bl);
 #pragma unroll
-        for (int ss = 0; ss < SS; ++ss) {
-            a[ss][0] = an[ss][0];
-            a[ss][1] = an[ss][1];
+            for (int xs = 0; xs < 2; ++xs) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = mfma16(uu[ss][xs].x, b[t][xs].x, acc[t]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = mfma16(uu[ss][xs].y, b[t][xs].y, acc[t]);
+            }
+#pragma unroll
+            for (int c = 0; c < TC; ++c)
+#pragma unroll
+                for (int xs = 0; xs < 2; ++xs) {
+                    const C2 f = row[(8 * NT + c) * 4 + xs];   // (re, im); same address for the 16 lanes
+                    const C2 v = uu[ss][xs];
+                    tre[c] = __builtin_fma(v.x, f.x, __builtin_fma(v.y, f.y, tre[c]));
+                    tim[c] = __builtin_fma(v.x, f.y, __builtin_fma(-v.y, f.x, tim[c]));
+                }
         }
-        buf ^= 1;
+        // keep the tail sums of this tile here: sunk into a later step they would hold this
+        // tile's u registers past the loads that reuse them
+#pragma unroll
+        for (int c = 0; c < TC; ++c) asm volatile("" : "+v"(tre[c]), "+v"(tim[c]));
+    };
+
+    // padding columns stay zero in every buffer
+    for (int e = threadIdx.x; e < R * TILE; e += 64 * W) (&sP[0][0])[e] = C2{0, 0};
+
+    C2 ua[R][SS][2];
+    C2 pr[R][PER];
+#pragma unroll
+    for (int r = 0; r + 1 < R; ++r) issue(x_begin + r * XT, pr[r], ua[r]);
+    __syncthreads();
+    stage(sP[0], pr[0]);
+    // step on tile x0 held in ring slot c: request tile x0 + (R - 1) XT into slot c + R - 1,
+    // contract slot c, stage tile x0 + XT (slot c + 1) into its LDS buffer.  The barrier at
+    // the top publishes the previous step's staging and retires every read of the buffer
+    // staged now.
+    auto step = [&](int x0, C2 (&pn)[PER], C2 (&un)[SS][2], const C2* cur, const C2 (&uc)[SS][2],
+                    C2* nxt, const C2 (&p1)[PER]) {
+        __syncthreads();
+        issue(x0 + (R - 1) * XT, pn, un);
+        __builtin_amdgcn_sched_barrier(0);
+        contract(cur, uc);
+        stage(nxt, p1);
+    };
+    // whole turns of the ring (tiles past the chunk end are zero): no exit between steps, so
+    // every step sees the same loads outstanding
+    if constexpr (R == 3) {
+        for (int x0 = x_begin; x0 < x_end; x0 += 3 * XT) {
+            step(x0, pr[2], ua[2], sP[0], ua[0], sP[1], pr[1]);
+            step(x0 + XT, pr[0], ua[0], sP[1], ua[1], sP[2], pr[2]);
+            step(x0 + 2 * XT, pr[1], ua[1], sP[2], ua[2], sP[0], pr[0]);
+        }
+    } else {
+        for (int x0 = x_begin; x0 < x_end; x0 += 2 * XT) {
+            step(x0, pr[1], ua[1], sP[0], ua[0], sP[1], pr[1]);
+            step(x0 + XT, pr[0], ua[0], sP[1], ua[1], sP[0], pr[0]);
+        }
     }
+    __builtin_amdgcn_s_waitcnt(0);   // retire the loads past the chunk end before the exit
 
     double* out = part + ((size_t)s * Nk + k) * Nb * 2 * cols + 2 * col0;
 #pragma unroll
@@ -341,55 +458,73 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
             if (nn < Nb) out[(size_t)nn * 2 * cols + jr] = (double)acc[t][r];
         }
     }
+#pragma unroll
+    for (int c = 0; c < TC; ++c) {
+        T re = tre[c], im = tim[c];
+        re += __shfl_xor(re, 16);
+        im += __shfl_xor(im, 16);
+        re += __shfl_xor(re, 32);
+        im += __shfl_xor(im, 32);
+        if (kq == 0 && nval) {
+            out[(size_t)n * 2 * cols + 2 * (8 * NT + c)] = (double)re;
+            out[(size_t)n * 2 * cols + 2 * (8 * NT + c) + 1] = (double)im;
+        }
+    }
 }
 
 template <typename T> struct Tiles;
-template <> struct Tiles<double> { static constexpr int KC = 16, XT = 32; };
-template <> struct Tiles<float> { static constexpr int KC = 32, XT = 64; };
+template <> struct Tiles<double> { static constexpr int KC = 16, XT = 16, R = 3; };
+template <> struct Tiles<float> { static constexpr int KC = 32, XT = 64, R = 2; };
 
 template <typename T, int MS>
-hipError_t fwd_dispatch_nt(int NT, dim3 grid, hipStream_t st, const void* U, const double* x,
+hipError_t fwd_dispatch_nt(int NT, int TC, dim3 grid, hipStream_t st, const void* U, const double* x,
                            void* phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0, int ncb,
                            int x_tiles) {
     typedef typename Cplx<T>::c2 C2;
     const C2* u = static_cast<const C2*>(U);
     C2* p = static_cast<C2*>(phi);
     const double2* ps = reinterpret_cast<const double2*>(x);
-    switch (NT) {
-        case 1: proj_fwd_kernel<T, MS, 1, Tiles<T>::KC><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
-        case 2: proj_fwd_kernel<T, MS, 2, Tiles<T>::KC><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
-        default: proj_fwd_kernel<T, MS, 3, Tiles<T>::KC><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); break;
+#define OCEAN_FWD(nt, tc) \
+    if (NT == nt && TC == tc) { \
+        proj_fwd_kernel<T, MS, nt, tc, Tiles<T>::KC><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); \
+        return hipGetLastError(); \
     }
-    return hipGetLastError();
+    OCEAN_FWD(1, 0) OCEAN_FWD(2, 0) OCEAN_FWD(3, 0)
+    if constexpr (sizeof(T) == 8) { OCEAN_FWD(1, 1) OCEAN_FWD(1, 2) OCEAN_FWD(2, 1) OCEAN_FWD(2, 2) }
+#undef OCEAN_FWD
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int W>
-hipError_t bwd_dispatch_w(int NT, dim3 grid, hipStream_t st, const void* U, const void* phi,
+hipError_t bwd_dispatch_w(int NT, int TC, dim3 grid, hipStream_t st, const void* U, const void* phi,
                           double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int bb,
                           int S, int chunk) {
     typedef typename Cplx<T>::c2 C2;
     constexpr int XT = Tiles<T>::XT;
     const C2* u = static_cast<const C2*>(U);
     const C2* p = static_cast<const C2*>(phi);
-    switch (NT) {
-        case 1: proj_bwd_kernel<T, 1, XT, W><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
-        case 2: proj_bwd_kernel<T, 2, XT, W><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
-        default: proj_bwd_kernel<T, 3, XT, W><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); break;
+#define OCEAN_BWD(nt, tc) \
+    if (NT == nt && TC == tc) { \
+        proj_bwd_kernel<T, nt, tc, XT, Tiles<T>::R, W><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); \
+        return hipGetLastError(); \
     }
-    return hipGetLastError();
+    OCEAN_BWD(1, 0) OCEAN_BWD(2, 0) OCEAN_BWD(3, 0)
+    if constexpr (sizeof(T) == 8) { OCEAN_BWD(1, 1) OCEAN_BWD(1, 2) OCEAN_BWD(2, 1) OCEAN_BWD(2, 2) }
+#undef OCEAN_BWD
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t bwd_dispatch(int W, int NT, dim3 grid, hipStream_t st, const void* U, const void* phi,
+hipError_t bwd_dispatch(int W, int NT, int TC, dim3 grid, hipStream_t st, const void* U, const void* phi,
                         double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int bb,
                         int S, int chunk) {
     switch (W) {
 #define OCEAN_BWD_W(w) \
-        case w: return bwd_dispatch_w<T, w>(NT, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
+        case w: return bwd_dispatch_w<T, w>(NT, TC, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
         OCEAN_BWD_W(1) OCEAN_BWD_W(2) OCEAN_BWD_W(3) OCEAN_BWD_W(4) OCEAN_BWD_W(5) OCEAN_BWD_W(6)
         OCEAN_BWD_W(7)
 #undef OCEAN_BWD_W
-        default: return bwd_dispatch_w<T, 8>(NT, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
+        default: return bwd_dispatch_w<T, 8>(NT, TC, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
     }
 }
 
@@ -397,7 +532,7 @@ hipError_t bwd_dispatch(int W, int NT, dim3 grid, hipStream_t st, const void* U,
 
 
 // Backward-projection geometry: band blocks of up to 8 waves x 16 bands, and x chunks
-// (multiples of 8 points) so that the grid holds about bwd_target_blocks blocks.
+// (multiples of the 16-point phi x-block) so that the grid holds about bwd_target_blocks blocks.
 int bwd_waves(int Nb) {
     const int nb16 = (Nb + 15) / 16;
     return nb16 < 8 ? nb16 : 8;
@@ -412,7 +547,7 @@ void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks,
     if (s < 1) s = 1;
     if (s > smax) s = smax;
     int c = (int)((h->Nx + s - 1) / s);
-    c = (c + 7) / 8 * 8;
+    c = (c + kXB - 1) / kXB * kXB;
     *chunk = c;
     *S = (h->Nx + c - 1) / c;
     *band_blocks = bb;
@@ -428,24 +563,35 @@ bool is_bf16_mode(int precision) {
 
 int fwd_band_chunk(const ocean_bse_s* h) { return is_bf16_mode(h->precision) ? 32 : 0; }
 
+// MFMA column tiles and FMA tail columns for ncb complex columns.  In FP64 a remainder of at
+// most 4 real columns (2 complex) after whole 16-wide tiles goes to the FMA tail; FP32 MFMAs
+// are cheap next to FP32 FMAs, so FP32 always rounds up to whole tiles.
+void column_split(int ncb, bool fp64, int* NT, int* TC) {
+    const int full = 2 * ncb / 16, rem = 2 * ncb - 16 * full;
+    if (rem == 0) { *NT = full; *TC = 0; }
+    else if (fp64 && rem <= 4 && full >= 1) { *NT = full; *TC = rem / 2; }
+    else { *NT = full + 1; *TC = 0; }
+}
+
 hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, int ncb) {
     if (is_bf16_mode(h->precision)) return launch_proj_fwd_bf16(h, x, nv, col0, ncb);
     const int MS = h->fwd_ms == 1 ? 1 : 2;   // 16 * MS rows per wave, 64 * MS per block
     const int cols = nv * h->Nc;
-    const int NT = (2 * ncb + 15) / 16;
+    int NT, TC;
+    column_split(ncb, h->precision == OCEAN_PREC_FP64, &NT, &TC);
     const int x_tiles = (h->Nx + 64 * MS - 1) / (64 * MS);
     dim3 grid((unsigned)(h->Nk * x_tiles));
     hipError_t e;
     const int slot = prof_begin(h, "proj_fwd");
     if (h->precision == OCEAN_PREC_FP64)
-        e = MS == 1 ? fwd_dispatch_nt<double, 1>(NT, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
+        e = MS == 1 ? fwd_dispatch_nt<double, 1>(NT, TC, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
                                                  h->Nb, h->Nc, cols, col0, ncb, x_tiles)
-                    : fwd_dispatch_nt<double, 2>(NT, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
+                    : fwd_dispatch_nt<double, 2>(NT, TC, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
                                                  h->Nb, h->Nc, cols, col0, ncb, x_tiles);
     else
-        e = MS == 1 ? fwd_dispatch_nt<float, 1>(NT, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
+        e = MS == 1 ? fwd_dispatch_nt<float, 1>(NT, TC, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
                                                 h->Nb, h->Nc, cols, col0, ncb, x_tiles)
-                    : fwd_dispatch_nt<float, 2>(NT, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
+                    : fwd_dispatch_nt<float, 2>(NT, TC, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
                                                 h->Nb, h->Nc, cols, col0, ncb, x_tiles);
     prof_end(h, slot);
     return e;
@@ -454,7 +600,8 @@ hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, in
 hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     if (is_bf16_mode(h->precision)) return launch_proj_bwd_bf16(h, nv, col0, ncb);
     const int cols = nv * h->Nc;
-    const int NT = (2 * ncb + 15) / 16;
+    int NT, TC;
+    column_split(ncb, h->precision == OCEAN_PREC_FP64, &NT, &TC);
     int bb, S, chunk;
     bwd_geometry(h, &bb, &S, &chunk);
     const int W = bwd_waves(h->Nb);
@@ -462,10 +609,10 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     const int slot = prof_begin(h, "proj_bwd");
     hipError_t e;
     if (h->precision == OCEAN_PREC_FP64)
-        e = bwd_dispatch<double>(W, NT, grid, h->stream, h->U64, h->ws.phi, h->ws.part, h->Nk,
+        e = bwd_dispatch<double>(W, NT, TC, grid, h->stream, h->U64, h->ws.phi, h->ws.part, h->Nk,
                                  h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
     else
-        e = bwd_dispatch<float>(W, NT, grid, h->stream, h->U32, h->ws.phi, h->ws.part, h->Nk,
+        e = bwd_dispatch<float>(W, NT, TC, grid, h->stream, h->U32, h->ws.phi, h->ws.part, h->Nk,
                                 h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
     prof_end(h, slot);
     return e;

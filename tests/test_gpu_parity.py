@@ -79,6 +79,30 @@ def test_apply_fp64_matches_oracle(case, n_vec):
     h.close()
 
 
+# (n_core, n_vec): the projections take the exciton columns n_vec * n_core in passes of up to
+# 24 and split each pass into 16-wide matrix-core tiles plus, in FP64, a multiply-add tail of
+# 1 or 2 columns.  Odd core counts reach the one-column tail.
+COLUMN_SPLITS = [(1, 2), (1, 9), (3, 3), (1, 17), (3, 5), (1, 18), (3, 8), (1, 41)]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-5)])
+@pytest.mark.parametrize("n_core,n_vec", COLUMN_SPLITS)
+def test_apply_column_splits_match_oracle(n_core, n_vec, precision, tol):
+    ob = _ob()
+    cr = synth.make_crystal(f"split-c{n_core}", a=7.0, tau=(0.5, 1.0, 1.5), nk=(2, 1, 2),
+                            nx=(7, 5, 6), n_bands=23, n_core=n_core, e_range_ev=25.0, eps=4.0,
+                            seed=40 + n_core, psi0="none")
+    _say(f"[apply column split] n_core={n_core} n_vec={n_vec} cols={n_core * n_vec} {precision}")
+    h = ob.Bse.from_crystal(cr, precision=precision, check_inputs=True)
+    x = synth.complex_gaussian(np.random.default_rng(500 + n_vec), (n_vec, cr.n_k, cr.n_bands, n_core))
+    y = h.apply(_to_dev(x)).cpu().numpy()
+    f, ut, w = orc.dft_matrix(cr), orc.folded_u(cr), orc.w_supercell(cr)
+    for v in range(n_vec):
+        ref = orc.apply_h(cr, x[v], ut=ut, w=w, f=f)
+        assert _rel(y[v], ref) <= tol, (n_core, n_vec, precision, v, _rel(y[v], ref))
+    h.close()
+
+
 @pytest.mark.parametrize("case", ["c1", "l_tiles", "k8_axis", "cube4", "cube8"])
 def test_apply_borrowed_fp64_matches_oracle(case):
     """A borrowed FP64 u is used as given, so the k-grid transform applies the Bloch phase
