@@ -69,25 +69,25 @@ def proj_bytes(cr, cols, u_elem, phi_elem):
 # WRITE_SIZE 1.0 GiB for 1 GiB written).  A figure holds only for the kernel source it was
 # taken with (sha256 of the .hip file); for any other source the traffic is reported null.
 TRAFFIC = {
-    ("fp64", "proj_fwd"): {"bytes": 7589081753, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 3, 16>
-        "sha256": "baaa90afaf9e5e18a261018ca03bc0b13c98a368c905df6009b7d46cbd3ab2af"},
-    ("fp64", "proj_bwd"): {"bytes": 7535490156, "src": "proj.hip",  # proj_bwd_kernel<double, 3, 32, 6>
-        "sha256": "baaa90afaf9e5e18a261018ca03bc0b13c98a368c905df6009b7d46cbd3ab2af"},
-    ("fp32", "proj_fwd"): {"bytes": 3849091773, "src": "proj.hip",  # proj_fwd_kernel<float, 1, 3, 32>
-        "sha256": "baaa90afaf9e5e18a261018ca03bc0b13c98a368c905df6009b7d46cbd3ab2af"},
-    ("fp32", "proj_bwd"): {"bytes": 3796830825, "src": "proj.hip",  # proj_bwd_kernel<float, 3, 64, 6>
-        "sha256": "baaa90afaf9e5e18a261018ca03bc0b13c98a368c905df6009b7d46cbd3ab2af"},
-    ("split_bf16", "proj_fwd"): {"bytes": 3755327983, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<1, 3, true>
+    ("fp64", "proj_fwd"): {"bytes": 7587380916, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 2, 2, 16>
+        "sha256": "a7910e0e1f38b57d26464e7766731e2e74ce9c991611d6e814fa409a8a1c71bb"},
+    ("fp64", "proj_bwd"): {"bytes": 7547354756, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 16, 3, 6>
+        "sha256": "a7910e0e1f38b57d26464e7766731e2e74ce9c991611d6e814fa409a8a1c71bb"},
+    ("fp32", "proj_fwd"): {"bytes": 3851645039, "src": "proj.hip",  # proj_fwd_kernel<float, 2, 3, 0, 32>
+        "sha256": "a7910e0e1f38b57d26464e7766731e2e74ce9c991611d6e814fa409a8a1c71bb"},
+    ("fp32", "proj_bwd"): {"bytes": 3796871199, "src": "proj.hip",  # proj_bwd_kernel<float, 3, 0, 64, 2, 6>
+        "sha256": "a7910e0e1f38b57d26464e7766731e2e74ce9c991611d6e814fa409a8a1c71bb"},
+    ("split_bf16", "proj_fwd"): {"bytes": 3784066161, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<2, 3, true>
         "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
-    ("split_bf16", "proj_bwd"): {"bytes": 3927675907, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
+    ("split_bf16", "proj_bwd"): {"bytes": 3880147403, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
         "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
-    ("bf16", "proj_fwd"): {"bytes": 2184760631, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<2, 3, false>
+    ("bf16", "proj_fwd"): {"bytes": 2184754980, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<2, 3, false>
         "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
-    ("bf16", "proj_bwd"): {"bytes": 2245180462, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
+    ("bf16", "proj_bwd"): {"bytes": 2234627163, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
         "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
-    ("fp64", "fft_w"): {"bytes": 2392643054, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
+    ("fp64", "fft_w"): {"bytes": 2392654332, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
         "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
-    ("fp32", "fft_w"): {"bytes": 1196251897, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
+    ("fp32", "fft_w"): {"bytes": 1196248320, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
         "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
 }
 

@@ -118,12 +118,13 @@ def apply_w0(cr, psi, ut=None, w=None, f=None):
     nk = psi.shape[0]
     # band -> real space: phi(k, x, alpha) = sum_n psi_{n,k,alpha} e^{ik.x} u_nk(x)
     phi_k = np.stack([ut[k] @ psi[k] for k in range(nk)])            # [k, x, c]
-    # k -> R: phi(R) = F_{k->R}[phi(k)]
-    phi_r = np.einsum("rk,kxc->rxc", f, phi_k)
+    nx, nc = phi_k.shape[1], phi_k.shape[2]
+    # k -> R: phi(R) = F_{k->R}[phi(k)], one matrix product over k for every (x, alpha)
+    phi_r = (f @ phi_k.reshape(nk, nx * nc)).reshape(-1, nx, nc)
     # screened potential: phi(R) = W(x, R) phi(R)
     phi_r = w.T[:, :, None] * phi_r
     # R -> k: phi(k) = F_{R->k}[phi(R)]
-    phi_k = np.einsum("kr,rxc->kxc", f.conj().T, phi_r)
+    phi_k = (f.conj().T @ phi_r.reshape(-1, nx * nc)).reshape(nk, nx, nc)
     # real space -> band: psi'_{n,k,alpha} = sum_x conj(e^{ik.x} u_nk(x)) phi(k, x, alpha)
     return np.stack([(ut[k].T @ phi_k[k].conj()).conj() for k in range(nk)])
 

@@ -943,46 +943,45 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
         return OCEAN_OK;
     };
     int rc = OCEAN_OK;
-    // one knob at a time, the others held at their current values
-    {
-        int best = h->fwd_ms;
-        float best_ms = 1e30f;
-        for (int ms : {1, 2}) {
-            h->fwd_ms = ms;
-            float t;
-            if ((rc = time_kernels({"proj_fwd"}, &t)) != OCEAN_OK) break;
-            if (t < best_ms) { best_ms = t; best = ms; }
-        }
-        h->fwd_ms = best;
-    }
-    if (rc == OCEAN_OK) {
-        int best = h->bwd_target_blocks;
-        float best_ms = 1e30f;
-        for (int bt : {1024, 2048, 4096, 8192}) {
-            h->bwd_target_blocks = bt;
+    // warm the clocks and caches before the first candidate is timed
+    for (int r = 0; r < 3 && rc == OCEAN_OK; ++r) rc = apply_pipeline(h, x, y, n_vec, nullptr);
+    // One knob at a time, the others held at their current values.  Each candidate is timed
+    // twice, the list walked forward and then backward, so that a drift of the clock over the
+    // sweep does not favour the candidates timed last.
+    auto sweep = [&](const std::vector<int>& cand, int* knob, std::initializer_list<const char*> names,
+                     bool bwd) {
+        std::vector<double> tot(cand.size(), 0.0);
+        for (int pass = 0; pass < 2 && rc == OCEAN_OK; ++pass)
+            for (size_t j = 0; j < cand.size() && rc == OCEAN_OK; ++j) {
+                const size_t c = pass == 0 ? j : cand.size() - 1 - j;
+                *knob = cand[c];
+                if (bwd) {
+                    int bb, S, ch;
+                    bwd_geometry(h, &bb, &S, &ch);
+                    h->ws.bwd_chunks = S;
+                }
+                float t;
+                rc = time_kernels(names, &t);
+                tot[c] += t;
+            }
+        if (rc != OCEAN_OK) return;
+        size_t best = 0;
+        for (size_t c = 1; c < cand.size(); ++c)
+            if (tot[c] < tot[best]) best = c;
+        *knob = cand[best];
+        if (bwd) {
             int bb, S, ch;
             bwd_geometry(h, &bb, &S, &ch);
             h->ws.bwd_chunks = S;
-            float t;
-            if ((rc = time_kernels({"proj_bwd", "reduce_part", "combine"}, &t)) != OCEAN_OK) break;
-            if (t < best_ms) { best_ms = t; best = bt; }
         }
-        h->bwd_target_blocks = best;
-        int bb, S, ch;
-        bwd_geometry(h, &bb, &S, &ch);
-        h->ws.bwd_chunks = S;
-    }
+    };
+    if (rc == OCEAN_OK) sweep({1, 2}, &h->fwd_ms, {"proj_fwd"}, false);
+    if (rc == OCEAN_OK) sweep({1024, 2048, 4096, 8192}, &h->bwd_target_blocks, {"proj_bwd", "reduce_part", "combine"}, true);
     if (rc == OCEAN_OK && h->Nk > 1) {
-        int best = h->fft_lines;
-        float best_ms = 1e30f;
-        for (int L : {4, 8, 16, 32, 64}) {
-            if (fft_lds_bytes(h, L) > 160 * 1024) continue;
-            h->fft_lines = L;
-            float t;
-            if ((rc = time_kernels({"fft_w"}, &t)) != OCEAN_OK) break;
-            if (t < best_ms) { best_ms = t; best = L; }
-        }
-        h->fft_lines = best;
+        std::vector<int> lines;
+        for (int L : {4, 8, 16, 32, 64})
+            if (fft_lds_bytes(h, L) <= 160 * 1024) lines.push_back(L);
+        if (!lines.empty()) sweep(lines, &h->fft_lines, {"fft_w"}, false);
     }
     h->stats = saved_stats;
     h->profiling = saved_prof;
