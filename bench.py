@@ -327,6 +327,8 @@ def main():
             torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         del a, b
+    ceilings = ob.device_ceilings(1 << 30)
+    log("measured ceilings: " + ", ".join(f"{k}={v:.1f}" for k, v in ceilings.items()))
     cr, u = build_workload(args.seed)
     n_pol = 3
     cols = n_pol * cr.n_core
@@ -388,7 +390,12 @@ def main():
                 "frac": ach / PEAK_HBM_GBS, "traffic": kernel_traffic("fp64", dom),
                 "algorithmic_bytes": proj_bytes(cr, cols, 16, 16),
                 "mfma_fp64_tflops": proj_flops(cr, cols) / (avg[dom] * 1e-3) / 1e12,
-                "mfma_fp64_frac": proj_flops(cr, cols) / (avg[dom] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+                "mfma_fp64_frac": proj_flops(cr, cols) / (avg[dom] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                "measured_ceilings": ceilings,
+                "frac_of_measured_copy": ach / ceilings["copy_GBs"],
+                "frac_of_measured_read": ach / ceilings["read_GBs"],
+                "fp64_frac_of_measured_mfma": proj_flops(cr, cols) / (avg[dom] * 1e-3) / 1e12
+                                              / ceilings["mfma_f64_tflops"]}
     ok = [m for m in MODES[1:] if results[m].get("spectrum_l1_vs_fp64", 1.0) <= 1e-3]
     best = max(ok, key=lambda m: results[m]["hv_per_s"]) if ok else None
     mixed_best = None if best is None else {

@@ -279,6 +279,22 @@ int ocean_bse_kernel_times(ocean_bse_t h, const char** names, double* total_ms,
  * workspace), or < 0 on error. */
 long long ocean_bse_device_bytes(ocean_bse_t h);
 
+/* Measured ceilings of the current device, for the roofline of the projections of
+ * Algorithm 1 (section 3.2.1), which issue FP64 matrix-core instructions, FP64 multiply-adds
+ * and an HBM stream:
+ *   mfma_f64_tflops  16x16x4 FP64 MFMAs, four independent accumulators per wave, four waves
+ *                    per SIMD (TFLOP/s, 2 flops per multiply-add);
+ *   fma_f64_tflops   wave-wide FP64 multiply-adds, eight independent chains per lane;
+ *   copy_gbs         a copy of copy_bytes (>= 1 MiB), one 16-byte element per thread, bytes
+ *                    read plus bytes written per second (GB/s);
+ *   read_gbs         a read of the same copy_bytes, 1024 consecutive 16-byte elements per
+ *                    block (GB/s).
+ * Each figure is the fastest of three timed launches after an untimed one.  Allocates and frees 2 copy_bytes
+ * of device memory plus small result buffers; synchronous, on a private stream.
+ * Errors: INVALID_ARG (copy_bytes < 1 MiB, NULL output), OUT_OF_MEMORY, DEVICE. */
+int ocean_device_ceilings(long long copy_bytes, double* mfma_f64_tflops, double* fma_f64_tflops,
+                          double* copy_gbs, double* read_gbs);
+
 /* Message describing the last error on the calling thread ("" if none). */
 const char* ocean_last_error(void);
 

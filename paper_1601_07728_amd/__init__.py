@@ -45,6 +45,7 @@ EXPORTED = [
     "ocean_mlp_param_count", "ocean_mlp_create", "ocean_mlp_destroy", "ocean_mlp_set_params",
     "ocean_mlp_get_params", "ocean_mlp_encode", "ocean_mlp_forward", "ocean_mlp_loss_grad",
     "ocean_mlp_train_step", "ocean_mlp_predict", "ocean_mlp_save", "ocean_mlp_load",
+    "ocean_device_ceilings",
 ]
 MLP_BF16 = 0
 MLP_FP32 = 1
@@ -89,6 +90,8 @@ def lib() -> ctypes.CDLL:
     L.ocean_bse_dim.restype = ll
     L.ocean_bse_device_bytes.argtypes = [vp]
     L.ocean_bse_device_bytes.restype = ll
+    L.ocean_device_ceilings.argtypes = [ll] + [ctypes.POINTER(ctypes.c_double)] * 4
+    L.ocean_device_ceilings.restype = ci
     L.ocean_bse_apply.argtypes = [vp, vp, vp, ci]
     L.ocean_bse_apply.restype = ci
     L.ocean_haydock.argtypes = [vp, vp, ci, ci, cu, vp, vp, vp, vp]
@@ -187,6 +190,16 @@ def dipole_amplitudes(pol) -> np.ndarray:
     d = np.zeros((5, 3), dtype=np.complex128)
     _check(lib().ocean_dipole_amplitudes(_ptr(e), _ptr(d)))
     return d
+
+
+def device_ceilings(copy_bytes: int = 1 << 30) -> dict:
+    """Measured FP64 matrix-core and multiply-add rates (TFLOP/s) and the streaming rates of a
+    plain copy (GB/s, read + written) and a plain read on the current device
+    (ocean_device_ceilings)."""
+    m, f, c, r = (ctypes.c_double() for _ in range(4))
+    _check(lib().ocean_device_ceilings(int(copy_bytes), ctypes.byref(m), ctypes.byref(f), ctypes.byref(c),
+                                       ctypes.byref(r)))
+    return {"mfma_f64_tflops": m.value, "fma_f64_tflops": f.value, "copy_GBs": c.value, "read_GBs": r.value}
 
 
 def spectrum(a, b, norm2, omega, gamma: float, terminator: str = "none", n_used=None) -> np.ndarray:

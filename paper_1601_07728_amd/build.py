@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libocean_bse.so")
-SOURCES = ["proj.hip", "proj_bf16.hip", "fftw.hip", "vec.hip", "runtime.hip", "mlp.hip", "multiplet.cpp"]
+SOURCES = ["proj.hip", "proj_bf16.hip", "fftw.hip", "vec.hip", "runtime.hip", "mlp.hip", "ceilings.hip",
+           "multiplet.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions are kept out of every kernel
