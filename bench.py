@@ -125,8 +125,9 @@ def timed_haydock(h, psi0, steps):
     return time.perf_counter() - t0, out
 
 
-def cpu_baseline(cr, u_dev, psi0_host):
-    """The oracle as it stands: one full H*v of one L-edge vector at this size."""
+def cpu_baseline(cr, u_dev, psi0_host, min_seconds=12.0, max_reps=40):
+    """The oracle as it stands, on the same workload: the H*v of the three polarisation
+    vectors of one step, repeated until about min_seconds of CPU time have passed."""
     from oracle import bse as orc
     from oracle import multiplet as omp
     cores = len(os.sched_getaffinity(0))
@@ -135,13 +136,17 @@ def cpu_baseline(cr, u_dev, psi0_host):
     ut = orc.folded_u(cr)
     w = orc.w_supercell(cr)
     f = orc.dft_matrix(cr)
+    n_hv = 0
     t0 = time.perf_counter()
-    orc.apply_h(cr, psi0_host, hc, kl, ut=ut, w=w, f=f)
+    while n_hv < max_reps * len(psi0_host) and (n_hv == 0 or time.perf_counter() - t0 < min_seconds):
+        for v in psi0_host:
+            orc.apply_h(cr, v, hc, kl, ut=ut, w=w, f=f)
+            n_hv += 1
     dt = time.perf_counter() - t0
     cr.u = None
-    return {"value": 1.0 / dt, "unit": "H*v/s", "cores": cores, "kind": "oracle",
-            "sample": f"one full H*v of one vector (6 core columns) at the benchmark size, "
-                      f"{dt:.1f} s, numpy FP64 with {cores} host threads"}
+    return {"value": n_hv / dt, "unit": "H*v/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_hv} full H*v at the benchmark size (the 3 polarisation vectors of a step, "
+                      f"repeated), {dt:.1f} s, numpy FP64 with {cores} host threads"}
 
 
 def bench_batched(ob, seed, steps=200):
@@ -419,8 +424,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle (one H*v)")
-        cpu = cpu_baseline(cr, u, psi0[0].cpu().numpy())
+        log("timing the CPU oracle (H*v of the step's polarisation vectors, about 12 s)")
+        cpu = cpu_baseline(cr, u, psi0.cpu().numpy())
         log(f"cpu baseline {cpu['value']:.4f} H*v/s on {cpu['cores']} cores")
 
     line = {
