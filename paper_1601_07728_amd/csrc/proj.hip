@@ -544,8 +544,14 @@ void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks,
     const long long per_chunk = (long long)h->Nk * bb;
     long long s = (target_blocks + per_chunk - 1) / per_chunk;
     const long long smax = std::max(1, (h->Nx + 511) / 512);  // >= 512 points per chunk
+    // The partials of one chunk (up to kColsPerPass complex FP64 columns per band) written
+    // and read back stay within 5% of the u bytes the chunk streams.  This binds for
+    // Gamma-only systems with many x points, whose grid otherwise comes from x chunks alone.
+    const int ue = h->precision == OCEAN_PREC_FP64 ? 16 : h->precision == OCEAN_PREC_BF16 ? 4 : 8;
+    const long long scap = std::max(1LL, (long long)h->Nx * ue / (20LL * 16 * kColsPerPass));
     if (s < 1) s = 1;
     if (s > smax) s = smax;
+    if (s > scap) s = scap;
     int c = (int)((h->Nx + s - 1) / s);
     c = (c + kXB - 1) / kXB * kXB;
     *chunk = c;
