@@ -87,7 +87,15 @@ typedef struct {
     int n_bands;          /* Nb >= 1 conduction bands per k */
     int n_core;           /* Nc >= 1 core states (2: 1s with spin, 6: 2p with spin) */
     int n_local;          /* Nmu >= 0 local channels; 0 disables the short-range term */
-    double cell[3];       /* orthorhombic cell edge lengths, bohr (> 0) */
+    double cell[3][3];    /* rows: lattice vectors a1, a2, a3 of the cell, bohr, any shape with
+                             nonzero volume.  Grid point j of the cell is x = sum_d (j_d / g_d) a_d,
+                             lattice vector r of the supercell is R = sum_d r_d a_d.  The minimum
+                             image of x + R - tau in the Born-von-Karman supercell (rows n_d a_d) is
+                             taken over the 27 translations around its wrapped fractional
+                             coordinates: exact for a reduced (not strongly skewed) basis.
+                             A k grid offset by a fraction of a step needs no input: the offset
+                             cancels in W0 (only k - k' enters), so u_nk and E_nk at the offset
+                             points are all that changes. */
     double tau[3];        /* absorbing-site position, bohr */
     const double* energies;   /* [Nk][Nb] real, Ha: H_e eigenvalues E_nk (section 2) */
     const double* u;          /* [Nk][Nx][Nb] complex: periodic Bloch parts u_nk(x), columns

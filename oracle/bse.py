@@ -14,13 +14,16 @@ equation calculations", section 2 and section 3.2):
 * the short-range terms through the local basis (eq. local_basis, section 3.2.2)
 * the Haydock recursion (eq. haydock1 and the cited Haydock method)
 
-Readings where the paper is silent (each is listed in the design doc):
+Readings where the paper is silent:
 
 * Fourier pair of Algorithm 1 (k -> R and back): unitary, e^{+ik.R} forward and
   e^{-ik.R} back, with Nk^{-1/2} each way.
 * W(x, R) = W_rad(|x + R - tau|) with the minimum image in the Born-von-Karman
   supercell (the k grid fixes the range of W, section 3.2.1); W_rad is the
   linear interpolation of the radial table, and W(r_max) r_max / r beyond it.
+* The cell is given by three lattice vectors (any shape); x and R are fractional
+  multiples of them.  The k grid may be offset by a fraction of a grid step along
+  each reciprocal vector (the paper's runs use shifted 2x2x2 grids, section 4).
 * -V_D enters with a minus sign; eps_c = 0; Gamma is a constant Lorentzian
   broadening z = w + i Gamma.
 * Haydock is the three-term Lanczos recursion; b_0 = 0; optional full
@@ -46,19 +49,33 @@ def _grid_indices(n):
     return np.stack([i1.ravel(), i2.ravel(), i3.ravel()], axis=1).astype(np.float64)
 
 
+def cell_vectors(cr):
+    """Rows a1, a2, a3 of the cell, bohr (cr.lattice, or a cubic cell of edge cr.a)."""
+    lat = getattr(cr, "lattice", None)
+    return np.asarray(lat, dtype=np.float64) if lat is not None else cr.a * np.eye(3)
+
+
+def reciprocal_vectors(cr):
+    """Rows b1, b2, b3 with a_i . b_j = 2 pi delta_ij."""
+    return 2.0 * math.pi * np.linalg.inv(cell_vectors(cr)).T
+
+
 def kpoints(cr):
-    """Gamma-centred unshifted k grid, k = (2 pi / a)(i / n)."""
-    return (2.0 * math.pi / cr.a) * _grid_indices(cr.nk) / np.asarray(cr.nk, dtype=np.float64)
+    """k = sum_d ((i_d + s_d) / n_d) b_d: the k grid, offset by s_d grid steps along b_d
+    (s = 0 is the Gamma-centred unshifted grid; the paper's runs use s = 1/2)."""
+    shift = np.asarray(getattr(cr, "kshift", (0.0, 0.0, 0.0)), dtype=np.float64)
+    frac = (_grid_indices(cr.nk) + shift) / np.asarray(cr.nk, dtype=np.float64)
+    return frac @ reciprocal_vectors(cr)
 
 
 def lattice_vectors(cr):
-    """R = a r, r_d in [0, n_d): the cells of the Born-von-Karman supercell."""
-    return cr.a * _grid_indices(cr.nk)
+    """R = sum_d r_d a_d, r_d in [0, n_d): the cells of the Born-von-Karman supercell."""
+    return _grid_indices(cr.nk) @ cell_vectors(cr)
 
 
 def xpoints(cr):
-    """x = a j / g, j_d in [0, g_d): the real-space grid of one cell."""
-    return cr.a * _grid_indices(cr.nx) / np.asarray(cr.nx, dtype=np.float64)
+    """x = sum_d (j_d / g_d) a_d, j_d in [0, g_d): the real-space grid of one cell."""
+    return (_grid_indices(cr.nx) / np.asarray(cr.nx, dtype=np.float64)) @ cell_vectors(cr)
 
 
 # --- the screened core-hole potential W(x, R) ---------------------------------------------
@@ -81,16 +98,35 @@ def w_radial(w_r, w_val, r):
     return out
 
 
+def min_image_distance(d, sup):
+    """|d| for the image of d nearest the origin in the lattice whose rows are sup.  The
+    fractional coordinates are wrapped into [-1/2, 1/2) and the 27 images around the
+    wrapped point are compared; for an orthogonal lattice the wrapped point itself is the
+    nearest.  (For a reduced, not too skewed basis the nearest image is among the 27; the
+    pins compare against a wider search.)"""
+    f = d @ np.linalg.inv(sup)
+    f = f - np.round(f)
+    if np.allclose(sup, np.diag(np.diag(sup))):
+        return np.sqrt(np.sum((f @ sup) ** 2, axis=-1))
+    best = None
+    for m in np.ndindex(3, 3, 3):
+        dist = np.sqrt(np.sum(((f + (np.array(m) - 1)) @ sup) ** 2, axis=-1))
+        best = dist if best is None else np.minimum(best, dist)
+    return best
+
+
 def w_supercell(cr):
-    """W[x, R] = W_rad(|x + R - tau|) with the minimum image in the supercell of
-    side n_d a along each axis."""
+    """W[x, R] = W_rad(|x + R - tau|) with the minimum image in the Born-von-Karman
+    supercell (rows n_d a_d)."""
     x = xpoints(cr)
     rv = lattice_vectors(cr)
-    side = cr.a * np.asarray(cr.nk, dtype=np.float64)
-    d = x[:, None, :] + rv[None, :, :] - cr.tau[None, None, :]
-    d = d - side * np.round(d / side)
-    dist = np.sqrt(np.sum(d * d, axis=2))
-    return w_radial(cr.w_r, cr.w_val, dist.ravel()).reshape(dist.shape)
+    sup = np.asarray(cr.nk, dtype=np.float64)[:, None] * cell_vectors(cr)
+    out = np.empty((len(x), len(rv)))
+    step = max(1, (1 << 22) // max(1, len(rv)))   # x points per chunk: about 4M (x, R) pairs
+    for x0 in range(0, len(x), step):
+        d = x[x0:x0 + step, None, :] + rv[None, :, :] - np.asarray(cr.tau)[None, None, :]
+        out[x0:x0 + step] = w_radial(cr.w_r, cr.w_val, min_image_distance(d, sup).ravel()).reshape(d.shape[:2])
+    return out
 
 
 def folded_u(cr):

@@ -51,6 +51,19 @@ MLP_BF16 = 0
 MLP_FP32 = 1
 
 
+def cell_matrix(cell) -> np.ndarray:
+    """Lattice vectors as the rows of a 3x3 array (bohr) from an edge length (cubic cell),
+    three edge lengths (orthorhombic) or the 3x3 rows themselves."""
+    c = np.asarray(cell, dtype=np.float64)
+    if c.ndim == 0:
+        return float(c) * np.eye(3)
+    if c.shape == (3,):
+        return np.diag(c)
+    if c.shape == (3, 3):
+        return c.copy()
+    raise ValueError("cell: an edge length, three edge lengths or a 3x3 array of lattice vectors")
+
+
 class OceanError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"[{code}] {msg}")
@@ -60,7 +73,7 @@ class OceanError(RuntimeError):
 class Desc(ctypes.Structure):
     _fields_ = [
         ("nk", ctypes.c_int * 3), ("nx", ctypes.c_int * 3), ("n_bands", ctypes.c_int),
-        ("n_core", ctypes.c_int), ("n_local", ctypes.c_int), ("cell", ctypes.c_double * 3),
+        ("n_core", ctypes.c_int), ("n_local", ctypes.c_int), ("cell", (ctypes.c_double * 3) * 3),
         ("tau", ctypes.c_double * 3), ("energies", ctypes.c_void_p), ("u", ctypes.c_void_p),
         ("n_wr", ctypes.c_int), ("w_r", ctypes.c_void_p), ("w_val", ctypes.c_void_p),
         ("local_proj", ctypes.c_void_p), ("local_mat", ctypes.c_void_p),
@@ -258,7 +271,7 @@ class Bse:
         import torch
         nk = tuple(int(v) for v in nk)
         nx = tuple(int(v) for v in nx)
-        cell = np.broadcast_to(np.asarray(cell, dtype=np.float64), (3,))
+        cell = cell_matrix(cell)
         self._keep = []
         e = _host_f64(energies)
         n_bands = e.shape[-1]
@@ -287,7 +300,8 @@ class Bse:
         d.n_bands = n_bands
         d.n_core = int(n_core)
         d.n_local = 0 if lp is None else lp.shape[-1]
-        d.cell[:] = [float(v) for v in cell]
+        for a in range(3):
+            d.cell[a][:] = [float(v) for v in cell[a]]
         d.tau[:] = [float(v) for v in np.asarray(tau, dtype=np.float64)]
         d.energies = _ptr(e)
         d.u = uptr
@@ -320,7 +334,7 @@ class Bse:
                 lp = cr.local_proj
             else:
                 local_mat = None
-        return cls(nk=cr.nk, nx=cr.nx, cell=cr.a, tau=cr.tau, energies=cr.energies,
+        return cls(nk=cr.nk, nx=cr.nx, cell=cr.cell_vectors(), tau=cr.tau, energies=cr.energies,
                    u=cr.u if u is None else u, w_r=cr.w_r, w_val=cr.w_val, n_core=cr.n_core,
                    local_proj=lp, local_mat=local_mat, core_mat=core_mat, precision=precision, **kw)
 

@@ -92,7 +92,7 @@ struct KernelStat {
 struct ocean_bse_s {
     int nk[3], nx[3];
     int Nk, Nx, Nb, Nc, Nmu;
-    double cell[3], tau[3];
+    double cell[9], tau[3];      // lattice vectors as rows (a1, a2, a3), bohr
     int precision;
     unsigned flags;
     int device;
@@ -166,6 +166,14 @@ template <> __device__ __forceinline__ void bstore<float2>(float2 v, Rsrc r, uns
 
 // Bloch phase e^{ik.x} of row g = k Nx + x of u, from the per-axis tables
 // ph[po[a] + i n_x[a]... ] = e^{2 pi i i_a j_a / (n_k[a] n_x[a])}.
+// Geometry of the W(x, R) table: cell rows A, supercell rows S = n_d a_d and S^-1 (row-major,
+// row-vector convention: cartesian = fractional . rows), tau, and whether the S_d are
+// mutually orthogonal (then the wrapped image is the nearest).
+struct WGeom {
+    double A[9], S[9], Sinv[9], tau[3];
+    int ortho;
+};
+
 struct PhaseArgs {
     const double* ph;
     int po[3], nk[3], nx[3];

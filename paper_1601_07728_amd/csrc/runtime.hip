@@ -351,8 +351,22 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
             set_error("ocean_bse_create: k-grid extent per axis above 16 is not supported");
             return OCEAN_ERR_UNSUPPORTED;
         }
-        if (!(d->cell[a] > 0.0) || !std::isfinite(d->cell[a]) || !std::isfinite(d->tau[a])) {
-            set_error("ocean_bse_create: cell lengths must be positive and finite");
+        if (!std::isfinite(d->cell[a][0]) || !std::isfinite(d->cell[a][1]) || !std::isfinite(d->cell[a][2]) ||
+            !std::isfinite(d->tau[a])) {
+            set_error("ocean_bse_create: lattice vectors and tau must be finite");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+    }
+    {
+        const double (*c)[3] = d->cell;
+        const double det = c[0][0] * (c[1][1] * c[2][2] - c[1][2] * c[2][1]) -
+                           c[0][1] * (c[1][0] * c[2][2] - c[1][2] * c[2][0]) +
+                           c[0][2] * (c[1][0] * c[2][1] - c[1][1] * c[2][0]);
+        const double scale = std::sqrt((c[0][0] * c[0][0] + c[0][1] * c[0][1] + c[0][2] * c[0][2]) *
+                                       (c[1][0] * c[1][0] + c[1][1] * c[1][1] + c[1][2] * c[1][2]) *
+                                       (c[2][0] * c[2][0] + c[2][1] * c[2][1] + c[2][2] * c[2][2]));
+        if (!(std::fabs(det) > 1e-9 * scale)) {
+            set_error("ocean_bse_create: the lattice vectors span no volume");
             return OCEAN_ERR_INVALID_ARG;
         }
     }
@@ -441,7 +455,7 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
     for (int a = 0; a < 3; ++a) {
         h->nk[a] = d->nk[a];
         h->nx[a] = d->nx[a];
-        h->cell[a] = d->cell[a];
+        for (int b = 0; b < 3; ++b) h->cell[3 * a + b] = d->cell[a][b];
         h->tau[a] = d->tau[a];
     }
     h->Nk = (int)Nk;

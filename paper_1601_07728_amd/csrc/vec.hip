@@ -454,8 +454,7 @@ __global__ __launch_bounds__(256) void build_w_kernel(double* __restrict__ W64, 
                                                       const double* __restrict__ wr,
                                                       const double* __restrict__ wv, int n_wr,
                                                       double hstep, int n1, int n2, int n3,
-                                                      int g1, int g2, int g3, double c1, double c2,
-                                                      double c3, double t1, double t2, double t3) {
+                                                      int g1, int g2, int g3, WGeom geo) {
     const long long Nk = (long long)n1 * n2 * n3;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long Nx = (long long)g1 * g2 * g3;
@@ -466,16 +465,31 @@ __global__ __launch_bounds__(256) void build_w_kernel(double* __restrict__ W64, 
     const int j3 = x % g3, j2 = (x / g3) % g2, j1 = x / (g2 * g3);
     const int r1 = q % n1, r23 = q / n1;
     const int r3 = r23 % n3, r2 = r23 / n3;
+    // x + R - tau in cartesian coordinates (fractional cell coordinates times the rows a_d)
+    const double c[3] = {(double)j1 / g1 + r1, (double)j2 / g2 + r2, (double)j3 / g3 + r3};
     double d[3];
-    d[0] = c1 * ((double)j1 / g1 + r1) - t1;
-    d[1] = c2 * ((double)j2 / g2 + r2) - t2;
-    d[2] = c3 * ((double)j3 / g3 + r3) - t3;
-    const double side[3] = {c1 * n1, c2 * n2, c3 * n3};
-    double dist2 = 0.0;
+    for (int b = 0; b < 3; ++b) d[b] = c[0] * geo.A[b] + c[1] * geo.A[3 + b] + c[2] * geo.A[6 + b] - geo.tau[b];
+    // fractional coordinates in the supercell (rows S_d = n_d a_d), wrapped into [-1/2, 1/2]
+    double f[3];
     for (int a = 0; a < 3; ++a) {
-        const double m = d[a] - side[a] * rint(d[a] / side[a]);
-        dist2 += m * m;
+        f[a] = d[0] * geo.Sinv[a] + d[1] * geo.Sinv[3 + a] + d[2] * geo.Sinv[6 + a];
+        f[a] -= rint(f[a]);
     }
+    // nearest image: the wrapped point itself for mutually orthogonal S_d, else the nearest
+    // of the 27 translations around it
+    double dist2 = 1e300;
+    const int reach = geo.ortho ? 0 : 1;
+    for (int m0 = -reach; m0 <= reach; ++m0)
+        for (int m1 = -reach; m1 <= reach; ++m1)
+            for (int m2 = -reach; m2 <= reach; ++m2) {
+                const double e0 = f[0] + m0, e1 = f[1] + m1, e2 = f[2] + m2;
+                double s2 = 0.0;
+                for (int b = 0; b < 3; ++b) {
+                    const double v = e0 * geo.S[b] + e1 * geo.S[3 + b] + e2 * geo.S[6 + b];
+                    s2 += v * v;
+                }
+                dist2 = fmin(dist2, s2);
+            }
     const double dist = sqrt(dist2);
     const double rmax = wr[n_wr - 1];
     double val;
@@ -747,9 +761,39 @@ hipError_t launch_spectrum(const double* a, const double* b, const int* n_used, 
 hipError_t launch_build_w(ocean_bse_s* h, const double* wr_dev, const double* wv_dev, int n_wr,
                           double h_r) {
     const long long n = (long long)h->Nx * h->Nk;
+    WGeom geo;
+    for (int i = 0; i < 9; ++i) {
+        geo.A[i] = h->cell[i];
+        geo.S[i] = h->cell[i] * h->nk[i / 3];
+    }
+    for (int b = 0; b < 3; ++b) geo.tau[b] = h->tau[b];
+    // inverse of S by cofactors (S nonsingular: checked at creation)
+    const double* S = geo.S;
+    const double det = S[0] * (S[4] * S[8] - S[5] * S[7]) - S[1] * (S[3] * S[8] - S[5] * S[6]) +
+                       S[2] * (S[3] * S[7] - S[4] * S[6]);
+    geo.Sinv[0] = (S[4] * S[8] - S[5] * S[7]) / det;
+    geo.Sinv[1] = (S[2] * S[7] - S[1] * S[8]) / det;
+    geo.Sinv[2] = (S[1] * S[5] - S[2] * S[4]) / det;
+    geo.Sinv[3] = (S[5] * S[6] - S[3] * S[8]) / det;
+    geo.Sinv[4] = (S[0] * S[8] - S[2] * S[6]) / det;
+    geo.Sinv[5] = (S[2] * S[3] - S[0] * S[5]) / det;
+    geo.Sinv[6] = (S[3] * S[7] - S[4] * S[6]) / det;
+    geo.Sinv[7] = (S[1] * S[6] - S[0] * S[7]) / det;
+    geo.Sinv[8] = (S[0] * S[4] - S[1] * S[3]) / det;
+    geo.ortho = 1;
+    for (int i = 0; i < 3; ++i)
+        for (int j = i + 1; j < 3; ++j) {
+            double dot = 0.0, ni = 0.0, nj = 0.0;
+            for (int b = 0; b < 3; ++b) {
+                dot += S[3 * i + b] * S[3 * j + b];
+                ni += S[3 * i + b] * S[3 * i + b];
+                nj += S[3 * j + b] * S[3 * j + b];
+            }
+            if (std::fabs(dot) > 1e-12 * std::sqrt(ni * nj)) geo.ortho = 0;
+        }
     build_w_kernel<<<(unsigned)((n + 255) / 256), 256, 0, h->stream>>>(
         h->W64, h->W32, wr_dev, wv_dev, n_wr, h_r, h->nk[0], h->nk[1], h->nk[2], h->nx[0],
-        h->nx[1], h->nx[2], h->cell[0], h->cell[1], h->cell[2], h->tau[0], h->tau[1], h->tau[2]);
+        h->nx[1], h->nx[2], geo);
     return hipGetLastError();
 }
 

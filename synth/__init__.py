@@ -65,6 +65,12 @@ class Crystal:
     gamma: float = 0.5 / HARTREE_EV           # Lorentzian HWHM, Ha
     omega: np.ndarray = field(default_factory=lambda: np.zeros(0))  # Ha
     eps: float = 5.0
+    lattice: Optional[np.ndarray] = None      # (3, 3) rows a1, a2, a3, bohr; None: cubic cell of edge a
+    kshift: tuple = (0.0, 0.0, 0.0)           # k-grid offset along b_d, in grid steps (0: Gamma-centred)
+
+    def cell_vectors(self) -> np.ndarray:
+        """Rows a1, a2, a3 of the cell (bohr)."""
+        return np.asarray(self.lattice, dtype=np.float64) if self.lattice is not None else self.a * np.eye(3)
 
     @property
     def n_k(self) -> int:

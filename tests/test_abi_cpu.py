@@ -61,12 +61,17 @@ def test_spectrum_rejects_bad_arguments(lib):
         ob.spectrum(a, a, [1.0], om, gamma=0.1, n_used=[9])
 
 
+def _set_cell(d, rows):
+    for a in range(3):
+        d.cell[a][:] = [float(x) for x in np.asarray(rows, dtype=float)[a]]
+
+
 def _desc(**over):
     d = ob.Desc()
     d.nk[:] = (2, 2, 2)
     d.nx[:] = (4, 4, 4)
     d.n_bands, d.n_core, d.n_local = 4, 2, 0
-    d.cell[:] = (7.0, 7.0, 7.0)
+    _set_cell(d, 7.0 * np.eye(3))
     keep = []
     e = np.zeros((8, 4))
     u = np.zeros((8, 64, 4), dtype=np.complex128)
@@ -83,7 +88,9 @@ def _desc(**over):
         elif k == "energies":
             keep.append(v)
             d.energies = ob._ptr(v)
-        elif k in ("nk", "nx", "cell"):
+        elif k == "cell":
+            _set_cell(d, v)
+        elif k in ("nk", "nx"):
             getattr(d, k)[:] = v
         else:
             setattr(d, k, v)
@@ -94,7 +101,8 @@ def _desc(**over):
     (dict(n_bands=0), ob.ERR_INVALID_ARG),
     (dict(nk=(0, 2, 2)), ob.ERR_INVALID_ARG),
     (dict(nk=(17, 1, 1)), ob.ERR_UNSUPPORTED),
-    (dict(cell=(7.0, -1.0, 7.0)), ob.ERR_INVALID_ARG),
+    (dict(cell=[[7.0, 0.0, 0.0], [7.0, 0.0, 0.0], [0.0, 0.0, 7.0]]), ob.ERR_INVALID_ARG),   # no volume
+    (dict(cell=[[7.0, 0.0, 0.0], [0.0, np.nan, 0.0], [0.0, 0.0, 7.0]]), ob.ERR_INVALID_ARG),
     (dict(n_core=9), ob.ERR_UNSUPPORTED),
     (dict(n_local=5), ob.ERR_INVALID_ARG),          # no projectors given
     (dict(precision=7), ob.ERR_UNSUPPORTED),

@@ -103,6 +103,62 @@ def test_apply_column_splits_match_oracle(n_core, n_vec, precision, tol):
     h.close()
 
 
+def _lattice_case(name):
+    """Cells of other shapes, and a k grid offset by half a step (the oracle applies the
+    offset in its phases and transform; the library needs no input for it, since the
+    offset cancels in W0)."""
+    skewed = np.array([[7.0, 0.0, 0.0], [2.1, 6.4, 0.0], [-1.3, 1.7, 6.9]])
+    hexagonal = np.array([[6.0, 0.0, 0.0], [3.0, 3.0 * np.sqrt(3.0), 0.0], [0.0, 0.0, 7.5]])
+    if name == "skewed":
+        cr = synth.small_l_edge(seed=31, nk=(2, 2, 2), nx=(5, 4, 6), n_bands=13)
+        cr.lattice = skewed
+    elif name == "hexagonal":
+        cr = synth.small_l_edge(seed=32, nk=(3, 3, 2), nx=(6, 6, 5), n_bands=11)
+        cr.lattice = hexagonal
+    elif name == "orthorhombic":
+        cr = synth.small_l_edge(seed=33, nk=(2, 4, 1), nx=(5, 6, 7), n_bands=9)
+        cr.lattice = np.diag([6.5, 7.2, 8.1])
+    else:   # skewed cell, grid offset by half a step along b1 and b3
+        cr = synth.small_l_edge(seed=34, nk=(2, 2, 2), nx=(4, 5, 4), n_bands=10)
+        cr.lattice = skewed
+        cr.kshift = (0.5, 0.0, 0.5)
+    cr.tau = np.array([1.3, 2.2, 0.7])
+    return cr
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-5)])
+@pytest.mark.parametrize("case", ["skewed", "hexagonal", "orthorhombic", "skewed_offset_grid"])
+def test_apply_lattices_match_oracle(case, precision, tol):
+    ob = _ob()
+    cr = _lattice_case(case)
+    _say(f"[apply lattice] case={case} {precision} nk={cr.nk} nx={cr.nx} nb={cr.n_bands}")
+    h = ob.Bse.from_crystal(cr, precision=precision, check_inputs=True)
+    hc, kl = _oracle_mats(cr)
+    x = synth.complex_gaussian(np.random.default_rng(91), (3, cr.n_k, cr.n_bands, cr.n_core))
+    y = h.apply(_to_dev(x)).cpu().numpy()
+    f, ut, w = orc.dft_matrix(cr), orc.folded_u(cr), orc.w_supercell(cr)
+    for v in range(3):
+        ref = orc.apply_h(cr, x[v], hc, kl, ut=ut, w=w, f=f)
+        assert _rel(y[v], ref) <= tol, (case, precision, v, _rel(y[v], ref))
+    h.close()
+
+
+@pytest.mark.parametrize("case", ["skewed", "skewed_offset_grid"])
+def test_apply_lattice_borrowed_fp64(case):
+    """The same with u borrowed from the device (the transform applies the phase)."""
+    ob = _ob()
+    cr = _lattice_case(case)
+    _say(f"[apply lattice borrowed] case={case}")
+    h = ob.Bse.from_crystal(cr, precision="fp64", u=_to_dev(cr.u))
+    hc, kl = _oracle_mats(cr)
+    x = synth.complex_gaussian(np.random.default_rng(92), (2, cr.n_k, cr.n_bands, cr.n_core))
+    y = h.apply(_to_dev(x)).cpu().numpy()
+    for v in range(2):
+        ref = orc.apply_h(cr, x[v], hc, kl)
+        assert _rel(y[v], ref) <= 1e-13, (case, v, _rel(y[v], ref))
+    h.close()
+
+
 @pytest.mark.parametrize("case", ["c1", "l_tiles", "k8_axis", "cube4", "cube8"])
 def test_apply_borrowed_fp64_matches_oracle(case):
     """A borrowed FP64 u is used as given, so the k-grid transform applies the Bloch phase

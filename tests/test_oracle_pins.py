@@ -53,19 +53,25 @@ def test_w0_matches_supercell_brute_force(small_l):
     local potential W(x + R) between normalised Bloch functions
     e^{ik.(R+x)} u_nk(x) / sqrt(Nk) on the Born-von-Karman supercell (section 3.2,
     expansion of Phi_alpha(x, R)).  No DFT matrix is used on this side."""
-    cr = small_l
+    _w0_brute_force_check(small_l)
+
+
+def _w0_brute_force_check(cr, reach=1):
+    """W0 of Algorithm 1 against the matrix element of W(x + R - tau) between Bloch
+    functions e^{ik.(R+x)} u_nk(x) / sqrt(Nk), built point by point, with the minimum image
+    found by trying every supercell translation with coefficients in [-reach, reach]
+    (no wrapping)."""
     kv = bse.kpoints(cr)
     rv = bse.lattice_vectors(cr)
     xv = bse.xpoints(cr)
-    side = cr.a * np.asarray(cr.nk, dtype=float)
+    sup = np.asarray(cr.nk, dtype=float)[:, None] * cr.cell_vectors()
+    shifts = [np.array(m) - reach for m in np.ndindex(*(2 * reach + 1,) * 3)]
     bloch = np.zeros((cr.n_k, cr.n_bands, cr.n_x, cr.n_k), dtype=np.complex128)
     wsc = np.zeros((cr.n_x, cr.n_k))
     for ix, x in enumerate(xv):
         for ir, r in enumerate(rv):
             pos = x + r
-            # brute-force minimum image: nearest of the 27 neighbouring images
-            best = min(np.linalg.norm(pos - cr.tau + side * np.array(s))
-                       for s in np.ndindex(3, 3, 3) for s in [np.array(s) - 1])
+            best = min(np.linalg.norm(pos - cr.tau + m @ sup) for m in shifts)
             wsc[ix, ir] = bse.w_radial(cr.w_r, cr.w_val, np.array([best]))[0]
             for ik, k in enumerate(kv):
                 bloch[ik, :, ix, ir] = np.exp(1j * k @ pos) * cr.u[ik, ix, :] / math.sqrt(cr.n_k)
@@ -74,6 +80,64 @@ def test_w0_matches_supercell_brute_force(small_l):
     m = bse.w0_matrix(cr)
     assert np.abs(m - m_ref).max() <= 1e-13 * np.abs(m_ref).max()
     assert np.abs(bse.w_supercell(cr) - wsc).max() <= 1e-15 * wsc.max()
+
+
+SKEWED = np.array([[7.0, 0.0, 0.0], [2.1, 6.4, 0.0], [-1.3, 1.7, 6.9]])   # a reduced triclinic cell
+HEXAGONAL = np.array([[6.0, 0.0, 0.0], [3.0, 3.0 * math.sqrt(3.0), 0.0], [0.0, 0.0, 7.5]])
+
+
+def test_w0_brute_force_skewed_cell_shifted_grid():
+    """The same definition on a triclinic cell with a k grid offset by half a step, with
+    images up to two supercell vectors away."""
+    cr = synth.small_l_edge(seed=21, nk=(2, 1, 2), nx=(3, 4, 3), n_bands=5)
+    cr.lattice = SKEWED
+    cr.kshift = (0.5, 0.0, 0.5)
+    _w0_brute_force_check(cr, reach=2)
+
+
+def test_min_image_on_a_60_degree_lattice():
+    """Closed forms on the plane hexagonal lattice of spacing L: the midpoint of a1 and
+    a2 lies L/2 from the lattice points a1 and a2 (wrapping the fractional coordinates
+    alone gives |a1 + a2| / 2 = L sqrt(3)/2, so the image search is needed); the centre of a
+    triangle lies L/sqrt(3) from its corners; a lattice point lies at distance 0."""
+    L = 6.0
+    sup = HEXAGONAL
+    a1, a2 = sup[0], sup[1]
+    d = np.array([0.5 * (a1 + a2), (a1 + a2) / 3.0, 2.0 * (a1 + a2) / 3.0, a1 - a2, 3 * a1 + 2 * sup[2]])
+    got = bse.min_image_distance(d, sup)
+    want = np.array([0.5 * L, L / math.sqrt(3.0), L / math.sqrt(3.0), 0.0, 0.0])
+    assert np.abs(got - want).max() <= 1e-12 * L
+
+
+def test_sheared_basis_gives_the_same_supercell_potential():
+    """a2' = a1 + a2 spans the same cubic lattice.  With equal counts along a1 and a2
+    the x grid, the supercell and hence the set of distances |x + R - tau| are the same, so
+    W(x, R) takes the same multiset of values."""
+    cr = synth.small_l_edge(seed=22, nk=(2, 2, 1), nx=(4, 4, 3), n_bands=3)
+    cr.tau = np.array([1.1, 0.4, 2.3])
+    w_cubic = np.sort(bse.w_supercell(cr).ravel())
+    cr.lattice = cr.a * np.array([[1.0, 0.0, 0.0], [1.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    w_sheared = np.sort(bse.w_supercell(cr).ravel())
+    assert np.abs(w_cubic - w_sheared).max() <= 1e-14 * w_cubic.max()
+
+
+def test_grid_offset_cancels_in_w0():
+    """An offset of the k grid by a fraction of a step cancels in W0: the transforms meet as
+    e^{-i(k - k').R} and the Bloch phases as e^{-i(k - k').x}, and k - k' is a whole number
+    of steps.  Given u_nk at the offset points, W0 is the same operator as on the unshifted
+    grid (the plain definition with the offset is checked point by point in
+    test_w0_brute_force_skewed_cell_shifted_grid)."""
+    cr = synth.small_l_edge(seed=23, nk=(2, 2, 2), nx=(4, 3, 5), n_bands=6)
+    cr.lattice = SKEWED
+    psi = _rand((cr.n_k, cr.n_bands, cr.n_core))
+    plain = bse.apply_w0(cr, psi)
+    cr.kshift = (0.5, 0.25, 0.5)
+    shifted = bse.apply_w0(cr, psi)
+    assert np.abs(shifted - plain).max() <= 1e-13 * np.abs(plain).max()
+    # the offset does change each factor: the folded u and the transform
+    assert np.abs(bse.folded_u(cr) - bse.folded_u(synth.small_l_edge(seed=23, nk=(2, 2, 2), nx=(4, 3, 5),
+                                                                       n_bands=6))).max() > 0.1 * np.abs(cr.u).max()
+
 
 
 def test_constant_w_is_rigid_shift(c1):
