@@ -312,6 +312,7 @@ def main():
     ap.add_argument("--term-epochs", type=int, default=120)
     ap.add_argument("--no-terminator", action="store_true")
     ap.add_argument("--no-spectra", action="store_true")
+    ap.add_argument("--no-full-spin", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first stream 1 GiB through a plain elementwise kernel (1 GiB read, 1 GiB "
                          "written): the reference for scaling the HBM byte counters")
@@ -353,6 +354,26 @@ def main():
         results[name].update({"ms_per_step": 1e3 * dt / args.steps,
                               "hv_per_s": n_pol * args.steps / dt})
         log(f"{name}: {results[name]['ms_per_step']:.3f} ms/step, {results[name]['hv_per_s']:.1f} H*v/s")
+
+    # the same crystal with the electron spin carried separately (12 core states, twice the
+    # columns per H*v); one FP64 and one BF16 handle
+    full_spin = None
+    if not args.no_full_spin:
+        import synth
+        crf = synth.full_spin(cr)
+        full_spin = {"config": "the c2 workload with the electron spin carried separately: 12 core states, "
+                               f"H dim {crf.dim}, 3 polarisations (36 columns per step)"}
+        for name in ("fp64", "bf16"):
+            hf = ob.Bse.from_crystal(crf, precision=name, u=u)
+            hf.autotune(n_vec=n_pol)
+            pf = hf.dipole_psi0(np.eye(3))
+            timed_haydock(hf, pf, args.warmup)
+            dt, _ = timed_haydock(hf, pf, args.steps)
+            full_spin[name] = {"ms_per_step": 1e3 * dt / args.steps, "hv_per_s": n_pol * args.steps / dt}
+            log(f"full spin {name}: {full_spin[name]['ms_per_step']:.3f} ms/step, "
+                f"{full_spin[name]['hv_per_s']:.1f} H*v/s")
+            hf.close()
+            del pf
 
     # full spectra: 3 polarisations x spectrum_steps each, then the continued fraction
     spec = {}
@@ -447,6 +468,7 @@ def main():
         "paths": results,
         "mixed_best_at_l1_1e-3": mixed_best,
         "batched": batched,
+        "full_spin": full_spin,
         "terminator": terminator,
         "roofline": roofline,
         "cpu_baseline": cpu,

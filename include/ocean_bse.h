@@ -85,7 +85,8 @@ typedef struct {
     int nk[3];            /* k grid (and Born-von-Karman supercell) n1 x n2 x n3, each >= 1 */
     int nx[3];            /* real-space grid of one cell g1 x g2 x g3, each >= 1 */
     int n_bands;          /* Nb >= 1 conduction bands per k */
-    int n_core;           /* Nc >= 1 core states (2: 1s with spin, 6: 2p with spin) */
+    int n_core;           /* Nc core states, 1..12 (2: 1s with spin, 6: 2p with spin, 12: 2p with
+                             the electron spin carried separately) */
     int n_local;          /* Nmu >= 0 local channels; 0 disables the short-range term */
     double cell[3][3];    /* rows: lattice vectors a1, a2, a3 of the cell, bohr, any shape with
                              nonzero volume.  Grid point j of the cell is x = sum_d (j_d / g_d) a_d,
@@ -262,6 +263,18 @@ int ocean_mlp_predict(ocean_mlp_t h, const double* a, const double* b, int n_seq
 int ocean_multiplet_matrices(double zeta, double F2, double G1, double G3,
                              double* core_mat, double* local_mat);
 
+/* Host helper: the same matrices on the full electron x hole spin space (section 3.2.2:
+ * the electron and hole spins carried separately), for n_core = 12 with core index
+ * ((m_c + 1) * 2 + sigma_h) * 2 + sigma_e.  core_mat [12*12] complex = -chi on (m_c, sigma_h),
+ * the identity on sigma_e; local_mat [60*60] complex on pairs (core index, m) ->
+ * core index * 5 + (m + 2):
+ *   -D delta(sigma_h', sigma_h) delta(sigma_e', sigma_e) + X delta(sigma_h', sigma_e') delta(sigma_h, sigma_e),
+ * with D and X as above: the direct term keeps both spins, the exchange term annihilates a
+ * pair of equal spins and creates another.  On the pairs with sigma_e = sigma_h this is the
+ * restricted matrix.  Either output may be NULL.  Errors: INVALID_ARG. */
+int ocean_multiplet_matrices_spin(double zeta, double F2, double G1, double G3,
+                                  double* core_mat, double* local_mat);
+
 /* Host helper: dipole amplitudes d[m+2][mc+1] = <Y_2m| e.r^ |Y_1mc> (radial
  * integral 1) for a polarisation e[3] (section 2: O = e.r for XAS).  d is [5][3]
  * complex.  Errors: INVALID_ARG. */
@@ -269,8 +282,9 @@ int ocean_dipole_amplitudes(const double* e, double* d);
 
 /* Initial vectors O|0> for an L2,3 edge on the device (section 2, eq. loss.fcn;
  * eq. local_basis): psi0[p][k][n][(mc, s)] = sum_m conj(A[k][n][m]) d_p[m][mc] for
- * n_pol polarisations pol[p][3], the same for both spins.  Needs Nc = 6 and
- * Nmu = 5.  psi0_dev: device, n_pol * dim complex.  Enqueued on the handle's
+ * n_pol polarisations pol[p][3], the same for both spins (Nc = 6).  With the electron spin
+ * carried separately (Nc = 12, index ((mc, s_h), s_e)) the amplitude sits on s_e = s_h
+ * and the other pairs are zero.  Needs Nc = 6 or 12 and Nmu = 5.  psi0_dev: device, n_pol * dim complex.  Enqueued on the handle's
  * stream.  Errors: INVALID_ARG, UNSUPPORTED (other edge shapes), DEVICE. */
 int ocean_dipole_psi0(ocean_bse_t h, const double* pol, int n_pol, double* psi0_dev);
 

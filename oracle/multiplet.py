@@ -149,6 +149,55 @@ def local_matrix(mult):
     return kmat
 
 
+# --- the full electron x hole spin space ---------------------------------------------------
+# The restricted space ties the photoelectron spin to the spin of the core hole.  Carrying the
+# electron spin sigma_e separately, the core index becomes (m_c, sigma_h, sigma_e), index
+# ((m_c + 1) * 2 + sigma_h) * 2 + sigma_e.  The spin-orbit term acts on (m_c, sigma_h); the
+# direct interaction conserves both spins; the exchange interaction annihilates a pair and
+# creates another, so it only connects pairs whose two spins agree (section 2: V_D, V_X;
+# the electron and hole spins carried separately, section 3.2.2).
+
+def core_matrix_spin(mult):
+    """Hc on the full spin space: -chi on (m_c, sigma_h), the identity on sigma_e."""
+    return np.kron(core_matrix(mult), np.eye(2))
+
+
+def local_matrix_spin(mult):
+    """K_loc on pairs ((m_c, sigma_h, sigma_e), m):
+    -D delta(sigma_h', sigma_h) delta(sigma_e', sigma_e) + X delta(sigma_h', sigma_e') delta(sigma_h, sigma_e)."""
+    d = direct_matrix(mult["F2"])
+    x = exchange_matrix({1: mult["G1"], 3: mult["G3"]})
+    nv = 5
+    kmat = np.zeros((12 * nv, 12 * nv), dtype=np.complex128)
+    for mcp in range(3):
+        for hp in range(2):
+            for ep in range(2):
+                for mp in range(nv):
+                    row = ((mcp * 2 + hp) * 2 + ep) * nv + mp
+                    for mc in range(3):
+                        for h in range(2):
+                            for e in range(2):
+                                for m in range(nv):
+                                    col = ((mc * 2 + h) * 2 + e) * nv + m
+                                    val = 0.0
+                                    if hp == h and ep == e:
+                                        val -= d[mcp * nv + mp, mc * nv + m]
+                                    if hp == ep and h == e:
+                                        val += x[mcp * nv + mp, mc * nv + m]
+                                    kmat[row, col] = val
+    return kmat
+
+
+def dipole_psi0_spin(local_proj, pol):
+    """psi0[k, n, (m_c, sigma_h, sigma_e)]: the dipole operator conserves spin, so only the
+    pairs with sigma_e = sigma_h are excited, with the restricted amplitudes."""
+    per_c = dipole_psi0(local_proj, pol)                         # [k, n, (m_c, sigma)]
+    out = np.zeros(per_c.shape[:2] + (12,), dtype=np.complex128)
+    for c in range(6):
+        out[:, :, 2 * c + (c % 2)] = per_c[:, :, c]
+    return out
+
+
 def dipole_amplitudes(pol):
     """d[m, m_c] = <Y_2m | e.r^ | Y_1mc> (radial integral 1), m = -2..2, m_c = -1..1."""
     e = np.asarray(pol, dtype=np.float64)

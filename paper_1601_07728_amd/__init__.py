@@ -39,7 +39,8 @@ TERM_SQRT = 1
 
 EXPORTED = [
     "ocean_bse_create", "ocean_bse_destroy", "ocean_bse_dim", "ocean_bse_apply", "ocean_haydock",
-    "ocean_spectrum", "ocean_multiplet_matrices", "ocean_dipole_amplitudes", "ocean_dipole_psi0",
+    "ocean_spectrum", "ocean_multiplet_matrices", "ocean_multiplet_matrices_spin",
+    "ocean_dipole_amplitudes", "ocean_dipole_psi0",
     "ocean_bse_set_profiling", "ocean_bse_kernel_times", "ocean_bse_device_bytes",
     "ocean_last_error", "ocean_haydock_batch", "ocean_bse_autotune", "ocean_bse_get_tuning",
     "ocean_mlp_param_count", "ocean_mlp_create", "ocean_mlp_destroy", "ocean_mlp_set_params",
@@ -113,6 +114,8 @@ def lib() -> ctypes.CDLL:
     L.ocean_spectrum.restype = ci
     L.ocean_multiplet_matrices.argtypes = [cd, cd, cd, cd, vp, vp]
     L.ocean_multiplet_matrices.restype = ci
+    L.ocean_multiplet_matrices_spin.argtypes = [cd, cd, cd, cd, vp, vp]
+    L.ocean_multiplet_matrices_spin.restype = ci
     L.ocean_dipole_amplitudes.argtypes = [vp, vp]
     L.ocean_dipole_amplitudes.restype = ci
     L.ocean_dipole_psi0.argtypes = [vp, vp, ci, vp]
@@ -190,11 +193,14 @@ def _dev_ptr(t) -> int:
     return t.data_ptr()
 
 
-def multiplet_matrices(zeta: float, f2: float, g1: float, g3: float):
-    """L2,3-edge core matrix (6x6) and local interaction matrix (30x30), Ha."""
-    core = np.zeros((6, 6), dtype=np.complex128)
-    loc = np.zeros((30, 30), dtype=np.complex128)
-    _check(lib().ocean_multiplet_matrices(zeta, f2, g1, g3, _ptr(core), _ptr(loc)))
+def multiplet_matrices(zeta: float, f2: float, g1: float, g3: float, full_spin: bool = False):
+    """L2,3-edge core matrix and local interaction matrix, Ha: 6x6 and 30x30 with the
+    electron spin tied to the hole's, or 12x12 and 60x60 with it carried separately."""
+    nc = 12 if full_spin else 6
+    core = np.zeros((nc, nc), dtype=np.complex128)
+    loc = np.zeros((5 * nc, 5 * nc), dtype=np.complex128)
+    fn = lib().ocean_multiplet_matrices_spin if full_spin else lib().ocean_multiplet_matrices
+    _check(fn(zeta, f2, g1, g3, _ptr(core), _ptr(loc)))
     return core, loc
 
 
@@ -329,7 +335,8 @@ class Bse:
         lp = None
         if cr.multiplet is not None:
             m = cr.multiplet
-            core_mat, local_mat = multiplet_matrices(m["zeta"], m["F2"], m["G1"], m["G3"])
+            core_mat, local_mat = multiplet_matrices(m["zeta"], m["F2"], m["G1"], m["G3"],
+                                                     full_spin=cr.n_core == 12)
             if with_local and cr.local_proj is not None:
                 lp = cr.local_proj
             else:

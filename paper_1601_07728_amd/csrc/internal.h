@@ -13,7 +13,7 @@
 
 namespace ocean {
 
-constexpr int kMaxCore = 8;     // Nc limit of the combine kernel
+constexpr int kMaxCore = 12;    // Nc limit of the combine and local kernels (12: 2p with electron spin)
 constexpr int kMaxLocal = 16;   // Nmu limit
 constexpr int kMaxPairs = 128;  // Nc * Nmu limit of the local kernels
 constexpr int kMaxDft = 16;     // largest k-grid extent per axis

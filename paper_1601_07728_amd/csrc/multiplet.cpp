@@ -49,6 +49,18 @@ double gaunt_ck(int k, int l, int m, int lp, int mp) {
 
 }  // namespace
 
+// Matrix elements on (core m_c, d channel m) of the screened direct (F2, m' - m = m_c' - m_c)
+// and bare exchange (G1, G3, m' - m_c' = m - m_c) interactions.
+double direct_element(double F2, int mcp, int mp, int mc, int m) {
+    if (mp - m != mcp - mc) return 0.0;
+    return F2 * gaunt_ck(2, 2, mp, 2, m) * gaunt_ck(2, 1, mcp, 1, mc);
+}
+double exchange_element(double G1, double G3, int mcp, int mp, int mc, int m) {
+    if (mp - mcp != m - mc) return 0.0;
+    return G1 * gaunt_ck(1, 2, mp, 1, mcp) * gaunt_ck(1, 2, m, 1, mc) +
+           G3 * gaunt_ck(3, 2, mp, 1, mcp) * gaunt_ck(3, 2, m, 1, mc);
+}
+
 extern "C" {
 
 int ocean_multiplet_matrices(double zeta, double F2, double G1, double G3, double* core_mat,
@@ -85,16 +97,52 @@ int ocean_multiplet_matrices(double zeta, double F2, double G1, double G3, doubl
                             for (int m = -lv; m <= lv; ++m) {
                                 const int col = ((mc + 1) * 2 + s) * 5 + (m + 2);
                                 double v = 0.0;
-                                // screened direct (F2), diagonal in spin, m' - m = m_c' - m_c
-                                if (sp == s && mp - m == mcp - mc)
-                                    v -= F2 * gaunt_ck(2, lv, mp, lv, m) * gaunt_ck(2, lc, mcp, lc, mc);
-                                // bare exchange (G1, G3), all spin pairs, m' - m_c' = m - m_c
-                                if (mp - mcp == m - mc)
-                                    v += G1 * gaunt_ck(1, lv, mp, lc, mcp) * gaunt_ck(1, lv, m, lc, mc) +
-                                         G3 * gaunt_ck(3, lv, mp, lc, mcp) * gaunt_ck(3, lv, m, lc, mc);
+                                // screened direct, diagonal in spin; bare exchange, all spin pairs
+                                if (sp == s) v -= direct_element(F2, mcp, mp, mc, m);
+                                v += exchange_element(G1, G3, mcp, mp, mc, m);
                                 local_mat[2 * (row * 30 + col)] = v;
                             }
                 }
+    }
+    return OCEAN_OK;
+}
+
+int ocean_multiplet_matrices_spin(double zeta, double F2, double G1, double G3, double* core_mat,
+                                  double* local_mat) {
+    // the restricted core matrix on (m_c, sigma_h), then the identity on sigma_e
+    double core6[72];
+    const int rc = ocean_multiplet_matrices(zeta, F2, G1, G3, core6, nullptr);
+    if (rc != OCEAN_OK) return rc;
+    if (core_mat) {
+        for (int i = 0; i < 12 * 12 * 2; ++i) core_mat[i] = 0.0;
+        for (int r = 0; r < 6; ++r)
+            for (int c = 0; c < 6; ++c)
+                for (int e = 0; e < 2; ++e) {
+                    core_mat[2 * ((2 * r + e) * 12 + 2 * c + e)] = core6[2 * (r * 6 + c)];
+                    core_mat[2 * ((2 * r + e) * 12 + 2 * c + e) + 1] = core6[2 * (r * 6 + c) + 1];
+                }
+    }
+    if (local_mat) {
+        // pairs ((m_c, sigma_h, sigma_e), m) -> (((m_c + 1) * 2 + sigma_h) * 2 + sigma_e) * 5 + (m + 2)
+        for (int i = 0; i < 60 * 60 * 2; ++i) local_mat[i] = 0.0;
+        for (int mcp = -1; mcp <= 1; ++mcp)
+            for (int hp = 0; hp < 2; ++hp)
+                for (int ep = 0; ep < 2; ++ep)
+                    for (int mp = -2; mp <= 2; ++mp) {
+                        const int row = (((mcp + 1) * 2 + hp) * 2 + ep) * 5 + (mp + 2);
+                        for (int mc = -1; mc <= 1; ++mc)
+                            for (int h = 0; h < 2; ++h)
+                                for (int e = 0; e < 2; ++e)
+                                    for (int m = -2; m <= 2; ++m) {
+                                        const int col = (((mc + 1) * 2 + h) * 2 + e) * 5 + (m + 2);
+                                        double v = 0.0;
+                                        // direct: both spins kept
+                                        if (hp == h && ep == e) v -= direct_element(F2, mcp, mp, mc, m);
+                                        // exchange: a pair of equal spins annihilated, another created
+                                        if (hp == ep && h == e) v += exchange_element(G1, G3, mcp, mp, mc, m);
+                                        local_mat[2 * (row * 60 + col)] = v;
+                                    }
+                    }
     }
     return OCEAN_OK;
 }

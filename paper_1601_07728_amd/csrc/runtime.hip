@@ -375,7 +375,7 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
         return OCEAN_ERR_INVALID_ARG;
     }
     if (d->n_core > kMaxCore || d->n_local > kMaxLocal || d->n_core * d->n_local > kMaxPairs) {
-        set_error("ocean_bse_create: n_core <= 8, n_local <= 16 and n_core*n_local <= 128 supported");
+        set_error("ocean_bse_create: n_core <= 12, n_local <= 16 and n_core*n_local <= 128 supported");
         return OCEAN_ERR_UNSUPPORTED;
     }
     if (!d->energies || !d->u || !d->w_r || !d->w_val || d->n_wr < 2) {
@@ -1080,8 +1080,9 @@ int ocean_dipole_psi0(ocean_bse_t h, const double* pol, int n_pol, double* psi0_
         set_error("ocean_dipole_psi0: invalid argument");
         return OCEAN_ERR_INVALID_ARG;
     }
-    if (h->Nc != 6 || h->Nmu != 5 || !h->A) {
-        set_error("ocean_dipole_psi0: needs an L2,3 edge (n_core = 6) with a d-channel local basis (n_local = 5)");
+    if ((h->Nc != 6 && h->Nc != 12) || h->Nmu != 5 || !h->A) {
+        set_error("ocean_dipole_psi0: needs an L2,3 edge (n_core = 6, or 12 with the electron spin) with a "
+                  "d-channel local basis (n_local = 5)");
         return OCEAN_ERR_UNSUPPORTED;
     }
     std::vector<double> d((size_t)n_pol * 30);

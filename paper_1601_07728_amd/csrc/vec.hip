@@ -524,10 +524,13 @@ __global__ __launch_bounds__(256) void u_phase_kernel(const double* __restrict__
 }
 
 // psi0[p][kn][(mc, s)] = sum_m conj(A[kn][m]) d_p[m][mc]
+// Nc = 6: core index (m_c, sigma), the same amplitude for both spins.  Nc = 12 (electron spin
+// carried separately): index ((m_c, sigma_h), sigma_e), amplitude on sigma_e = sigma_h only,
+// since the dipole operator does not flip the spin.
 __global__ __launch_bounds__(256) void dipole_kernel(const double2* __restrict__ A,
                                                      const double2* __restrict__ d,
                                                      double2* __restrict__ psi0, int n_pol,
-                                                     long long NkNb) {
+                                                     long long NkNb, int Nc) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)n_pol * NkNb) return;
     const int p = (int)(idx / NkNb);
@@ -536,8 +539,14 @@ __global__ __launch_bounds__(256) void dipole_kernel(const double2* __restrict__
     for (int mc = 0; mc < 3; ++mc) {
         double2 acc = make_double2(0.0, 0.0);
         for (int m = 0; m < 5; ++m) acc = cadd(acc, cmulc(A[kn * 5 + m], dp[m * 3 + mc]));
-        psi0[idx * 6 + mc * 2 + 0] = acc;
-        psi0[idx * 6 + mc * 2 + 1] = acc;
+        if (Nc == 6) {
+            psi0[idx * 6 + mc * 2 + 0] = acc;
+            psi0[idx * 6 + mc * 2 + 1] = acc;
+        } else {
+            for (int s = 0; s < 2; ++s)
+                for (int e = 0; e < 2; ++e)
+                    psi0[idx * 12 + (mc * 2 + s) * 2 + e] = s == e ? acc : make_double2(0.0, 0.0);
+        }
     }
 }
 
@@ -824,7 +833,7 @@ hipError_t launch_dipole_psi0(ocean_bse_s* h, const double* d_dev, int n_pol, do
     const long long n = NkNb * n_pol;
     dipole_kernel<<<(unsigned)((n + 255) / 256), 256, 0, h->stream>>>(
         reinterpret_cast<const double2*>(h->A), reinterpret_cast<const double2*>(d_dev),
-        reinterpret_cast<double2*>(psi0), n_pol, NkNb);
+        reinterpret_cast<double2*>(psi0), n_pol, NkNb, h->Nc);
     return hipGetLastError();
 }
 

@@ -213,6 +213,19 @@ def small_l_edge(seed: int = 1, nk=(2, 2, 2), nx=(6, 6, 6), n_bands=12, **kw) ->
     return config2_shape(nk=nk, nx=nx, n_bands=n_bands, seed=seed, **kw)
 
 
+def full_spin(cr: Crystal) -> Crystal:
+    """The same crystal with the electron spin carried separately: 12 core states
+    (m_c, sigma_h, sigma_e).  Inputs are unchanged; only the space doubles."""
+    import dataclasses
+    out = dataclasses.replace(cr, n_core=12, psi0=None)
+    if cr.psi0 is not None:
+        p = np.zeros(cr.psi0.shape[:3] + (12,), dtype=np.complex128)
+        for c in range(cr.n_core):
+            p[..., 2 * c + (c % 2)] = cr.psi0[..., c]
+        out.psi0 = p
+    return out
+
+
 # --- device-side generation for the full-size workloads ---------------------------------
 
 def gpu_orthonormal_u(n_k: int, n_x: int, n_bands: int, seed: int, device="cuda"):

@@ -45,6 +45,15 @@ def test_multiplet_matrices_match_oracle_quadrature(lib):
     assert np.abs(loc - mp.local_matrix(mult)).max() <= 1e-14
 
 
+def test_full_spin_multiplet_matrices_match_oracle(lib):
+    """The same on the full electron x hole spin space (12 core states)."""
+    zeta, f2, g1, g3 = 0.14, 0.29, 0.22, 0.13
+    core, loc = ob.multiplet_matrices(zeta, f2, g1, g3, full_spin=True)
+    mult = {"zeta": zeta, "F2": f2, "G1": g1, "G3": g3}
+    assert np.abs(core - mp.core_matrix_spin(mult)).max() <= 1e-15
+    assert np.abs(loc - mp.local_matrix_spin(mult)).max() <= 1e-14
+
+
 def test_dipole_amplitudes_match_oracle(lib):
     for pol in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (0.3, -0.5, 0.81)]:
         d = ob.dipole_amplitudes(pol)
@@ -103,7 +112,7 @@ def _desc(**over):
     (dict(nk=(17, 1, 1)), ob.ERR_UNSUPPORTED),
     (dict(cell=[[7.0, 0.0, 0.0], [7.0, 0.0, 0.0], [0.0, 0.0, 7.0]]), ob.ERR_INVALID_ARG),   # no volume
     (dict(cell=[[7.0, 0.0, 0.0], [0.0, np.nan, 0.0], [0.0, 0.0, 7.0]]), ob.ERR_INVALID_ARG),
-    (dict(n_core=9), ob.ERR_UNSUPPORTED),
+    (dict(n_core=13), ob.ERR_UNSUPPORTED),
     (dict(n_local=5), ob.ERR_INVALID_ARG),          # no projectors given
     (dict(precision=7), ob.ERR_UNSUPPORTED),
     (dict(w_r=np.linspace(1, 6, 64)), ob.ERR_INVALID_ARG),
