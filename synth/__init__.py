@@ -310,3 +310,27 @@ def terminator_system(seed: int, nk=(2, 2, 2), nx=(5, 5, 5), n_bands: int = 24,
     width = float(rng.uniform(20.0, 60.0))
     return config2_shape(nk=nk, nx=nx, n_bands=n_bands, seed=seed, eps=eps, n_steps=n_steps,
                          psi0="none", e_range_ev=width)
+
+
+# --- screening inputs (the RPA response on the real-space sphere around the core site) --------
+
+def screening_inputs(seed: int = 0, n_points: int = 900, n_states: int = 2048, n_occ: int = 512,
+                     n_t: int = 16, gap_ev: float = 2.0, occ_width_ev: float = 20.0,
+                     unocc_width_ev: float = 60.0, t_scale_ev: float = 10.0):
+    """Bloch functions on the screening grid (the paper's 36 angles x 25 radii = 900 points),
+    their energies, the chemical potential in the gap, and the imaginary-frequency
+    quadrature.  Draw order: psi (complex Gaussian, scaled by 1/sqrt(n_points)), then the
+    occupied and empty energies.  The nodes t_j and weights w_j integrate over t in
+    [0, inf): Gauss-Legendre on x in (-1, 1) (numpy.polynomial.legendre.leggauss) mapped by
+    t = T (1 + x) / (1 - x), dt = 2 T / (1 - x)^2 dx, with T = t_scale.  Energies in Ha."""
+    rng = np.random.default_rng(seed)
+    psi = complex_gaussian(rng, (n_points, n_states)) / math.sqrt(n_points)
+    e_occ = np.sort(rng.uniform(-occ_width_ev, 0.0, size=n_occ))
+    e_unocc = np.sort(rng.uniform(gap_ev, gap_ev + unocc_width_ev, size=n_states - n_occ))
+    eps = np.concatenate([e_occ, e_unocc]) / HARTREE_EV
+    mu = 0.5 * gap_ev / HARTREE_EV
+    x, wx = np.polynomial.legendre.leggauss(n_t)
+    tsc = t_scale_ev / HARTREE_EV
+    t = tsc * (1.0 + x) / (1.0 - x)
+    w = wx * 2.0 * tsc / (1.0 - x) ** 2
+    return psi, eps, mu, t, w
