@@ -149,6 +149,34 @@ def cpu_baseline(cr, u_dev, psi0_host, min_seconds=12.0, max_reps=40):
                       f"repeated), {dt:.1f} s, numpy FP64 with {cores} host threads"}
 
 
+def bench_screening(ob, seed, ceilings, reps=3, n_points=900, n_states=16384, n_occ=8192, n_t=16):
+    """Static RPA response of the screening stage on the paper's 900-point grid (36 angles x 25
+    radii): n_states Bloch functions (all bands and k summed over), n_t imaginary
+    frequencies.  One build = n_t complex GEMMs of n_points x n_points x n_states."""
+    import torch
+    import synth
+    psi, eps, mu, t, w = synth.screening_inputs(seed=seed + 77, n_points=n_points, n_states=n_states,
+                                                n_occ=n_occ, n_t=n_t)
+    p = torch.from_numpy(psi).to("cuda")
+    out = torch.empty((n_points, n_points), dtype=torch.float64, device="cuda")
+    ob.screening_chi0(p, eps, mu, t, w, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ob.screening_chi0(p, eps, mu, t, w, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    flops = 8.0 * n_t * n_points * n_points * n_states
+    tf = flops / dt / 1e12
+    log(f"screening chi0: {n_points} points, {n_states} states, {n_t} nodes: {dt * 1e3:.2f} ms, {tf:.1f} TFLOP/s")
+    return {"workload": f"static RPA response on a {n_points}-point grid, {n_states} states, {n_t} imaginary "
+                        "frequencies (FP64, complex GEMMs on the matrix cores)",
+            "ms_per_build": dt * 1e3, "builds_per_s": 1.0 / dt, "flops_per_build": flops,
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / PEAK_FP64_TFLOPS,
+                         "frac_of_measured_mfma": tf / ceilings["mfma_f64_tflops"]}}
+
+
 def bench_batched(ob, seed, steps=200):
     """Molecule in a box: 40 sites (K and L2,3 edges), 3 polarisations each, uneven band
     windows, Gamma point on a 48^3 grid; all 120 solves advance together, one HIP graph per
@@ -313,6 +341,7 @@ def main():
     ap.add_argument("--no-terminator", action="store_true")
     ap.add_argument("--no-spectra", action="store_true")
     ap.add_argument("--no-full-spin", action="store_true")
+    ap.add_argument("--no-screening", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first stream 1 GiB through a plain elementwise kernel (1 GiB read, 1 GiB "
                          "written): the reference for scaling the HBM byte counters")
@@ -440,6 +469,7 @@ def main():
     batched = None
     for h in hs.values():
         h.close()
+    screening = None if args.no_screening else bench_screening(ob, args.seed, ceilings)
     if not args.no_batched:
         batched = bench_batched(ob, args.seed)
 
@@ -469,6 +499,7 @@ def main():
         "mixed_best_at_l1_1e-3": mixed_best,
         "batched": batched,
         "full_spin": full_spin,
+        "screening": screening,
         "terminator": terminator,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -301,6 +301,28 @@ int ocean_bse_kernel_times(ocean_bse_t h, const char** names, double* total_ms,
  * workspace), or < 0 on error. */
 long long ocean_bse_device_bytes(ocean_bse_t h);
 
+/* ---- Screening response (section 3.3) ---------------------------------------------------
+ * Static RPA response chi0 on the real-space grid around the core site (eq. chi_rpa at
+ * omega = 0, with the Green's function of eq. greens.fcn):
+ *   G_j(r, r') = sum_s psi_s(r) psi_s*(r') / (mu + i t_j - eps_s),
+ *   chi0(r, r') = sum_j (w_j / pi) Re[G_j(r, r') G_j(r', r)],
+ * i.e. the frequency integral along the imaginary axis through the chemical potential mu,
+ * folded onto t >= 0 (the integrand at -t is the conjugate of the one at t), with nodes t_j
+ * and weights w_j chosen by the caller.  One spin channel.
+ *   psi_dev   device, [n_points][n_states] complex (row-major, states fastest): the Bloch
+ *             functions of every state summed over (all bands and k) on the grid points.
+ *   eps       host, [n_states] energies (Ha); mu (Ha); t, w host [n_t], t_j >= 0.
+ *   chi0_dev  device, [n_points][n_points] real (row-major), overwritten.  Real and symmetric.
+ * Per node: the state columns are scaled by 1/(mu + i t_j - eps_s), G_j is one complex GEMM
+ * on the matrix cores (rocBLAS), and the symmetric product is added into chi0.
+ * stream: hipStream_t or NULL for the default stream; the call returns after the work has
+ * finished.  Allocates n_points * (n_states + n_points) complex of device scratch.
+ * Errors: INVALID_ARG (NULL, sizes < 1, non-finite input, negative node), OUT_OF_MEMORY,
+ * DEVICE. */
+int ocean_screening_chi0(const double* psi_dev, const double* eps, int n_points, int n_states,
+                         double mu, const double* t, const double* w, int n_t, double* chi0_dev,
+                         void* stream);
+
 /* Measured ceilings of the current device, for the roofline of the projections of
  * Algorithm 1 (section 3.2.1), which issue FP64 matrix-core instructions, FP64 multiply-adds
  * and an HBM stream:

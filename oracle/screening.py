@@ -52,3 +52,14 @@ def chi0_adler_wiser(psi, eps, mu):
         c = 1.0 / (eo - eu[j])                                  # [o]
         out += 2.0 * np.real((v * c[None, :]) @ v.conj().T)
     return out
+
+
+def chi0_element(psi, eps, mu, t_nodes, weights, r, rp):
+    """One element chi0[r, r'] of the quadrature sum, from the two grid rows alone."""
+    out = 0.0
+    for t, w in zip(t_nodes, weights):
+        g = 1.0 / (mu + 1j * t - eps)
+        grr = np.sum(psi[r] * g * np.conj(psi[rp]))
+        gpr = np.sum(psi[rp] * g * np.conj(psi[r]))
+        out += (w / math.pi) * float(np.real(grr * gpr))
+    return out

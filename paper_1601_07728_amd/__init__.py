@@ -46,7 +46,7 @@ EXPORTED = [
     "ocean_mlp_param_count", "ocean_mlp_create", "ocean_mlp_destroy", "ocean_mlp_set_params",
     "ocean_mlp_get_params", "ocean_mlp_encode", "ocean_mlp_forward", "ocean_mlp_loss_grad",
     "ocean_mlp_train_step", "ocean_mlp_predict", "ocean_mlp_save", "ocean_mlp_load",
-    "ocean_device_ceilings",
+    "ocean_device_ceilings", "ocean_screening_chi0",
 ]
 MLP_BF16 = 0
 MLP_FP32 = 1
@@ -106,6 +106,8 @@ def lib() -> ctypes.CDLL:
     L.ocean_bse_device_bytes.restype = ll
     L.ocean_device_ceilings.argtypes = [ll] + [ctypes.POINTER(ctypes.c_double)] * 4
     L.ocean_device_ceilings.restype = ci
+    L.ocean_screening_chi0.argtypes = [vp, vp, ci, ci, cd, vp, vp, ci, vp, vp]
+    L.ocean_screening_chi0.restype = ci
     L.ocean_bse_apply.argtypes = [vp, vp, vp, ci]
     L.ocean_bse_apply.restype = ci
     L.ocean_haydock.argtypes = [vp, vp, ci, ci, cu, vp, vp, vp, vp]
@@ -219,6 +221,29 @@ def device_ceilings(copy_bytes: int = 1 << 30) -> dict:
     _check(lib().ocean_device_ceilings(int(copy_bytes), ctypes.byref(m), ctypes.byref(f), ctypes.byref(c),
                                        ctypes.byref(r)))
     return {"mfma_f64_tflops": m.value, "fma_f64_tflops": f.value, "copy_GBs": c.value, "read_GBs": r.value}
+
+
+def screening_chi0(psi, eps, mu: float, t, w, out=None):
+    """Static RPA response chi0 [n_points, n_points] (real, device) from Bloch functions on
+    the screening grid psi [n_points, n_states] (complex128, device), energies eps
+    [n_states], chemical potential mu and imaginary-frequency nodes t / weights w
+    (ocean_screening_chi0)."""
+    import torch
+    if psi.dtype != torch.complex128 or not psi.is_cuda or psi.dim() != 2 or not psi.is_contiguous():
+        raise ValueError("psi must be a contiguous [n_points, n_states] complex128 CUDA tensor")
+    npt, ns = psi.shape
+    e = _host_f64(eps)
+    tt, ww = _host_f64(t), _host_f64(w)
+    if e.shape != (ns,) or tt.shape != ww.shape:
+        raise ValueError("eps must have n_states entries and t, w the same length")
+    if out is None:
+        out = torch.empty((npt, npt), dtype=torch.float64, device=psi.device)
+    if out.dtype != torch.float64 or not out.is_cuda or tuple(out.shape) != (npt, npt) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [n_points, n_points] float64 CUDA tensor")
+    _device_sync()
+    _check(lib().ocean_screening_chi0(_dev_ptr(psi), _ptr(e), npt, ns, float(mu), _ptr(tt), _ptr(ww), len(tt),
+                                      ctypes.c_void_p(out.data_ptr()), None))
+    return out
 
 
 def spectrum(a, b, norm2, omega, gamma: float, terminator: str = "none", n_used=None) -> np.ndarray:

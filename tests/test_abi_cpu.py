@@ -141,3 +141,20 @@ def test_binding_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(ob, "_lib", None)
     with pytest.raises(RuntimeError):
         ob.lib()
+
+
+def test_screening_validates_before_device_work(lib):
+    """Invalid arguments are rejected before any device pointer is touched."""
+    eps = np.array([0.0, 1.0])
+    tn = np.array([0.5])
+    wn = np.array([1.0])
+    fake = ctypes.c_void_p(8)
+    bad = [(None, eps, 1, 2, 0.1, tn, wn, 1),
+           (fake, eps, 0, 2, 0.1, tn, wn, 1),
+           (fake, np.array([0.0, np.nan]), 1, 2, 0.1, tn, wn, 1),
+           (fake, eps, 1, 2, 0.1, np.array([-0.5]), wn, 1),
+           (fake, eps, 1, 2, float("inf"), tn, wn, 1)]
+    for psi, e, npt, ns, mu, t, w, nt in bad:
+        rc = lib.ocean_screening_chi0(psi, ob._ptr(e), npt, ns, mu, ob._ptr(t), ob._ptr(w), nt, fake, None)
+        assert rc == ob.ERR_INVALID_ARG
+        assert len(lib.ocean_last_error()) > 0
