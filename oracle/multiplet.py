@@ -13,7 +13,9 @@ Builds, from the multiplet parameters alone:
   dipole operator e.r).
 
 Index conventions: core index c = (m_c + 1) * 2 + sigma (sigma = 0 spin up),
-local channel mu = m + 2 for m = -2..2, pair index (c, mu) -> c * 5 + mu.
+local channel mu = m + 2 for m = -2..2, pair index (c, mu) -> c * 5 + mu.  The general
+local basis below (channels of l = 0..3, several radial functions) orders mu by channel,
+then m.
 
 Gaunt coefficients c^k(lm; l'm') = sqrt(4 pi / (2k+1)) Int Y*_{lm} Y_{k,m-m'} Y_{l'm'} dOmega are
 computed here by Gauss-Legendre x uniform-phi quadrature over the sphere (exact
@@ -147,6 +149,106 @@ def local_matrix(mult):
                                 val -= d[mcp * nv + mp, mc * nv + m]
                             kmat[row, col] = val
     return kmat
+
+
+# --- a general local basis: channels of any l (s, p, d, f), several radial functions each ------
+# Channel i has angular momentum l_i; local index mu runs over (channel i, m = -l_i..l_i) in
+# that order.  The radial integrals are inputs: F2[i, j] for the screened direct term (F0 is
+# the long-range W0 and is left out; a 2p core allows k = 0, 2 only) and G[k][i, j] for the
+# bare exchange term (k = 0..4, as the Gaunt selection rules allow).  With the single d
+# channel this is the matrix above.
+
+def channel_offsets(ls):
+    """Start of each channel in the local index, and the total N_mu."""
+    off = np.concatenate([[0], np.cumsum([2 * l + 1 for l in ls])]).astype(int)
+    return off[:-1], int(off[-1])
+
+
+def direct_matrix_channels(ls, f2):
+    """D[(m_c', i', m'), (m_c, i, m)] = F2[i', i] c^2(l_i' m'; l_i m) c^2(1 m_c'; 1 m_c)."""
+    off, nmu = channel_offsets(ls)
+    d = np.zeros((3 * nmu, 3 * nmu))
+    for ip, lp in enumerate(ls):
+        for i, l in enumerate(ls):
+            if f2[ip, i] == 0.0:
+                continue
+            for mcp in range(-1, 2):
+                for mc in range(-1, 2):
+                    for mp in range(-lp, lp + 1):
+                        for m in range(-l, l + 1):
+                            if mp - m != mcp - mc:
+                                continue
+                            d[(mcp + 1) * nmu + off[ip] + mp + lp, (mc + 1) * nmu + off[i] + m + l] = (
+                                f2[ip, i] * gaunt(2, lp, mp, l, m) * gaunt(2, 1, mcp, 1, mc))
+    return d
+
+
+def exchange_matrix_channels(ls, gk):
+    """X[(m_c', i', m'), (m_c, i, m)] = sum_k G^k[i', i] c^k(l_i' m'; 1 m_c') c^k(l_i m; 1 m_c)."""
+    off, nmu = channel_offsets(ls)
+    x = np.zeros((3 * nmu, 3 * nmu))
+    for k, g in gk.items():
+        for ip, lp in enumerate(ls):
+            for i, l in enumerate(ls):
+                if g[ip, i] == 0.0:
+                    continue
+                for mcp in range(-1, 2):
+                    for mc in range(-1, 2):
+                        for mp in range(-lp, lp + 1):
+                            for m in range(-l, l + 1):
+                                if mp - mcp != m - mc:
+                                    continue
+                                x[(mcp + 1) * nmu + off[ip] + mp + lp, (mc + 1) * nmu + off[i] + m + l] += (
+                                    g[ip, i] * gaunt(k, lp, mp, 1, mcp) * gaunt(k, l, m, 1, mc))
+    return x
+
+
+def local_matrix_channels(ls, f2, gk, full_spin=False):
+    """K_loc on pairs (core index, mu) -> core index * N_mu + mu, in the restricted spin
+    model (core index (m_c, sigma)) or with the electron spin carried separately (core
+    index (m_c, sigma_h, sigma_e)); the spin structure is the one of local_matrix and
+    local_matrix_spin."""
+    d = direct_matrix_channels(ls, f2)
+    x = exchange_matrix_channels(ls, gk)
+    _, nmu = channel_offsets(ls)
+    spins = [(h, e) for h in range(2) for e in range(2)] if full_spin else [(s, s) for s in range(2)]
+    ns = len(spins)
+    kmat = np.zeros((3 * ns * nmu, 3 * ns * nmu), dtype=np.complex128)
+    for mcp in range(3):
+        for a, (hp, ep) in enumerate(spins):
+            rows = slice((mcp * ns + a) * nmu, (mcp * ns + a + 1) * nmu)
+            for mc in range(3):
+                for b, (h, e) in enumerate(spins):
+                    cols = slice((mc * ns + b) * nmu, (mc * ns + b + 1) * nmu)
+                    blk = np.zeros((nmu, nmu))
+                    if hp == h and ep == e:
+                        blk -= d[mcp * nmu:(mcp + 1) * nmu, mc * nmu:(mc + 1) * nmu]
+                    if hp == ep and h == e:
+                        blk += x[mcp * nmu:(mcp + 1) * nmu, mc * nmu:(mc + 1) * nmu]
+                    kmat[rows, cols] = blk
+    return kmat
+
+
+def dipole_psi0_channels(local_proj, ls, radial, pol, full_spin=False):
+    """psi0[k, n, core index] = sum_{i, m} conj(A[k, n, (i, m)]) R_i <Y_{l_i m} | e.r^ | Y_1mc>
+    with R_i the radial dipole integral of channel i (only s and d channels couple to 2p)."""
+    off, nmu = channel_offsets(ls)
+    e = np.asarray(pol, dtype=np.float64)
+    rhat = np.stack([np.sin(_TH) * np.cos(_PH), np.sin(_TH) * np.sin(_PH), np.cos(_TH)])
+    edotr = np.tensordot(e, rhat, axes=1)
+    dm = np.zeros((nmu, 3), dtype=np.complex128)
+    for i, l in enumerate(ls):
+        for m in range(-l, l + 1):
+            for mc in range(-1, 2):
+                dm[off[i] + m + l, mc + 1] = radial[i] * sphere_integral(np.conj(ylm(l, m)) * edotr * ylm(1, mc))
+    per_mc = np.einsum("knm,mc->knc", local_proj.conj(), dm)
+    if not full_spin:
+        return np.repeat(per_mc, 2, axis=2)
+    out = np.zeros(per_mc.shape[:2] + (12,), dtype=np.complex128)
+    for mc in range(3):
+        for s in range(2):
+            out[:, :, (mc * 2 + s) * 2 + s] = per_mc[:, :, mc]
+    return out
 
 
 # --- the full electron x hole spin space ---------------------------------------------------
