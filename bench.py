@@ -342,6 +342,7 @@ def main():
     ap.add_argument("--no-spectra", action="store_true")
     ap.add_argument("--no-full-spin", action="store_true")
     ap.add_argument("--no-screening", action="store_true")
+    ap.add_argument("--no-full-basis", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first stream 1 GiB through a plain elementwise kernel (1 GiB read, 1 GiB "
                          "written): the reference for scaling the HBM byte counters")
@@ -403,6 +404,27 @@ def main():
                 f"{full_spin[name]['hv_per_s']:.1f} H*v/s")
             hf.close()
             del pf
+
+    # the same crystal with the full local basis (s, p, d, f x 4 radial functions: 64 local
+    # functions, a 384 x 384 short-range matrix)
+    full_basis = None
+    if not args.no_full_basis:
+        import synth
+        crb = synth.full_local_basis(cr, seed=args.seed + 5)
+        full_basis = {"config": "the c2 workload with the full local basis: s, p, d, f x 4 radial functions "
+                                "(64 local functions, 384 core-channel pairs), 3 polarisations"}
+        ch = crb.channels
+        for name in ("fp64", "bf16"):
+            hb = ob.Bse.from_crystal(crb, precision=name, u=u)
+            hb.autotune(n_vec=n_pol)
+            pb = hb.dipole_psi0_channels(ch["l"], ch["radial"], np.eye(3))
+            timed_haydock(hb, pb, args.warmup)
+            dt, _ = timed_haydock(hb, pb, args.steps)
+            full_basis[name] = {"ms_per_step": 1e3 * dt / args.steps, "hv_per_s": n_pol * args.steps / dt}
+            log(f"full local basis {name}: {full_basis[name]['ms_per_step']:.3f} ms/step, "
+                f"{full_basis[name]['hv_per_s']:.1f} H*v/s")
+            hb.close()
+            del pb
 
     # full spectra: 3 polarisations x spectrum_steps each, then the continued fraction
     spec = {}
@@ -500,6 +522,7 @@ def main():
         "batched": batched,
         "full_spin": full_spin,
         "screening": screening,
+        "full_local_basis": full_basis,
         "terminator": terminator,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -87,7 +87,8 @@ typedef struct {
     int n_bands;          /* Nb >= 1 conduction bands per k */
     int n_core;           /* Nc core states, 1..12 (2: 1s with spin, 6: 2p with spin, 12: 2p with
                              the electron spin carried separately) */
-    int n_local;          /* Nmu >= 0 local channels; 0 disables the short-range term */
+    int n_local;          /* Nmu >= 0 local functions (<= 64; n_core * n_local <= 768); 0 disables the
+                             short-range term */
     double cell[3][3];    /* rows: lattice vectors a1, a2, a3 of the cell, bohr, any shape with
                              nonzero volume.  Grid point j of the cell is x = sum_d (j_d / g_d) a_d,
                              lattice vector r of the supercell is R = sum_d r_d a_d.  The minimum
@@ -275,6 +276,28 @@ int ocean_multiplet_matrices(double zeta, double F2, double G1, double G3,
 int ocean_multiplet_matrices_spin(double zeta, double F2, double G1, double G3,
                                   double* core_mat, double* local_mat);
 
+/* Host helper: the short-range matrix of a general local basis (section 3.2.2: radial
+ * projectors for each l, the multipole expansion with its selection rules).  n_ch channels,
+ * channel i with angular momentum l[i] in 0..3 (several channels may share an l: the radial
+ * functions); local index mu = (channel, m = -l..l) in that order, N_mu = sum (2 l + 1) <= 64.
+ *   f2 [n_ch][n_ch]     screened direct radial integrals F^2 (F^0 is the long-range W0);
+ *   gk [5][n_ch][n_ch]  bare exchange radial integrals G^k, k = 0..4 (only the k that the
+ *                       Gaunt selection rules allow for a 2p core contribute).
+ *   D[(m_c', i', m'), (m_c, i, m)] = F2[i'][i] c^2(l_i' m'; l_i m) c^2(1 m_c'; 1 m_c),
+ *   X[(m_c', i', m'), (m_c, i, m)] = sum_k G^k[i'][i] c^k(l_i' m'; 1 m_c') c^k(l_i m; 1 m_c),
+ * assembled with the spin structure of ocean_multiplet_matrices (full_spin = 0: core index
+ * (m_c, sigma), N_c = 6) or of ocean_multiplet_matrices_spin (full_spin = 1, N_c = 12).
+ * local_mat: [(N_c N_mu)^2] complex, pair index core index * N_mu + mu.  With one d channel,
+ * f2 = F2 and gk = {G1, G3 at k = 1, 3} this is ocean_multiplet_matrices' matrix.
+ * Errors: INVALID_ARG (NULL, l out of range, non-finite), UNSUPPORTED (N_mu > 64). */
+int ocean_local_matrix_channels(int n_ch, const int* l, const double* f2, const double* gk, int full_spin,
+                                double* local_mat);
+
+/* Host helper: dipole amplitudes of a general local basis, d[mu][mc+1] =
+ * radial[i] <Y_{l_i m}| e.r^ |Y_1mc> for mu = (channel i, m); only s and d channels couple to
+ * a 2p core.  d is [N_mu][3] complex.  Errors: INVALID_ARG. */
+int ocean_dipole_amplitudes_channels(int n_ch, const int* l, const double* radial, const double* e, double* d);
+
 /* Host helper: dipole amplitudes d[m+2][mc+1] = <Y_2m| e.r^ |Y_1mc> (radial
  * integral 1) for a polarisation e[3] (section 2: O = e.r for XAS).  d is [5][3]
  * complex.  Errors: INVALID_ARG. */
@@ -287,6 +310,13 @@ int ocean_dipole_amplitudes(const double* e, double* d);
  * and the other pairs are zero.  Needs Nc = 6 or 12 and Nmu = 5.  psi0_dev: device, n_pol * dim complex.  Enqueued on the handle's
  * stream.  Errors: INVALID_ARG, UNSUPPORTED (other edge shapes), DEVICE. */
 int ocean_dipole_psi0(ocean_bse_t h, const double* pol, int n_pol, double* psi0_dev);
+
+/* The same for a general local basis: channels l[n_ch] with radial dipole integrals
+ * radial[n_ch] (ocean_dipole_amplitudes_channels), spanning exactly the handle's n_local
+ * functions; n_core 6 or 12 (spin layout as in ocean_dipole_psi0).  Errors: INVALID_ARG,
+ * UNSUPPORTED (other shapes), DEVICE. */
+int ocean_dipole_psi0_channels(ocean_bse_t h, int n_ch, const int* l, const double* radial, const double* pol,
+                               int n_pol, double* psi0_dev);
 
 /* Per-kernel timing.  While enabled, every launch of the handle is bracketed by
  * HIP events on the handle's stream and its duration is accumulated per kernel

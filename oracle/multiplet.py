@@ -23,6 +23,7 @@ for these polynomial degrees), not by any closed form.
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
@@ -55,6 +56,7 @@ def sphere_integral(f):
     return np.sum(_WT * f)
 
 
+@functools.lru_cache(maxsize=None)
 def gaunt(k, l, m, lp, mp):
     """c^k(lm; l'm') by quadrature."""
     q = m - mp

@@ -46,7 +46,8 @@ EXPORTED = [
     "ocean_mlp_param_count", "ocean_mlp_create", "ocean_mlp_destroy", "ocean_mlp_set_params",
     "ocean_mlp_get_params", "ocean_mlp_encode", "ocean_mlp_forward", "ocean_mlp_loss_grad",
     "ocean_mlp_train_step", "ocean_mlp_predict", "ocean_mlp_save", "ocean_mlp_load",
-    "ocean_device_ceilings", "ocean_screening_chi0",
+    "ocean_device_ceilings", "ocean_screening_chi0", "ocean_local_matrix_channels",
+    "ocean_dipole_amplitudes_channels", "ocean_dipole_psi0_channels",
 ]
 MLP_BF16 = 0
 MLP_FP32 = 1
@@ -118,6 +119,12 @@ def lib() -> ctypes.CDLL:
     L.ocean_multiplet_matrices.restype = ci
     L.ocean_multiplet_matrices_spin.argtypes = [cd, cd, cd, cd, vp, vp]
     L.ocean_multiplet_matrices_spin.restype = ci
+    L.ocean_local_matrix_channels.argtypes = [ci, vp, vp, vp, ci, vp]
+    L.ocean_local_matrix_channels.restype = ci
+    L.ocean_dipole_amplitudes_channels.argtypes = [ci, vp, vp, vp, vp]
+    L.ocean_dipole_amplitudes_channels.restype = ci
+    L.ocean_dipole_psi0_channels.argtypes = [vp, ci, vp, vp, vp, ci, vp]
+    L.ocean_dipole_psi0_channels.restype = ci
     L.ocean_dipole_amplitudes.argtypes = [vp, vp]
     L.ocean_dipole_amplitudes.restype = ci
     L.ocean_dipole_psi0.argtypes = [vp, vp, ci, vp]
@@ -204,6 +211,42 @@ def multiplet_matrices(zeta: float, f2: float, g1: float, g3: float, full_spin: 
     fn = lib().ocean_multiplet_matrices_spin if full_spin else lib().ocean_multiplet_matrices
     _check(fn(zeta, f2, g1, g3, _ptr(core), _ptr(loc)))
     return core, loc
+
+
+def _gk_array(gk, n):
+    """G^k tables as a [5, n, n] array (from a dict k -> [n, n] or an array)."""
+    if isinstance(gk, dict):
+        out = np.zeros((5, n, n))
+        for k, g in gk.items():
+            out[int(k)] = np.asarray(g, dtype=np.float64)
+        return out
+    return np.ascontiguousarray(np.asarray(gk, dtype=np.float64).reshape(5, n, n))
+
+
+def local_matrix_channels(ls, f2, gk, full_spin: bool = False) -> np.ndarray:
+    """Short-range matrix of a general local basis (ocean_local_matrix_channels): channels of
+    angular momentum ls, direct F^2 table f2 [n, n], exchange G^k tables gk ({k: [n, n]} or
+    [5, n, n]); restricted (6 core states) or full spin (12)."""
+    la = np.ascontiguousarray(np.asarray(ls, dtype=np.int32))
+    n = len(la)
+    f = _host_f64(np.asarray(f2, dtype=np.float64).reshape(n, n))
+    g = _gk_array(gk, n)
+    nmu = int(np.sum(2 * la + 1))
+    npair = (12 if full_spin else 6) * nmu
+    out = np.zeros((npair, npair), dtype=np.complex128)
+    _check(lib().ocean_local_matrix_channels(n, la.ctypes.data_as(ctypes.c_void_p), _ptr(f), _ptr(g),
+                                             int(bool(full_spin)), _ptr(out)))
+    return out
+
+
+def dipole_amplitudes_channels(ls, radial, pol) -> np.ndarray:
+    la = np.ascontiguousarray(np.asarray(ls, dtype=np.int32))
+    r = _host_f64(radial)
+    e = _host_f64(pol)
+    d = np.zeros((int(np.sum(2 * la + 1)), 3), dtype=np.complex128)
+    _check(lib().ocean_dipole_amplitudes_channels(len(la), la.ctypes.data_as(ctypes.c_void_p), _ptr(r), _ptr(e),
+                                                  _ptr(d)))
+    return d
 
 
 def dipole_amplitudes(pol) -> np.ndarray:
@@ -362,6 +405,9 @@ class Bse:
             m = cr.multiplet
             core_mat, local_mat = multiplet_matrices(m["zeta"], m["F2"], m["G1"], m["G3"],
                                                      full_spin=cr.n_core == 12)
+            if getattr(cr, "channels", None) is not None:
+                ch = cr.channels
+                local_mat = local_matrix_channels(ch["l"], ch["f2"], ch["gk"], full_spin=cr.n_core == 12)
             if with_local and cr.local_proj is not None:
                 lp = cr.local_proj
             else:
@@ -411,6 +457,19 @@ class Bse:
                                  HAYDOCK_REORTH if reorth else 0, _ptr(a), _ptr(b), _ptr(n2), _ptr(sd))
         _check(rc, allow_info=True)
         return a, b, n2, sd, rc
+
+    def dipole_psi0_channels(self, ls, radial, pols):
+        """Dipole start vectors for a general local basis (ocean_dipole_psi0_channels)."""
+        import torch
+        la = np.ascontiguousarray(np.asarray(ls, dtype=np.int32))
+        r = _host_f64(radial)
+        p = _host_f64(np.atleast_2d(pols))
+        out = torch.empty((p.shape[0], self.n_k, self.n_bands, self.n_core), dtype=torch.complex128,
+                          device="cuda")
+        _device_sync()
+        _check(lib().ocean_dipole_psi0_channels(self._h, len(la), la.ctypes.data_as(ctypes.c_void_p), _ptr(r),
+                                                _ptr(p), p.shape[0], _dev_ptr(out)))
+        return out
 
     def dipole_psi0(self, pols):
         import torch

@@ -14,8 +14,8 @@
 namespace ocean {
 
 constexpr int kMaxCore = 12;    // Nc limit of the combine and local kernels (12: 2p with electron spin)
-constexpr int kMaxLocal = 16;   // Nmu limit
-constexpr int kMaxPairs = 128;  // Nc * Nmu limit of the local kernels
+constexpr int kMaxLocal = 64;   // Nmu limit (4 radial functions x 16 lm of s, p, d, f)
+constexpr int kMaxPairs = 768;  // Nc * Nmu limit of the local kernels (12 x 64)
 constexpr int kMaxDft = 16;     // largest k-grid extent per axis
 constexpr int kColsPerPass = 24;  // exciton columns per projection launch (3 MFMA column tiles)
 constexpr int kRedBlocks = 240;   // blocks per vector in the Lanczos reductions

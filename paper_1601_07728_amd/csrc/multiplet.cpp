@@ -42,6 +42,7 @@ double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3) {
 double gaunt_ck(int k, int l, int m, int lp, int mp) {
     const int q = m - mp;
     if (std::abs(q) > k) return 0.0;
+    if ((l + k + lp) & 1) return 0.0;   // (l k l'; 0 0 0) vanishes for odd l + k + l'
     const double sgn = (m & 1) ? -1.0 : 1.0;
     return sgn * std::sqrt((2.0 * l + 1) * (2.0 * lp + 1)) * wigner3j(l, k, lp, 0, 0, 0) *
            wigner3j(l, k, lp, -m, q, mp);
@@ -143,6 +144,111 @@ int ocean_multiplet_matrices_spin(double zeta, double F2, double G1, double G3, 
                                         local_mat[2 * (row * 60 + col)] = v;
                                     }
                     }
+    }
+    return OCEAN_OK;
+}
+
+int ocean_local_matrix_channels(int n_ch, const int* l, const double* f2, const double* gk, int full_spin,
+                                double* local_mat) {
+    if (n_ch < 1 || !l || !f2 || !gk || !local_mat) {
+        ocean::set_error("ocean_local_matrix_channels: invalid argument");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    std::vector<int> off(n_ch + 1, 0);
+    for (int i = 0; i < n_ch; ++i) {
+        if (l[i] < 0 || l[i] > 3) {
+            ocean::set_error("ocean_local_matrix_channels: channel l must be 0..3");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        off[i + 1] = off[i] + 2 * l[i] + 1;
+    }
+    for (int e = 0; e < n_ch * n_ch * 6; ++e)
+        if (!std::isfinite(e < n_ch * n_ch ? f2[e] : gk[e - n_ch * n_ch])) {
+            ocean::set_error("ocean_local_matrix_channels: radial integrals must be finite");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+    const int nmu = off[n_ch];
+    if (nmu > ocean::kMaxLocal) {
+        ocean::set_error("ocean_local_matrix_channels: at most 64 local functions");
+        return OCEAN_ERR_UNSUPPORTED;
+    }
+    // direct D and exchange X on (m_c, mu) pairs, mu = (channel i, m)
+    std::vector<double> dm((size_t)9 * nmu * nmu, 0.0), xm((size_t)9 * nmu * nmu, 0.0);
+    auto at = [nmu](int mcp, int mup, int mc, int mu) { return ((size_t)(mcp + 1) * nmu + mup) * 3 * nmu + (mc + 1) * nmu + mu; };
+    for (int ip = 0; ip < n_ch; ++ip)
+        for (int i = 0; i < n_ch; ++i)
+            for (int mcp = -1; mcp <= 1; ++mcp)
+                for (int mc = -1; mc <= 1; ++mc)
+                    for (int mp = -l[ip]; mp <= l[ip]; ++mp)
+                        for (int m = -l[i]; m <= l[i]; ++m) {
+                            const int mup = off[ip] + mp + l[ip], mu = off[i] + m + l[i];
+                            // screened direct, k = 2 (k = 0 is the long-range W0), m' - m = m_c' - m_c
+                            if (mp - m == mcp - mc)
+                                dm[at(mcp, mup, mc, mu)] = f2[ip * n_ch + i] * gaunt_ck(2, l[ip], mp, l[i], m) *
+                                                           gaunt_ck(2, 1, mcp, 1, mc);
+                            // bare exchange, every k, m' - m_c' = m - m_c
+                            if (mp - mcp == m - mc) {
+                                double v = 0.0;
+                                for (int k = 0; k <= 4; ++k)
+                                    v += gk[(k * n_ch + ip) * n_ch + i] * gaunt_ck(k, l[ip], mp, 1, mcp) *
+                                         gaunt_ck(k, l[i], m, 1, mc);
+                                xm[at(mcp, mup, mc, mu)] = v;
+                            }
+                        }
+    // spin structure: restricted (core (m_c, sigma), electron spin = sigma) or full
+    // ((m_c, sigma_h, sigma_e)); direct keeps the spins, exchange links equal-spin pairs
+    const int ns = full_spin ? 4 : 2;
+    const int np = 3 * ns * nmu;
+    for (size_t e = 0; e < (size_t)np * np * 2; ++e) local_mat[e] = 0.0;
+    for (int mcp = -1; mcp <= 1; ++mcp)
+        for (int a = 0; a < ns; ++a)
+            for (int mc = -1; mc <= 1; ++mc)
+                for (int b = 0; b < ns; ++b) {
+                    const int hp = full_spin ? a >> 1 : a, ep = full_spin ? a & 1 : a;
+                    const int h = full_spin ? b >> 1 : b, e = full_spin ? b & 1 : b;
+                    const bool direct = hp == h && ep == e, exch = hp == ep && h == e;
+                    if (!direct && !exch) continue;
+                    for (int mup = 0; mup < nmu; ++mup)
+                        for (int mu = 0; mu < nmu; ++mu) {
+                            double v = 0.0;
+                            if (direct) v -= dm[at(mcp, mup, mc, mu)];
+                            if (exch) v += xm[at(mcp, mup, mc, mu)];
+                            const size_t row = (size_t)((mcp + 1) * ns + a) * nmu + mup;
+                            const size_t col = (size_t)((mc + 1) * ns + b) * nmu + mu;
+                            local_mat[2 * (row * np + col)] = v;
+                        }
+                }
+    return OCEAN_OK;
+}
+
+int ocean_dipole_amplitudes_channels(int n_ch, const int* l, const double* radial, const double* e, double* d) {
+    if (n_ch < 1 || !l || !radial || !e || !d || !std::isfinite(e[0]) || !std::isfinite(e[1]) ||
+        !std::isfinite(e[2])) {
+        ocean::set_error("ocean_dipole_amplitudes_channels: invalid argument");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    const double r2 = 1.0 / std::sqrt(2.0);
+    int mu0 = 0;
+    for (int i = 0; i < n_ch; ++i) {
+        if (l[i] < 0 || l[i] > 3 || !std::isfinite(radial[i])) {
+            ocean::set_error("ocean_dipole_amplitudes_channels: channel l must be 0..3, radial finite");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        // <Y_lm| e.r^ |Y_1mc>: the expansion of e.r^ in Y_1q as in ocean_dipole_amplitudes
+        for (int m = -l[i]; m <= l[i]; ++m)
+            for (int mc = -1; mc <= 1; ++mc) {
+                const double c1 = gaunt_ck(1, l[i], m, 1, mc);
+                const int q = m - mc;
+                std::complex<double> v(0.0, 0.0);
+                if (q == 0) v += e[2] * c1;
+                if (q == -1) v += std::complex<double>(e[0] * r2, e[1] * r2) * c1;
+                if (q == 1) v += std::complex<double>(-e[0] * r2, e[1] * r2) * c1;
+                v *= radial[i];
+                const int mu = mu0 + m + l[i];
+                d[2 * (mu * 3 + (mc + 1))] = v.real();
+                d[2 * (mu * 3 + (mc + 1)) + 1] = v.imag();
+            }
+        mu0 += 2 * l[i] + 1;
     }
     return OCEAN_OK;
 }

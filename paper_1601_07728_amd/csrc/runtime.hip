@@ -375,7 +375,7 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
         return OCEAN_ERR_INVALID_ARG;
     }
     if (d->n_core > kMaxCore || d->n_local > kMaxLocal || d->n_core * d->n_local > kMaxPairs) {
-        set_error("ocean_bse_create: n_core <= 12, n_local <= 16 and n_core*n_local <= 128 supported");
+        set_error("ocean_bse_create: n_core <= 12, n_local <= 64 and n_core*n_local <= 768 supported");
         return OCEAN_ERR_UNSUPPORTED;
     }
     if (!d->energies || !d->u || !d->w_r || !d->w_val || d->n_wr < 2) {
@@ -1074,6 +1074,22 @@ int ocean_spectrum(const double* a, const double* b, const int* n_used, const do
     return rc;
 }
 
+// upload per-polarisation amplitudes [n_pol][Nmu][3] and build psi0 on the device
+static int dipole_from_amplitudes(ocean_bse_s* h, const std::vector<double>& d, int n_pol, double* psi0_dev,
+                                  const char* who) {
+    double* dd = nullptr;
+    if (hipMalloc((void**)&dd, d.size() * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(std::string(who) + ": hipMalloc failed");
+        return OCEAN_ERR_OUT_OF_MEMORY;
+    }
+    int rc = check_hip(hipMemcpyAsync(dd, d.data(), d.size() * 8, hipMemcpyHostToDevice, h->stream), "upload");
+    if (rc == OCEAN_OK) rc = check_hip(launch_dipole_psi0(h, dd, n_pol, psi0_dev), "dipole launch");
+    if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "dipole");
+    (void)hipFree(dd);
+    return rc;
+}
+
 int ocean_dipole_psi0(ocean_bse_t h, const double* pol, int n_pol, double* psi0_dev) {
     g_last_error.clear();
     if (!h || !pol || !psi0_dev || n_pol < 1) {
@@ -1087,17 +1103,26 @@ int ocean_dipole_psi0(ocean_bse_t h, const double* pol, int n_pol, double* psi0_
     }
     std::vector<double> d((size_t)n_pol * 30);
     for (int p = 0; p < n_pol; ++p) OCEAN_TRY(ocean_dipole_amplitudes(pol + 3 * p, d.data() + 30 * p));
-    double* dd = nullptr;
-    if (hipMalloc((void**)&dd, d.size() * 8) != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("ocean_dipole_psi0: hipMalloc failed");
-        return OCEAN_ERR_OUT_OF_MEMORY;
+    return dipole_from_amplitudes(h, d, n_pol, psi0_dev, "ocean_dipole_psi0");
+}
+
+int ocean_dipole_psi0_channels(ocean_bse_t h, int n_ch, const int* l, const double* radial, const double* pol,
+                               int n_pol, double* psi0_dev) {
+    g_last_error.clear();
+    if (!h || !l || !radial || !pol || !psi0_dev || n_pol < 1 || n_ch < 1) {
+        set_error("ocean_dipole_psi0_channels: invalid argument");
+        return OCEAN_ERR_INVALID_ARG;
     }
-    int rc = check_hip(hipMemcpyAsync(dd, d.data(), d.size() * 8, hipMemcpyHostToDevice, h->stream), "upload");
-    if (rc == OCEAN_OK) rc = check_hip(launch_dipole_psi0(h, dd, n_pol, psi0_dev), "dipole launch");
-    if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(h->stream), "dipole");
-    (void)hipFree(dd);
-    return rc;
+    int nmu = 0;
+    for (int i = 0; i < n_ch; ++i) nmu += (l[i] >= 0 && l[i] <= 3) ? 2 * l[i] + 1 : 1000;
+    if ((h->Nc != 6 && h->Nc != 12) || nmu != h->Nmu || !h->A) {
+        set_error("ocean_dipole_psi0_channels: needs n_core 6 or 12 and channels spanning exactly n_local functions");
+        return OCEAN_ERR_UNSUPPORTED;
+    }
+    std::vector<double> d((size_t)n_pol * nmu * 6);
+    for (int p = 0; p < n_pol; ++p)
+        OCEAN_TRY(ocean_dipole_amplitudes_channels(n_ch, l, radial, pol + 3 * p, d.data() + (size_t)p * nmu * 6));
+    return dipole_from_amplitudes(h, d, n_pol, psi0_dev, "ocean_dipole_psi0_channels");
 }
 
 int ocean_bse_set_profiling(ocean_bse_t h, int enable) {

@@ -40,41 +40,59 @@ __device__ double2 block_sum2(double2 v, double* sh) {
 }
 
 // ---- local term --------------------------------------------------------------------------------
-// part[blk][v][c*Nmu+mu] = sum_{kn in rows of blk} A[kn][mu] x[v][kn][c].  A block takes
-// kLocRows consecutive (k, n) rows: the A rows and, per vector, the x rows go to LDS with
-// coalesced loads, then thread (pair, g) sums the rows r = g, g + G, ... of its (c, mu) pair
-// and the G partial sums are added in a fixed order.
-constexpr int kLocRows = 128;
+// part[blk][v][c*Nmu+mu] = sum_{kn in rows of blk} A[kn][mu] x[v][kn][c].  A block takes R
+// consecutive (k, n) rows (R from the LDS budget: 128 for the d channel, about 40 for 64
+// channels): the A rows and, per vector, the x rows go to LDS with coalesced loads.  With
+// NP = Nc Nmu <= 256 pairs, thread (pair, g) sums the rows r = g, g + G, ... of its pair and
+// the G partial sums are added in a fixed order; with more pairs a thread takes pairs
+// t, t + 256, ... over all rows.
+constexpr int kLocRowsMax = 128;
+constexpr int kLocLdsElems = 3072;   // complex elements of A and x rows staged per block (48 KiB)
+
+int local_rows(int Nc, int Nmu) {
+    const int r = kLocLdsElems / (Nmu + Nc);
+    return r < kLocRowsMax ? r : kLocRowsMax;
+}
 
 __global__ __launch_bounds__(256) void local_in_kernel(const double2* __restrict__ x,
                                                        const double2* __restrict__ A,
                                                        double2* __restrict__ part, int nv,
-                                                       long long NkNb, int Nc, int Nmu) {
-    __shared__ double2 sA[kLocRows * kMaxLocal];
-    __shared__ double2 sX[kLocRows * kMaxCore];
+                                                       long long NkNb, int Nc, int Nmu, int R) {
+    extern __shared__ double2 lds[];
+    double2* sA = lds;                 // [R][Nmu]
+    double2* sX = lds + R * Nmu;       // [R][Nc]
     __shared__ double2 red[256];
     const int NP = Nc * Nmu;
-    const int G = 256 / NP;
+    const int G = NP <= 256 ? 256 / NP : 1;
     const int t = threadIdx.x;
-    const int pair = t % NP, g = t / NP;
-    const int c = pair / Nmu, mu = pair - c * Nmu;
-    const long long r0 = (long long)blockIdx.x * kLocRows;
-    const int rows = (int)min((long long)kLocRows, NkNb - r0);
-    for (int e = t; e < kLocRows * Nmu; e += 256)
+    const long long r0 = (long long)blockIdx.x * R;
+    const int rows = (int)min((long long)R, NkNb - r0);
+    for (int e = t; e < R * Nmu; e += 256)
         sA[e] = e < rows * Nmu ? A[r0 * Nmu + e] : make_double2(0.0, 0.0);
     for (int v = 0; v < nv; ++v) {
         const double2* xv = x + ((size_t)v * NkNb + r0) * Nc;
-        for (int e = t; e < kLocRows * Nc; e += 256) sX[e] = e < rows * Nc ? xv[e] : make_double2(0.0, 0.0);
+        for (int e = t; e < R * Nc; e += 256) sX[e] = e < rows * Nc ? xv[e] : make_double2(0.0, 0.0);
         __syncthreads();
-        double2 acc = make_double2(0.0, 0.0);
-        if (g < G)
-            for (int r = g; r < rows; r += G) acc = cadd(acc, cmul(sA[r * Nmu + mu], sX[r * Nc + c]));
-        red[t] = acc;
-        __syncthreads();
-        if (t < NP) {
-            double2 sum = red[t];
-            for (int gg = 1; gg < G; ++gg) sum = cadd(sum, red[gg * NP + t]);
-            part[((size_t)blockIdx.x * nv + v) * NP + t] = sum;
+        if (NP <= 256) {
+            const int pair = t % NP, g = t / NP;
+            const int c = pair / Nmu, mu = pair - c * Nmu;
+            double2 acc = make_double2(0.0, 0.0);
+            if (g < G)
+                for (int r = g; r < rows; r += G) acc = cadd(acc, cmul(sA[r * Nmu + mu], sX[r * Nc + c]));
+            red[t] = acc;
+            __syncthreads();
+            if (t < NP) {
+                double2 sum = red[t];
+                for (int gg = 1; gg < G; ++gg) sum = cadd(sum, red[gg * NP + t]);
+                part[((size_t)blockIdx.x * nv + v) * NP + t] = sum;
+            }
+        } else {
+            for (int pair = t; pair < NP; pair += 256) {
+                const int c = pair / Nmu, mu = pair - c * Nmu;
+                double2 acc = make_double2(0.0, 0.0);
+                for (int r = 0; r < rows; ++r) acc = cadd(acc, cmul(sA[r * Nmu + mu], sX[r * Nc + c]));
+                part[((size_t)blockIdx.x * nv + v) * NP + pair] = acc;
+            }
         }
         __syncthreads();
     }
@@ -530,15 +548,15 @@ __global__ __launch_bounds__(256) void u_phase_kernel(const double* __restrict__
 __global__ __launch_bounds__(256) void dipole_kernel(const double2* __restrict__ A,
                                                      const double2* __restrict__ d,
                                                      double2* __restrict__ psi0, int n_pol,
-                                                     long long NkNb, int Nc) {
+                                                     long long NkNb, int Nc, int Nmu) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)n_pol * NkNb) return;
     const int p = (int)(idx / NkNb);
     const long long kn = idx - (long long)p * NkNb;
-    const double2* dp = d + (size_t)p * 15;
+    const double2* dp = d + (size_t)p * Nmu * 3;   // [mu][m_c] amplitudes of polarisation p
     for (int mc = 0; mc < 3; ++mc) {
         double2 acc = make_double2(0.0, 0.0);
-        for (int m = 0; m < 5; ++m) acc = cadd(acc, cmulc(A[kn * 5 + m], dp[m * 3 + mc]));
+        for (int m = 0; m < Nmu; ++m) acc = cadd(acc, cmulc(A[kn * Nmu + m], dp[m * 3 + mc]));
         if (Nc == 6) {
             psi0[idx * 6 + mc * 2 + 0] = acc;
             psi0[idx * 6 + mc * 2 + 1] = acc;
@@ -595,16 +613,18 @@ inline long long per_block(long long dim) { return (dim + kRedBlocks - 1) / kRed
 // ---- launchers ---------------------------------------------------------------------------------------------
 long long local_blocks(const ocean_bse_s* h) {
     const long long NkNb = (long long)h->Nk * h->Nb;
-    return (NkNb + kLocRows - 1) / kLocRows;
+    const int R = local_rows(h->Nc, h->Nmu);
+    return (NkNb + R - 1) / R;
 }
 
 hipError_t launch_local_in(ocean_bse_s* h, const double* x, int nv) {
     const long long NkNb = (long long)h->Nk * h->Nb;
     const long long nblk = local_blocks(h);
     const int slot = prof_begin(h, "local_in");
-    local_in_kernel<<<(unsigned)nblk, 256, 0, h->stream>>>(
+    const int R = local_rows(h->Nc, h->Nmu);
+    local_in_kernel<<<(unsigned)nblk, 256, (size_t)R * (h->Nmu + h->Nc) * sizeof(double2), h->stream>>>(
         reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(h->A),
-        reinterpret_cast<double2*>(h->ws.loc_part), nv, NkNb, h->Nc, h->Nmu);
+        reinterpret_cast<double2*>(h->ws.loc_part), nv, NkNb, h->Nc, h->Nmu, R);
     prof_end(h, slot);
     return hipGetLastError();
 }
@@ -833,7 +853,7 @@ hipError_t launch_dipole_psi0(ocean_bse_s* h, const double* d_dev, int n_pol, do
     const long long n = NkNb * n_pol;
     dipole_kernel<<<(unsigned)((n + 255) / 256), 256, 0, h->stream>>>(
         reinterpret_cast<const double2*>(h->A), reinterpret_cast<const double2*>(d_dev),
-        reinterpret_cast<double2*>(psi0), n_pol, NkNb, h->Nc);
+        reinterpret_cast<double2*>(psi0), n_pol, NkNb, h->Nc, h->Nmu);
     return hipGetLastError();
 }
 

@@ -67,6 +67,7 @@ class Crystal:
     eps: float = 5.0
     lattice: Optional[np.ndarray] = None      # (3, 3) rows a1, a2, a3, bohr; None: cubic cell of edge a
     kshift: tuple = (0.0, 0.0, 0.0)           # k-grid offset along b_d, in grid steps (0: Gamma-centred)
+    channels: Optional[dict] = None           # general local basis: l, f2, gk, radial (see full_local_basis)
 
     def cell_vectors(self) -> np.ndarray:
         """Rows a1, a2, a3 of the cell (bohr)."""
@@ -334,3 +335,30 @@ def screening_inputs(seed: int = 0, n_points: int = 900, n_states: int = 2048, n
     t = tsc * (1.0 + x) / (1.0 - x)
     w = wx * 2.0 * tsc / (1.0 - x) ** 2
     return psi, eps, mu, t, w
+
+
+def full_local_basis(cr: Crystal, seed: int = 0, n_radial: int = 4, f2_ev: float = 8.0, g_ev: float = 6.0) -> Crystal:
+    """The same crystal with the local basis of section 3.2.2 in full: n_radial radial functions
+    for each of l = s, p, d, f (64 local functions for 4), channel order (l, radial).
+    Draw order: A (QR of a complex Gaussian over (k, n)), then the radial tables: the direct
+    F^2 and each exchange G^k (k = 0..4) as Gram matrices B B^T / n of Gaussian B (positive
+    semidefinite, scaled to f2_ev / g_ev), then the dipole radial integrals (Gaussian, s and d
+    channels only; others are ignored by the selection rules).  Energies in Ha."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    ls = [l for l in range(4) for _ in range(n_radial)]
+    n = len(ls)
+    nmu = sum(2 * l + 1 for l in ls)
+    z = complex_gaussian(rng, (cr.n_k * cr.n_bands, nmu))
+    a = orthonormal_columns(z).reshape(cr.n_k, cr.n_bands, nmu)
+
+    def gram(scale):
+        b = rng.normal(size=(n, n))
+        return scale / HARTREE_EV * (b @ b.T) / n
+
+    f2 = gram(f2_ev)
+    gk = np.stack([gram(g_ev) for _ in range(5)])
+    radial = rng.normal(size=n)
+    out = dataclasses.replace(cr, local_proj=a, psi0=None)
+    out.channels = {"l": ls, "f2": f2, "gk": gk, "radial": radial}
+    return out

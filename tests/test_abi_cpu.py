@@ -158,3 +158,25 @@ def test_screening_validates_before_device_work(lib):
         rc = lib.ocean_screening_chi0(psi, ob._ptr(e), npt, ns, mu, ob._ptr(t), ob._ptr(w), nt, fake, None)
         assert rc == ob.ERR_INVALID_ARG
         assert len(lib.ocean_last_error()) > 0
+
+
+def test_local_matrix_channels_match_oracle(lib):
+    """General local basis: closed-form (Racah 3j) helper vs the oracle's quadrature, both spin
+    models, and the dipole amplitudes of the channels."""
+    rng = np.random.default_rng(3)
+    ls = [0, 1, 2, 3, 2, 1]
+    n = len(ls)
+    f2 = rng.normal(size=(n, n))
+    f2 = f2 @ f2.T / n
+    gk = rng.normal(size=(5, n, n))
+    gk = np.einsum("kij,klj->kil", gk, gk) / n
+    for full in (False, True):
+        got = ob.local_matrix_channels(ls, f2, gk, full_spin=full)
+        ref = mp.local_matrix_channels(ls, f2, {k: gk[k] for k in range(5)}, full_spin=full)
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    radial = rng.normal(size=n)
+    for pol in [(0, 0, 1), (0.3, -0.5, 0.81)]:
+        d = ob.dipole_amplitudes_channels(ls, radial, pol)
+        one = np.eye(d.shape[0])[None]      # A = identity: psi0 rows are the amplitudes d
+        ref = mp.dipole_psi0_channels(one, ls, radial, pol)[0, :, ::2]
+        assert np.abs(d - ref).max() <= 1e-14

@@ -1,0 +1,97 @@
+"""GPU parity with the full local basis of section 3.2.2 (s, p, d, f channels with four
+radial functions each: 64 local functions), through the C ABI, against the oracle: H*v in
+both spin models (384 and 768 core-channel pairs), the dipole vector of the channels and the
+recursion; and one H*v at the c2 size.  Tolerances as for the d-channel basis."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bse as orc
+from oracle import multiplet as omp
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _mats(cr, full):
+    ch = cr.channels
+    gk = {k: ch["gk"][k] for k in range(5)}
+    core = omp.core_matrix_spin(cr.multiplet) if full else omp.core_matrix(cr.multiplet)
+    return core, omp.local_matrix_channels(ch["l"], ch["f2"], gk, full_spin=full)
+
+
+def _crystal(full, seed=51):
+    cr = synth.full_local_basis(synth.small_l_edge(seed=seed, nk=(2, 2, 2), nx=(5, 4, 4), n_bands=13), seed=seed)
+    return synth.full_spin(cr) if full else cr
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-5)])
+@pytest.mark.parametrize("full", [False, True])
+def test_full_basis_apply_matches_oracle(full, precision, tol):
+    import paper_1601_07728_amd as ob
+    cr = _crystal(full)
+    _say(f"[channels apply] full_spin={full} {precision} n_core={cr.n_core} n_local={cr.local_proj.shape[-1]}")
+    h = ob.Bse.from_crystal(cr, precision=precision, check_inputs=True)
+    hc, kl = _mats(cr, full)
+    x = synth.complex_gaussian(np.random.default_rng(61), (2, cr.n_k, cr.n_bands, cr.n_core))
+    y = h.apply(_dev(x)).cpu().numpy()
+    for v in range(2):
+        ref = orc.apply_h(cr, x[v], hc, kl)
+        loc = orc.apply_local(x[v], cr.local_proj, kl)
+        assert np.abs(loc).max() > 0.05 * np.abs(ref).max()          # the local term is visible
+        err = float(np.abs(y[v] - ref).max() / np.abs(ref).max())
+        assert err <= tol, (full, precision, v, err)
+    h.close()
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_full_basis_dipole_and_recursion(full):
+    import paper_1601_07728_amd as ob
+    cr = _crystal(full, seed=52)
+    _say(f"[channels dipole + haydock] full_spin={full}")
+    h = ob.Bse.from_crystal(cr, precision="fp64")
+    ch = cr.channels
+    pol = np.array([[0.2, 0.7, -0.4]])
+    p0 = h.dipole_psi0_channels(ch["l"], ch["radial"], pol)
+    ref0 = omp.dipole_psi0_channels(cr.local_proj, ch["l"], ch["radial"], pol[0], full_spin=full)
+    assert np.abs(p0[0].cpu().numpy() - ref0).max() <= 1e-14 * np.abs(ref0).max()
+    hc, kl = _mats(cr, full)
+    n = 50
+    a, b, n2, steps, rc = h.haydock(p0, n, reorth=True)
+    ar, br, n2r, _, _ = orc.haydock(lambda v: orc.apply_h(cr, v, hc, kl), ref0, n, reorth=True)
+    scale = np.abs(ar).max() + 2 * np.abs(br).max()
+    assert np.abs(a[0, :n] - ar).max() <= 1e-10 * scale
+    assert np.abs(b[0, :n] - br).max() <= 1e-10 * scale
+    h.close()
+
+
+def test_full_basis_c2_size_apply():
+    """The c2 crystal (8^3 k, 96 bands, 20^3 x) with the 64-function basis: every element of one
+    H*v against the oracle."""
+    import torch
+    import paper_1601_07728_amd as ob
+    base = synth.config2_shape(seed=0, u_override="skip", psi0="none")
+    u = synth.gpu_orthonormal_u(base.n_k, base.n_x, base.n_bands, seed=1000)
+    cr = synth.full_local_basis(base, seed=3)
+    _say("[channels c2 size]")
+    h = ob.Bse.from_crystal(cr, precision="fp64", u=u)
+    hc, kl = _mats(cr, False)
+    x = synth.complex_gaussian(np.random.default_rng(62), (1, cr.n_k, cr.n_bands, cr.n_core))
+    y = h.apply(_dev(x)).cpu().numpy()[0]
+    h.close()
+    cr.u = u.cpu().numpy()
+    del u
+    torch.cuda.empty_cache()
+    ref = orc.apply_h(cr, x[0], hc, kl)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
