@@ -318,6 +318,34 @@ int ocean_dipole_psi0(ocean_bse_t h, const double* pol, int n_pol, double* psi0_
 int ocean_dipole_psi0_channels(ocean_bse_t h, int n_ch, const int* l, const double* radial, const double* pol,
                                int n_pol, double* psi0_dev);
 
+/* Host helper: amplitudes of the non-resonant scattering operator e^{iq.r} (section 2,
+ * eq. loss.fcn: the operator named there for NRIXS) on a general local basis.  With the
+ * plane-wave expansion e^{iq.r} = 4 pi sum_{LM} i^L j_L(qr) conj(Y_LM(q^)) Y_LM(r^),
+ *   d[mu][mc+1] = sum_L radial[i][L] i^L sqrt(4 pi (2L+1)) conj(Y_{L,m-mc}(q^)) c^L(l_i m; 1 mc)
+ * for mu = (channel i, m), where radial[i][L] = int R_i(r) j_L(|q| r) R_2p(r) r^2 dr is the
+ * caller's (row-major [n_ch][n_L], 1 <= n_L <= 16; terms with L > l_i + 1 vanish).  q[3] is
+ * the momentum transfer (nonzero; only its direction enters here).  d is [N_mu][3] complex.
+ * Errors: INVALID_ARG (NULL, l out of 0..3, n_L out of range, non-finite, q = 0). */
+int ocean_nrixs_amplitudes_channels(int n_ch, const int* l, int n_L, const double* radial, const double* q,
+                                    double* d);
+
+/* Host helper: XAS amplitudes with the first term beyond the dipole (section 2, eq. loss.fcn:
+ * O = e.r + (i/2)(e.r)(q.r)),
+ *   d[mu][mc+1] = radial1[i] <Y_lm| e.r^ |Y_1mc> + (i/2) radial2[i] <Y_lm| (e.r^)(q.r^) |Y_1mc>,
+ * radial1[i] and radial2[i] the channel's integrals of r and r^2 against the 2p function,
+ * e[3] a real polarisation and q[3] the photon wave vector (any length; q = 0 gives the
+ * dipole amplitudes).  d is [N_mu][3] complex.  Errors: INVALID_ARG. */
+int ocean_quadrupole_amplitudes_channels(int n_ch, const int* l, const double* radial1, const double* radial2,
+                                         const double* e, const double* q, double* d);
+
+/* Initial vectors O|0> on the device for any transition operator given by its local
+ * amplitudes (section 2, eq. loss.fcn; eq. local_basis): d is host [n_pol][N_mu][3] complex
+ * (from the helpers above, or the caller's own), and psi0[p][k][n][core] =
+ * sum_mu conj(A[k][n][mu]) d_p[mu][mc] with the spin layout of ocean_dipole_psi0.  Needs
+ * n_core 6 or 12.  psi0_dev: device, n_pol * dim complex.  Errors: INVALID_ARG (NULL,
+ * non-finite), UNSUPPORTED (other core shapes), DEVICE. */
+int ocean_psi0_amplitudes(ocean_bse_t h, const double* d, int n_pol, double* psi0_dev);
+
 /* Per-kernel timing.  While enabled, every launch of the handle is bracketed by
  * HIP events on the handle's stream and its duration is accumulated per kernel
  * name.  ocean_bse_kernel_times copies up to max_entries (name, total ms, launch

@@ -10,7 +10,9 @@ Builds, from the multiplet parameters alone:
   (section 3.2.2: the local direct term is screened -- F2 -- and the exchange term is
   bare -- G1, G3; F0 is the long-range W0 and is left out here);
 * dipole amplitudes <Y_2m | e.r^ | Y_1mc> for the initial vector (eq. loss.fcn,
-  dipole operator e.r).
+  dipole operator e.r), and on the general basis those of e^{iq.r} (non-resonant
+  scattering, by the Legendre series of the plane wave) and of the quadrupole term
+  (i/2)(e.r)(q.r), each angular factor a sphere integral of the operator itself.
 
 Index conventions: core index c = (m_c + 1) * 2 + sigma (sigma = 0 spin up),
 local channel mu = m + 2 for m = -2..2, pair index (c, mu) -> c * 5 + mu.  The general
@@ -244,6 +246,59 @@ def dipole_psi0_channels(local_proj, ls, radial, pol, full_spin=False):
             for mc in range(-1, 2):
                 dm[off[i] + m + l, mc + 1] = radial[i] * sphere_integral(np.conj(ylm(l, m)) * edotr * ylm(1, mc))
     per_mc = np.einsum("knm,mc->knc", local_proj.conj(), dm)
+    if not full_spin:
+        return np.repeat(per_mc, 2, axis=2)
+    out = np.zeros(per_mc.shape[:2] + (12,), dtype=np.complex128)
+    for mc in range(3):
+        for s in range(2):
+            out[:, :, (mc * 2 + s) * 2 + s] = per_mc[:, :, mc]
+    return out
+
+
+# --- non-resonant inelastic scattering: O = e^{iq.r} (section 2, eq. loss.fcn) -------------
+# e^{iq.r} = sum_L i^L (2L + 1) j_L(q r) P_L(q^.r^).  With radial integrals
+# R[i, L] = int R_i(r) j_L(q r) R_2p(r) r^2 dr given per channel i, the amplitude of channel
+# function (i, m) from core m_c is sum_L R[i, L] i^L (2L + 1) <Y_{l_i m} | P_L(q^.r^) | Y_1mc>,
+# the angular integral taken here by sphere quadrature of the Legendre polynomial itself.
+
+def nrixs_amplitudes_channels(ls, radial, qhat):
+    """d[mu, m_c] for mu = (channel i, m); radial[i, L] for L = 0..L_max."""
+    from scipy.special import eval_legendre
+    off, nmu = channel_offsets(ls)
+    qv = np.asarray(qhat, dtype=np.float64)
+    qv = qv / np.linalg.norm(qv)
+    rhat = np.stack([np.sin(_TH) * np.cos(_PH), np.sin(_TH) * np.sin(_PH), np.cos(_TH)])
+    cosg = np.tensordot(qv, rhat, axes=1)
+    radial = np.asarray(radial, dtype=np.float64)
+    d = np.zeros((nmu, 3), dtype=np.complex128)
+    for i, l in enumerate(ls):
+        f = sum(radial[i, L] * (1j ** L) * (2 * L + 1) * eval_legendre(L, cosg) for L in range(radial.shape[1]))
+        for m in range(-l, l + 1):
+            for mc in range(-1, 2):
+                d[off[i] + m + l, mc + 1] = sphere_integral(np.conj(ylm(l, m)) * f * ylm(1, mc))
+    return d
+
+
+def quadrupole_amplitudes_channels(ls, radial1, radial2, pol, q):
+    """XAS beyond the dipole term: O = e.r + (i/2)(e.r)(q.r) (section 2, eq. loss.fcn).
+    radial1[i] and radial2[i] are the channel's integrals of r and r^2 against the 2p
+    function; the angular factors are taken by sphere quadrature."""
+    off, nmu = channel_offsets(ls)
+    rhat = np.stack([np.sin(_TH) * np.cos(_PH), np.sin(_TH) * np.sin(_PH), np.cos(_TH)])
+    edotr = np.tensordot(np.asarray(pol, dtype=np.float64), rhat, axes=1)
+    qdotr = np.tensordot(np.asarray(q, dtype=np.float64), rhat, axes=1)
+    d = np.zeros((nmu, 3), dtype=np.complex128)
+    for i, l in enumerate(ls):
+        f = radial1[i] * edotr + 0.5j * radial2[i] * edotr * qdotr
+        for m in range(-l, l + 1):
+            for mc in range(-1, 2):
+                d[off[i] + m + l, mc + 1] = sphere_integral(np.conj(ylm(l, m)) * f * ylm(1, mc))
+    return d
+
+
+def psi0_from_amplitudes(local_proj, d, full_spin=False):
+    """psi0[k, n, core index] = sum_mu conj(A[k, n, mu]) d[mu, m_c], spin as in dipole_psi0."""
+    per_mc = np.einsum("knm,mc->knc", local_proj.conj(), d)
     if not full_spin:
         return np.repeat(per_mc, 2, axis=2)
     out = np.zeros(per_mc.shape[:2] + (12,), dtype=np.complex128)

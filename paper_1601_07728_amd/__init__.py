@@ -47,7 +47,8 @@ EXPORTED = [
     "ocean_mlp_get_params", "ocean_mlp_encode", "ocean_mlp_forward", "ocean_mlp_loss_grad",
     "ocean_mlp_train_step", "ocean_mlp_predict", "ocean_mlp_save", "ocean_mlp_load",
     "ocean_device_ceilings", "ocean_screening_chi0", "ocean_local_matrix_channels",
-    "ocean_dipole_amplitudes_channels", "ocean_dipole_psi0_channels",
+    "ocean_dipole_amplitudes_channels", "ocean_dipole_psi0_channels", "ocean_nrixs_amplitudes_channels",
+    "ocean_quadrupole_amplitudes_channels", "ocean_psi0_amplitudes",
 ]
 MLP_BF16 = 0
 MLP_FP32 = 1
@@ -125,6 +126,12 @@ def lib() -> ctypes.CDLL:
     L.ocean_dipole_amplitudes_channels.restype = ci
     L.ocean_dipole_psi0_channels.argtypes = [vp, ci, vp, vp, vp, ci, vp]
     L.ocean_dipole_psi0_channels.restype = ci
+    L.ocean_nrixs_amplitudes_channels.argtypes = [ci, vp, ci, vp, vp, vp]
+    L.ocean_nrixs_amplitudes_channels.restype = ci
+    L.ocean_quadrupole_amplitudes_channels.argtypes = [ci, vp, vp, vp, vp, vp, vp]
+    L.ocean_quadrupole_amplitudes_channels.restype = ci
+    L.ocean_psi0_amplitudes.argtypes = [vp, vp, ci, vp]
+    L.ocean_psi0_amplitudes.restype = ci
     L.ocean_dipole_amplitudes.argtypes = [vp, vp]
     L.ocean_dipole_amplitudes.restype = ci
     L.ocean_dipole_psi0.argtypes = [vp, vp, ci, vp]
@@ -246,6 +253,27 @@ def dipole_amplitudes_channels(ls, radial, pol) -> np.ndarray:
     d = np.zeros((int(np.sum(2 * la + 1)), 3), dtype=np.complex128)
     _check(lib().ocean_dipole_amplitudes_channels(len(la), la.ctypes.data_as(ctypes.c_void_p), _ptr(r), _ptr(e),
                                                   _ptr(d)))
+    return d
+
+
+def nrixs_amplitudes_channels(ls, radial, q) -> np.ndarray:
+    """e^{iq.r} amplitudes [N_mu][3]; radial[i][L] = channel i's j_L radial integral."""
+    la = np.ascontiguousarray(np.asarray(ls, dtype=np.int32))
+    r = _host_f64(np.atleast_2d(radial))
+    qv = _host_f64(q)
+    d = np.zeros((int(np.sum(2 * la + 1)), 3), dtype=np.complex128)
+    _check(lib().ocean_nrixs_amplitudes_channels(len(la), la.ctypes.data_as(ctypes.c_void_p), r.shape[1], _ptr(r),
+                                                 _ptr(qv), _ptr(d)))
+    return d
+
+
+def quadrupole_amplitudes_channels(ls, radial1, radial2, pol, q) -> np.ndarray:
+    """e.r + (i/2)(e.r)(q.r) amplitudes [N_mu][3]."""
+    la = np.ascontiguousarray(np.asarray(ls, dtype=np.int32))
+    r1, r2, e, qv = _host_f64(radial1), _host_f64(radial2), _host_f64(pol), _host_f64(q)
+    d = np.zeros((int(np.sum(2 * la + 1)), 3), dtype=np.complex128)
+    _check(lib().ocean_quadrupole_amplitudes_channels(len(la), la.ctypes.data_as(ctypes.c_void_p), _ptr(r1),
+                                                      _ptr(r2), _ptr(e), _ptr(qv), _ptr(d)))
     return d
 
 
@@ -469,6 +497,18 @@ class Bse:
         _device_sync()
         _check(lib().ocean_dipole_psi0_channels(self._h, len(la), la.ctypes.data_as(ctypes.c_void_p), _ptr(r),
                                                 _ptr(p), p.shape[0], _dev_ptr(out)))
+        return out
+
+    def psi0_amplitudes(self, d):
+        """Start vectors from local amplitudes d[n_pol][N_mu][3] (ocean_psi0_amplitudes)."""
+        import torch
+        dd = np.ascontiguousarray(np.asarray(d, dtype=np.complex128))
+        if dd.ndim == 2:
+            dd = dd[None]
+        out = torch.empty((dd.shape[0], self.n_k, self.n_bands, self.n_core), dtype=torch.complex128,
+                          device="cuda")
+        _device_sync()
+        _check(lib().ocean_psi0_amplitudes(self._h, _ptr(dd), dd.shape[0], _dev_ptr(out)))
         return out
 
     def dipole_psi0(self, pols):

@@ -62,6 +62,46 @@ double exchange_element(double G1, double G3, int mcp, int mp, int mc, int m) {
            G3 * gaunt_ck(3, 2, mp, 1, mcp) * gaunt_ck(3, 2, m, 1, mc);
 }
 
+
+// <Y_lm| v.r^ |Y_l'm'> for a real vector v: v.r^ in spherical components (Y_1q, q = m - m')
+// times the Gaunt coefficient c^1(lm; l'm').
+static std::complex<double> vdotr_element(const double* v, int l, int m, int lp, int mp) {
+    const int q = m - mp;
+    if (std::abs(q) > 1) return 0.0;
+    const double c1 = gaunt_ck(1, l, m, lp, mp);
+    if (c1 == 0.0) return 0.0;
+    const double r2 = 1.0 / std::sqrt(2.0);
+    if (q == 0) return v[2] * c1;
+    if (q == -1) return std::complex<double>(v[0] * r2, v[1] * r2) * c1;
+    return std::complex<double>(-v[0] * r2, v[1] * r2) * c1;
+}
+
+// Y_LM at the unit vector u (Condon-Shortley phase), from the associated Legendre recurrence
+// in L at fixed |M| and Y_{L,-M} = (-1)^M conj(Y_LM).
+static std::complex<double> ylm_at(int L, int M, const double* u) {
+    const int am = std::abs(M);
+    if (am > L) return 0.0;
+    const double x = std::max(-1.0, std::min(1.0, u[2]));
+    const double s = std::sqrt(std::max(0.0, 1.0 - x * x));
+    double pmm = 1.0;   // P_|M|^|M| = (-1)^|M| (2|M| - 1)!! s^|M|
+    for (int i = 1; i <= am; ++i) pmm *= -(2.0 * i - 1.0) * s;
+    double p = pmm;
+    if (L > am) {
+        double pm1 = pmm, pl = x * (2.0 * am + 1.0) * pmm;
+        for (int ll = am + 2; ll <= L; ++ll) {
+            const double pn = ((2.0 * ll - 1.0) * x * pl - (ll + am - 1.0) * pm1) / (ll - am);
+            pm1 = pl;
+            pl = pn;
+        }
+        p = pl;
+    }
+    const double norm = std::sqrt((2.0 * L + 1.0) / (4.0 * M_PI) * fact(L - am) / fact(L + am));
+    const double phi = (u[0] == 0.0 && u[1] == 0.0) ? 0.0 : std::atan2(u[1], u[0]);
+    std::complex<double> y = norm * p * std::exp(std::complex<double>(0.0, am * phi));
+    if (M < 0) y = ((am & 1) ? -1.0 : 1.0) * std::conj(y);
+    return y;
+}
+
 extern "C" {
 
 int ocean_multiplet_matrices(double zeta, double F2, double G1, double G3, double* core_mat,
@@ -273,6 +313,81 @@ int ocean_dipole_amplitudes(const double* e, double* d) {
             d[2 * ((m + 2) * 3 + (mc + 1))] = v.real();
             d[2 * ((m + 2) * 3 + (mc + 1)) + 1] = v.imag();
         }
+    return OCEAN_OK;
+}
+
+int ocean_nrixs_amplitudes_channels(int n_ch, const int* l, int n_L, const double* radial, const double* q,
+                                    double* d) {
+    if (n_ch < 1 || n_L < 1 || n_L > 16 || !l || !radial || !q || !d || !std::isfinite(q[0]) ||
+        !std::isfinite(q[1]) || !std::isfinite(q[2])) {
+        ocean::set_error("ocean_nrixs_amplitudes_channels: invalid argument");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    if (!(qn > 0.0)) {
+        ocean::set_error("ocean_nrixs_amplitudes_channels: the momentum transfer must be nonzero");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    const double u[3] = {q[0] / qn, q[1] / qn, q[2] / qn};
+    for (int i = 0; i < n_ch; ++i) {
+        bool ok = l[i] >= 0 && l[i] <= 3;
+        for (int L = 0; L < n_L; ++L) ok = ok && std::isfinite(radial[i * n_L + L]);
+        if (!ok) {
+            ocean::set_error("ocean_nrixs_amplitudes_channels: channel l must be 0..3, radial finite");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+    }
+    // e^{iq.r} = 4 pi sum_LM i^L j_L(q r) conj(Y_LM(q^)) Y_LM(r^) and
+    // <Y_lm|Y_LM|Y_1mc> = sqrt((2L + 1) / 4 pi) c^L(lm; 1 mc) with M = m - mc
+    const std::complex<double> iu(0.0, 1.0);
+    int mu0 = 0;
+    for (int i = 0; i < n_ch; ++i) {
+        for (int m = -l[i]; m <= l[i]; ++m)
+            for (int mc = -1; mc <= 1; ++mc) {
+                std::complex<double> v(0.0, 0.0), ipow(1.0, 0.0);
+                for (int L = 0; L < n_L; ++L, ipow *= iu) {
+                    const double c = gaunt_ck(L, l[i], m, 1, mc);
+                    if (c == 0.0) continue;
+                    v += radial[i * n_L + L] * ipow * std::sqrt(4.0 * M_PI * (2.0 * L + 1.0)) *
+                         std::conj(ylm_at(L, m - mc, u)) * c;
+                }
+                const int mu = mu0 + m + l[i];
+                d[2 * (mu * 3 + (mc + 1))] = v.real();
+                d[2 * (mu * 3 + (mc + 1)) + 1] = v.imag();
+            }
+        mu0 += 2 * l[i] + 1;
+    }
+    return OCEAN_OK;
+}
+
+int ocean_quadrupole_amplitudes_channels(int n_ch, const int* l, const double* radial1, const double* radial2,
+                                         const double* e, const double* q, double* d) {
+    bool ok = n_ch >= 1 && l && radial1 && radial2 && e && q && d;
+    for (int a = 0; ok && a < 3; ++a) ok = std::isfinite(e[a]) && std::isfinite(q[a]);
+    for (int i = 0; ok && i < n_ch; ++i)
+        ok = l[i] >= 0 && l[i] <= 3 && std::isfinite(radial1[i]) && std::isfinite(radial2[i]);
+    if (!ok) {
+        ocean::set_error("ocean_quadrupole_amplitudes_channels: invalid argument (channel l 0..3, all finite)");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    // (e.r^)(q.r^) Y_1mc lies in the l = 0 and l = 2 shells, so the product's matrix element is
+    // the sum over those intermediate states of the two single-vector elements
+    int mu0 = 0;
+    for (int i = 0; i < n_ch; ++i) {
+        for (int m = -l[i]; m <= l[i]; ++m)
+            for (int mc = -1; mc <= 1; ++mc) {
+                std::complex<double> quad(0.0, 0.0);
+                for (int lm = 0; lm <= 2; lm += 2)
+                    for (int mm = -lm; mm <= lm; ++mm)
+                        quad += vdotr_element(e, l[i], m, lm, mm) * vdotr_element(q, lm, mm, 1, mc);
+                const std::complex<double> v =
+                    radial1[i] * vdotr_element(e, l[i], m, 1, mc) + std::complex<double>(0.0, 0.5) * radial2[i] * quad;
+                const int mu = mu0 + m + l[i];
+                d[2 * (mu * 3 + (mc + 1))] = v.real();
+                d[2 * (mu * 3 + (mc + 1)) + 1] = v.imag();
+            }
+        mu0 += 2 * l[i] + 1;
+    }
     return OCEAN_OK;
 }
 

@@ -1125,6 +1125,25 @@ int ocean_dipole_psi0_channels(ocean_bse_t h, int n_ch, const int* l, const doub
     return dipole_from_amplitudes(h, d, n_pol, psi0_dev, "ocean_dipole_psi0_channels");
 }
 
+int ocean_psi0_amplitudes(ocean_bse_t h, const double* d, int n_pol, double* psi0_dev) {
+    g_last_error.clear();
+    if (!h || !d || !psi0_dev || n_pol < 1) {
+        set_error("ocean_psi0_amplitudes: invalid argument");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    if ((h->Nc != 6 && h->Nc != 12) || !h->A) {
+        set_error("ocean_psi0_amplitudes: needs a 2p core (n_core 6 or 12) and a local basis");
+        return OCEAN_ERR_UNSUPPORTED;
+    }
+    const size_t n = (size_t)n_pol * h->Nmu * 6;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(d[i])) {
+            set_error("ocean_psi0_amplitudes: amplitudes must be finite");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+    return dipole_from_amplitudes(h, std::vector<double>(d, d + n), n_pol, psi0_dev, "ocean_psi0_amplitudes");
+}
+
 int ocean_bse_set_profiling(ocean_bse_t h, int enable) {
     if (!h) {
         set_error("ocean_bse_set_profiling: NULL handle");

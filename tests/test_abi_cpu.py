@@ -180,3 +180,34 @@ def test_local_matrix_channels_match_oracle(lib):
         one = np.eye(d.shape[0])[None]      # A = identity: psi0 rows are the amplitudes d
         ref = mp.dipole_psi0_channels(one, ls, radial, pol)[0, :, ::2]
         assert np.abs(d - ref).max() <= 1e-14
+
+
+def test_transition_amplitudes_match_oracle(lib):
+    """e^{iq.r} (addition theorem with closed-form Y_LM and Gaunt factors) and the quadrupole
+    term (products through the l = 0, 2 shells) against the oracle's sphere quadrature."""
+    rng = np.random.default_rng(8)
+    ls = [0, 1, 2, 3, 2, 1]
+    n = len(ls)
+    rad = rng.normal(size=(n, 6))
+    for q in ([0.3, -0.5, 0.8], [0, 0, 1.0], [0, 0, -2.0], [1.0, 0, 0], [0, -1e-3, 0]):
+        q = np.asarray(q)
+        got = ob.nrixs_amplitudes_channels(ls, rad, q)
+        ref = mp.nrixs_amplitudes_channels(ls, rad, q)
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    r1, r2 = rng.normal(size=n), rng.normal(size=n)
+    for e, q in (([0.6, 0, 0.8], [0.7, -1.1, 0.4]), ([0, 0, 1.0], [1.0, 0, 0]), ([0.3, -0.5, 0.81], [0, 0, 0])):
+        got = ob.quadrupole_amplitudes_channels(ls, r1, r2, e, q)
+        ref = mp.quadrupole_amplitudes_channels(ls, r1, r2, e, q)
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    la = np.array(ls, dtype=np.int32)
+    d = np.zeros((sum(2 * l + 1 for l in ls), 3), dtype=np.complex128)
+    p = lambda a: np.ascontiguousarray(a).ctypes.data_as(ctypes.c_void_p)
+    r = np.ascontiguousarray(rad)
+    assert lib.ocean_nrixs_amplitudes_channels(n, p(la), 6, p(r), p(np.zeros(3)), p(d)) == ob.ERR_INVALID_ARG
+    assert lib.ocean_nrixs_amplitudes_channels(n, p(la), 0, p(r), p(np.ones(3)), p(d)) == ob.ERR_INVALID_ARG
+    assert lib.ocean_nrixs_amplitudes_channels(n, p(np.array([4] * n, dtype=np.int32)), 6, p(r), p(np.ones(3)),
+                                               p(d)) == ob.ERR_INVALID_ARG
+    assert lib.ocean_quadrupole_amplitudes_channels(n, p(la), p(r1), p(r2), p(np.array([np.nan, 0, 1.0])),
+                                                    p(np.ones(3)), p(d)) == ob.ERR_INVALID_ARG
+    assert lib.ocean_psi0_amplitudes(None, p(d), 1, None) == ob.ERR_INVALID_ARG
+    assert len(lib.ocean_last_error()) > 0

@@ -95,3 +95,36 @@ def test_full_basis_c2_size_apply():
     torch.cuda.empty_cache()
     ref = orc.apply_h(cr, x[0], hc, kl)
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_nrixs_and_quadrupole_start_vectors(full):
+    """Start vectors of e^{iq.r} and of the quadrupole term through ocean_psi0_amplitudes, against
+    the oracle's amplitudes (sphere quadrature) and its psi0; then the recursion from the
+    e^{iq.r} vector."""
+    import paper_1601_07728_amd as ob
+    cr = _crystal(full, seed=53)
+    _say(f"[channels nrixs + quadrupole] full_spin={full}")
+    h = ob.Bse.from_crystal(cr, precision="fp64")
+    ls = cr.channels["l"]
+    rng = np.random.default_rng(63)
+    q = np.array([0.9, -0.4, 1.3])
+    rad = rng.normal(size=(len(ls), 5))
+    r1, r2 = rng.normal(size=len(ls)), rng.normal(size=len(ls))
+    e = np.array([0.6, 0.0, 0.8])
+    d_lib = np.stack([ob.nrixs_amplitudes_channels(ls, rad, q), ob.quadrupole_amplitudes_channels(ls, r1, r2, e, q)])
+    d_ref = [omp.nrixs_amplitudes_channels(ls, rad, q), omp.quadrupole_amplitudes_channels(ls, r1, r2, e, q)]
+    p0 = h.psi0_amplitudes(d_lib).cpu().numpy()
+    for p in range(2):
+        ref = omp.psi0_from_amplitudes(cr.local_proj, d_ref[p], full_spin=full)
+        assert np.abs(ref).max() > 0
+        assert np.abs(p0[p] - ref).max() <= 1e-13 * np.abs(ref).max(), p
+    hc, kl = _mats(cr, full)
+    n = 30
+    ref0 = omp.psi0_from_amplitudes(cr.local_proj, d_ref[0], full_spin=full)
+    a, b, n2, steps, rc = h.haydock(_dev(p0[0:1]), n, reorth=True)
+    ar, br, _, _, _ = orc.haydock(lambda v: orc.apply_h(cr, v, hc, kl), ref0, n, reorth=True)
+    scale = np.abs(ar).max() + 2 * np.abs(br).max()
+    assert np.abs(a[0, :n] - ar).max() <= 1e-10 * scale
+    assert np.abs(b[0, :n] - br).max() <= 1e-10 * scale
+    h.close()
