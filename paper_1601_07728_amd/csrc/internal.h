@@ -18,6 +18,7 @@ constexpr int kMaxLocal = 64;   // Nmu limit (4 radial functions x 16 lm of s, p
 constexpr int kMaxPairs = 768;  // Nc * Nmu limit of the local kernels (12 x 64)
 constexpr int kMaxDft = 16;     // largest k-grid extent per axis
 constexpr int kColsPerPass = 24;  // exciton columns per projection launch (3 MFMA column tiles)
+constexpr int kColsPerWidePass = 40;  // FP64 single pass for 25..40 columns (5 column tiles)
 constexpr int kRedBlocks = 240;   // blocks per vector in the Lanczos reductions
 constexpr int kXB = 16;           // x-block of the phi work array (a power of two: phi_index_x)
 constexpr int kStageTile = 4096;
@@ -233,6 +234,7 @@ hipError_t launch_spectrum(const double* a, const double* b, const int* n_used, 
 
 // geometry helpers
 int bwd_waves(int Nb);
+int cols_per_pass(const ocean_bse_s* h, int cols);
 void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk);
 void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks, int* S, int* chunk);
 constexpr int kMaxBwdTarget = 8192;  // largest back-projection grid target the tuner tries

@@ -82,7 +82,7 @@ __device__ __forceinline__ void stage_pair(T* buf, int ss, int kq, int ns, int c
 // [xt*64*MS + w*16*MS, +16*MS) and every column tile.  The bands are walked in chunks of
 // KC: the psi chunk (B operand, shared by all waves) is staged in LDS in MFMA order, double
 // buffered, while each wave keeps the u values (A operand) of the next chunk in flight.
-template <typename T, int MS, int NT, int TC, int KC>
+template <typename T, int MS, int NT, int TC, int KC, int CP>
 __global__ __launch_bounds__(256) void proj_fwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const double2* __restrict__ psi,
     typename Cplx<T>::c2* __restrict__ phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0,
@@ -115,12 +115,12 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
         urow[ms] = (unsigned)((row - brow0) * Nb) * sizeof(C2);
     }
     // cooperative psi chunk loads: element e = (n_local, c_local), c fastest
-    constexpr int PER = (KC * kColsPerPass + 255) / 256;
+    constexpr int PER = (KC * CP + 255) / 256;
     auto load_p = [&](int n0, double2 (&pv)[PER]) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 256 * j;
-            const int nl = e / kColsPerPass, cl = e - nl * kColsPerPass;
+            const int nl = e / CP, cl = e - nl * CP;
             const int n = n0 + nl;
             const bool ok = nl < KC && cl < ncb && n < Nb;
             const int col = col0 + cl;
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 256 * j;
-            const int nl = e / kColsPerPass, cl = e - nl * kColsPerPass;
+            const int nl = e / CP, cl = e - nl * CP;
             if (nl < KC && cl < ncb) {
                 const int r8 = nl & 7;
                 const int kq8 = sizeof(T) == 8 ? (r8 & 3) : (r8 >> 1), ns8 = sizeof(T) == 8 ? (r8 >> 2) : (r8 & 1);
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 // 16x16x4 FP64 MFMA costs the issue slots of 16 wave-wide FMAs, so a tile holding 4 real
 // columns of 16 wastes three quarters of them.  Lane (i, kq) sums its own points for band
 // i, and the four lane groups are added at the end.
-template <typename T, int NT, int TC, int XT, int R, int W>
+template <typename T, int NT, int TC, int XT, int R, int W, int CP>
 __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const typename Cplx<T>::c2* __restrict__ phi,
     double* __restrict__ part, int Nk, int Nx, int Nb, int cols, int col0, int ncb,
@@ -311,9 +311,9 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     typedef typename Cplx<T>::c2 C2;
     typedef typename Cplx<T>::acc ACC;
     constexpr int SS = XT / 8;
-    constexpr int TILE = 2 * XT * kColsPerPass;          // complex pairs of one phi' tile
-    constexpr int PER = (XT * kColsPerPass + 64 * W - 1) / (64 * W);
-    static_assert(8 * NT + TC <= kColsPerPass, "columns per pass");
+    constexpr int TILE = 2 * XT * CP;          // complex pairs of one phi' tile
+    constexpr int PER = (XT * CP + 64 * W - 1) / (64 * W);
+    static_assert(8 * NT + TC <= CP, "columns per pass");
     static_assert(R == 2 || R == 3, "ring depth");
     __shared__ __align__(16) C2 sP[R][TILE];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 64 * W * j;
-            const int xl = e / kColsPerPass, cl = e - xl * kColsPerPass;
+            const int xl = e / CP, cl = e - xl * CP;
             const int x = x0 + xl;
             const bool ok = xl < XT && cl < ncb && x < x_end;
             const unsigned off = (unsigned)((phi_index_x(x, col0 + cl, k, Nk, cols) - (size_t)xb0 * Nk * kXB * cols) * sizeof(C2));
@@ -361,9 +361,9 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 64 * W * j;
-            const int xl = e / kColsPerPass, cl = e - xl * kColsPerPass;
+            const int xl = e / CP, cl = e - xl * CP;
             if (xl < XT && cl < ncb) {
-                C2* d = dst + ((((xl >> 3) * 4 + ((xl & 7) >> 1)) * kColsPerPass + cl) * 2) * 2 + (xl & 1);
+                C2* d = dst + ((((xl >> 3) * 4 + ((xl & 7) >> 1)) * CP + cl) * 2) * 2 + (xl & 1);
                 d[0] = pp[j];
                 d[2] = C2{pp[j].y, -pp[j].x};
             }
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     auto contract = [&](const C2* src, const C2 (&uu)[SS][2]) {
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
-            const C2* row = src + (ss * 4 + kq) * kColsPerPass * 4;
+            const C2* row = src + (ss * 4 + kq) * CP * 4;
             // lane (i, kq): real column (8 t + i / 2, q = i % 2) -> pair (column, q)
             const C2* mine = row + (i >> 1) * 4 + (i & 1) * 2;
             C2 b[NT][2];
@@ -484,13 +484,21 @@ hipError_t fwd_dispatch_nt(int NT, int TC, dim3 grid, hipStream_t st, const void
     const C2* u = static_cast<const C2*>(U);
     C2* p = static_cast<C2*>(phi);
     const double2* ps = reinterpret_cast<const double2*>(x);
-#define OCEAN_FWD(nt, tc) \
+#define OCEAN_FWD(nt, tc, cp) \
     if (NT == nt && TC == tc) { \
-        proj_fwd_kernel<T, MS, nt, tc, Tiles<T>::KC><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); \
+        proj_fwd_kernel<T, MS, nt, tc, Tiles<T>::KC, cp><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); \
         return hipGetLastError(); \
     }
-    OCEAN_FWD(1, 0) OCEAN_FWD(2, 0) OCEAN_FWD(3, 0)
-    if constexpr (sizeof(T) == 8) { OCEAN_FWD(1, 1) OCEAN_FWD(1, 2) OCEAN_FWD(2, 1) OCEAN_FWD(2, 2) }
+    if (ncb <= kColsPerPass) {
+        OCEAN_FWD(1, 0, kColsPerPass) OCEAN_FWD(2, 0, kColsPerPass) OCEAN_FWD(3, 0, kColsPerPass)
+        if constexpr (sizeof(T) == 8) {
+            OCEAN_FWD(1, 1, kColsPerPass) OCEAN_FWD(1, 2, kColsPerPass)
+            OCEAN_FWD(2, 1, kColsPerPass) OCEAN_FWD(2, 2, kColsPerPass)
+        }
+    } else if constexpr (sizeof(T) == 8 && MS == 1) {
+        OCEAN_FWD(3, 1, kColsPerWidePass) OCEAN_FWD(3, 2, kColsPerWidePass) OCEAN_FWD(4, 0, kColsPerWidePass)
+        OCEAN_FWD(4, 1, kColsPerWidePass) OCEAN_FWD(4, 2, kColsPerWidePass) OCEAN_FWD(5, 0, kColsPerWidePass)
+    }
 #undef OCEAN_FWD
     return hipErrorInvalidValue;
 }
@@ -503,13 +511,21 @@ hipError_t bwd_dispatch_w(int NT, int TC, dim3 grid, hipStream_t st, const void*
     constexpr int XT = Tiles<T>::XT;
     const C2* u = static_cast<const C2*>(U);
     const C2* p = static_cast<const C2*>(phi);
-#define OCEAN_BWD(nt, tc) \
+#define OCEAN_BWD(nt, tc, cp) \
     if (NT == nt && TC == tc) { \
-        proj_bwd_kernel<T, nt, tc, XT, Tiles<T>::R, W><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); \
+        proj_bwd_kernel<T, nt, tc, XT, Tiles<T>::R, W, cp><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); \
         return hipGetLastError(); \
     }
-    OCEAN_BWD(1, 0) OCEAN_BWD(2, 0) OCEAN_BWD(3, 0)
-    if constexpr (sizeof(T) == 8) { OCEAN_BWD(1, 1) OCEAN_BWD(1, 2) OCEAN_BWD(2, 1) OCEAN_BWD(2, 2) }
+    if (ncb <= kColsPerPass) {
+        OCEAN_BWD(1, 0, kColsPerPass) OCEAN_BWD(2, 0, kColsPerPass) OCEAN_BWD(3, 0, kColsPerPass)
+        if constexpr (sizeof(T) == 8) {
+            OCEAN_BWD(1, 1, kColsPerPass) OCEAN_BWD(1, 2, kColsPerPass)
+            OCEAN_BWD(2, 1, kColsPerPass) OCEAN_BWD(2, 2, kColsPerPass)
+        }
+    } else if constexpr (sizeof(T) == 8) {
+        OCEAN_BWD(3, 1, kColsPerWidePass) OCEAN_BWD(3, 2, kColsPerWidePass) OCEAN_BWD(4, 0, kColsPerWidePass)
+        OCEAN_BWD(4, 1, kColsPerWidePass) OCEAN_BWD(4, 2, kColsPerWidePass) OCEAN_BWD(5, 0, kColsPerWidePass)
+    }
 #undef OCEAN_BWD
     return hipErrorInvalidValue;
 }
@@ -544,8 +560,8 @@ void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks,
     const long long per_chunk = (long long)h->Nk * bb;
     long long s = (target_blocks + per_chunk - 1) / per_chunk;
     const long long smax = std::max(1, (h->Nx + 511) / 512);  // >= 512 points per chunk
-    // The partials of one chunk (up to kColsPerPass complex FP64 columns per band) written
-    // and read back stay within 5% of the u bytes the chunk streams.  This binds for
+    // The partials of one chunk (kColsPerPass complex FP64 columns per band; a wide FP64 pass
+    // writes 5/3 of that) written and read back stay within 5% of the u bytes the chunk streams.  This binds for
     // Gamma-only systems with many x points, whose grid otherwise comes from x chunks alone.
     const int ue = h->precision == OCEAN_PREC_FP64 ? 16 : h->precision == OCEAN_PREC_BF16 ? 4 : 8;
     const long long scap = std::max(1LL, (long long)h->Nx * ue / (20LL * 16 * kColsPerPass));
@@ -569,6 +585,15 @@ bool is_bf16_mode(int precision) {
 
 int fwd_band_chunk(const ocean_bse_s* h) { return is_bf16_mode(h->precision) ? 32 : 0; }
 
+// Columns per projection launch: every pass streams all of u once, so FP64 runs up to
+// kColsPerWidePass columns (five MFMA column tiles, or four and the FMA tail) in one pass,
+// e.g. the 36 columns of three polarisations with the electron and hole spins separate.
+// The other precisions keep kColsPerPass.
+int cols_per_pass(const ocean_bse_s* h, int cols) {
+    return h->precision == OCEAN_PREC_FP64 && cols > kColsPerPass && cols <= kColsPerWidePass ? kColsPerWidePass
+                                                                                            : kColsPerPass;
+}
+
 // MFMA column tiles and FMA tail columns for ncb complex columns.  In FP64 a remainder of at
 // most 4 real columns (2 complex) after whole 16-wide tiles goes to the FMA tail; FP32 MFMAs
 // are cheap next to FP32 FMAs, so FP32 always rounds up to whole tiles.
@@ -581,7 +606,9 @@ void column_split(int ncb, bool fp64, int* NT, int* TC) {
 
 hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, int ncb) {
     if (is_bf16_mode(h->precision)) return launch_proj_fwd_bf16(h, x, nv, col0, ncb);
-    const int MS = h->fwd_ms == 1 ? 1 : 2;   // 16 * MS rows per wave, 64 * MS per block
+    // 16 * MS rows per wave, 64 * MS per block; a wide pass (more than kColsPerPass columns)
+    // holds more accumulators per wave and runs with MS = 1
+    const int MS = (h->fwd_ms == 1 || ncb > kColsPerPass) ? 1 : 2;
     const int cols = nv * h->Nc;
     int NT, TC;
     column_split(ncb, h->precision == OCEAN_PREC_FP64, &NT, &TC);

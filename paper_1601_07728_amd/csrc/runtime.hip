@@ -215,14 +215,15 @@ oom:
 // The H*v pipeline for nv vectors: y = H x.  dot_part (optional): Re<x|y> partials.
 static int apply_pipeline(ocean_bse_s* h, const double* x, double* y, int nv, double* dot_part) {
     const int cols = nv * h->Nc;
-    for (int c0 = 0; c0 < cols; c0 += kColsPerPass)
-        OCEAN_HIP(launch_proj_fwd(h, x, nv, c0, std::min(kColsPerPass, cols - c0)), "proj_fwd launch");
+    const int cpp = cols_per_pass(h, cols);
+    for (int c0 = 0; c0 < cols; c0 += cpp)
+        OCEAN_HIP(launch_proj_fwd(h, x, nv, c0, std::min(cpp, cols - c0)), "proj_fwd launch");
     if (h->Nk == 1)
         OCEAN_HIP(launch_w_gamma(h, cols), "w_gamma launch");
     else
         OCEAN_HIP(launch_fft_w(h, cols), "fft_w launch");
-    for (int c0 = 0; c0 < cols; c0 += kColsPerPass)
-        OCEAN_HIP(launch_proj_bwd(h, nv, c0, std::min(kColsPerPass, cols - c0)), "proj_bwd launch");
+    for (int c0 = 0; c0 < cols; c0 += cpp)
+        OCEAN_HIP(launch_proj_bwd(h, nv, c0, std::min(cpp, cols - c0)), "proj_bwd launch");
     if (h->ws.bwd_chunks > kCombineDirectChunks) OCEAN_HIP(launch_reduce_part(h, nv), "reduce_part launch");
     if (h->Nmu > 0 && h->K != nullptr) {
         OCEAN_HIP(launch_local_in(h, x, nv), "local_in launch");

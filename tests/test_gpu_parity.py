@@ -80,9 +80,11 @@ def test_apply_fp64_matches_oracle(case, n_vec):
 
 
 # (n_core, n_vec): the projections take the exciton columns n_vec * n_core in passes of up to
-# 24 and split each pass into 16-wide matrix-core tiles plus, in FP64, a multiply-add tail of
+# 24 (FP64: a single pass when there are at most 40) and split each pass into 16-wide matrix-core tiles plus, in FP64, a multiply-add tail of
 # 1 or 2 columns.  Odd core counts reach the one-column tail.
-COLUMN_SPLITS = [(1, 2), (1, 9), (3, 3), (1, 17), (3, 5), (1, 18), (3, 8), (1, 41)]
+COLUMN_SPLITS = [(1, 2), (1, 9), (3, 3), (1, 17), (3, 5), (1, 18), (3, 8), (1, 41),
+                 # one wide FP64 pass of 25..40 columns: 3 tiles + tail 1 or 2, 4 tiles + tail 0..2, 5 tiles
+                 (5, 5), (2, 13), (6, 5), (3, 11), (2, 17), (12, 3), (4, 10)]
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-5)])
