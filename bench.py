@@ -69,25 +69,25 @@ def proj_bytes(cr, cols, u_elem, phi_elem):
 # WRITE_SIZE 1.0 GiB for 1 GiB written).  A figure holds only for the kernel source it was
 # taken with (sha256 of the .hip file); for any other source the traffic is reported null.
 TRAFFIC = {
-    ("fp64", "proj_fwd"): {"bytes": 7588340422, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 2, 2, 16>
-        "sha256": "55d91d952c58f2b2be809e4a78a3db001df8d56e51acdaf4b3b0b2532e2efa8f"},
-    ("fp64", "proj_bwd"): {"bytes": 7548012006, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 16, 3, 6>
-        "sha256": "55d91d952c58f2b2be809e4a78a3db001df8d56e51acdaf4b3b0b2532e2efa8f"},
-    ("fp32", "proj_fwd"): {"bytes": 3849502318, "src": "proj.hip",  # proj_fwd_kernel<float, 1, 3, 0, 32>
-        "sha256": "55d91d952c58f2b2be809e4a78a3db001df8d56e51acdaf4b3b0b2532e2efa8f"},
-    ("fp32", "proj_bwd"): {"bytes": 3788077836, "src": "proj.hip",  # proj_bwd_kernel<float, 3, 0, 64, 2, 6>
-        "sha256": "55d91d952c58f2b2be809e4a78a3db001df8d56e51acdaf4b3b0b2532e2efa8f"},
-    ("split_bf16", "proj_fwd"): {"bytes": 3755385430, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<1, 3, true>
+    ("fp64", "proj_fwd"): {"bytes": 7588300510, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 2, 2, 16, 24>
+        "sha256": "d5b42a45ea2b6dd68d08a09c314701fdbd3587e0210a2742830973fa2fd22d6c"},
+    ("fp64", "proj_bwd"): {"bytes": 7547923656, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 16, 3, 6, 24>
+        "sha256": "d5b42a45ea2b6dd68d08a09c314701fdbd3587e0210a2742830973fa2fd22d6c"},
+    ("fp32", "proj_fwd"): {"bytes": 3849478253, "src": "proj.hip",  # proj_fwd_kernel<float, 1, 3, 0, 32, 24>
+        "sha256": "d5b42a45ea2b6dd68d08a09c314701fdbd3587e0210a2742830973fa2fd22d6c"},
+    ("fp32", "proj_bwd"): {"bytes": 3788078337, "src": "proj.hip",  # proj_bwd_kernel<float, 3, 0, 64, 2, 6, 24>
+        "sha256": "d5b42a45ea2b6dd68d08a09c314701fdbd3587e0210a2742830973fa2fd22d6c"},
+    ("split_bf16", "proj_fwd"): {"bytes": 3755389016, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<1, 3, true>
         "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
-    ("split_bf16", "proj_bwd"): {"bytes": 3900896244, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
+    ("split_bf16", "proj_bwd"): {"bytes": 3901305513, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
         "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
-    ("bf16", "proj_fwd"): {"bytes": 2184749365, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<2, 3, false>
+    ("bf16", "proj_fwd"): {"bytes": 2184715081, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<2, 3, false>
         "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
-    ("bf16", "proj_bwd"): {"bytes": 2217509367, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
+    ("bf16", "proj_bwd"): {"bytes": 2217509768, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
         "sha256": "835032ec751d1fa947e0ca12a358653b65aad9f5454d689fc67d583efdbb58b5"},
-    ("fp64", "fft_w"): {"bytes": 2392632578, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
+    ("fp64", "fft_w"): {"bytes": 2392647923, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
         "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
-    ("fp32", "fft_w"): {"bytes": 1196241539, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
+    ("fp32", "fft_w"): {"bytes": 1196247164, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
         "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
 }
 
