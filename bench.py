@@ -222,6 +222,56 @@ def bench_batched(ob, seed, steps=200):
     return out
 
 
+def bench_supercell(ob, seed, steps=10, spec_steps=100):
+    """One Ti L2,3 site of the 4x4x4 SrTiO3-shaped supercell: 2^3 k, 1200 bands, 64^3 x, u 40 GB
+    in FP64 (drawn on the device and borrowed by the FP64 handle), three polarisations per
+    step, every precision.  Each path also runs a spec_steps recursion whose spectrum is
+    compared with the FP64 one."""
+    import torch
+    import synth
+    t0 = time.time()
+    cr = synth.config3_shape(seed=seed)
+    u = synth.gpu_orthonormal_u(cr.n_k, cr.n_x, cr.n_bands, seed=3000 + seed)
+    torch.cuda.synchronize()
+    log(f"supercell: u on the device ({u.numel() * 16 / 1e9:.1f} GB) in {time.time() - t0:.1f} s")
+    n_pol = 3
+    cols = n_pol * cr.n_core
+    out, sig = {}, {}
+    for prec in MODES:
+        h = ob.Bse.from_crystal(cr, precision=prec, u=u)
+        tune = h.autotune(n_vec=n_pol)
+        psi0 = h.dipole_psi0(np.eye(3))
+        timed_haydock(h, psi0, 2)
+        dt, _ = timed_haydock(h, psi0, steps)
+        h.set_profiling(True)
+        h.haydock(psi0, steps)
+        kt = h.kernel_times()
+        h.set_profiling(False)
+        km = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
+        pb = proj_bytes(cr, cols, U_BYTES[prec], PHI_BYTES[prec])
+        _, (a, b, n2, sd, _) = timed_haydock(h, psi0, spec_steps)
+        sig[prec] = ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd)
+        r = {"tiles": tune, "ms_per_step": 1e3 * dt / steps, "hv_per_s": n_pol * steps / dt,
+             "kernel_ms": {k: round(km[k], 4) for k in ("proj_fwd", "proj_bwd", "fft_w") if k in km},
+             "proj_hbm_frac": {k: pb / (km[k] * 1e6) / PEAK_HBM_GBS for k in ("proj_fwd", "proj_bwd")}}
+        if prec == "fp64":
+            r["proj_mfma_fp64_frac"] = {k: proj_flops(cr, cols) / (km[k] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS
+                                        for k in ("proj_fwd", "proj_bwd")}
+        out[prec] = r
+        log(f"supercell {prec}: {r['ms_per_step']:.2f} ms/step, {r['hv_per_s']:.1f} H*v/s, kernels {r['kernel_ms']}")
+        h.close()
+        del psi0
+    ref = sig["fp64"]
+    for prec in MODES[1:]:
+        out[prec]["spectrum_l1_vs_fp64"] = float(np.sum(np.abs(sig[prec] - ref)) / np.sum(np.abs(ref)))
+    out["workload"] = ("one Ti L2,3 site of a 4x4x4 SrTiO3-shaped supercell: 2^3 k, 1200 bands, 64^3 x, "
+                       f"6 core states, H dim {cr.dim}, u 40 GB (FP64), 3 polarisations per step; spectra "
+                       f"of {spec_steps} steps compared with FP64")
+    del u
+    torch.cuda.empty_cache()
+    return out
+
+
 def he_init(rng, sizes=(64, 256, 256, 256, 448)):
     """He-normal weights, zero biases, packed [W1, b1, ..., W4, b4] (W stored [in][out])."""
     parts = []
@@ -343,6 +393,7 @@ def main():
     ap.add_argument("--no-full-spin", action="store_true")
     ap.add_argument("--no-screening", action="store_true")
     ap.add_argument("--no-full-basis", action="store_true")
+    ap.add_argument("--no-supercell", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first stream 1 GiB through a plain elementwise kernel (1 GiB read, 1 GiB "
                          "written): the reference for scaling the HBM byte counters")
@@ -494,6 +545,7 @@ def main():
     screening = None if args.no_screening else bench_screening(ob, args.seed, ceilings)
     if not args.no_batched:
         batched = bench_batched(ob, args.seed)
+    supercell = None if args.no_supercell else bench_supercell(ob, args.seed)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -523,6 +575,7 @@ def main():
         "full_spin": full_spin,
         "screening": screening,
         "full_local_basis": full_basis,
+        "supercell": supercell,
         "terminator": terminator,
         "roofline": roofline,
         "cpu_baseline": cpu,
