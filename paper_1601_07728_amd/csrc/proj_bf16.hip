@@ -327,19 +327,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    u32x4 ah[SS], al[SS], ahn[SS], aln[SS];
-    float2 bl[PER][4];
-    load_b(x_begin, bl);
-    load_a(x_begin, ah, al);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    store_b(0, bl);
-    int buf = 0;
-    for (int x0 = x_begin; x0 < x_end; x0 += XT) {
-        __syncthreads();
-        load_b(x0 + XT, bl);
-        load_a(x0 + XT, ahn, aln);
-        __builtin_amdgcn_sched_barrier(0);
+    auto contract = [&](int buf, const u32x4 (&ah)[SS], const u32x4 (&al)[SS]) {
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
             const bf16x8 a_h = __builtin_bit_cast(bf16x8, ah[ss]);
@@ -352,14 +340,38 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
                 if (LO) acc[t] = mfma_bf16(__builtin_bit_cast(bf16x8, al[ss]), b_h, acc[t]);
             }
         }
-        store_b(buf ^ 1, bl);
-#pragma unroll
-        for (int ss = 0; ss < SS; ++ss) {
-            ah[ss] = ahn[ss];
-            if (LO) al[ss] = aln[ss];
-        }
+    };
+
+    // Ring of three tiles: while tile t is contracted, the u and phi' loads of tiles t + 1 and
+    // t + 2 are in flight; phi' is staged into LDS one tile ahead (two buffers).  The loop runs
+    // whole turns of three tiles (tiles past the chunk end load as zero), so that every step
+    // sees the same loads outstanding.
+    u32x4 ah[3][SS], al[3][SS];
+    float2 bl[3][PER][4];
+    load_b(x_begin, bl[0]);
+    load_a(x_begin, ah[0], al[0]);
+    load_b(x_begin + XT, bl[1]);
+    load_a(x_begin + XT, ah[1], al[1]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    store_b(0, bl[0]);
+    int buf = 0;
+    auto step = [&](int x0, const u32x4 (&ch)[SS], const u32x4 (&cl)[SS], u32x4 (&nh)[SS], u32x4 (&nl)[SS],
+                    float2 (&nb)[PER][4], const float2 (&sb)[PER][4]) {
+        __syncthreads();
+        load_b(x0 + 2 * XT, nb);
+        load_a(x0 + 2 * XT, nh, nl);
+        __builtin_amdgcn_sched_barrier(0);
+        contract(buf, ch, cl);
+        store_b(buf ^ 1, sb);
         buf ^= 1;
+    };
+    for (int x0 = x_begin; x0 < x_end; x0 += 3 * XT) {
+        step(x0, ah[0], al[0], ah[2], al[2], bl[2], bl[1]);
+        step(x0 + XT, ah[1], al[1], ah[0], al[0], bl[0], bl[2]);
+        step(x0 + 2 * XT, ah[2], al[2], ah[1], al[1], bl[1], bl[0]);
     }
+    __builtin_amdgcn_s_waitcnt(0);   // retire the loads past the chunk end before the exit
 
     double* out = part + ((size_t)s * Nk + k) * Nb * 2 * cols + 2 * col0;
 #pragma unroll
