@@ -474,7 +474,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
 
 template <typename T> struct Tiles;
 template <> struct Tiles<double> { static constexpr int KC = 16, XT = 16, R = 3; };
-template <> struct Tiles<float> { static constexpr int KC = 32, XT = 64, R = 2; };
+template <> struct Tiles<float> { static constexpr int KC = 32, XT = 32, R = 3; };
 
 template <typename T, int MS>
 hipError_t fwd_dispatch_nt(int NT, int TC, dim3 grid, hipStream_t st, const void* U, const double* x,
