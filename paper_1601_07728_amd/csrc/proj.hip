@@ -291,8 +291,8 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 // Backward projection with split-K over x.  Block = (k, band block of W x 16 bands,
 // x chunk); wave w owns the 16 bands [band block * 16 W + 16 w, +16).  The chunk is walked
 // in tiles of XT points through a ring of R slots: while tile t is contracted, the u values
-// and the phi' values of tiles up to t + R - 1 are in flight (R = 3 for FP64, whose 16-byte
-// loads make short tiles; R = 2 with tiles twice as long for FP32).  phi' tiles (shared by all waves) sit in
+// and the phi' values of tiles up to t + R - 1 are in flight (R = 3: 16-point tiles in FP64,
+// 32-point tiles in FP32).  phi' tiles (shared by all waves) sit in
 // LDS as [sub-step][lane group kq][column][q][point pair] complex pairs, q = 0 holding
 // (re, im) and q = 1 holding (im, -re): the B operands of real column (column, q) are then
 // the two halves of one pair, and a lane picks its orientation by address, with no per-lane
