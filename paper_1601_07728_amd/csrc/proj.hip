@@ -298,11 +298,11 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 // the two halves of one pair, and a lane picks its orientation by address, with no per-lane
 // select.
 //
-// Columns [0, 8 NT) go through NT MFMA column tiles.  The last TC (0..2) columns, which
-// would fill at most a quarter of one more tile, are contracted with plain FMAs instead: a
-// 16x16x4 FP64 MFMA costs the issue slots of 16 wave-wide FMAs, so a tile holding 4 real
-// columns of 16 wastes three quarters of them.  Lane (i, kq) sums its own points for band
-// i, and the four lane groups are added at the end.
+// Columns [0, 8 NT) go through NT MFMA column tiles.  The last TC (0..2; up to 4 in a wide
+// pass) columns, which would fill at most a quarter (half) of one more tile, are contracted
+// with plain FMAs instead: a 16x16x4 FP64 MFMA costs the issue slots of 16 wave-wide FMAs,
+// so a tile holding 4 real columns of 16 wastes three quarters of them.  Lane (i, kq) sums
+// its own points for band i, and the four lane groups are added at the end.
 template <typename T, int NT, int TC, int XT, int R, int W, int CP>
 __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const typename Cplx<T>::c2* __restrict__ phi,
@@ -523,8 +523,10 @@ hipError_t bwd_dispatch_w(int NT, int TC, dim3 grid, hipStream_t st, const void*
             OCEAN_BWD(2, 1, kColsPerPass) OCEAN_BWD(2, 2, kColsPerPass)
         }
     } else if constexpr (sizeof(T) == 8) {
-        OCEAN_BWD(3, 1, kColsPerWidePass) OCEAN_BWD(3, 2, kColsPerWidePass) OCEAN_BWD(4, 0, kColsPerWidePass)
-        OCEAN_BWD(4, 1, kColsPerWidePass) OCEAN_BWD(4, 2, kColsPerWidePass) OCEAN_BWD(5, 0, kColsPerWidePass)
+        OCEAN_BWD(3, 1, kColsPerWidePass) OCEAN_BWD(3, 2, kColsPerWidePass) OCEAN_BWD(3, 3, kColsPerWidePass)
+        OCEAN_BWD(3, 4, kColsPerWidePass) OCEAN_BWD(4, 0, kColsPerWidePass) OCEAN_BWD(4, 1, kColsPerWidePass)
+        OCEAN_BWD(4, 2, kColsPerWidePass) OCEAN_BWD(4, 3, kColsPerWidePass) OCEAN_BWD(4, 4, kColsPerWidePass)
+        OCEAN_BWD(5, 0, kColsPerWidePass)
     }
 #undef OCEAN_BWD
     return hipErrorInvalidValue;
@@ -597,10 +599,17 @@ int cols_per_pass(const ocean_bse_s* h, int cols) {
 // MFMA column tiles and FMA tail columns for ncb complex columns.  In FP64 a remainder of at
 // most 4 real columns (2 complex) after whole 16-wide tiles goes to the FMA tail; FP32 MFMAs
 // are cheap next to FP32 FMAs, so FP32 always rounds up to whole tiles.
-void column_split(int ncb, bool fp64, int* NT, int* TC) {
+// A wide FP64 back-projection (more than kColsPerPass columns) is bound by the matrix cores
+// rather than by HBM; there the tail takes up to 4 columns, so the 36 columns of the full
+// spin space use four tiles and a 4-column tail rather than five tiles (measured: 2.56
+// against 2.71 ms at 36 columns).  The wide forward keeps the 2-column limit: with a
+// 4-column tail it needs 182 VGPRs, one wave per SIMD fewer, and was slower (2.66 against
+// 2.50 ms).
+void column_split(int ncb, bool fp64, bool wide_tail, int* NT, int* TC) {
     const int full = 2 * ncb / 16, rem = 2 * ncb - 16 * full;
+    const int max_tail = wide_tail && ncb > kColsPerPass ? 8 : 4;   // real columns
     if (rem == 0) { *NT = full; *TC = 0; }
-    else if (fp64 && rem <= 4 && full >= 1) { *NT = full; *TC = rem / 2; }
+    else if (fp64 && rem <= max_tail && full >= 1) { *NT = full; *TC = rem / 2; }
     else { *NT = full + 1; *TC = 0; }
 }
 
@@ -611,7 +620,7 @@ hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, in
     const int MS = (h->fwd_ms == 1 || ncb > kColsPerPass) ? 1 : 2;
     const int cols = nv * h->Nc;
     int NT, TC;
-    column_split(ncb, h->precision == OCEAN_PREC_FP64, &NT, &TC);
+    column_split(ncb, h->precision == OCEAN_PREC_FP64, false, &NT, &TC);
     const int x_tiles = (h->Nx + 64 * MS - 1) / (64 * MS);
     dim3 grid((unsigned)(h->Nk * x_tiles));
     hipError_t e;
@@ -634,7 +643,7 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     if (is_bf16_mode(h->precision)) return launch_proj_bwd_bf16(h, nv, col0, ncb);
     const int cols = nv * h->Nc;
     int NT, TC;
-    column_split(ncb, h->precision == OCEAN_PREC_FP64, &NT, &TC);
+    column_split(ncb, h->precision == OCEAN_PREC_FP64, true, &NT, &TC);
     int bb, S, chunk;
     bwd_geometry(h, &bb, &S, &chunk);
     const int W = bwd_waves(h->Nb);

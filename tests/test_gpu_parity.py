@@ -83,8 +83,8 @@ def test_apply_fp64_matches_oracle(case, n_vec):
 # 24 (FP64: a single pass when there are at most 40) and split each pass into 16-wide matrix-core tiles plus, in FP64, a multiply-add tail of
 # 1 or 2 columns.  Odd core counts reach the one-column tail.
 COLUMN_SPLITS = [(1, 2), (1, 9), (3, 3), (1, 17), (3, 5), (1, 18), (3, 8), (1, 41),
-                 # one wide FP64 pass of 25..40 columns: 3 tiles + tail 1 or 2, 4 tiles + tail 0..2, 5 tiles
-                 (5, 5), (2, 13), (6, 5), (3, 11), (2, 17), (12, 3), (4, 10)]
+                 # one wide FP64 pass of 25..40 columns: 3 tiles + tail 1..4, 4 tiles + tail 0..4, 5 tiles
+                 (5, 5), (2, 13), (3, 9), (7, 4), (6, 5), (3, 11), (2, 17), (5, 7), (12, 3), (4, 10)]
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-5)])
