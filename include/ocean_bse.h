@@ -155,6 +155,31 @@ int ocean_bse_apply(ocean_bse_t h, const double* x_dev, double* y_dev, int n_vec
 int ocean_haydock(ocean_bse_t h, const double* psi0_dev, int n_vec, int n_steps, unsigned flags,
                   double* a, double* b, double* norm2, int* steps_done);
 
+/* Checkpoint and resume of the recursion.  Each Haydock step (section 3.2, eq. haydock1)
+ * needs only v_i, v_{i-1} and b_i besides H; the coefficients already produced are the
+ * caller's.  So the state of a recursion is the two vectors plus, per vector,
+ * OCEAN_HAYDOCK_STATE_LEN doubles: {b_i, the running breakdown scale max(|a|, b), |psi0|^2,
+ * a_{i-1}, stopped (0 or 1), steps of the last call}.
+ *
+ * ocean_haydock_export copies the state the last ocean_haydock / ocean_haydock_batch /
+ * ocean_haydock_continue call on this handle ended in: v_dev and vprev_dev are device
+ * buffers of n_vec * dim complex (caller-owned), state is host [n_vec][6].  n_vec must be
+ * that call's.  Synchronises the handle's stream.  Errors: INVALID_ARG (NULL, no such
+ * run), DEVICE.
+ *
+ * ocean_haydock_continue runs n_steps more steps from such a state, on this handle or on
+ * another handle of the same system: a[v*n_steps + j], b[v*n_steps + j] are the next
+ * coefficients (a_{i+j}, b_{i+j+1}), steps_done[v] the steps completed in this call.  The
+ * coefficients of a run split this way equal those of one uninterrupted run bit for bit.
+ * Without re-orthogonalisation only (it would need every earlier vector).  Returns
+ * OCEAN_INFO_INVARIANT_SUBSPACE as ocean_haydock does (a vector that had already stopped
+ * completes 0 steps).  Errors: INVALID_ARG (NULL, n_vec or n_steps < 1, a state that no
+ * export wrote), UNSUPPORTED (OCEAN_HAYDOCK_REORTH), OUT_OF_MEMORY, DEVICE. */
+#define OCEAN_HAYDOCK_STATE_LEN 6
+int ocean_haydock_export(ocean_bse_t h, int n_vec, double* v_dev, double* vprev_dev, double* state);
+int ocean_haydock_continue(ocean_bse_t h, const double* v_dev, const double* vprev_dev, const double* state,
+                           int n_vec, int n_steps, unsigned flags, double* a, double* b, int* steps_done);
+
 /* Batched Haydock recursion for n_sys independent systems (sites, edges,
  * polarisations: section 4.3 keeps the wavefunctions resident and amortises them over
  * many spectra; section 4.5 runs hundreds of site-edge calculations).  System s uses

@@ -34,6 +34,7 @@ PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF1
 FLAG_BORROW_DEVICE_U = 0x1
 FLAG_CHECK_INPUTS = 0x2
 HAYDOCK_REORTH = 0x1
+HAYDOCK_STATE_LEN = 6
 TERM_NONE = 0
 TERM_SQRT = 1
 
@@ -48,7 +49,8 @@ EXPORTED = [
     "ocean_mlp_train_step", "ocean_mlp_predict", "ocean_mlp_save", "ocean_mlp_load",
     "ocean_device_ceilings", "ocean_screening_chi0", "ocean_local_matrix_channels",
     "ocean_dipole_amplitudes_channels", "ocean_dipole_psi0_channels", "ocean_nrixs_amplitudes_channels",
-    "ocean_quadrupole_amplitudes_channels", "ocean_psi0_amplitudes",
+    "ocean_quadrupole_amplitudes_channels", "ocean_psi0_amplitudes", "ocean_haydock_export",
+    "ocean_haydock_continue",
 ]
 MLP_BF16 = 0
 MLP_FP32 = 1
@@ -132,6 +134,10 @@ def lib() -> ctypes.CDLL:
     L.ocean_quadrupole_amplitudes_channels.restype = ci
     L.ocean_psi0_amplitudes.argtypes = [vp, vp, ci, vp]
     L.ocean_psi0_amplitudes.restype = ci
+    L.ocean_haydock_export.argtypes = [vp, ci, vp, vp, vp]
+    L.ocean_haydock_export.restype = ci
+    L.ocean_haydock_continue.argtypes = [vp, vp, vp, vp, ci, ci, ctypes.c_uint, vp, vp, vp]
+    L.ocean_haydock_continue.restype = ci
     L.ocean_dipole_amplitudes.argtypes = [vp, vp]
     L.ocean_dipole_amplitudes.restype = ci
     L.ocean_dipole_psi0.argtypes = [vp, vp, ci, vp]
@@ -498,6 +504,33 @@ class Bse:
         _check(lib().ocean_dipole_psi0_channels(self._h, len(la), la.ctypes.data_as(ctypes.c_void_p), _ptr(r),
                                                 _ptr(p), p.shape[0], _dev_ptr(out)))
         return out
+
+    def haydock_export(self, n_vec: int):
+        """State of the last recursion on this handle: (v, vprev) device tensors
+        [n_vec, Nk, Nb, Nc] and the host state [n_vec, 6] (ocean_haydock_export)."""
+        import torch
+        shape = (n_vec, self.n_k, self.n_bands, self.n_core)
+        v = torch.empty(shape, dtype=torch.complex128, device="cuda")
+        vp = torch.empty(shape, dtype=torch.complex128, device="cuda")
+        st = np.zeros((n_vec, HAYDOCK_STATE_LEN))
+        _device_sync()
+        _check(lib().ocean_haydock_export(self._h, n_vec, _dev_ptr(v), _dev_ptr(vp), _ptr(st)))
+        return v, vp, st
+
+    def haydock_continue(self, v, vprev, state, n_steps: int):
+        """n_steps more steps from an exported state; returns (a, b, steps_done, rc)."""
+        st = np.ascontiguousarray(np.asarray(state, dtype=np.float64))
+        nv = st.shape[0]
+        if v.numel() != nv * self.dim or vprev.numel() != nv * self.dim:
+            raise ValueError("vectors do not match the state's vector count")
+        a = np.zeros((nv, n_steps))
+        b = np.zeros((nv, n_steps))
+        sd = np.zeros(nv, dtype=np.int32)
+        _device_sync()
+        rc = lib().ocean_haydock_continue(self._h, _dev_ptr(v), _dev_ptr(vprev), _ptr(st), nv, int(n_steps), 0,
+                                          _ptr(a), _ptr(b), _ptr(sd))
+        _check(rc, allow_info=True)
+        return a, b, sd, rc
 
     def psi0_amplitudes(self, d):
         """Start vectors from local amplitudes d[n_pol][N_mu][3] (ocean_psi0_amplitudes)."""

@@ -697,6 +697,10 @@ int ocean_bse_apply(ocean_bse_t h, const double* x_dev, double* y_dev, int n_vec
     return apply_pipeline(h, x_dev, y_dev, n_vec, nullptr);
 }
 
+static int run_steps(ocean_bse_s* h, int n_vec, int n_steps, bool reorth);
+static int read_coefficients(ocean_bse_s* h, int n_vec, int n_steps, double* a, double* b, double* norm2,
+                             int* steps_done, const char* who);
+
 int ocean_haydock(ocean_bse_t h, const double* psi0_dev, int n_vec, int n_steps, unsigned flags,
                   double* a, double* b, double* norm2, int* steps_done) {
     g_last_error.clear();
@@ -712,7 +716,13 @@ int ocean_haydock(ocean_bse_t h, const double* psi0_dev, int n_vec, int n_steps,
     OCEAN_HIP(hipMemsetAsync(L.a, 0, (size_t)n_vec * n_steps * 8, h->stream), "memset");
     OCEAN_HIP(hipMemsetAsync(L.b, 0, (size_t)n_vec * n_steps * 8, h->stream), "memset");
     OCEAN_HIP(lz_init(h, psi0_dev, n_vec), "lz_init launch");
+    OCEAN_TRY(run_steps(h, n_vec, n_steps, reorth));
+    return read_coefficients(h, n_vec, n_steps, a, b, norm2, steps_done, "ocean_haydock");
+}
 
+// n_steps Haydock steps on the handle's Lanczos buffers, one captured graph replayed per
+// step when possible; synchronises the stream.
+static int run_steps(ocean_bse_s* h, int n_vec, int n_steps, bool reorth) {
     const bool use_graph = !h->profiling && env_int("OCEAN_NO_GRAPH", 0) == 0 && h->own_stream;
     bool graph_done = false;
     if (use_graph) {
@@ -743,21 +753,107 @@ int ocean_haydock(ocean_bse_t h, const double* psi0_dev, int n_vec, int n_steps,
     }
     OCEAN_HIP(hipStreamSynchronize(h->stream), "haydock");
     prof_collect(h);
+    return OCEAN_OK;
+}
+
+// Copy the coefficients and the per-vector state of the last run to the host.
+static int read_coefficients(ocean_bse_s* h, int n_vec, int n_steps, double* a, double* b, double* norm2,
+                             int* steps_done, const char* who) {
+    auto& L = h->lz;
     std::vector<LzState> st(n_vec);
     OCEAN_HIP(hipMemcpy(a, L.a, (size_t)n_vec * n_steps * 8, hipMemcpyDeviceToHost), "copy a");
     OCEAN_HIP(hipMemcpy(b, L.b, (size_t)n_vec * n_steps * 8, hipMemcpyDeviceToHost), "copy b");
     OCEAN_HIP(hipMemcpy(st.data(), L.state, n_vec * sizeof(LzState), hipMemcpyDeviceToHost), "copy state");
     int ret = OCEAN_OK;
     for (int v = 0; v < n_vec; ++v) {
-        norm2[v] = st[v].norm2;
+        if (norm2) norm2[v] = st[v].norm2;
         steps_done[v] = st[v].steps;
         if (!(st[v].norm2 > 0.0)) {
-            set_error("ocean_haydock: a starting vector is zero");
+            set_error(std::string(who) + ": a starting vector is zero");
             return OCEAN_ERR_INVALID_ARG;
         }
         if (st[v].steps < n_steps) ret = OCEAN_INFO_INVARIANT_SUBSPACE;
     }
     return ret;
+}
+
+int ocean_haydock_export(ocean_bse_t h, int n_vec, double* v_dev, double* vprev_dev, double* state) {
+    g_last_error.clear();
+    if (!h || !v_dev || !vprev_dev || !state || n_vec < 1) {
+        set_error("ocean_haydock_export: NULL argument or n_vec < 1");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    auto& L = h->lz;
+    if (!L.v || L.nv != n_vec) {
+        set_error("ocean_haydock_export: no recursion of n_vec vectors has run on this handle");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    (void)hipSetDevice(h->device);
+    const size_t vec_b = (size_t)n_vec * h->Nk * h->Nb * h->Nc * 16;
+    std::vector<LzState> st(n_vec);
+    OCEAN_HIP(hipMemcpyAsync(v_dev, L.v, vec_b, hipMemcpyDeviceToDevice, h->stream), "copy v");
+    OCEAN_HIP(hipMemcpyAsync(vprev_dev, L.vprev, vec_b, hipMemcpyDeviceToDevice, h->stream), "copy vprev");
+    OCEAN_HIP(hipMemcpyAsync(st.data(), L.state, n_vec * sizeof(LzState), hipMemcpyDeviceToHost, h->stream),
+              "copy state");
+    OCEAN_HIP(hipStreamSynchronize(h->stream), "export");
+    for (int v = 0; v < n_vec; ++v) {
+        double* o = state + (size_t)v * OCEAN_HAYDOCK_STATE_LEN;
+        o[0] = st[v].b_cur;
+        o[1] = st[v].scale;
+        o[2] = st[v].norm2;
+        o[3] = st[v].a_cur;
+        o[4] = st[v].done;
+        o[5] = st[v].steps;
+    }
+    return OCEAN_OK;
+}
+
+int ocean_haydock_continue(ocean_bse_t h, const double* v_dev, const double* vprev_dev, const double* state,
+                           int n_vec, int n_steps, unsigned flags, double* a, double* b, int* steps_done) {
+    g_last_error.clear();
+    if (!h || !v_dev || !vprev_dev || !state || !a || !b || !steps_done || n_vec < 1 || n_steps < 1) {
+        set_error("ocean_haydock_continue: NULL argument, n_vec < 1 or n_steps < 1");
+        return OCEAN_ERR_INVALID_ARG;
+    }
+    if (flags & OCEAN_HAYDOCK_REORTH) {
+        set_error("ocean_haydock_continue: re-orthogonalisation needs every earlier vector; continue runs "
+                  "the plain three-term recursion only");
+        return OCEAN_ERR_UNSUPPORTED;
+    }
+    std::vector<LzState> st(n_vec);
+    for (int v = 0; v < n_vec; ++v) {
+        const double* o = state + (size_t)v * OCEAN_HAYDOCK_STATE_LEN;
+        bool ok = true;
+        for (int j = 0; j < OCEAN_HAYDOCK_STATE_LEN; ++j) ok = ok && std::isfinite(o[j]);
+        if (!ok || o[0] < 0.0 || o[1] < 0.0 || !(o[2] > 0.0) || (o[4] != 0.0 && o[4] != 1.0) ||
+            (o[4] == 0.0 && !(o[0] > 0.0) && o[5] > 0.0)) {
+            set_error("ocean_haydock_continue: state is not one written by ocean_haydock_export");
+            return OCEAN_ERR_INVALID_ARG;
+        }
+        st[v].b_cur = o[0];
+        st[v].scale = o[1];
+        st[v].norm2 = o[2];
+        st[v].a_cur = o[3];
+        st[v].done = o[4] != 0.0 ? 1 : 0;
+        st[v].steps = 0;
+        st[v].pad[0] = st[v].pad[1] = 0;
+    }
+    (void)hipSetDevice(h->device);
+    OCEAN_TRY(ensure_workspace(h, n_vec));
+    OCEAN_TRY(ensure_lanczos(h, n_vec, n_steps, false));
+    auto& L = h->lz;
+    const size_t vec_b = (size_t)n_vec * h->Nk * h->Nb * h->Nc * 16;
+    OCEAN_HIP(hipMemcpyAsync(L.v, v_dev, vec_b, hipMemcpyDeviceToDevice, h->stream), "copy v");
+    OCEAN_HIP(hipMemcpyAsync(L.vprev, vprev_dev, vec_b, hipMemcpyDeviceToDevice, h->stream), "copy vprev");
+    OCEAN_HIP(hipMemcpyAsync(L.state, st.data(), n_vec * sizeof(LzState), hipMemcpyHostToDevice, h->stream),
+              "copy state");
+    OCEAN_HIP(hipMemsetAsync(L.step, 0, sizeof(int), h->stream), "memset");
+    OCEAN_HIP(hipMemsetAsync(L.a, 0, (size_t)n_vec * n_steps * 8, h->stream), "memset");
+    OCEAN_HIP(hipMemsetAsync(L.b, 0, (size_t)n_vec * n_steps * 8, h->stream), "memset");
+    OCEAN_TRY(run_steps(h, n_vec, n_steps, false));
+    // a vector whose recursion had already stopped reports 0 steps, and the call returns
+    // OCEAN_INFO_INVARIANT_SUBSPACE as for a new stop
+    return read_coefficients(h, n_vec, n_steps, a, b, nullptr, steps_done, "ocean_haydock_continue");
 }
 
 int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* psi0, const int* n_vec,

@@ -132,6 +132,8 @@ def test_null_handle_calls(lib):
     assert lib.ocean_bse_dim(None) == ob.ERR_INVALID_ARG
     assert lib.ocean_bse_apply(None, None, None, 1) == ob.ERR_INVALID_ARG
     assert lib.ocean_haydock(None, None, 1, 1, 0, None, None, None, None) == ob.ERR_INVALID_ARG
+    assert lib.ocean_haydock_export(None, 1, None, None, None) == ob.ERR_INVALID_ARG
+    assert lib.ocean_haydock_continue(None, None, None, None, 1, 1, 0, None, None, None) == ob.ERR_INVALID_ARG
     lib.ocean_bse_destroy(None)
 
 
