@@ -16,7 +16,9 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libocean_bse.so")
+# OCEAN_BSE_LIB names another build of the same library (the AddressSanitizer build of the
+# host-side checks); by default the in-tree library is loaded
+LIB_PATH = os.environ.get("OCEAN_BSE_LIB") or os.path.join(_HERE, "libocean_bse.so")
 
 OK = 0
 INFO_INVARIANT_SUBSPACE = 1
