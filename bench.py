@@ -579,6 +579,8 @@ def main():
         "terminator": terminator,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "environment": {"hip": torch.version.hip, "torch": torch.__version__,
+                        "device": torch.cuda.get_device_name(0), "host_threads": len(os.sched_getaffinity(0))},
     }
     print(json.dumps(line), flush=True)
 
