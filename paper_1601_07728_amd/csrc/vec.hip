@@ -568,25 +568,29 @@ __global__ __launch_bounds__(256) void dipole_kernel(const double2* __restrict__
     }
 }
 
-// w0[kn][col] = sum over chunks s of part[s][kn][col]: element e = blockIdx.x * 64 + (t % 64)
-// is summed by four threads over s = g, g + 4, ... (g = t / 64), then ((g0 + g1) + g2) + g3.
+// w0[kn][col] = sum over chunks s of part[s][kn][col].  A block of 256 threads sums 256 / G
+// elements: element e = blockIdx.x * (256 / G) + t % (256 / G) is summed by G threads over
+// s = g, g + G, ... (g = t / (256 / G)), and the G partial sums are then added in the order
+// g = 0, 1, ...  G = 4 for a few chunks; G = 16 when there are many (Gamma-only systems with
+// large grids), so that more blocks share the work and each thread walks fewer chunks.
+template <int G>
 __global__ __launch_bounds__(256) void reduce_part_kernel(const double2* __restrict__ part,
                                                          double2* __restrict__ w0, int S,
                                                          long long n_elem) {
+    constexpr int EB = 256 / G;   // elements per block
     __shared__ double2 sh[256];
     const int t = threadIdx.x;
-    const int g = t >> 6;
-    const long long e = (long long)blockIdx.x * 64 + (t & 63);
+    const int g = t / EB;
+    const long long e = (long long)blockIdx.x * EB + (t % EB);
     double2 acc = make_double2(0.0, 0.0);
     if (e < n_elem)
-        for (int s = g; s < S; s += 4) acc = cadd(acc, part[(size_t)s * n_elem + e]);
+        for (int s = g; s < S; s += G) acc = cadd(acc, part[(size_t)s * n_elem + e]);
     sh[t] = acc;
     __syncthreads();
     if (g == 0 && e < n_elem) {
         double2 r = sh[t];
-        r = cadd(r, sh[t + 64]);
-        r = cadd(r, sh[t + 128]);
-        r = cadd(r, sh[t + 192]);
+#pragma unroll
+        for (int j = 1; j < G; ++j) r = cadd(r, sh[t + j * EB]);
         w0[e] = r;
     }
 }
@@ -642,9 +646,14 @@ hipError_t launch_local_mat(ocean_bse_s* h, int nv) {
 hipError_t launch_reduce_part(ocean_bse_s* h, int nv) {
     const long long n_elem = (long long)h->Nk * h->Nb * nv * h->Nc;
     const int slot = prof_begin(h, "reduce_part");
-    reduce_part_kernel<<<(unsigned)((n_elem + 63) / 64), 256, 0, h->stream>>>(
-        reinterpret_cast<const double2*>(h->ws.part), reinterpret_cast<double2*>(h->ws.w0), h->ws.bwd_chunks,
-        n_elem);
+    const double2* part = reinterpret_cast<const double2*>(h->ws.part);
+    double2* w0 = reinterpret_cast<double2*>(h->ws.w0);
+    if (h->ws.bwd_chunks > 16)
+        reduce_part_kernel<16><<<(unsigned)((n_elem + 15) / 16), 256, 0, h->stream>>>(part, w0, h->ws.bwd_chunks,
+                                                                                    n_elem);
+    else
+        reduce_part_kernel<4><<<(unsigned)((n_elem + 63) / 64), 256, 0, h->stream>>>(part, w0, h->ws.bwd_chunks,
+                                                                                  n_elem);
     prof_end(h, slot);
     return hipGetLastError();
 }
