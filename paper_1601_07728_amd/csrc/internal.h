@@ -157,6 +157,19 @@ template <> __device__ __forceinline__ double2 bload<double2>(Rsrc r, unsigned o
 template <> __device__ __forceinline__ float2 bload<float2>(Rsrc r, unsigned off) {
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
+// Loads of a stream read once in whole 128-byte lines (u in the back-projections): the
+// non-temporal cache policy (cache-policy bit 1, "nt" on gfx950), so the stream does not
+// displace reused lines.  The forward projections read each line of u in two 64-byte halves
+// by consecutive instructions and rely on the second half hitting in the cache; with this
+// policy the FP64 forward was 10% slower, the back-projection 2% faster.
+constexpr int kStreamPolicy = 2;
+template <typename C2> __device__ __forceinline__ C2 bload_stream(Rsrc r, unsigned off);
+template <> __device__ __forceinline__ double2 bload_stream<double2>(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, kStreamPolicy));
+}
+template <> __device__ __forceinline__ float2 bload_stream<float2>(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, kStreamPolicy));
+}
 template <typename C2> __device__ __forceinline__ void bstore(C2 v, Rsrc r, unsigned off);
 template <> __device__ __forceinline__ void bstore<double2>(double2 v, Rsrc r, unsigned off) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r, (int)off, 0, 0);

@@ -353,7 +353,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
             for (int xs = 0; xs < 2; ++xs) {
                 const int x = x0 + 8 * ss + 2 * kq + xs;
                 const bool ok = nval && x < x_end;
-                uu[ss][xs] = bload<C2>(ur, ok ? (unsigned)(((x - x_begin) * Nb + n) * sizeof(C2)) : kOob);
+                uu[ss][xs] = bload_stream<C2>(ur, ok ? (unsigned)(((x - x_begin) * Nb + n) * sizeof(C2)) : kOob);
             }
     };
     // point xl of the tile = (sub-step xl / 8, lane group (xl % 8) / 2, pair slot xl % 2)
