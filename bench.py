@@ -69,25 +69,25 @@ def proj_bytes(cr, cols, u_elem, phi_elem):
 # WRITE_SIZE 1.0 GiB for 1 GiB written).  A figure holds only for the kernel source it was
 # taken with (sha256 of the .hip file); for any other source the traffic is reported null.
 TRAFFIC = {
-    ("fp64", "proj_fwd"): {"bytes": 7588394643, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 2, 2, 16, 24>
-        "sha256": "c7c8c33229527b16bbe8681b3e93443d37e0b7ba2b327c87bf61801c128d85fe"},
-    ("fp64", "proj_bwd"): {"bytes": 7548005999, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 16, 3, 6, 24>
-        "sha256": "c7c8c33229527b16bbe8681b3e93443d37e0b7ba2b327c87bf61801c128d85fe"},
-    ("fp32", "proj_fwd"): {"bytes": 3849487541, "src": "proj.hip",  # proj_fwd_kernel<float, 1, 3, 0, 32, 24>
-        "sha256": "c7c8c33229527b16bbe8681b3e93443d37e0b7ba2b327c87bf61801c128d85fe"},
-    ("fp32", "proj_bwd"): {"bytes": 3788064982, "src": "proj.hip",  # proj_bwd_kernel<float, 3, 0, 32, 3, 6, 24>
-        "sha256": "c7c8c33229527b16bbe8681b3e93443d37e0b7ba2b327c87bf61801c128d85fe"},
-    ("split_bf16", "proj_fwd"): {"bytes": 3755395052, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<1, 3, true>
+    ("fp64", "proj_fwd"): {"bytes": 7588231854, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 2, 2, 16, 24>
+        "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
+    ("fp64", "proj_bwd"): {"bytes": 7547770093, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 16, 3, 6, 24>
+        "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
+    ("fp32", "proj_fwd"): {"bytes": 3849412277, "src": "proj.hip",  # proj_fwd_kernel<float, 1, 3, 0, 32, 24>
+        "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
+    ("fp32", "proj_bwd"): {"bytes": 3788065483, "src": "proj.hip",  # proj_bwd_kernel<float, 3, 0, 32, 3, 6, 24>
+        "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
+    ("split_bf16", "proj_fwd"): {"bytes": 3755214322, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<1, 3, true>
         "sha256": "b8b9ae7200e8832d78bbbff6e34acc8d5fd42827dd5a2eed9ab8511acf9e5061"},
-    ("split_bf16", "proj_bwd"): {"bytes": 3808093913, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
+    ("split_bf16", "proj_bwd"): {"bytes": 3808176434, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
         "sha256": "b8b9ae7200e8832d78bbbff6e34acc8d5fd42827dd5a2eed9ab8511acf9e5061"},
-    ("bf16", "proj_fwd"): {"bytes": 2184709926, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<2, 3, false>
+    ("bf16", "proj_fwd"): {"bytes": 2184769847, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<2, 3, false>
         "sha256": "b8b9ae7200e8832d78bbbff6e34acc8d5fd42827dd5a2eed9ab8511acf9e5061"},
-    ("bf16", "proj_bwd"): {"bytes": 2222189870, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
+    ("bf16", "proj_bwd"): {"bytes": 2222313148, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
         "sha256": "b8b9ae7200e8832d78bbbff6e34acc8d5fd42827dd5a2eed9ab8511acf9e5061"},
-    ("fp64", "fft_w"): {"bytes": 2392650236, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
+    ("fp64", "fft_w"): {"bytes": 2392651246, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
         "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
-    ("fp32", "fft_w"): {"bytes": 1196248320, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
+    ("fp32", "fft_w"): {"bytes": 1196251897, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
         "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
 }
 
