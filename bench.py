@@ -205,8 +205,12 @@ def bench_batched(ob, seed, steps=200):
         sig = [ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd)
                for (a, b, n2, sd), (cr, _) in zip(res, sites)]
         dt = time.perf_counter() - t0
+        # both projections of every site, each step: the algorithmic bytes of the HBM stream
+        step_bytes = sum(2 * proj_bytes(cr, 3 * cr.n_core, U_BYTES[prec], PHI_BYTES[prec]) for cr, _ in sites)
         out[prec] = {"spectra_per_s": n_solves / dt, "hv_per_s": n_solves * steps / dt,
-                     "seconds": dt, "sig": sig}
+                     "seconds": dt, "sig": sig,
+                     "projection_GBs": step_bytes * steps / dt / 1e9,
+                     "projection_hbm_frac": step_bytes * steps / dt / 1e9 / PEAK_HBM_GBS}
         log(f"batched {prec}: {n_solves} solves x {steps} steps in {dt:.2f} s: "
             f"{n_solves / dt:.1f} spectra/s, {n_solves * steps / dt:.0f} H*v/s")
         for h in hs:
