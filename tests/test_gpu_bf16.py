@@ -94,7 +94,7 @@ def test_split_bf16_is_more_accurate_than_bf16():
 @pytest.mark.parametrize("prec", ["split_bf16", "bf16"])
 def test_bf16_spectrum_l1_within_1e_3(prec):
     """Spectrum at full Krylov depth against the dense FP64 oracle spectrum (the same system
-    the FP32 path is judged on)."""
+    the FP32 path is tested on)."""
     import paper_1601_07728_amd as ob
     cr = synth.small_l_edge(seed=10, nk=(2, 2, 2), nx=(6, 6, 6), n_bands=10)
     hc, kl = _mats(cr)

@@ -104,7 +104,7 @@ def _dataset(ob, seeds, n_steps, **shape):
 
 
 def test_learned_terminator_gains_on_held_out_systems():
-    """Train on solver-generated coefficients, judge on held-out systems against the
+    """Train on solver-generated coefficients, evaluate on held-out systems against the
     full-depth recursion.  Asserted: training lowers the loss, and the learned closure
     beats the plain 32-level continued fraction by a wide margin.  Reported beside it: the
     classic square-root terminator and the untrained network (on these synthetic systems

@@ -170,7 +170,7 @@ def test_w_radial_interpolation_and_tail(c1):
     assert abs(w[-1] - 1.0 / (c1.eps * 6.0)) < 1e-16
 
 
-# --- independent-particle limit (north star; Lorentzians at the band energies) --------------
+# --- independent-particle limit (W = 0: Lorentzians at the band energies) ------------------
 
 def test_ip_limit_closed_form(c1):
     """W = 0, no core matrix, no local term: sigma(w) = (1/pi) sum |psi0|^2 Gamma /
