@@ -358,7 +358,7 @@ def spectra_gain(ob, cr, hs, psi0, mlp, ref_steps=600, base_steps=300):
     base = {"path": "fp64", "steps": base_steps, "terminator": "none", "spectra_per_s": n_pol / dt,
             "l1": float(np.mean(term.l1(sig, ref)))}
     rows.append(base)
-    for steps in (32, 40, 48, 56, 64, 96, 128, 192):
+    for steps in (32, 40, 44, 48, 52, 56, 64, 96, 128, 192):
         for name, h in hs.items():
             dt, (a, b, n2, sd, _) = timed_haydock(h, psi0, steps)
             for tname in ("sqrt", "mlp") if steps == 32 else ("sqrt",):
