@@ -196,8 +196,9 @@ int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* p
                         const int* n_vec, int n_steps, unsigned flags, double* a, double* b,
                         double* norm2, int* steps_done);
 
-/* Tile autotuner: times the candidate tile shapes of the projection, back-projection
- * and k-grid transform kernels on this handle's shape with n_vec vectors (mean of the
+/* Tile autotuner (not in the paper: the kernels of Algorithm 1, section 3.2.1, have tile
+ * shapes that depend on the system): times the candidate tile shapes of the projection,
+ * back-projection and k-grid transform kernels on this handle's shape with n_vec vectors (mean of the
  * tuned kernel's own HIP-event time over reps applies per candidate, after one untimed
  * apply; reps < 1 means 5) and keeps the fastest.  If the environment variable
  * OCEAN_AUTOTUNE_CACHE names a file, a cached choice for the same shape is reused and new
@@ -318,9 +319,10 @@ int ocean_multiplet_matrices_spin(double zeta, double F2, double G1, double G3,
 int ocean_local_matrix_channels(int n_ch, const int* l, const double* f2, const double* gk, int full_spin,
                                 double* local_mat);
 
-/* Host helper: dipole amplitudes of a general local basis, d[mu][mc+1] =
- * radial[i] <Y_{l_i m}| e.r^ |Y_1mc> for mu = (channel i, m); only s and d channels couple to
- * a 2p core.  d is [N_mu][3] complex.  Errors: INVALID_ARG. */
+/* Host helper: dipole amplitudes (section 2, eq. loss.fcn, O = e.r) of a general local
+ * basis (section 3.2.2, eq. local_basis), d[mu][mc+1] = radial[i] <Y_{l_i m}| e.r^ |Y_1mc>
+ * for mu = (channel i, m); only s and d channels couple to a 2p core.  d is [N_mu][3]
+ * complex.  Errors: INVALID_ARG. */
 int ocean_dipole_amplitudes_channels(int n_ch, const int* l, const double* radial, const double* e, double* d);
 
 /* Host helper: dipole amplitudes d[m+2][mc+1] = <Y_2m| e.r^ |Y_1mc> (radial
@@ -336,7 +338,7 @@ int ocean_dipole_amplitudes(const double* e, double* d);
  * stream.  Errors: INVALID_ARG, UNSUPPORTED (other edge shapes), DEVICE. */
 int ocean_dipole_psi0(ocean_bse_t h, const double* pol, int n_pol, double* psi0_dev);
 
-/* The same for a general local basis: channels l[n_ch] with radial dipole integrals
+/* The same for a general local basis (section 3.2.2): channels l[n_ch] with radial dipole integrals
  * radial[n_ch] (ocean_dipole_amplitudes_channels), spanning exactly the handle's n_local
  * functions; n_core 6 or 12 (spin layout as in ocean_dipole_psi0).  Errors: INVALID_ARG,
  * UNSUPPORTED (other shapes), DEVICE. */
