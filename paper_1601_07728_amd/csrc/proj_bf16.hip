@@ -464,7 +464,8 @@ hipError_t bwd_bf16(int W, int NT, dim3 grid, hipStream_t st, const u16* uh, con
 }  // namespace
 
 hipError_t launch_proj_fwd_bf16(ocean_bse_s* h, const double* x, int nv, int col0, int ncb) {
-    const int MS = h->fwd_ms == 1 ? 1 : 2;   // 16 * MS rows per wave, 64 * MS per block
+    // 16 * MS rows per wave, 64 * MS per block
+    const int MS = h->fwd_ms == 1 ? 1 : h->fwd_ms == 4 ? 4 : 2;
     const int cols = nv * h->Nc;
     const int NT = (2 * ncb + 15) / 16;
     const int x_tiles = (h->Nx + 64 * MS - 1) / (64 * MS);
@@ -489,9 +490,12 @@ hipError_t launch_proj_fwd_bf16(ocean_bse_s* h, const double* x, int nv, int col
     if (MS == 1)
         e = lo ? fwd_bf16_nt<1, true>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks)
                : fwd_bf16_nt<1, false>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks);
-    else
+    else if (MS == 2)
         e = lo ? fwd_bf16_nt<2, true>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks)
                : fwd_bf16_nt<2, false>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks);
+    else
+        e = lo ? fwd_bf16_nt<4, true>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks)
+               : fwd_bf16_nt<4, false>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks);
     prof_end(h, slot);
     return e;
 }

@@ -1086,7 +1086,10 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
             h->ws.bwd_chunks = S;
         }
     };
-    if (rc == OCEAN_OK) sweep({1, 2}, &h->fwd_ms, {"proj_fwd"}, false);
+    // rows per forward wave: 16 or 32 (64 as well in the bf16 modes, whose blocks stream little)
+    if (rc == OCEAN_OK)
+        sweep(is_bf16_mode(h->precision) ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2}, &h->fwd_ms,
+              {"proj_fwd"}, false);
     if (rc == OCEAN_OK) sweep({1024, 2048, 4096, 8192}, &h->bwd_target_blocks, {"proj_bwd", "reduce_part", "combine"}, true);
     if (rc == OCEAN_OK && h->Nk > 1) {
         std::vector<int> lines;
