@@ -69,25 +69,25 @@ def proj_bytes(cr, cols, u_elem, phi_elem):
 # WRITE_SIZE 1.0 GiB for 1 GiB written).  A figure holds only for the kernel source it was
 # taken with (sha256 of the .hip file); for any other source the traffic is reported null.
 TRAFFIC = {
-    ("fp64", "proj_fwd"): {"bytes": 7588231854, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 2, 2, 16, 24>
+    ("fp64", "proj_fwd"): {"bytes": 7588385450, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 2, 2, 16, 24>
         "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
-    ("fp64", "proj_bwd"): {"bytes": 7547770093, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 16, 3, 6, 24>
+    ("fp64", "proj_bwd"): {"bytes": 7547771731, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 16, 3, 6, 24>
         "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
-    ("fp32", "proj_fwd"): {"bytes": 3849412277, "src": "proj.hip",  # proj_fwd_kernel<float, 1, 3, 0, 32, 24>
+    ("fp32", "proj_fwd"): {"bytes": 3849504435, "src": "proj.hip",  # proj_fwd_kernel<float, 1, 3, 0, 32, 24>
         "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
-    ("fp32", "proj_bwd"): {"bytes": 3788065483, "src": "proj.hip",  # proj_bwd_kernel<float, 3, 0, 32, 3, 6, 24>
+    ("fp32", "proj_bwd"): {"bytes": 3788065380, "src": "proj.hip",  # proj_bwd_kernel<float, 3, 0, 32, 3, 6, 24>
         "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
-    ("split_bf16", "proj_fwd"): {"bytes": 3755214322, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<1, 3, true>
-        "sha256": "b8b9ae7200e8832d78bbbff6e34acc8d5fd42827dd5a2eed9ab8511acf9e5061"},
-    ("split_bf16", "proj_bwd"): {"bytes": 3808176434, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
-        "sha256": "b8b9ae7200e8832d78bbbff6e34acc8d5fd42827dd5a2eed9ab8511acf9e5061"},
-    ("bf16", "proj_fwd"): {"bytes": 2184769847, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<2, 3, false>
-        "sha256": "b8b9ae7200e8832d78bbbff6e34acc8d5fd42827dd5a2eed9ab8511acf9e5061"},
-    ("bf16", "proj_bwd"): {"bytes": 2222313148, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
-        "sha256": "b8b9ae7200e8832d78bbbff6e34acc8d5fd42827dd5a2eed9ab8511acf9e5061"},
-    ("fp64", "fft_w"): {"bytes": 2392651246, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
+    ("split_bf16", "proj_fwd"): {"bytes": 3855217262, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<4, 3, true>
+        "sha256": "bc329187f81262ffe42d7523be8761ce4b4234907f4abd4102886b6960e1a2a6"},
+    ("split_bf16", "proj_bwd"): {"bytes": 3809242797, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
+        "sha256": "bc329187f81262ffe42d7523be8761ce4b4234907f4abd4102886b6960e1a2a6"},
+    ("bf16", "proj_fwd"): {"bytes": 2189376719, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<4, 3, false>
+        "sha256": "bc329187f81262ffe42d7523be8761ce4b4234907f4abd4102886b6960e1a2a6"},
+    ("bf16", "proj_bwd"): {"bytes": 2225063332, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
+        "sha256": "bc329187f81262ffe42d7523be8761ce4b4234907f4abd4102886b6960e1a2a6"},
+    ("fp64", "fft_w"): {"bytes": 2392659438, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
         "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
-    ("fp32", "fft_w"): {"bytes": 1196251897, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
+    ("fp32", "fft_w"): {"bytes": 1196253945, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
         "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
 }
 
