@@ -168,3 +168,22 @@ def test_checkpoint_resume_is_exact(tmp_path):
         m3.load(path)           # a bf16 checkpoint does not load into an FP32 handle
     for m in (m1, m2, m3):
         m.close()
+
+
+def test_corrupt_network_falls_back_to_the_full_recursion():
+    """A network whose outputs are not finite (NaN parameters here) flags every sequence
+    invalid, and the learned closure then uses the full-depth recursion for those sequences:
+    its spectra equal the full-depth ones."""
+    import paper_1601_07728_amd as ob
+    from paper_1601_07728_amd import terminator as term
+    crs, a, b, n2, sd = _dataset(ob, range(501, 509), 256, nk=(2, 2, 2), nx=(4, 4, 4), n_bands=16)
+    m = ob.Mlp("bf16")
+    m.set_params(np.full(m.n_params, np.nan, dtype=np.float32))
+    ae, be, valid = m.predict(a[:, :32], b[:, :32])
+    assert not valid.any()
+    om, gam = crs[0].omega, crs[0].gamma
+    res, valid2 = term.terminated_spectra(m, a, b, n2, om, gam, a_full=a, b_full=b, n_full=sd)
+    ref = ob.spectrum(a, b, n2, om, gam, n_used=sd)
+    assert not valid2.any()
+    assert np.array_equal(res["mlp"], ref)
+    m.close()
