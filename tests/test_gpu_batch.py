@@ -101,3 +101,38 @@ def test_terminator_systems_fullsize_prefix():
         assert np.abs(b[0, :30] - rb).max() <= 1e-10 * S
         assert abs(n2[0] - rn2) <= 1e-13 * rn2
         h.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("bf16", 1e-2)])
+def test_every_tuning_candidate_gives_the_same_result(tmp_path, monkeypatch, precision, tol):
+    """Each tile choice the autotuner can make (rows per forward wave, back-projection grid
+    target, lines per transform block), forced through the cache file: H*v against the oracle,
+    and in FP64 every choice within rounding of every other."""
+    import torch
+
+    import paper_1601_07728_amd as ob
+    cr = synth.small_l_edge(seed=23, nk=(4, 4, 4), nx=(10, 9, 8), n_bands=37)
+    hc, kl = omp.core_matrix(cr.multiplet), omp.local_matrix(cr.multiplet)
+    x = synth.complex_gaussian(np.random.default_rng(5), (3, cr.n_k, cr.n_bands, cr.n_core))
+    refs = [orc.apply_h(cr, x[v], hc, kl) for v in range(3)]
+    prec_id = {"fp64": ob.PREC_FP64, "bf16": ob.PREC_BF16}[precision]
+    key = (f"nk=4,4,4 nx=10,9,8 nb={cr.n_bands} nc={cr.n_core} nmu=5 prec={prec_id} cols={3 * cr.n_core}")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("OCEAN_AUTOTUNE_CACHE", str(cache))
+    xd = torch.from_numpy(x).to("cuda")
+    first = None
+    for ms in ((1, 2, 4) if precision == "bf16" else (1, 2)):
+        for bt in (1024, 2048, 4096, 8192):
+            for fl in (4, 8, 16, 32, 64):
+                cache.write_text(f"{key}|{ms} {bt} {fl}\n")
+                h = ob.Bse.from_crystal(cr, precision=precision)
+                assert h.autotune(n_vec=3) == {"fwd_ms": ms, "bwd_blocks": bt, "fft_lines": fl}
+                y = h.apply(xd).cpu().numpy()
+                h.close()
+                for v in range(3):
+                    err = float(np.abs(y[v] - refs[v]).max() / np.abs(refs[v]).max())
+                    assert err <= tol, (ms, bt, fl, v, err)
+                if first is None:
+                    first = y
+                elif precision == "fp64":
+                    assert np.abs(y - first).max() <= 1e-13 * np.abs(first).max(), (ms, bt, fl)
