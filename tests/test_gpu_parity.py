@@ -321,3 +321,25 @@ def test_fp32_spectrum_l1_within_1e_3():
     yr = orc.apply_h(cr, x, hc, kl)
     assert _rel(y, yr) <= 1e-5
     h.close()
+
+
+def test_long_range_term_does_not_mix_core_states():
+    """Algorithm 1 treats each core index on its own (section 3.2.1): with no core matrix and no
+    local term, H*v of a vector living on one core state stays on that state, and equals the
+    same vector's H*v computed alone with one core state."""
+    ob = _ob()
+    cr = synth.make_crystal("nomix", a=6.8, tau=(0.3, 1.1, 2.0), nk=(2, 2, 2), nx=(6, 5, 6), n_bands=13,
+                            n_core=6, e_range_ev=20.0, eps=4.0, seed=91, psi0="none")
+    h = ob.Bse.from_crystal(cr, precision="fp64")
+    rng = np.random.default_rng(92)
+    x = np.zeros((1, cr.n_k, cr.n_bands, 6), dtype=np.complex128)
+    x[0, :, :, 4] = synth.complex_gaussian(rng, (cr.n_k, cr.n_bands))
+    y = h.apply(_to_dev(x)).cpu().numpy()[0]
+    h.close()
+    assert np.abs(y[:, :, [0, 1, 2, 3, 5]]).max() == 0.0
+    c1 = synth.make_crystal("nomix1", a=6.8, tau=(0.3, 1.1, 2.0), nk=(2, 2, 2), nx=(6, 5, 6), n_bands=13,
+                            n_core=1, e_range_ev=20.0, eps=4.0, seed=91, psi0="none")
+    h1 = ob.Bse.from_crystal(c1, precision="fp64")
+    y1 = h1.apply(_to_dev(np.ascontiguousarray(x[:, :, :, 4:5]))).cpu().numpy()[0]
+    h1.close()
+    assert np.abs(y[:, :, 4] - y1[:, :, 0]).max() <= 1e-14 * np.abs(y1).max()
