@@ -1,7 +1,8 @@
 """Runtime paths forced from the host: the device-memory cap (OCEAN_MAX_DEVICE_BYTES) turns
 an allocation past it into OUT_OF_MEMORY, at create and at the recursion's first use of its
 buffers, and leaves the handle usable once lifted; the eager step loop (OCEAN_NO_GRAPH)
-gives the same coefficients as the replayed graph, bit for bit, alone and batched."""
+gives the same coefficients as the replayed graph, bit for bit, alone and batched; per-kernel
+timing reports every kernel of the step and changes no result."""
 import numpy as np
 import pytest
 
@@ -49,3 +50,25 @@ def test_eager_steps_equal_graph_replay(monkeypatch):
     assert np.array_equal(sg[0], se[0]) and np.array_equal(sg[1], se[1])
     for (ag, bgg, ng, sdg), (ae, bee, ne, sde) in zip(bg, be):
         assert np.array_equal(ag, ae) and np.array_equal(bgg, bee) and np.array_equal(sdg, sde)
+
+
+def test_profiling_times_every_kernel_and_changes_nothing():
+    """With per-kernel timing on, the recursion runs its kernels eagerly between HIP events:
+    the coefficients equal the graph-replayed ones bit for bit, and every kernel of the step
+    is reported once per step with a positive time."""
+    import paper_1601_07728_amd as ob
+    cr = synth.small_l_edge(seed=85, nk=(2, 2, 2), nx=(6, 5, 6), n_bands=15)
+    h = ob.Bse.from_crystal(cr, precision="fp64")
+    p0 = h.dipole_psi0(np.eye(3))
+    a, b, n2, sd, rc = h.haydock(p0, 12)
+    h.set_profiling(True)
+    ap, bp, n2p, sdp, rcp = h.haydock(p0, 12)
+    kt = h.kernel_times()
+    h.set_profiling(False)
+    h.close()
+    assert np.array_equal(a, ap) and np.array_equal(b, bp) and np.array_equal(n2, n2p)
+    for name in ("proj_fwd", "proj_bwd", "fft_w", "combine", "local_in", "local_mat", "lz_update",
+                 "lz_finalize", "lz_scale"):
+        assert name in kt, (name, sorted(kt))
+        ms, count = kt[name]
+        assert ms > 0.0 and count == 12, (name, ms, count)
