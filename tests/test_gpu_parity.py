@@ -343,3 +343,22 @@ def test_long_range_term_does_not_mix_core_states():
     y1 = h1.apply(_to_dev(np.ascontiguousarray(x[:, :, :, 4:5]))).cpu().numpy()[0]
     h1.close()
     assert np.abs(y[:, :, 4] - y1[:, :, 0]).max() <= 1e-14 * np.abs(y1).max()
+
+
+def test_one_vector_stops_while_the_other_continues():
+    """Two starting vectors in one recursion, one an eigenvector (it stops after one step) and
+    one generic: the stopped vector reports 1 step and zeros after it, the generic one runs on
+    with exactly the coefficients it has when run alone."""
+    ob = _ob()
+    cr = synth.config1()
+    cr.w_val = cr.w_val * 0.0
+    h = ob.Bse.from_crystal(cr)
+    psi = np.zeros((2, cr.n_k, cr.n_bands, cr.n_core), dtype=np.complex128)
+    psi[0, 1, 3, 0] = 1.0
+    psi[1] = synth.complex_gaussian(np.random.default_rng(93), (cr.n_k, cr.n_bands, cr.n_core))
+    a, b, n2, sd, rc = h.haydock(_to_dev(psi), 30)
+    assert rc == ob.INFO_INVARIANT_SUBSPACE and sd[0] == 1 and sd[1] == 30
+    assert np.all(a[0, 1:] == 0) and np.all(b[0] == 0)
+    a1, b1, n21, sd1, _ = h.haydock(_to_dev(np.ascontiguousarray(psi[1:])), 30)
+    assert np.array_equal(a[1], a1[0]) and np.array_equal(b[1], b1[0]) and n2[1] == n21[0]
+    h.close()
