@@ -279,6 +279,27 @@ int ocean_mlp_train_step(ocean_mlp_t h, const float* x_dev, const float* t_dev, 
 int ocean_mlp_predict(ocean_mlp_t h, const double* a, const double* b, int n_seq, int stride,
                       double* a_ext, double* b_ext, int* valid);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * or harnesses that forbid hipMalloc): ocean_mlp_predict on device buffers, allocating nothing.
+ * Inputs a_dev, b_dev [n_seq][stride] (device, FP64, b[j] = b_{j+1}, stride >= 32); outputs
+ * a_ext_dev, b_ext_dev [n_seq][256] (device, FP64) and valid_dev [n_seq] (device, int), with the
+ * meaning of ocean_mlp_predict's (results equal that call's bit for bit).  The encoding
+ * constants and the activations of every layer live in one fixed array of device memory of
+ * about 21 MB (OCEAN_MLP_NOALLOC_MAX_SEQ sequences at most), which each device that the library
+ * runs on holds until the process ends; its address is resolved once per device by
+ * ocean_mlp_create.  Every call on one device shares that array and every element a call reads
+ * is written by the same call first, so nothing carries over between calls, but calls that
+ * overlap on one device (other streams, other threads, other handles) race: the caller must
+ * serialise them.  Enqueued on `stream` (a hipStream_t on the handle's device, or NULL for the
+ * default stream); returns without synchronising.  The parameters are read on that stream, so
+ * work still pending on the handle's own stream (an asynchronous ocean_mlp_train_step) must
+ * have finished first.  Calls no hipMalloc, hipFree or other allocating routine.
+ * Errors: INVALID_ARG (NULL, n_seq < 1 or > OCEAN_MLP_NOALLOC_MAX_SEQ, stride < 32), DEVICE
+ * (launch failure). */
+#define OCEAN_MLP_NOALLOC_MAX_SEQ 4096
+int ocean_mlp_predict_noalloc(ocean_mlp_t h, const double* a_dev, const double* b_dev, int n_seq, int stride,
+                              double* a_ext_dev, double* b_ext_dev, int* valid_dev, void* stream);
+
 /* Host helper: the L2,3-edge (2p core, d channel) matrices for ocean_bse_desc
  * from the spin-orbit parameter zeta and the Slater integrals F2 (screened
  * direct) and G1, G3 (bare exchange), all in Ha (section 2: H_h, V_D, V_X;

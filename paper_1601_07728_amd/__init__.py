@@ -52,10 +52,11 @@ EXPORTED = [
     "ocean_device_ceilings", "ocean_screening_chi0", "ocean_local_matrix_channels",
     "ocean_dipole_amplitudes_channels", "ocean_dipole_psi0_channels", "ocean_nrixs_amplitudes_channels",
     "ocean_quadrupole_amplitudes_channels", "ocean_psi0_amplitudes", "ocean_haydock_export",
-    "ocean_haydock_continue",
+    "ocean_haydock_continue", "ocean_mlp_predict_noalloc",
 ]
 MLP_BF16 = 0
 MLP_FP32 = 1
+MLP_NOALLOC_MAX_SEQ = 4096      # OCEAN_MLP_NOALLOC_MAX_SEQ
 
 
 def cell_matrix(cell) -> np.ndarray:
@@ -174,6 +175,8 @@ def lib() -> ctypes.CDLL:
     L.ocean_mlp_train_step.restype = ci
     L.ocean_mlp_predict.argtypes = [vp, vp, vp, ci, ci, vp, vp, vp]
     L.ocean_mlp_predict.restype = ci
+    L.ocean_mlp_predict_noalloc.argtypes = [vp, vp, vp, ci, ci, vp, vp, vp, vp]
+    L.ocean_mlp_predict_noalloc.restype = ci
     L.ocean_mlp_save.argtypes = [vp, ctypes.c_char_p]
     L.ocean_mlp_save.restype = ci
     L.ocean_mlp_load.argtypes = [vp, ctypes.c_char_p]
@@ -674,3 +677,19 @@ class Mlp:
         valid = np.zeros(n, dtype=np.int32)
         _check(lib().ocean_mlp_predict(self._h, _ptr(a), _ptr(b), n, stride, _ptr(ae), _ptr(be), _ptr(valid)))
         return ae, be, valid.astype(bool)
+
+    def predict_noalloc(self, a_dev, b_dev, a_ext_dev, b_ext_dev, valid_dev, stream=None):
+        """ocean_mlp_predict_noalloc on caller-owned device tensors: a_dev, b_dev float64
+        [n, stride >= 32]; outputs a_ext_dev, b_ext_dev float64 [n, 256] and valid_dev int32 [n].
+        Enqueued on `stream` (a torch.cuda.Stream, or None for the default stream)."""
+        import torch
+        n, stride = a_dev.shape
+        for t, shape, dt in ((a_dev, (n, stride), torch.float64), (b_dev, (n, stride), torch.float64),
+                             (a_ext_dev, (n, 256), torch.float64), (b_ext_dev, (n, 256), torch.float64),
+                             (valid_dev, (n,), torch.int32)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous() \
+                    or tuple(t.shape) != shape:
+                raise ValueError(f"expected a contiguous {dt} CUDA tensor of shape {shape}")
+        st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(lib().ocean_mlp_predict_noalloc(self._h, a_dev.data_ptr(), b_dev.data_ptr(), n, stride,
+                                               a_ext_dev.data_ptr(), b_ext_dev.data_ptr(), valid_dev.data_ptr(), st))

@@ -6,6 +6,7 @@
 // Parameters are FP32 masters packed [W1, b1, W2, b2, W3, b3, W4, b4], W stored [in][out].
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -252,25 +253,69 @@ int mlp_ensure(ocean_mlp_s* h, int batch) {
     return OCEAN_OK;
 }
 
-hipError_t gemm(ocean_mlp_s* h, const float* A, int lda, int ta, const float* B, int ldb, int tb, float* C,
-                int M, int N, int K, const float* bias, int relu, const float* mask) {
+hipError_t gemm_on(ocean_mlp_s* h, hipStream_t st, const float* A, int lda, int ta, const float* B, int ldb,
+                   int tb, float* C, int M, int N, int K, const float* bias, int relu, const float* mask) {
     dim3 grid((N + 31) / 32, (M + 31) / 32);
     if (h->precision == OCEAN_MLP_BF16)
-        mlp_gemm_kernel<true><<<grid, 256, 0, h->stream>>>(A, lda, ta, B, ldb, tb, C, M, N, K, bias, relu, mask);
+        mlp_gemm_kernel<true><<<grid, 256, 0, st>>>(A, lda, ta, B, ldb, tb, C, M, N, K, bias, relu, mask);
     else
-        mlp_gemm_kernel<false><<<grid, 256, 0, h->stream>>>(A, lda, ta, B, ldb, tb, C, M, N, K, bias, relu, mask);
+        mlp_gemm_kernel<false><<<grid, 256, 0, st>>>(A, lda, ta, B, ldb, tb, C, M, N, K, bias, relu, mask);
     return hipGetLastError();
 }
 
-// act[0] must hold the input; fills act[1..4]
-int mlp_forward(ocean_mlp_s* h, int batch) {
+hipError_t gemm(ocean_mlp_s* h, const float* A, int lda, int ta, const float* B, int ldb, int tb, float* C,
+                int M, int N, int K, const float* bias, int relu, const float* mask) {
+    return gemm_on(h, h->stream, A, lda, ta, B, ldb, tb, C, M, N, K, bias, relu, mask);
+}
+
+// act[0] must hold the input; fills act[1..4] on stream st
+int mlp_forward_on(ocean_mlp_s* h, float* const* act, int batch, hipStream_t st) {
     for (int l = 0; l < kLayers; ++l) {
         const float* W = h->p + layer_offset(l);
         const float* bias = W + kSizes[l] * kSizes[l + 1];
-        const hipError_t e = gemm(h, h->act[l], kSizes[l], 0, W, kSizes[l + 1], 0, h->act[l + 1], batch,
-                                  kSizes[l + 1], kSizes[l], bias, l < kLayers - 1 ? 1 : 0, nullptr);
+        const hipError_t e = gemm_on(h, st, act[l], kSizes[l], 0, W, kSizes[l + 1], 0, act[l + 1], batch,
+                                     kSizes[l + 1], kSizes[l], bias, l < kLayers - 1 ? 1 : 0, nullptr);
         if (e != hipSuccess) return mlp_hip(e, "mlp forward");
     }
+    return OCEAN_OK;
+}
+
+int mlp_forward(ocean_mlp_s* h, int batch) { return mlp_forward_on(h, h->act, batch, h->stream); }
+
+// ---- fixed scratch for ocean_mlp_predict_noalloc ----------------------------------------------
+// Per sequence: the encoding constants (c, s) and the activations of the five layers.  The
+// array lives in every device's memory for the life of the process; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+constexpr int kNoAllocMaxSeq = OCEAN_MLP_NOALLOC_MAX_SEQ;
+constexpr size_t kActFloatsPerSeq = 64 + 3 * 256 + 448;
+constexpr size_t kScratchBytes = (size_t)kNoAllocMaxSeq * (2 * sizeof(double) + kActFloatsPerSeq * sizeof(float));
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Resolve (once per device, with that device current) the device address of `scratch`.
+int scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return mlp_fail("ocean_mlp: device index out of range", OCEAN_ERR_DEVICE);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return mlp_fail("ocean_mlp: hipGetDevice failed", OCEAN_ERR_DEVICE);
+        if (cur != device && hipSetDevice(device) != hipSuccess)
+            return mlp_fail("ocean_mlp: hipSetDevice failed", OCEAN_ERR_DEVICE);
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return mlp_fail(std::string("ocean_mlp: hipGetSymbolAddress of the fixed scratch array failed: ") +
+                                hipGetErrorString(e),
+                            OCEAN_ERR_DEVICE);
+        }
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
     return OCEAN_OK;
 }
 
@@ -330,6 +375,13 @@ int ocean_mlp_create(int precision, ocean_mlp_t* out) {
     (void)hipMemsetAsync(h->m, 0, pb, h->stream);
     (void)hipMemsetAsync(h->v, 0, pb, h->stream);
     (void)hipStreamSynchronize(h->stream);
+    // set-up of the allocation-free prediction path: the fixed scratch array's address on
+    // this device
+    void* scr = nullptr;
+    if (const int rc = scratch_address(h->device, &scr); rc != OCEAN_OK) {
+        ocean_mlp_destroy(h);
+        return rc;
+    }
     *out = h;
     return OCEAN_OK;
 }
@@ -505,6 +557,40 @@ int ocean_mlp_predict(ocean_mlp_t h, const double* a, const double* b, int n_seq
     if (rc == OCEAN_OK) rc = mlp_hip(hipMemcpyAsync(valid, dv, (size_t)n_seq * 4, hipMemcpyDeviceToHost, h->stream), "download");
     if (rc == OCEAN_OK) rc = mlp_hip(hipStreamSynchronize(h->stream), "predict");
     (void)hipFree(buf);
+    return rc;
+}
+
+int ocean_mlp_predict_noalloc(ocean_mlp_t h, const double* a_dev, const double* b_dev, int n_seq, int stride,
+                              double* a_ext_dev, double* b_ext_dev, int* valid_dev, void* stream) {
+    if (!h || !a_dev || !b_dev || !a_ext_dev || !b_ext_dev || !valid_dev || n_seq < 1 || stride < kMIn)
+        return mlp_fail("ocean_mlp_predict_noalloc: NULL argument, n_seq < 1 or stride < 32", OCEAN_ERR_INVALID_ARG);
+    if (n_seq > kNoAllocMaxSeq)
+        return mlp_fail("ocean_mlp_predict_noalloc: n_seq " + std::to_string(n_seq) + " exceeds the fixed scratch (" +
+                            std::to_string(kNoAllocMaxSeq) + " sequences)",
+                        OCEAN_ERR_INVALID_ARG);
+    void* base = nullptr;
+    if (const int rc = scratch_address(h->device, &base); rc != OCEAN_OK) return rc;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || (cur != h->device && hipSetDevice(h->device) != hipSuccess))
+        return mlp_fail("ocean_mlp_predict_noalloc: cannot select the handle's device", OCEAN_ERR_DEVICE);
+    // fixed layout: [kNoAllocMaxSeq][2] doubles, then act[0..4] each sized for kNoAllocMaxSeq
+    double* cs = static_cast<double*>(base);
+    float* act[kLayers + 1];
+    float* f = reinterpret_cast<float*>(cs + 2 * (size_t)kNoAllocMaxSeq);
+    for (int l = 0; l <= kLayers; ++l) {
+        act[l] = f;
+        f += (size_t)kNoAllocMaxSeq * kSizes[l];
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    encode_kernel<<<n_seq, 64, 0, st>>>(a_dev, b_dev, n_seq, stride, act[0], nullptr, cs);
+    int rc = mlp_hip(hipGetLastError(), "ocean_mlp_predict_noalloc: encode launch");
+    if (rc == OCEAN_OK) rc = mlp_forward_on(h, act, n_seq, st);
+    if (rc == OCEAN_OK) {
+        decode_kernel<<<n_seq, 256, 0, st>>>(a_dev, b_dev, stride, act[kLayers], cs, n_seq, a_ext_dev, b_ext_dev,
+                                              valid_dev);
+        rc = mlp_hip(hipGetLastError(), "ocean_mlp_predict_noalloc: decode launch");
+    }
+    if (cur != h->device) (void)hipSetDevice(cur);
     return rc;
 }
 
