@@ -19,9 +19,13 @@
  *  - Complex numbers are pairs of doubles (re, im), i.e. C99 double _Complex /
  *    numpy complex128 / torch.complex128 memory layout.
  *  - Energies in Hartree, lengths in bohr.
- *  - Grids: orthorhombic cell with edge lengths cell[d]; Gamma-centred unshifted
- *    k grid k_d = 2 pi i_d / (nk_d cell_d); real-space points x_d = cell_d j_d / nx_d.
- *    Flat grid indices are row-major with the last axis fastest.
+ *  - Grids: a cell of any shape given by its lattice vectors a_1, a_2, a_3 (the rows of
+ *    ocean_bse_desc.cell, bohr) and the reciprocal vectors b_d with a_i . b_j = 2 pi delta_ij;
+ *    k grid k = sum_d ((i_d + s_d) / nk_d) b_d, i_d = 0 .. nk_d - 1 (s_d = 0 is the
+ *    Gamma-centred grid; an offset s_d needs no input, see ocean_bse_desc.cell); real-space
+ *    points x = sum_d (j_d / nx_d) a_d; lattice vectors of the Born-von-Karman supercell
+ *    R = sum_d r_d a_d, r_d = 0 .. nk_d - 1.  Flat grid indices are row-major with the last
+ *    axis fastest.
  *  - An exciton vector is stored [k][n][c]: k-point slowest, core index c fastest,
  *    Nk*Nb*Nc complex numbers.  n_vec vectors are stored one after another.
  *  - Core index for an L2,3 edge: c = (m_c + 1) * 2 + sigma (sigma = 0 spin up);
@@ -201,14 +205,19 @@ int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* p
  * back-projection and k-grid transform kernels on this handle's shape with n_vec vectors (mean of the
  * tuned kernel's own HIP-event time over reps applies per candidate, after one untimed
  * apply; reps < 1 means 5) and keeps the fastest.  If the environment variable
- * OCEAN_AUTOTUNE_CACHE names a file, a cached choice for the same shape is reused and new
- * choices are appended.  Results do not change numerics beyond summation order of the
- * split-K partials.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+ * OCEAN_AUTOTUNE_CACHE names a file, a cached choice for the same shape and the same version
+ * of the kernels is reused when every knob is one the tuner itself could have picked (any
+ * other line is ignored and the shape is tuned again), and new choices are appended.  Results
+ * do not change numerics beyond summation order of the split-K partials.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps);
 
 /* Current tile choices: forward rows per wave / 16, back-projection grid target, lines
- * per k-grid transform block.  Any pointer may be NULL.  Errors: INVALID_ARG. */
-int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_lines);
+ * per k-grid transform block, and row tiles per block of the FP64/FP32 forward projection that
+ * keeps psi[k] of every band resident in LDS (0: the band-chunked forward; the resident form
+ * applies only where psi[k] of a pass fits in 64 KiB).  Any pointer may be NULL.
+ * Errors: INVALID_ARG. */
+int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_lines, int* fwd_tiles);
 
 /* Spectra from Haydock coefficients (section 2, eq. loss.fcn with
  * G = [w - H]^-1 as a continued fraction), evaluated on the GPU in FP64:
@@ -217,13 +226,17 @@ int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_l
  * Host inputs: a, b [n_spec][n_steps] as written by ocean_haydock, n_used[s]
  * (levels to use, <= n_steps; NULL = n_steps), norm2 [n_spec], omega [n_omega] (Ha).
  * gamma (Ha, > 0) is the Lorentzian half width.  terminator: OCEAN_TERM_NONE (t = 0)
- * or OCEAN_TERM_SQRT (constant-chain square-root terminator with a_inf, b_inf
- * the means of the last 16 used a_i and b_{i+1}; the root with Im t <= 0).
- * Host output sigma [n_spec][n_omega].  Synchronous; uses its own stream.
- * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+ * or OCEAN_TERM_SQRT (the Green's function of a semi-infinite chain with constant
+ * coefficients a_inf, b_inf: t = [(z - a_inf) - sqrt((z - a_inf)^2 - 4 b_inf^2)] / (2 b_inf^2),
+ * the root with Im t <= 0).  a_inf, b_inf: host [n_spec] (both given, finite, b_inf > 0), or
+ * both NULL for the means of the last 16 used a_i and b_{i+1}; ignored with
+ * OCEAN_TERM_NONE.  The learned terminator of the recursion's tail is the composition
+ * ocean_mlp_predict (the coefficients extended to 256 levels) then OCEAN_TERM_SQRT on the
+ * extended chain.  Host output sigma [n_spec][n_omega].  Synchronous; uses its own stream.
+ * Errors: INVALID_ARG (also a_inf without b_inf or the reverse), OUT_OF_MEMORY, DEVICE. */
 int ocean_spectrum(const double* a, const double* b, const int* n_used, const double* norm2,
-                   int n_spec, int n_steps, int terminator, const double* omega, int n_omega,
-                   double gamma, double* sigma);
+                   int n_spec, int n_steps, int terminator, const double* a_inf, const double* b_inf,
+                   const double* omega, int n_omega, double gamma, double* sigma);
 
 /* ---- Learned continued-fraction terminator ------------------------------------------
  * Not part of the paper: a small network that extends the Haydock coefficients of

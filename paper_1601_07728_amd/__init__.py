@@ -119,7 +119,7 @@ def lib() -> ctypes.CDLL:
     L.ocean_bse_apply.restype = ci
     L.ocean_haydock.argtypes = [vp, vp, ci, ci, cu, vp, vp, vp, vp]
     L.ocean_haydock.restype = ci
-    L.ocean_spectrum.argtypes = [vp, vp, vp, vp, ci, ci, ci, vp, ci, cd, vp]
+    L.ocean_spectrum.argtypes = [vp, vp, vp, vp, ci, ci, ci, vp, vp, vp, ci, cd, vp]
     L.ocean_spectrum.restype = ci
     L.ocean_multiplet_matrices.argtypes = [cd, cd, cd, cd, vp, vp]
     L.ocean_multiplet_matrices.restype = ci
@@ -153,7 +153,7 @@ def lib() -> ctypes.CDLL:
     L.ocean_haydock_batch.restype = ci
     L.ocean_bse_autotune.argtypes = [vp, ci, ci]
     L.ocean_bse_autotune.restype = ci
-    L.ocean_bse_get_tuning.argtypes = [vp, vp, vp, vp]
+    L.ocean_bse_get_tuning.argtypes = [vp, vp, vp, vp, vp]
     L.ocean_bse_get_tuning.restype = ci
     L.ocean_mlp_param_count.argtypes = []
     L.ocean_mlp_param_count.restype = ci
@@ -328,17 +328,22 @@ def screening_chi0(psi, eps, mu: float, t, w, out=None):
     return out
 
 
-def spectrum(a, b, norm2, omega, gamma: float, terminator: str = "none", n_used=None) -> np.ndarray:
-    """Continued-fraction spectra on the GPU.  a, b: [n_spec, n_steps]; norm2: [n_spec]."""
+def spectrum(a, b, norm2, omega, gamma: float, terminator: str = "none", n_used=None, a_inf=None,
+             b_inf=None) -> np.ndarray:
+    """Continued-fraction spectra on the GPU.  a, b: [n_spec, n_steps]; norm2: [n_spec].
+    With terminator "sqrt", a_inf and b_inf ([n_spec] each, or None for the means of the
+    last 16 used coefficients) are the constant chain's coefficients."""
     a = _host_f64(np.atleast_2d(a))
     b = _host_f64(np.atleast_2d(b))
     n2 = _host_f64(np.atleast_1d(norm2))
     om = _host_f64(omega)
     n_spec, n_steps = a.shape
     used = None if n_used is None else np.ascontiguousarray(np.atleast_1d(n_used), dtype=np.int32)
+    ai = None if a_inf is None else _host_f64(np.broadcast_to(np.asarray(a_inf, dtype=np.float64), (n_spec,)))
+    bi = None if b_inf is None else _host_f64(np.broadcast_to(np.asarray(b_inf, dtype=np.float64), (n_spec,)))
     sig = np.zeros((n_spec, len(om)))
     term = {"none": TERM_NONE, "sqrt": TERM_SQRT}[terminator]
-    _check(lib().ocean_spectrum(_ptr(a), _ptr(b), _ptr(used), _ptr(n2), n_spec, n_steps, term,
+    _check(lib().ocean_spectrum(_ptr(a), _ptr(b), _ptr(used), _ptr(n2), n_spec, n_steps, term, _ptr(ai), _ptr(bi),
                                 _ptr(om), len(om), float(gamma), _ptr(sig)))
     return sig
 
@@ -565,9 +570,10 @@ class Bse:
 
     @property
     def tuning(self):
-        m, b, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(lib().ocean_bse_get_tuning(self._h, ctypes.byref(m), ctypes.byref(b), ctypes.byref(f)))
-        return {"fwd_ms": m.value, "bwd_blocks": b.value, "fft_lines": f.value}
+        m, b, f, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().ocean_bse_get_tuning(self._h, ctypes.byref(m), ctypes.byref(b), ctypes.byref(f),
+                                          ctypes.byref(t)))
+        return {"fwd_ms": m.value, "bwd_blocks": b.value, "fft_lines": f.value, "fwd_tiles": t.value}
 
     def set_profiling(self, on: bool):
         _check(lib().ocean_bse_set_profiling(self._h, 1 if on else 0))

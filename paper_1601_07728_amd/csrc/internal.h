@@ -130,6 +130,9 @@ struct ocean_bse_s {
     int fft_lines = 16;          // lines per block of the k-grid transform
     int bwd_target_blocks = 2048;  // back-projection grid size the x chunking aims at
     int fwd_ms = 2;              // forward projection: 16 * fwd_ms rows per wave
+    int quad_tail = 1;           // FP32: a remainder of <= 4 real columns on the 4x4x1 MFMA (0: a padded tile)
+    int fwd_tiles = 0;           // FP64/FP32 forward with psi[k] resident in LDS: row tiles per block
+                                 // (0: the band-chunked kernel; used only where psi[k] fits)
 
     // profiling
     bool profiling = false;
@@ -242,7 +245,8 @@ hipError_t lz_scale(ocean_bse_s* h, int nv);
 hipError_t lz_advance(ocean_bse_s* h);
 
 hipError_t launch_spectrum(const double* a, const double* b, const int* n_used, const double* norm2,
-                           int n_spec, int n_steps, int terminator, const double* omega,
+                           int n_spec, int n_steps, int terminator, const double* a_inf,
+                           const double* b_inf, const double* omega,
                            int n_omega, double gamma, double* sigma, hipStream_t stream);
 
 // geometry helpers
@@ -252,6 +256,7 @@ void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk);
 void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks, int* S, int* chunk);
 constexpr int kMaxBwdTarget = 8192;  // largest back-projection grid target the tuner tries
 size_t fft_lds_bytes(const ocean_bse_s* h, int lines);
+size_t fwd_res_lds_bytes(const ocean_bse_s* h, int ncb);   // 0: psi[k] does not fit
 long long local_blocks(const ocean_bse_s* h);
 
 // profiling helpers used by the launchers

@@ -37,6 +37,16 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// f32 4x4x1 MFMA with 16 blocks: block b = lane / 4 computes D_b[r][j] += A_b[r] B_b[j] with A_b[r]
+// the value of lane 4 b + r and B_b[j] that of lane 4 b + j; D_b[r][j] sits in lane 4 b + j,
+// register r (measured on gfx950).  With the 16x16 operand layout (lane = i + 16 kq) a block is
+// rows 4 (b % 4) .. +3 of lane group kq = b / 4, so one call contracts each lane group's own
+// point for a 16-row by 4-column tile; the four lane groups are added at the end.  It runs at the
+// matrix cores' full rate, so a 4-column remainder costs a quarter of a 16-column tile.
+__device__ __forceinline__ v4f mfma_quad(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
 template <typename T> struct Cplx;
 template <> struct Cplx<double> { typedef double2 c2; typedef v4d acc; };
 template <> struct Cplx<float> { typedef float2 c2; typedef v4f acc; };
@@ -288,6 +298,210 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 }
 
 // ---------------------------------------------------------------------------------------------
+// Forward projection with the B operand resident.  When every band of psi[k] fits in LDS (small
+// band counts, such as 96 bands at the SrTiO3-shaped workload), a block stages psi[k] once, in
+// the MFMA order above, and then streams u for `tiles` consecutive tiles of 16 * WAVES rows of
+// that k.  Each wave owns 16 rows of every tile and walks its (tile, band chunk) items as one
+// continuous pipeline: the u loads of the next item (the next chunk, or the first chunk of the
+// next tile) are in flight while the current one is contracted.  After the staging there is no
+// barrier, and a block starts once per `tiles` tiles instead of once per tile.
+template <typename T, int NT, int TC, int TQ, int KC, int CP, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
+    const typename Cplx<T>::c2* __restrict__ U, const double2* __restrict__ psi,
+    typename Cplx<T>::c2* __restrict__ phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0,
+    int ncb, int groups, int tiles) {
+    typedef typename Cplx<T>::c2 C2;
+    typedef typename Cplx<T>::acc ACC;
+    typedef typename Vec4<T>::t V4;
+    constexpr int SS = KC / 8;
+    constexpr int NTH = 64 * WAVES;
+    constexpr int RPT = 16 * WAVES;            // rows per tile
+    constexpr int NS = NT + TQ;                // staged column tiles: the quad tail reads the last
+    static_assert(TQ == 0 || sizeof(T) == 4, "quad tail: FP32");
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nch = (Nb + KC - 1) / KC;
+    T* sB = reinterpret_cast<T*>(smem);                                   // [nch SS][NS][64][4]
+    C2* sT = reinterpret_cast<C2*>(sB + (size_t)nch * SS * NS * 256);     // [nch KC][TC]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+    const int k = blockIdx.x / groups;
+    const int g = blockIdx.x - k * groups;
+    const int x_tiles = (Nx + RPT - 1) / RPT;
+    const int t0 = g * tiles, t1 = min(x_tiles, t0 + tiles);
+    if (t0 >= t1) return;   // the whole block, before any barrier
+    const C2* Uk = U + (size_t)k * Nx * Nb;
+    const Rsrc ur = make_rsrc(Uk, (size_t)Nx * Nb * sizeof(C2));
+
+    // psi[k], every band, in MFMA order; bands past Nb and padding columns stay zero
+    const int nB = nch * SS * NS * 256;
+    for (int e = threadIdx.x; e < nB; e += NTH) sB[e] = (T)0;
+    if constexpr (TC > 0)
+        for (int e = threadIdx.x; e < nch * KC * TC; e += NTH) sT[e] = C2{(T)0, (T)0};
+    __syncthreads();
+    for (int e = threadIdx.x; e < Nb * ncb; e += NTH) {
+        const int n = e / ncb, cl = e - n * ncb;
+        const int col = col0 + cl;
+        const int vv = col / Nc, c = col - vv * Nc;
+        const double2 pv = psi[(((size_t)vv * Nk + k) * Nb + n) * Nc + c];
+        const int r8 = n & 7;
+        const int kq8 = sizeof(T) == 8 ? (r8 & 3) : (r8 >> 1), ns8 = sizeof(T) == 8 ? (r8 >> 2) : (r8 & 1);
+        if (cl < 8 * NS) stage_pair<T, NS>(sB, n >> 3, kq8, ns8, cl, pv.x, pv.y);
+        else if constexpr (TC > 0) sT[n * TC + (cl - 8 * NT)] = C2{(T)pv.x, (T)pv.y};
+    }
+    __syncthreads();
+
+    const int rowoff = wave * 16 + i;
+    // quad tail: lane l takes real column 16 NT + l % 4 of its lane group, i.e. the B values
+    // that lane (l % 4) + 16 kq holds for the staged tile NT
+    const int qlane = (lane & 3) + (lane & 48);
+    // u values of item (tile, chunk): lane (i, kq) holds row rowoff of the tile, the bands
+    // fwd_band(kq, ns) of each 8-band sub-step; masked to zero past Nx, Nb or when !live
+    auto load_a = [&](int tile, int ch, bool live, C2 (&aa)[SS][2]) {
+        const int row = tile * RPT + rowoff;
+        const bool rok = live && row < Nx;
+        const unsigned rb = (unsigned)(row * Nb) * (unsigned)sizeof(C2);
+        const int n0 = ch * KC;
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss) {
+            if constexpr (sizeof(T) == 8) {
+#pragma unroll
+                for (int ns = 0; ns < 2; ++ns) {
+                    const int n = n0 + 8 * ss + fwd_band<T>(kq, ns);
+                    aa[ss][ns] = bload<C2>(ur, (rok && n < Nb) ? rb + (unsigned)(n * sizeof(C2)) : kOob);
+                }
+            } else {
+                const int n = n0 + 8 * ss + 2 * kq;
+                if ((Nb & 1) == 0) {
+                    const bool ok = rok && n < Nb;
+                    const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                        ur, (int)(ok ? rb + (unsigned)(n * sizeof(C2)) : kOob), 0, 0));
+                    aa[ss][0] = C2{(T)v.x, (T)v.y};
+                    aa[ss][1] = C2{(T)v.z, (T)v.w};
+                } else {
+#pragma unroll
+                    for (int ns = 0; ns < 2; ++ns) {
+                        const bool ok = rok && n + ns < Nb;
+                        aa[ss][ns] = bload<C2>(ur, ok ? rb + (unsigned)((n + ns) * sizeof(C2)) : kOob);
+                    }
+                }
+            }
+        }
+    };
+
+    ACC acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = ACC{0, 0, 0, 0};
+    v4f accq = {0.f, 0.f, 0.f, 0.f};
+    T tre[TC > 0 ? TC : 1], tim[TC > 0 ? TC : 1];
+#pragma unroll
+    for (int c = 0; c < TC; ++c) tre[c] = tim[c] = (T)0;
+    T* out = reinterpret_cast<T*>(phi);
+
+    C2 a[SS][2], an[SS][2];
+    int tile = t0, ch = 0;
+    load_a(tile, ch, true, a);
+    for (;;) {
+        int ntile = tile, nchk = ch + 1;
+        if (nchk == nch) {
+            nchk = 0;
+            ++ntile;
+        }
+        const bool more = ntile < t1;
+        load_a(ntile, nchk, more, an);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss) {
+            const int sg = ch * SS + ss;
+            V4 bv[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bv[t] = *reinterpret_cast<const V4*>(&sB[((sg * NS + t) * 64 + lane) * 4]);
+            V4 bq;
+            if constexpr (TQ > 0) bq = *reinterpret_cast<const V4*>(&sB[((sg * NS + NT) * 64 + qlane) * 4]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const T av = (s & 1) ? a[ss][s >> 1].y : a[ss][s >> 1].x;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const T b = s == 0 ? bv[t].x : s == 1 ? bv[t].y : s == 2 ? bv[t].z : bv[t].w;
+                    acc[t] = mfma16(av, b, acc[t]);
+                }
+                if constexpr (TQ > 0) {
+                    const T b = s == 0 ? bq.x : s == 1 ? bq.y : s == 2 ? bq.z : bq.w;
+                    accq = mfma_quad((float)av, (float)b, accq);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < TC; ++c)
+#pragma unroll
+                for (int ns = 0; ns < 2; ++ns) {
+                    const C2 f = sT[(ch * KC + 8 * ss + fwd_band<T>(kq, ns)) * TC + c];   // same address for 16 lanes
+                    const C2 v = a[ss][ns];
+                    tre[c] = __builtin_fma(v.x, f.x, __builtin_fma(-v.y, f.y, tre[c]));
+                    tim[c] = __builtin_fma(v.x, f.y, __builtin_fma(v.y, f.x, tim[c]));
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < TC; ++c) asm volatile("" : "+v"(tre[c]), "+v"(tim[c]));
+        if (nchk == 0) {
+            // tile done: write its 16 rows of phi and start the next one from zero
+            const int rbase = tile * RPT + wave * 16;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int jr = 16 * t + i;
+                if ((jr >> 1) < ncb) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = rbase + acc_row<T>(kq, r);
+                        if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = acc[t][r];
+                    }
+                }
+                acc[t] = ACC{0, 0, 0, 0};
+            }
+            if constexpr (TQ > 0) {
+                // sum the lane groups; lane l < 16 then holds rows 4 (l / 4) + r, real column
+                // 16 NT + l % 4
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    accq[r] += __shfl_xor(accq[r], 16);
+                    accq[r] += __shfl_xor(accq[r], 32);
+                }
+                const int jr = 16 * NT + (lane & 3);
+                if (kq == 0 && (jr >> 1) < ncb) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = rbase + 4 * (lane >> 2) + r;
+                        if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = accq[r];
+                    }
+                }
+                accq = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int c = 0; c < TC; ++c) {
+                T re = tre[c], im = tim[c];
+                re += __shfl_xor(re, 16);
+                im += __shfl_xor(im, 16);
+                re += __shfl_xor(re, 32);
+                im += __shfl_xor(im, 32);
+                const int row = rbase + i;
+                if (kq == 0 && row < Nx) {
+                    out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c)] = re;
+                    out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c) + 1] = im;
+                }
+                tre[c] = tim[c] = (T)0;
+            }
+        }
+        if (!more) break;
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss) {
+            a[ss][0] = an[ss][0];
+            a[ss][1] = an[ss][1];
+        }
+        tile = ntile;
+        ch = nchk;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Backward projection with split-K over x.  Block = (k, band block of W x 16 bands,
 // x chunk); wave w owns the 16 bands [band block * 16 W + 16 w, +16).  The chunk is walked
 // in tiles of XT points through a ring of R slots: while tile t is contracted, the u values
@@ -303,7 +517,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 // with plain FMAs instead: a 16x16x4 FP64 MFMA costs the issue slots of 16 wave-wide FMAs,
 // so a tile holding 4 real columns of 16 wastes three quarters of them.  Lane (i, kq) sums
 // its own points for band i, and the four lane groups are added at the end.
-template <typename T, int NT, int TC, int XT, int R, int W, int CP>
+template <typename T, int NT, int TC, int TQ, int XT, int R, int W, int CP>
 __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const typename Cplx<T>::c2* __restrict__ phi,
     double* __restrict__ part, int Nk, int Nx, int Nb, int cols, int col0, int ncb,
@@ -313,8 +527,9 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     constexpr int SS = XT / 8;
     constexpr int TILE = 2 * XT * CP;          // complex pairs of one phi' tile
     constexpr int PER = (XT * CP + 64 * W - 1) / (64 * W);
-    static_assert(8 * NT + TC <= CP, "columns per pass");
+    static_assert(8 * NT + TC + 2 * TQ <= CP, "columns per pass");
     static_assert(R == 2 || R == 3, "ring depth");
+    static_assert(TQ == 0 || sizeof(T) == 4, "quad tail: FP32");
     __shared__ __align__(16) C2 sP[R][TILE];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
@@ -375,6 +590,9 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     T tre[TC > 0 ? TC : 1], tim[TC > 0 ? TC : 1];
 #pragma unroll
     for (int c = 0; c < TC; ++c) tre[c] = tim[c] = (T)0;
+    v4f accq = {0.f, 0.f, 0.f, 0.f};
+    // quad tail: lane l takes real column 16 NT + l % 4, i.e. (column 8 NT + (l % 4) / 2, q = l % 2)
+    const int qoff = (8 * NT + ((lane & 3) >> 1)) * 4 + (lane & 1) * 2;
     auto contract = [&](const C2* src, const C2 (&uu)[SS][2]) {
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
@@ -387,12 +605,19 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
                 b[t][0] = mine[32 * t];
                 b[t][1] = mine[32 * t + 1];
             }
+            C2 bq[2];
+            if constexpr (TQ > 0) {
+                bq[0] = row[qoff];
+                bq[1] = row[qoff + 1];
+            }
 #pragma unroll
             for (int xs = 0; xs < 2; ++xs) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t) acc[t] = mfma16(uu[ss][xs].x, b[t][xs].x, acc[t]);
+                if constexpr (TQ > 0) accq = mfma_quad((float)uu[ss][xs].x, (float)bq[xs].x, accq);
 #pragma unroll
                 for (int t = 0; t < NT; ++t) acc[t] = mfma16(uu[ss][xs].y, b[t][xs].y, acc[t]);
+                if constexpr (TQ > 0) accq = mfma_quad((float)uu[ss][xs].y, (float)bq[xs].y, accq);
             }
 #pragma unroll
             for (int c = 0; c < TC; ++c)
@@ -470,6 +695,22 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
             out[(size_t)n * 2 * cols + 2 * (8 * NT + c) + 1] = (double)im;
         }
     }
+    if constexpr (TQ > 0) {
+        // sum the lane groups; lane l < 16 then holds bands 4 (l / 4) + r, real column 16 NT + l % 4
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            accq[r] += __shfl_xor(accq[r], 16);
+            accq[r] += __shfl_xor(accq[r], 32);
+        }
+        const int jr = 16 * NT + (lane & 3);
+        if (kq == 0 && (jr >> 1) < ncb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int nn = nbase + 4 * (lane >> 2) + r;
+                if (nn < Nb) out[(size_t)nn * 2 * cols + jr] = (double)accq[r];
+            }
+        }
+    }
 }
 
 template <typename T> struct Tiles;
@@ -503,24 +744,53 @@ hipError_t fwd_dispatch_nt(int NT, int TC, dim3 grid, hipStream_t st, const void
     return hipErrorInvalidValue;
 }
 
+constexpr int kResWaves = 8;
+
+template <typename T>
+hipError_t fwd_res_dispatch(int NT, int TC, int TQ, dim3 grid, size_t lds, hipStream_t st, const void* U, const double* x,
+                            void* phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0, int ncb, int groups,
+                            int tiles) {
+    typedef typename Cplx<T>::c2 C2;
+    const C2* u = static_cast<const C2*>(U);
+    C2* p = static_cast<C2*>(phi);
+    const double2* ps = reinterpret_cast<const double2*>(x);
+#define OCEAN_FWDR(nt, tc, tq) \
+    if (NT == nt && TC == tc && TQ == tq) { \
+        proj_fwd_res_kernel<T, nt, tc, tq, Tiles<T>::KC, kColsPerPass, kResWaves><<<grid, 64 * kResWaves, lds, st>>>( \
+            u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, groups, tiles); \
+        return hipGetLastError(); \
+    }
+    OCEAN_FWDR(1, 0, 0) OCEAN_FWDR(2, 0, 0) OCEAN_FWDR(3, 0, 0)
+    if constexpr (sizeof(T) == 8) {
+        OCEAN_FWDR(1, 1, 0) OCEAN_FWDR(1, 2, 0) OCEAN_FWDR(2, 1, 0) OCEAN_FWDR(2, 2, 0)
+    } else {
+        OCEAN_FWDR(1, 0, 1) OCEAN_FWDR(2, 0, 1)
+    }
+#undef OCEAN_FWDR
+    return hipErrorInvalidValue;
+}
+
 template <typename T, int W>
-hipError_t bwd_dispatch_w(int NT, int TC, dim3 grid, hipStream_t st, const void* U, const void* phi,
+hipError_t bwd_dispatch_w(int NT, int TC, int TQ, dim3 grid, hipStream_t st, const void* U, const void* phi,
                           double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int bb,
                           int S, int chunk) {
     typedef typename Cplx<T>::c2 C2;
     constexpr int XT = Tiles<T>::XT;
     const C2* u = static_cast<const C2*>(U);
     const C2* p = static_cast<const C2*>(phi);
-#define OCEAN_BWD(nt, tc, cp) \
-    if (NT == nt && TC == tc) { \
-        proj_bwd_kernel<T, nt, tc, XT, Tiles<T>::R, W, cp><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); \
+#define OCEAN_BWDQ(nt, tc, tq, cp) \
+    if (NT == nt && TC == tc && TQ == tq) { \
+        proj_bwd_kernel<T, nt, tc, tq, XT, Tiles<T>::R, W, cp><<<grid, 64 * W, 0, st>>>(u, p, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk); \
         return hipGetLastError(); \
     }
+#define OCEAN_BWD(nt, tc, cp) OCEAN_BWDQ(nt, tc, 0, cp)
     if (ncb <= kColsPerPass) {
         OCEAN_BWD(1, 0, kColsPerPass) OCEAN_BWD(2, 0, kColsPerPass) OCEAN_BWD(3, 0, kColsPerPass)
         if constexpr (sizeof(T) == 8) {
             OCEAN_BWD(1, 1, kColsPerPass) OCEAN_BWD(1, 2, kColsPerPass)
             OCEAN_BWD(2, 1, kColsPerPass) OCEAN_BWD(2, 2, kColsPerPass)
+        } else {
+            OCEAN_BWDQ(1, 0, 1, kColsPerPass) OCEAN_BWDQ(2, 0, 1, kColsPerPass)
         }
     } else if constexpr (sizeof(T) == 8) {
         OCEAN_BWD(3, 1, kColsPerWidePass) OCEAN_BWD(3, 2, kColsPerWidePass) OCEAN_BWD(3, 3, kColsPerWidePass)
@@ -529,20 +799,21 @@ hipError_t bwd_dispatch_w(int NT, int TC, dim3 grid, hipStream_t st, const void*
         OCEAN_BWD(5, 0, kColsPerWidePass)
     }
 #undef OCEAN_BWD
+#undef OCEAN_BWDQ
     return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t bwd_dispatch(int W, int NT, int TC, dim3 grid, hipStream_t st, const void* U, const void* phi,
+hipError_t bwd_dispatch(int W, int NT, int TC, int TQ, dim3 grid, hipStream_t st, const void* U, const void* phi,
                         double* part, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int bb,
                         int S, int chunk) {
     switch (W) {
 #define OCEAN_BWD_W(w) \
-        case w: return bwd_dispatch_w<T, w>(NT, TC, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
+        case w: return bwd_dispatch_w<T, w>(NT, TC, TQ, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
         OCEAN_BWD_W(1) OCEAN_BWD_W(2) OCEAN_BWD_W(3) OCEAN_BWD_W(4) OCEAN_BWD_W(5) OCEAN_BWD_W(6)
         OCEAN_BWD_W(7)
 #undef OCEAN_BWD_W
-        default: return bwd_dispatch_w<T, 8>(NT, TC, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
+        default: return bwd_dispatch_w<T, 8>(NT, TC, TQ, grid, st, U, phi, part, Nk, Nx, Nb, cols, col0, ncb, bb, S, chunk);
     }
 }
 
@@ -605,22 +876,64 @@ int cols_per_pass(const ocean_bse_s* h, int cols) {
 // against 2.71 ms at 36 columns).  The wide forward keeps the 2-column limit: with a
 // 4-column tail it needs 182 VGPRs, one wave per SIMD fewer, and was slower (2.66 against
 // 2.50 ms).
-void column_split(int ncb, bool fp64, bool wide_tail, int* NT, int* TC) {
+// With quad (FP32 kernels that have it), a remainder of at most 4 real columns after whole
+// tiles goes to the 4x4x1 quad tail instead (TQ = 1), at the matrix cores' full rate.
+void column_split(int ncb, bool fp64, bool wide_tail, bool quad, int* NT, int* TC, int* TQ) {
     const int full = 2 * ncb / 16, rem = 2 * ncb - 16 * full;
     const int max_tail = wide_tail && ncb > kColsPerPass ? 8 : 4;   // real columns
+    *TQ = 0;
     if (rem == 0) { *NT = full; *TC = 0; }
     else if (fp64 && rem <= max_tail && full >= 1) { *NT = full; *TC = rem / 2; }
+    else if (!fp64 && quad && rem <= 4 && full >= 1) { *NT = full; *TC = 0; *TQ = 1; }
     else { *NT = full + 1; *TC = 0; }
+}
+
+// LDS bytes of the resident-operand forward for a pass of ncb columns, or 0 if psi[k] of every
+// band does not fit in 64 KiB (or the pass is wide, or the precision is a bf16 mode, or one k of
+// u spans more than 2 GiB).
+size_t fwd_res_lds_bytes(const ocean_bse_s* h, int ncb) {
+    if (is_bf16_mode(h->precision) || ncb > kColsPerPass) return 0;
+    const bool fp64 = h->precision == OCEAN_PREC_FP64;
+    int NT, TC, TQ;
+    column_split(ncb, fp64, false, true, &NT, &TC, &TQ);
+    const size_t elem = fp64 ? 8 : 4;
+    const int KC = fp64 ? Tiles<double>::KC : Tiles<float>::KC;
+    const size_t nch = (h->Nb + KC - 1) / KC;
+    if ((size_t)h->Nx * h->Nb * 2 * elem >= (1ull << 31)) return 0;
+    const size_t b = nch * (KC / 8) * (NT + TQ) * 256 * elem + nch * KC * TC * 2 * elem;
+    return b <= 64 * 1024 ? b : 0;
 }
 
 hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, int ncb) {
     if (is_bf16_mode(h->precision)) return launch_proj_fwd_bf16(h, x, nv, col0, ncb);
+    if (h->fwd_tiles > 0) {
+        const size_t lds = fwd_res_lds_bytes(h, ncb);
+        if (lds > 0) {
+            int NT, TC, TQ;
+            column_split(ncb, h->precision == OCEAN_PREC_FP64, false, h->quad_tail != 0, &NT, &TC, &TQ);
+            const int rpt = 16 * kResWaves;
+            const int x_tiles = (h->Nx + rpt - 1) / rpt;
+            const int tiles = std::min(h->fwd_tiles, x_tiles);
+            const int groups = (x_tiles + tiles - 1) / tiles;
+            dim3 grid((unsigned)((long long)h->Nk * groups));
+            const int slot = prof_begin(h, "proj_fwd");
+            hipError_t e;
+            if (h->precision == OCEAN_PREC_FP64)
+                e = fwd_res_dispatch<double>(NT, TC, TQ, grid, lds, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
+                                             h->Nb, h->Nc, nv * h->Nc, col0, ncb, groups, tiles);
+            else
+                e = fwd_res_dispatch<float>(NT, TC, TQ, grid, lds, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
+                                            h->Nb, h->Nc, nv * h->Nc, col0, ncb, groups, tiles);
+            prof_end(h, slot);
+            return e;
+        }
+    }
     // 16 * MS rows per wave, 64 * MS per block; a wide pass (more than kColsPerPass columns)
     // holds more accumulators per wave and runs with MS = 1
     const int MS = (h->fwd_ms == 1 || ncb > kColsPerPass) ? 1 : 2;
     const int cols = nv * h->Nc;
-    int NT, TC;
-    column_split(ncb, h->precision == OCEAN_PREC_FP64, false, &NT, &TC);
+    int NT, TC, TQ;
+    column_split(ncb, h->precision == OCEAN_PREC_FP64, false, false, &NT, &TC, &TQ);
     const int x_tiles = (h->Nx + 64 * MS - 1) / (64 * MS);
     dim3 grid((unsigned)(h->Nk * x_tiles));
     hipError_t e;
@@ -642,8 +955,8 @@ hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, in
 hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     if (is_bf16_mode(h->precision)) return launch_proj_bwd_bf16(h, nv, col0, ncb);
     const int cols = nv * h->Nc;
-    int NT, TC;
-    column_split(ncb, h->precision == OCEAN_PREC_FP64, true, &NT, &TC);
+    int NT, TC, TQ;
+    column_split(ncb, h->precision == OCEAN_PREC_FP64, true, h->quad_tail != 0, &NT, &TC, &TQ);
     int bb, S, chunk;
     bwd_geometry(h, &bb, &S, &chunk);
     const int W = bwd_waves(h->Nb);
@@ -651,10 +964,10 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     const int slot = prof_begin(h, "proj_bwd");
     hipError_t e;
     if (h->precision == OCEAN_PREC_FP64)
-        e = bwd_dispatch<double>(W, NT, TC, grid, h->stream, h->U64, h->ws.phi, h->ws.part, h->Nk,
+        e = bwd_dispatch<double>(W, NT, TC, TQ, grid, h->stream, h->U64, h->ws.phi, h->ws.part, h->Nk,
                                  h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
     else
-        e = bwd_dispatch<float>(W, NT, TC, grid, h->stream, h->U32, h->ws.phi, h->ws.part, h->Nk,
+        e = bwd_dispatch<float>(W, NT, TC, TQ, grid, h->stream, h->U32, h->ws.phi, h->ws.part, h->Nk,
                                 h->Nx, h->Nb, cols, col0, ncb, bb, S, chunk);
     prof_end(h, slot);
     return e;

@@ -479,6 +479,8 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
         h->own_stream = true;
     }
     h->bwd_target_blocks = env_int("OCEAN_BWD_BLOCKS", 2048);
+    h->fwd_tiles = env_int("OCEAN_FWD_TILES", 0);
+    h->quad_tail = env_int("OCEAN_QUAD_TAIL", 1);
 
     auto fail = [&](int rc) {
         destroy_handle(h);
@@ -970,6 +972,20 @@ int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* p
     return ret;
 }
 
+// Cache lines carry this tag: choices written by another version of the kernels are not reused.
+static constexpr const char* kTuneCacheVersion = "ocean-tune-v3";
+
+// A cached choice is applied only if every knob is one the tuner itself could have picked for
+// this handle (a stale or hand-edited line is ignored and the shape is tuned again).
+static bool tuning_valid(const ocean_bse_s* h, int ms, int bt, int fl, int ft) {
+    const bool ms_ok = ms == 1 || ms == 2 || (ms == 4 && is_bf16_mode(h->precision));
+    const bool bt_ok = bt == 1024 || bt == 2048 || bt == 4096 || bt == 8192;
+    const bool fl_ok = (fl == 4 || fl == 8 || fl == 16 || fl == 32 || fl == 64) &&
+                       (h->Nk == 1 || fft_lds_bytes(h, fl) <= 160 * 1024);
+    const bool ft_ok = ft == 0 || ft == 4 || ft == 8 || ft == 16 || ft == 32;
+    return ms_ok && bt_ok && fl_ok && ft_ok;
+}
+
 // Project-written tile autotuner: times the candidate tile knobs of each kernel on this
 // handle's own shape (HIP events around repeated applies) and keeps the fastest.  Results
 // are cached per shape in the file named by OCEAN_AUTOTUNE_CACHE (one line per shape).
@@ -981,8 +997,8 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
     }
     if (reps < 1) reps = 5;
     (void)hipSetDevice(h->device);
-    char key[160];
-    std::snprintf(key, sizeof key, "nk=%d,%d,%d nx=%d,%d,%d nb=%d nc=%d nmu=%d prec=%d cols=%d", h->nk[0],
+    char key[192];
+    std::snprintf(key, sizeof key, "%s nk=%d,%d,%d nx=%d,%d,%d nb=%d nc=%d nmu=%d prec=%d cols=%d", kTuneCacheVersion, h->nk[0],
                   h->nk[1], h->nk[2], h->nx[0], h->nx[1], h->nx[2], h->Nb, h->Nc, h->Nmu, h->precision,
                   n_vec * h->Nc);
     const char* cache = std::getenv("OCEAN_AUTOTUNE_CACHE");
@@ -992,12 +1008,13 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
             while (std::fgets(line, sizeof line, f)) {
                 const char* sep = std::strchr(line, '|');
                 if (!sep || (size_t)(sep - line) != std::strlen(key) || std::strncmp(line, key, sep - line) != 0) continue;
-                int ms, bt, fl;
-                if (std::sscanf(sep + 1, "%d %d %d", &ms, &bt, &fl) == 3) {
+                int ms, bt, fl, ft;
+                if (std::sscanf(sep + 1, "%d %d %d %d", &ms, &bt, &fl, &ft) == 4 && tuning_valid(h, ms, bt, fl, ft)) {
                     std::fclose(f);
                     h->fwd_ms = ms;
                     h->bwd_target_blocks = std::min(bt, kMaxBwdTarget);
                     h->fft_lines = fl;
+                    h->fwd_tiles = ft;
                     return OCEAN_OK;
                 }
             }
@@ -1090,6 +1107,10 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
     if (rc == OCEAN_OK)
         sweep(is_bf16_mode(h->precision) ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2}, &h->fwd_ms,
               {"proj_fwd"}, false);
+    // the resident-operand forward (row tiles per block) against the chunked one (0), where
+    // psi[k] of a pass fits in LDS
+    if (rc == OCEAN_OK && fwd_res_lds_bytes(h, std::min(n_vec * h->Nc, cols_per_pass(h, n_vec * h->Nc))) > 0)
+        sweep({0, 4, 8, 16, 32}, &h->fwd_tiles, {"proj_fwd"}, false);
     if (rc == OCEAN_OK) sweep({1024, 2048, 4096, 8192}, &h->bwd_target_blocks, {"proj_bwd", "reduce_part", "combine"}, true);
     if (rc == OCEAN_OK && h->Nk > 1) {
         std::vector<int> lines;
@@ -1105,14 +1126,14 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
     if (rc != OCEAN_OK) return rc;
     if (cache && *cache) {
         if (FILE* f = std::fopen(cache, "a")) {
-            std::fprintf(f, "%s|%d %d %d\n", key, h->fwd_ms, h->bwd_target_blocks, h->fft_lines);
+            std::fprintf(f, "%s|%d %d %d %d\n", key, h->fwd_ms, h->bwd_target_blocks, h->fft_lines, h->fwd_tiles);
             std::fclose(f);
         }
     }
     return OCEAN_OK;
 }
 
-int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_lines) {
+int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_lines, int* fwd_tiles) {
     if (!h) {
         set_error("ocean_bse_get_tuning: NULL handle");
         return OCEAN_ERR_INVALID_ARG;
@@ -1120,15 +1141,17 @@ int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_l
     if (fwd_ms) *fwd_ms = h->fwd_ms;
     if (bwd_blocks) *bwd_blocks = h->bwd_target_blocks;
     if (fft_lines) *fft_lines = h->fft_lines;
+    if (fwd_tiles) *fwd_tiles = h->fwd_tiles;
     return OCEAN_OK;
 }
 
 int ocean_spectrum(const double* a, const double* b, const int* n_used, const double* norm2,
-                   int n_spec, int n_steps, int terminator, const double* omega, int n_omega,
-                   double gamma, double* sigma) {
+                   int n_spec, int n_steps, int terminator, const double* a_inf, const double* b_inf,
+                   const double* omega, int n_omega, double gamma, double* sigma) {
     g_last_error.clear();
     if (!a || !b || !norm2 || !omega || !sigma || n_spec < 1 || n_steps < 1 || n_omega < 1 ||
-        !(gamma > 0.0) || (terminator != OCEAN_TERM_NONE && terminator != OCEAN_TERM_SQRT)) {
+        !(gamma > 0.0) || (terminator != OCEAN_TERM_NONE && terminator != OCEAN_TERM_SQRT) ||
+        (a_inf == nullptr) != (b_inf == nullptr)) {
         set_error("ocean_spectrum: invalid argument");
         return OCEAN_ERR_INVALID_ARG;
     }
@@ -1138,13 +1161,20 @@ int ocean_spectrum(const double* a, const double* b, const int* n_used, const do
                 set_error("ocean_spectrum: n_used out of range");
                 return OCEAN_ERR_INVALID_ARG;
             }
+    if (a_inf)
+        for (int s = 0; s < n_spec; ++s)
+            if (!std::isfinite(a_inf[s]) || !std::isfinite(b_inf[s]) || !(b_inf[s] > 0.0)) {
+                set_error("ocean_spectrum: a_inf must be finite and b_inf finite and > 0");
+                return OCEAN_ERR_INVALID_ARG;
+            }
+    const bool given = a_inf != nullptr && terminator == OCEAN_TERM_SQRT;
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
         set_error("ocean_spectrum: hipStreamCreate failed");
         return OCEAN_ERR_DEVICE;
     }
     const size_t nab = (size_t)n_spec * n_steps;
-    const size_t bytes = nab * 16 + n_spec * 12 + (size_t)n_omega * 8 + (size_t)n_spec * n_omega * 8;
+    const size_t bytes = nab * 16 + (size_t)n_spec * 28 + (size_t)n_omega * 8 + (size_t)n_spec * n_omega * 8;
     char* buf = nullptr;
     if (hipMalloc((void**)&buf, bytes + 256) != hipSuccess) {
         (void)hipGetLastError();
@@ -1155,18 +1185,26 @@ int ocean_spectrum(const double* a, const double* b, const int* n_used, const do
     double* da = reinterpret_cast<double*>(buf);
     double* db = da + nab;
     double* dn = db + nab;
-    double* dom = dn + n_spec;
+    double* dai = dn + n_spec;
+    double* dbi = dai + n_spec;
+    double* dom = dbi + n_spec;
     double* dsig = dom + n_omega;
     int* dused = reinterpret_cast<int*>(dsig + (size_t)n_spec * n_omega);
     int rc = OCEAN_OK;
     rc = check_hip(hipMemcpyAsync(da, a, nab * 8, hipMemcpyHostToDevice, st), "upload");
     if (rc == OCEAN_OK) rc = check_hip(hipMemcpyAsync(db, b, nab * 8, hipMemcpyHostToDevice, st), "upload");
     if (rc == OCEAN_OK) rc = check_hip(hipMemcpyAsync(dn, norm2, n_spec * 8, hipMemcpyHostToDevice, st), "upload");
+    if (rc == OCEAN_OK && given)
+        rc = check_hip(hipMemcpyAsync(dai, a_inf, n_spec * 8, hipMemcpyHostToDevice, st), "upload");
+    if (rc == OCEAN_OK && given)
+        rc = check_hip(hipMemcpyAsync(dbi, b_inf, n_spec * 8, hipMemcpyHostToDevice, st), "upload");
     if (rc == OCEAN_OK) rc = check_hip(hipMemcpyAsync(dom, omega, n_omega * 8, hipMemcpyHostToDevice, st), "upload");
     if (rc == OCEAN_OK && n_used) rc = check_hip(hipMemcpyAsync(dused, n_used, n_spec * 4, hipMemcpyHostToDevice, st), "upload");
     if (rc == OCEAN_OK)
         rc = check_hip(launch_spectrum(da, db, n_used ? dused : nullptr, dn, n_spec, n_steps, terminator,
-                                       dom, n_omega, gamma, dsig, st), "spectrum launch");
+                                       given ? dai : nullptr, given ? dbi : nullptr, dom, n_omega, gamma, dsig,
+                                       st),
+                       "spectrum launch");
     if (rc == OCEAN_OK) rc = check_hip(hipMemcpyAsync(sigma, dsig, (size_t)n_spec * n_omega * 8, hipMemcpyDeviceToHost, st), "download");
     if (rc == OCEAN_OK) rc = check_hip(hipStreamSynchronize(st), "spectrum");
     (void)hipFree(buf);

@@ -430,6 +430,8 @@ __global__ __launch_bounds__(256) void spectrum_kernel(const double* __restrict_
                                                        const int* __restrict__ n_used,
                                                        const double* __restrict__ norm2,
                                                        int n_spec, int n_steps, int terminator,
+                                                       const double* __restrict__ a_inf,
+                                                       const double* __restrict__ b_inf,
                                                        const double* __restrict__ omega,
                                                        int n_omega, double gamma,
                                                        double* __restrict__ sigma) {
@@ -442,14 +444,19 @@ __global__ __launch_bounds__(256) void spectrum_kernel(const double* __restrict_
     const double2 z = make_double2(omega[o], gamma);
     double2 g = make_double2(0.0, 0.0);
     if (terminator == OCEAN_TERM_SQRT && N > 0) {
-        const int tail = N < 16 ? N : 16;
         double ai = 0.0, bi = 0.0;
-        for (int j = N - tail; j < N; ++j) {
-            ai += as[j];
-            bi += bs[j];
+        if (a_inf) {
+            ai = a_inf[sp];
+            bi = b_inf[sp];
+        } else {
+            const int tail = N < 16 ? N : 16;
+            for (int j = N - tail; j < N; ++j) {
+                ai += as[j];
+                bi += bs[j];
+            }
+            ai /= tail;
+            bi /= tail;
         }
-        ai /= tail;
-        bi /= tail;
         const double2 zz = make_double2(z.x - ai, z.y);
         const double2 disc = make_double2(zz.x * zz.x - zz.y * zz.y - 4.0 * bi * bi, 2.0 * zz.x * zz.y);
         const double2 sq = csqrt_principal(disc);
@@ -788,11 +795,12 @@ hipError_t lz_advance(ocean_bse_s* h) {
 }
 
 hipError_t launch_spectrum(const double* a, const double* b, const int* n_used, const double* norm2,
-                           int n_spec, int n_steps, int terminator, const double* omega,
+                           int n_spec, int n_steps, int terminator, const double* a_inf,
+                           const double* b_inf, const double* omega,
                            int n_omega, double gamma, double* sigma, hipStream_t stream) {
     const long long n = (long long)n_spec * n_omega;
     spectrum_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(
-        a, b, n_used, norm2, n_spec, n_steps, terminator, omega, n_omega, gamma, sigma);
+        a, b, n_used, norm2, n_spec, n_steps, terminator, a_inf, b_inf, omega, n_omega, gamma, sigma);
     return hipGetLastError();
 }
 

@@ -139,9 +139,23 @@ def make_crystal(name: str, *, a: float, tau, nk, nx, n_bands: int, n_core: int,
     elif u_override is not None:
         u = u_override
     else:
+        # the draws stay in order (k by k, real then imaginary parts); the QRs, independent per
+        # k, run on a thread pool (LAPACK releases the interpreter lock)
         u = np.empty((n_k, n_x, n_bands), dtype=np.complex128)
         for k in range(n_k):
-            u[k] = orthonormal_columns(complex_gaussian(rng, (n_x, n_bands)))
+            u[k] = complex_gaussian(rng, (n_x, n_bands))
+
+        def _qr(k):
+            u[k] = orthonormal_columns(u[k])
+
+        if n_k > 1 and n_x * n_bands >= 4096:
+            from concurrent.futures import ThreadPoolExecutor
+            import os
+            with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+                list(ex.map(_qr, range(n_k)))
+        else:
+            for k in range(n_k):
+                _qr(k)
     p0 = None
     if psi0 == "random":
         # dipole-like amplitudes M[k, n], identical for every core state (spin-
@@ -303,14 +317,27 @@ def molecule_sites(seed: int = 0, n_atoms: int = 52, n_sites: int = 40, box: flo
 
 
 def terminator_system(seed: int, nk=(2, 2, 2), nx=(5, 5, 5), n_bands: int = 24,
-                      n_steps: int = 512) -> Crystal:
-    """One system of the learned-terminator dataset: the SrTiO3-shaped L2,3 edge in
-    miniature, with eps ~ U[2, 10] and band width ~ U[20, 60] eV drawn from the seed."""
+                      n_steps: int = 512, u_override=None) -> Crystal:
+    """One system of the learned-terminator dataset: the SrTiO3-shaped L2,3 edge (any grid
+    and band count), with eps ~ U[2, 10] and band width ~ U[20, 60] eV drawn from the seed."""
     rng = np.random.default_rng([seed, 7])
     eps = float(rng.uniform(2.0, 10.0))
     width = float(rng.uniform(20.0, 60.0))
     return config2_shape(nk=nk, nx=nx, n_bands=n_bands, seed=seed, eps=eps, n_steps=n_steps,
-                         psi0="none", e_range_ev=width)
+                         psi0="none", e_range_ev=width, u_override=u_override)
+
+
+TERMINATOR_U_SEED_OFFSET = 1 << 20
+
+
+def terminator_system_device(seed: int, nk=(8, 8, 8), nx=(20, 20, 20), n_bands: int = 96,
+                             n_steps: int = 512, device="cuda"):
+    """A terminator-dataset system at the full SrTiO3-shaped size (default 8^3 k, 20^3 x,
+    96 bands), with u drawn on the device (gpu_orthonormal_u, seed + TERMINATOR_U_SEED_OFFSET).
+    Returns (Crystal, u)."""
+    cr = terminator_system(seed, nk=nk, nx=nx, n_bands=n_bands, n_steps=n_steps, u_override="skip")
+    u = gpu_orthonormal_u(cr.n_k, cr.n_x, cr.n_bands, seed=seed + TERMINATOR_U_SEED_OFFSET, device=device)
+    return cr, u
 
 
 # --- screening inputs (the RPA response on the real-space sphere around the core site) --------

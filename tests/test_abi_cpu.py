@@ -68,6 +68,15 @@ def test_spectrum_rejects_bad_arguments(lib):
     assert e.value.code == ob.ERR_INVALID_ARG
     with pytest.raises(ob.OceanError):
         ob.spectrum(a, a, [1.0], om, gamma=0.1, n_used=[9])
+    # the constant chain's coefficients: both or neither, finite, b_inf > 0
+    for ai, bi in ((np.zeros(1), None), (None, np.ones(1)), (np.zeros(1), np.zeros(1)),
+                   (np.array([np.nan]), np.ones(1)), (np.zeros(1), np.array([np.inf]))):
+        p = ob._ptr
+        aa, bb = (None if ai is None else np.ascontiguousarray(ai)), (None if bi is None else np.ascontiguousarray(bi))
+        n2 = np.ones(1)
+        sig = np.zeros(5)
+        rc = lib.ocean_spectrum(p(a), p(a), None, p(n2), 1, 4, ob.TERM_SQRT, p(aa), p(bb), p(om), 5, 0.1, p(sig))
+        assert rc == ob.ERR_INVALID_ARG and len(lib.ocean_last_error()) > 0
 
 
 def _set_cell(d, rows):

@@ -362,3 +362,54 @@ def test_one_vector_stops_while_the_other_continues():
     a1, b1, n21, sd1, _ = h.haydock(_to_dev(np.ascontiguousarray(psi[1:])), 30)
     assert np.array_equal(a[1], a1[0]) and np.array_equal(b[1], b1[0]) and n2[1] == n21[0]
     h.close()
+
+
+RES_CASES = {
+    "l_tiles": lambda: synth.small_l_edge(seed=4, nk=(4, 2, 2), nx=(10, 9, 11), n_bands=37),
+    "l_odd_bands": lambda: synth.small_l_edge(seed=12, nk=(2, 2, 2), nx=(6, 7, 5), n_bands=13),
+    "k_edge": lambda: synth.config1(),
+    "l_c2_bands": lambda: synth.small_l_edge(seed=13, nk=(2, 2, 1), nx=(12, 11, 10), n_bands=96),
+}
+
+
+@pytest.mark.parametrize("case", list(RES_CASES))
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
+def test_resident_operand_forward_matches_chunked_and_oracle(case, precision, tol, monkeypatch):
+    """The forward projection with psi[k] resident in LDS (OCEAN_FWD_TILES row tiles per
+    block: one tile, several, and more than the x grid holds) gives the band-chunked kernel's
+    H*v bit for bit (the same MFMA sequence per output element; FP32 with the 4x4x1 remainder
+    tiles off on both sides), and the oracle's to the precision's tolerance with them on, for
+    1..5 vectors (6 to 30 columns: one to three column tiles, with and without the FP64
+    multiply-add tail or the FP32 4-column remainder, one or two passes)."""
+    torch = _torch()
+    ob = _ob()
+    cr = RES_CASES[case]()
+    hc, kl = _oracle_mats(cr)
+    nvs = (1, 2, 3) if cr.n_core == 6 else (1, 3, 5)
+    for nv in nvs:
+        x = synth.complex_gaussian(np.random.default_rng(40 + nv), (nv, cr.n_k, cr.n_bands, cr.n_core))
+        xd = _to_dev(x)
+        refs = [orc.apply_h(cr, x[v], hc, kl) for v in range(nv)]
+        monkeypatch.setenv("OCEAN_QUAD_TAIL", "0")
+        monkeypatch.setenv("OCEAN_FWD_TILES", "0")
+        h = ob.Bse.from_crystal(cr, precision=precision)
+        y0 = h.apply(xd).cpu().numpy()
+        h.close()
+        for ft in ("1", "4", "64"):
+            _say(f"resident forward: {case} {precision} n_vec {nv} tiles {ft}")
+            monkeypatch.setenv("OCEAN_FWD_TILES", ft)
+            h = ob.Bse.from_crystal(cr, precision=precision)
+            y = h.apply(xd).cpu().numpy()
+            h.close()
+            torch.cuda.synchronize()
+            assert np.array_equal(y, y0), (case, precision, nv, ft, float(np.abs(y - y0).max()))
+        monkeypatch.setenv("OCEAN_QUAD_TAIL", "1")
+        for ft in ("0", "4"):
+            monkeypatch.setenv("OCEAN_FWD_TILES", ft)
+            h = ob.Bse.from_crystal(cr, precision=precision)
+            y = h.apply(xd).cpu().numpy()
+            h.close()
+            for v in range(nv):
+                assert _rel(y[v], refs[v]) <= tol, (case, precision, nv, ft, v)
+        for v in range(nv):
+            assert _rel(y0[v], refs[v]) <= tol, (case, precision, nv, v)
