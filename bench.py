@@ -37,14 +37,25 @@ def log(msg):
 
 
 def build_workload(seed: int = 0):
+    """The SrTiO3-shaped workload with u drawn on the host (numpy QR per k) -- the inputs of
+    the oracle's golden spectra for seed 0 -- and copied to the device."""
     import torch
     import synth
-    cr = synth.config2_shape(seed=seed, u_override="skip", psi0="none")
     t0 = time.time()
-    u = synth.gpu_orthonormal_u(cr.n_k, cr.n_x, cr.n_bands, seed=seed + 1000)
+    cr = synth.config2_shape(seed=seed, psi0="none")
+    u = torch.from_numpy(cr.u).to("cuda")
     torch.cuda.synchronize()
-    log(f"u generated on device in {time.time() - t0:.1f} s ({u.numel() * 16 / 1e9:.2f} GB)")
+    log(f"u drawn on the host and copied to the device in {time.time() - t0:.1f} s ({u.numel() * 16 / 1e9:.2f} GB)")
     return cr, u
+
+
+def golden_spectra(seed: int):
+    """The CPU oracle's 300-step spectra (x, y, z) of the seed-0 workload, written by
+    tests/golden/make_c2_golden.py; None for other seeds or if the files are absent."""
+    path = os.path.join(ROOT, "tests", "golden", "c2_l23_spectra.txt")
+    if seed != 0 or not os.path.exists(path):
+        return None
+    return np.loadtxt(path)[:, 1:].T
 
 
 MODES = ("fp64", "fp32", "split_bf16", "bf16")
@@ -125,13 +136,12 @@ def timed_haydock(h, psi0, steps):
     return time.perf_counter() - t0, out
 
 
-def cpu_baseline(cr, u_dev, psi0_host, min_seconds=12.0, max_reps=40):
+def cpu_baseline(cr, psi0_host, min_seconds=12.0, max_reps=40):
     """The oracle as it stands, on the same workload: the H*v of the three polarisation
     vectors of one step, repeated until about min_seconds of CPU time have passed."""
     from oracle import bse as orc
     from oracle import multiplet as omp
     cores = len(os.sched_getaffinity(0))
-    cr.u = u_dev.cpu().numpy()
     hc, kl = omp.core_matrix(cr.multiplet), omp.local_matrix(cr.multiplet)
     ut = orc.folded_u(cr)
     w = orc.w_supercell(cr)
@@ -143,7 +153,6 @@ def cpu_baseline(cr, u_dev, psi0_host, min_seconds=12.0, max_reps=40):
             orc.apply_h(cr, v, hc, kl, ut=ut, w=w, f=f)
             n_hv += 1
     dt = time.perf_counter() - t0
-    cr.u = None
     return {"value": n_hv / dt, "unit": "H*v/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_hv} full H*v at the benchmark size (the 3 polarisation vectors of a step, "
                       f"repeated), {dt:.1f} s, numpy FP64 with {cores} host threads"}
@@ -268,6 +277,15 @@ def bench_supercell(ob, seed, steps=10, spec_steps=100):
     ref = sig["fp64"]
     for prec in MODES[1:]:
         out[prec]["spectrum_l1_vs_fp64"] = float(np.sum(np.abs(sig[prec] - ref)) / np.sum(np.abs(ref)))
+    # the roofline of this workload's dominant FP64 kernel, in the form of the headline one
+    km = out["fp64"]["kernel_ms"]
+    dom = max(("proj_fwd", "proj_bwd"), key=lambda k: km[k])
+    ab = proj_bytes(cr, cols, 16, 16)
+    ach = ab / (km[dom] * 1e6)
+    tf = proj_flops(cr, cols) / (km[dom] * 1e-3) / 1e12
+    out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes": ab, "mfma_fp64_tflops": tf,
+                       "mfma_fp64_frac": tf / PEAK_FP64_TFLOPS}
     out["workload"] = ("one Ti L2,3 site of a 4x4x4 SrTiO3-shaped supercell: 2^3 k, 1200 bands, 64^3 x, "
                        f"6 core states, H dim {cr.dim}, u 40 GB (FP64), 3 polarisations per step; spectra "
                        f"of {spec_steps} steps compared with FP64")
@@ -313,80 +331,74 @@ def bench_paper_shape(ob, seed, steps=200):
     return out
 
 
-def he_init(rng, sizes=(64, 256, 256, 256, 448)):
-    """He-normal weights, zero biases, packed [W1, b1, ..., W4, b4] (W stored [in][out])."""
-    parts = []
-    for i, o in zip(sizes[:-1], sizes[1:]):
-        parts.append(rng.standard_normal(i * o) * np.sqrt(2.0 / i))
-        parts.append(np.zeros(o))
-    return np.concatenate(parts).astype(np.float32)
-
-
-def terminator_dataset(ob, seeds, n_steps, shape, chunk=256):
-    """(a, b, |psi0|^2, steps) of the z-polarised L-edge recursion of each seeded system,
-    generated by the solver in batches of `chunk` systems."""
-    import synth
-    A, B, N2, SD = [], [], [], []
-    seeds = list(seeds)
-    omega = gamma = None
-    for st in range(0, len(seeds), chunk):
-        crs = [synth.terminator_system(sd, n_steps=n_steps, **shape) for sd in seeds[st:st + chunk]]
-        hs = [ob.Bse.from_crystal(cr) for cr in crs]
-        p0 = [h.dipole_psi0([0.0, 0.0, 1.0]) for h in hs]
-        res, _ = ob.haydock_batch(hs, p0, n_steps)
-        for a, b, n2, sd in res:
-            A.append(a)
-            B.append(b)
-            N2.append(n2)
-            SD.append(sd)
-        omega, gamma = crs[0].omega, crs[0].gamma
-        for h in hs:
-            h.close()
-    return (np.concatenate(A), np.concatenate(B), np.concatenate(N2), np.concatenate(SD), omega, gamma)
-
-
-def bench_terminator(ob, seed, n_sys, n_held, n_steps=512, epochs=120, batch=256, lr=1e-3):
-    """Learned terminator: dataset from the solver (seeds 1..n_sys, the last n_held held
-    out), training by the library's kernels, held-out judging against the full recursion."""
+def bench_terminator(ob, n_held, n_steps=512, train_epochs=5):
+    """Learned terminator at the full SrTiO3-shaped size.  The shipped network
+    (paper_1601_07728_amd/terminator_srtio3_l23.npz, trained by train_terminator.py with the
+    library's kernels on 1280 systems x 3 polarisations) is judged on n_held held-out systems
+    generated here (never trained on), against their full 512-step spectra; the per-system cost
+    of generating data and the training rate of the kernels are timed on the same sequences."""
     import torch
+    import synth
     from paper_1601_07728_amd import terminator as term
-    shape = dict(nk=(4, 4, 4), nx=(5, 5, 5), n_bands=24)
-    t0 = time.perf_counter()
-    a, b, n2, sd, om, gam = terminator_dataset(ob, range(1, n_sys + 1), n_steps, shape)
-    t_gen = time.perf_counter() - t0
-    log(f"terminator dataset: {n_sys} systems x {n_steps} steps in {t_gen:.1f} s")
-    ntr = n_sys - n_held
-    ad, bd = torch.from_numpy(a).to("cuda"), torch.from_numpy(b).to("cuda")
-    x, t = ob.Mlp.encode(ad, bd)
+    from paper_1601_07728_amd import train_terminator as tt
+    seeds = list(tt.HELD_OUT)[:n_held]
+    d = term.generate(seeds, n_steps=n_steps, log=log)
+    per_sys = d["seconds"] / len(seeds)
+    log(f"terminator: {len(seeds)} held-out systems x 3 polarisations x {n_steps} steps in {d['seconds']:.1f} s "
+        f"({per_sys:.2f} s per system)")
+    a, b, n2, sd = d["a"], d["b"], d["norm2"], d["steps"]
+    omegas = [synth.terminator_omega(int(s_)) for s_ in d["seeds"]]
+    gam = 0.5 / synth.HARTREE_EV
+    ref = term.reference_spectra(a, b, n2, omegas, gam, n_used=sd)
+    path = os.path.join(ROOT, "paper_1601_07728_amd", tt.MODEL_FILE)
     mlp = ob.Mlp("bf16")
-    mlp.set_params(he_init(np.random.default_rng(seed)) * 0.1)
+    out = {"held_out_systems": len(seeds), "held_out_sequences": int(a.shape[0]), "steps": n_steps,
+           "shape": "SrTiO3-shaped L2,3 edge at full size: 8^3 k, 20^3 x, 96 bands, eps U[2,10], width U[20,60] eV",
+           "generation_s_per_system": per_sys,
+           "generation_s_projected_4096_sequences": per_sys * 4096 / 3}
+    l1 = {}
+    if os.path.exists(path):
+        model = np.load(path)
+        th = term.host_targets(a, b)
+        mlp.set_params(term.init_params(th, np.random.default_rng(0)))
+        r0, _ = term.terminated_spectra(mlp, a, b, n2, omegas, gam)
+        l1["mlp_untrained"] = float(np.mean(term.l1(r0["mlp"], ref)))
+        mlp.set_params(model["params"])
+        res, valid = term.terminated_spectra(mlp, a, b, n2, omegas, gam, a_full=a, b_full=b, n_full=sd)
+        for k, v in res.items():
+            l1[k] = float(np.mean(term.l1(v, ref)))
+        per = term.l1(res["mlp"], ref) < term.l1(res["sqrt"], ref)
+        out.update({"model": tt.MODEL_FILE, "model_train_sequences": int(model["n_sequences"]),
+                    "model_train_seconds": float(model["train_seconds"]), "invalid_predictions": int((~valid).sum()),
+                    "fraction_mlp_better_than_sqrt": float(per.mean())})
+    else:
+        log(f"terminator: no trained network at {path}")
+    out["heldout_mean_l1_vs_512_steps"] = l1
+    log(f"terminator: held-out mean L1 vs {n_steps}-step spectra: {l1}")
+    # training rate of the kernels: a few epochs of the recipe on these sequences (a scratch network)
+    fresh = ob.Mlp("bf16")
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = term.train(mlp, x[:ntr].contiguous(), t[:ntr].contiguous(), epochs=epochs, batch=batch, lr=lr,
-                      seed=seed, log_every=max(1, epochs // 4))
-    t_train = time.perf_counter() - t0
-    log(f"terminator training: {epochs} epochs in {t_train:.1f} s, loss {hist}")
-    te = slice(ntr, n_sys)
-    ref = ob.spectrum(a[te], b[te], n2[te], om, gam, n_used=sd[te])
-    res, valid = term.terminated_spectra(mlp, a[te], b[te], n2[te], om, gam, a_full=a[te], b_full=b[te],
-                                         n_full=sd[te])
-    l1 = {k: float(np.mean(term.l1(v, ref))) for k, v in res.items()}
-    l1_med = {k: float(np.median(term.l1(v, ref))) for k, v in res.items()}
-    log(f"held-out mean L1 vs {n_steps}-step spectra: {l1}")
-    return mlp, {"systems": n_sys, "held_out": n_held, "steps": n_steps,
-                 "shape": "SrTiO3-shaped L2,3 edge in miniature: 4^3 k, 5^3 x, 24 bands, eps U[2,10], width U[20,60] eV",
-                 "dataset_seconds": t_gen, "train_seconds": t_train, "epochs": epochs,
-                 "loss_history": hist, "heldout_mean_l1": l1, "heldout_median_l1": l1_med,
-                 "invalid_predictions": int((~valid).sum())}
+    term.fit(fresh, a, b, epochs=train_epochs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["train_sequences_per_s"] = train_epochs * (a.shape[0] // 64) * 64 / dt
+    fresh.close()
+    return mlp, out
 
 
-def spectra_gain(ob, cr, hs, psi0, mlp, ref_steps=600, base_steps=300):
+def spectra_gain(ob, cr, hs, psi0, mlp, gold, ref_steps=600, base_steps=300):
     """spectra/s of the plain FP64 recursion (base_steps) against the mixed path with fewer
-    steps closed by a terminator, at spectrum L1 <= 1e-3 against the FP64 reference."""
+    steps closed by a terminator, at spectrum L1 <= 1e-3 against the reference: the CPU
+    oracle's spectra of this workload (gold), or else a ref_steps FP64 recursion."""
     from paper_1601_07728_amd import terminator as term
     n_pol = psi0.shape[0]
     h64 = hs["fp64"]
-    _, (a, b, n2, sd, _) = timed_haydock(h64, psi0, ref_steps)
-    ref = ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd)
+    if gold is not None:
+        ref, ref_name = gold, "the CPU oracle's 300-step spectra (tests/golden)"
+    else:
+        _, (a, b, n2, sd, _) = timed_haydock(h64, psi0, ref_steps)
+        ref, ref_name = ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd), f"FP64, {ref_steps} steps"
     rows = []
     dt, (a, b, n2, sd, _) = timed_haydock(h64, psi0, base_steps)
     t0 = time.perf_counter()
@@ -398,7 +410,7 @@ def spectra_gain(ob, cr, hs, psi0, mlp, ref_steps=600, base_steps=300):
     for steps in (32, 40, 44, 48, 52, 56, 64, 96, 128, 192):
         for name, h in hs.items():
             dt, (a, b, n2, sd, _) = timed_haydock(h, psi0, steps)
-            for tname in ("sqrt", "mlp") if steps == 32 else ("sqrt",):
+            for tname in ("sqrt", "mlp") if steps == 32 and mlp is not None else ("sqrt",):
                 t0 = time.perf_counter()
                 if tname == "sqrt":
                     sig = ob.spectrum(a, b, n2, cr.omega, cr.gamma, "sqrt", n_used=sd)
@@ -412,7 +424,7 @@ def spectra_gain(ob, cr, hs, psi0, mlp, ref_steps=600, base_steps=300):
     best = max(ok, key=lambda r: r["spectra_per_s"]) if ok else None
     for r in rows:
         log(f"spectra: {r}")
-    return {"reference": f"FP64, {ref_steps} steps", "baseline": base, "best_at_l1_1e-3": best,
+    return {"reference": ref_name, "baseline": base, "best_at_l1_1e-3": best,
             "gain_vs_fp64_baseline": None if best is None else best["spectra_per_s"] / base["spectra_per_s"],
             "rows": rows}
 
@@ -426,9 +438,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--term-systems", type=int, default=4096)
-    ap.add_argument("--term-held-out", type=int, default=256)
-    ap.add_argument("--term-epochs", type=int, default=120)
+    ap.add_argument("--term-held-out", type=int, default=32, help="held-out terminator systems (3 sequences each)")
     ap.add_argument("--no-terminator", action="store_true")
     ap.add_argument("--no-spectra", action="store_true")
     ap.add_argument("--no-full-spin", action="store_true")
@@ -542,6 +552,11 @@ def main():
         l1 = float(np.sum(np.abs(spec[name] - ref)) / np.sum(np.abs(ref)))
         results[name]["spectrum_l1_vs_fp64"] = l1
         log(f"{name} vs fp64 spectrum L1 = {l1:.2e}")
+    gold = golden_spectra(args.seed)
+    for name in (MODES if spec and gold is not None and args.spectrum_steps == 300 else ()):
+        l1 = float(np.mean([np.sum(np.abs(spec[name][p] - gold[p])) / np.sum(np.abs(gold[p])) for p in range(3)]))
+        results[name]["spectrum_l1_vs_oracle"] = l1
+        log(f"{name} vs the oracle's 300-step spectra: mean L1 = {l1:.2e}")
 
     # per-kernel HIP-event timing over the same number of steps, each precision
     avgs = {}
@@ -583,10 +598,9 @@ def main():
 
     terminator = None
     if not args.no_terminator:
-        mlp, terminator = bench_terminator(ob, args.seed, args.term_systems, args.term_held_out,
-                                           epochs=args.term_epochs)
+        mlp, terminator = bench_terminator(ob, args.term_held_out)
         if not args.no_spectra:
-            terminator["srtio3_spectra_gain"] = spectra_gain(ob, cr, hs, psi0, mlp)
+            terminator["srtio3_spectra_gain"] = spectra_gain(ob, cr, hs, psi0, mlp, gold)
         mlp.close()
 
     batched = None
@@ -601,7 +615,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (H*v of the step's polarisation vectors, about 12 s)")
-        cpu = cpu_baseline(cr, u, psi0.cpu().numpy())
+        cpu = cpu_baseline(cr, psi0.cpu().numpy())
         log(f"cpu baseline {cpu['value']:.4f} H*v/s on {cpu['cores']} cores")
 
     line = {
@@ -616,7 +630,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded; u_nk orthonormalised on the device)",
+        "data": "synthetic (seeded; u_nk drawn and orthonormalised on the host, the oracle's golden inputs)",
         "config": {"workload": "SrTiO3-shaped Ti L2,3 edge: 8^3 k, 96 bands, 20^3 x, 6 core states, "
                                "d-channel local term, H dim 294912, 3 polarisations per step",
                    "n_vec_per_step": n_pol, "spectrum_steps": args.spectrum_steps},
@@ -627,6 +641,7 @@ def main():
         "screening": screening,
         "full_local_basis": full_basis,
         "supercell": supercell,
+        "roofline_supercell": None if supercell is None else supercell["roofline"],
         "paper_shape": paper_shape,
         "terminator": terminator,
         "roofline": roofline,

@@ -188,9 +188,10 @@ int ocean_haydock_continue(ocean_bse_t h, const double* v_dev, const double* vpr
  * polarisations: section 4.3 keeps the wavefunctions resident and amortises them over
  * many spectra; section 4.5 runs hundreds of site-edge calculations).  System s uses
  * handle hs[s] (distinct handles with distinct streams, one device), starting vectors
- * psi0[s] (device, n_vec[s] vectors as in ocean_haydock).  One step of every system
- * is captured into a single HIP graph as independent branches and replayed n_steps
- * times.  Host outputs are concatenated over systems in order: vector j of the batch
+ * psi0[s] (device, n_vec[s] vectors as in ocean_haydock).  Up to 8 steps of every system
+ * (OCEAN_BATCH_CHAIN in the environment sets the count) are captured into a single HIP graph,
+ * each system an independent branch whose steps follow one another with no join between
+ * systems, and the graph is replayed until n_steps steps are done.  Host outputs are concatenated over systems in order: vector j of the batch
  * (systems in order, their vectors in order) has a[j*n_steps + i], b[j*n_steps + i],
  * norm2[j], steps_done[j].  Each system's numbers are bitwise those of ocean_haydock on
  * the same handle.  Returns OCEAN_INFO_INVARIANT_SUBSPACE if any vector stopped early.
@@ -242,7 +243,8 @@ int ocean_spectrum(const double* a, const double* b, const int* n_used, const do
  * Not part of the paper: a small network that extends the Haydock coefficients of
  * section 3.2 from the first 32 pairs to 256, so that the continued fraction of
  * eq. loss.fcn needs 32 H*v instead of hundreds.  Network 64 -> 256 -> 256 -> 256 -> 448,
- * ReLU, mean-squared error, Adam (beta1 0.9, beta2 0.999, eps 1e-8).  Parameters are
+ * ReLU, mean-squared error (optionally weighted per output position), Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8).  Parameters are
  * FP32 masters packed [W1, b1, W2, b2, W3, b3, W4, b4] with W stored [in][out]
  * (ocean_mlp_param_count() floats).  The GEMMs run on the matrix cores: bf16 inputs
  * with FP32 accumulation (OCEAN_MLP_BF16), or FP32 inputs (OCEAN_MLP_FP32).
@@ -261,6 +263,11 @@ void ocean_mlp_destroy(ocean_mlp_t h);
 /* Copy parameters in (host, resets the Adam moments and step count) or out (host). */
 int ocean_mlp_set_params(ocean_mlp_t h, const float* params);
 int ocean_mlp_get_params(ocean_mlp_t h, float* params);
+/* Weight of each output position in the mean-squared error of ocean_mlp_loss_grad and
+ * ocean_mlp_train_step: loss = sum_{s, j} w_j (y_sj - t_sj)^2 / (batch * 448).  w is host [448]
+ * (finite, >= 0), copied; NULL restores unit weights.  Errors: INVALID_ARG, OUT_OF_MEMORY,
+ * DEVICE. */
+int ocean_mlp_set_loss_weights(ocean_mlp_t h, const float* w);
 /* Checkpoint: write the parameters, the Adam moments and step count to the file at path
  * (binary, little-endian: the 8 bytes "OCEANMLP", int32 version 1, int32 precision,
  * int32 Adam step, int32 parameter count, then three float32 arrays of that count:
@@ -277,8 +284,9 @@ int ocean_mlp_encode(const double* a_dev, const double* b_dev, int n_seq, int st
                      float* t_dev);
 /* y [batch][448] = network(x [batch][64]); device arrays.  Synchronous. */
 int ocean_mlp_forward(ocean_mlp_t h, const float* x_dev, int batch, float* y_dev);
-/* Loss and gradient of the mean-squared error over the batch; loss (host) and grad (host,
- * packed like the parameters) may each be NULL.  Synchronous. */
+/* Loss and gradient of the (weighted, see ocean_mlp_set_loss_weights) mean-squared error over
+ * the batch; loss (host) and grad (host, packed like the parameters) may each be NULL.
+ * Synchronous. */
 int ocean_mlp_loss_grad(ocean_mlp_t h, const float* x_dev, const float* t_dev, int batch,
                         double* loss, float* grad);
 /* One Adam step on the batch (forward, backward, update) with learning rate lr.  Returns
@@ -432,10 +440,12 @@ long long ocean_bse_device_bytes(ocean_bse_t h);
  *             functions of every state summed over (all bands and k) on the grid points.
  *   eps       host, [n_states] energies (Ha); mu (Ha); t, w host [n_t], t_j >= 0.
  *   chi0_dev  device, [n_points][n_points] real (row-major), overwritten.  Real and symmetric.
- * Per node: the state columns are scaled by 1/(mu + i t_j - eps_s), G_j is one complex GEMM
- * on the matrix cores (rocBLAS), and the symmetric product is added into chi0.
+ * With A_j = Psi diag(Re d_j) Psi^H and B_j = Psi diag(Im d_j) Psi^H (d_j(s) = 1/(mu + i t_j - eps_s)),
+ * Re[G_j(r, r') G_j(r', r)] = |A_j(r, r')|^2 - |B_j(r, r')|^2: one FP64 matrix-core kernel forms A_j and
+ * B_j tile by tile (upper-triangle tile pairs) and accumulates that expression; G_j is never stored.
+ * Node partials are added in node order, so results are bitwise reproducible.
  * stream: hipStream_t or NULL for the default stream; the call returns after the work has
- * finished.  Allocates n_points * (n_states + n_points) complex of device scratch.
+ * finished.  Allocates n_t * n_points^2 doubles of device scratch (the node partials).
  * Errors: INVALID_ARG (NULL, sizes < 1, non-finite input, negative node), OUT_OF_MEMORY,
  * DEVICE. */
 int ocean_screening_chi0(const double* psi_dev, const double* eps, int n_points, int n_states,

@@ -10,8 +10,9 @@ Encoding, per sequence (a_0.., b_1..):
   output y = [(a_n - c)/s for 32 <= n < 256] + [log(b_{n+1}/s) for 32 <= n < 256]  (448)
 so b stays positive after decoding.
 
-Network 64 -> 256 -> 256 -> 256 -> 448, ReLU on the hidden layers, mean-squared error,
-Adam (Kingma & Ba) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8.  Parameters are packed
+Network 64 -> 256 -> 256 -> 256 -> 448, ReLU on the hidden layers, mean-squared error with
+an optional weight per output position, Adam (Kingma & Ba) with beta1 = 0.9, beta2 = 0.999,
+eps = 1e-8.  Parameters are packed
 [W1 (64x256), b1, W2 (256x256), b2, W3 (256x256), b3, W4 (256x448), b4], each W stored
 [in][out] so that a layer computes x W + b.  FP64 throughout.
 """
@@ -87,13 +88,16 @@ def forward(p, x):
     return h, acts
 
 
-def loss_and_grad(p, x, t):
-    """Mean-squared error over all outputs and its gradient w.r.t. the packed parameters."""
+def loss_and_grad(p, x, t, weights=None):
+    """Mean-squared error over all outputs, each output position j weighted by weights[j]
+    (default 1), and its gradient w.r.t. the packed parameters:
+    loss = sum_{s, j} w_j (y_sj - t_sj)^2 / (n_seq * 448)."""
     y, acts = forward(p, x)
     n = y.size
     r = y - t
-    loss = float(np.sum(r * r) / n)
-    g = 2.0 * r / n
+    wr = r if weights is None else r * np.asarray(weights, dtype=np.float64)[None, :]
+    loss = float(np.sum(wr * r) / n)
+    g = 2.0 * wr / n
     layers = unpack(p)
     grads = []
     for li in range(len(layers) - 1, -1, -1):

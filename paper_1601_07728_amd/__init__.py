@@ -52,7 +52,7 @@ EXPORTED = [
     "ocean_device_ceilings", "ocean_screening_chi0", "ocean_local_matrix_channels",
     "ocean_dipole_amplitudes_channels", "ocean_dipole_psi0_channels", "ocean_nrixs_amplitudes_channels",
     "ocean_quadrupole_amplitudes_channels", "ocean_psi0_amplitudes", "ocean_haydock_export",
-    "ocean_haydock_continue", "ocean_mlp_predict_noalloc",
+    "ocean_haydock_continue", "ocean_mlp_predict_noalloc", "ocean_mlp_set_loss_weights",
 ]
 MLP_BF16 = 0
 MLP_FP32 = 1
@@ -100,6 +100,15 @@ def lib() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                            "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    # torch holds the device memory the kernels read, through the HIP runtime it ships with; that
+    # runtime has to see the GPU before the library's own runtime opens it, so it is started here
+    # first (a process whose first GPU call came from the library found no GPU in torch)
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, ci, cd, cu = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint
     ll = ctypes.c_longlong
@@ -177,6 +186,8 @@ def lib() -> ctypes.CDLL:
     L.ocean_mlp_predict.restype = ci
     L.ocean_mlp_predict_noalloc.argtypes = [vp, vp, vp, ci, ci, vp, vp, vp, vp]
     L.ocean_mlp_predict_noalloc.restype = ci
+    L.ocean_mlp_set_loss_weights.argtypes = [vp, vp]
+    L.ocean_mlp_set_loss_weights.restype = ci
     L.ocean_mlp_save.argtypes = [vp, ctypes.c_char_p]
     L.ocean_mlp_save.restype = ci
     L.ocean_mlp_load.argtypes = [vp, ctypes.c_char_p]
@@ -624,6 +635,16 @@ class Mlp:
         if p.size != self.n_params:
             raise ValueError("wrong parameter count")
         _check(lib().ocean_mlp_set_params(self._h, _ptr(p)))
+
+    def set_loss_weights(self, w):
+        """Per-output weights [448] of the training loss, or None for unit weights."""
+        if w is None:
+            _check(lib().ocean_mlp_set_loss_weights(self._h, None))
+            return
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != 448:
+            raise ValueError("448 loss weights expected")
+        _check(lib().ocean_mlp_set_loss_weights(self._h, _ptr(w)))
 
     def get_params(self):
         p = np.zeros(self.n_params, dtype=np.float32)

@@ -20,7 +20,6 @@ LIB_ASAN = os.path.join(OBJ_ASAN, "libocean_bse_asan.so")
 ASAN_FLAGS = ["-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
 SOURCES = ["proj.hip", "proj_bf16.hip", "fftw.hip", "vec.hip", "runtime.hip", "mlp.hip", "ceilings.hip",
            "screening.hip", "multiplet.cpp"]
-ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions are kept out of every kernel
@@ -48,10 +47,8 @@ def build(verbose: bool = False, asan: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
         objs = list(ex.map(lambda src: _compile(src, asan), SOURCES))
     tmp = out + ".tmp"
-    # rocBLAS for the plain complex GEMM of the screening response
     san = ["-Xarch_host", "-fsanitize=address", "-shared-libsan"] if asan else []
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, *san, "-L" + ROCM_LIB, "-lrocblas",
-           "-Wl,-rpath," + ROCM_LIB, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, *san, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

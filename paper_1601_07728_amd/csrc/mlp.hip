@@ -82,17 +82,19 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(const float* __restrict__
     }
 }
 
-// dY = 2 (Y - T) / n and per-block partial sums of (Y - T)^2 / n
+// dY = 2 w (Y - T) / n and per-block partial sums of w (Y - T)^2 / n, with w the weight of the
+// output position (e % 448), or 1 without weights
 __global__ __launch_bounds__(256) void mse_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T,
-                                                      float* __restrict__ dY, double* __restrict__ part,
-                                                      long long n) {
+                                                      const float* __restrict__ W, float* __restrict__ dY,
+                                                      double* __restrict__ part, long long n) {
     __shared__ double sh[256];
     double s = 0.0;
     const double inv = 1.0 / (double)n;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
         const float r = Y[e] - T[e];
-        dY[e] = (float)(2.0 * r * inv);
-        s += (double)r * r * inv;
+        const double w = W ? (double)W[e % kSizes[kLayers]] : 1.0;
+        dY[e] = (float)(2.0 * w * r * inv);
+        s += w * (double)r * r * inv;
     }
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -213,6 +215,7 @@ struct ocean_mlp_s {
     float* dact[ocean::kLayers + 1] = {};
     double* part = nullptr;
     double* loss = nullptr;
+    float* lw = nullptr;   // per-output loss weights [448], or NULL for 1
 };
 
 namespace ocean {
@@ -323,7 +326,7 @@ int scratch_address(int device, void** out) {
 int mlp_backward(ocean_mlp_s* h, const float* t_dev, int batch) {
     const long long n = (long long)batch * kSizes[kLayers];
     const int nblk = 120;
-    mse_grad_kernel<<<nblk, 256, 0, h->stream>>>(h->act[kLayers], t_dev, h->dact[kLayers], h->part, n);
+    mse_grad_kernel<<<nblk, 256, 0, h->stream>>>(h->act[kLayers], t_dev, h->lw, h->dact[kLayers], h->part, n);
     sum_parts_kernel<<<1, 64, 0, h->stream>>>(h->part, nblk, h->loss);
     for (int l = kLayers - 1; l >= 0; --l) {
         const int in = kSizes[l], out = kSizes[l + 1];
@@ -391,7 +394,7 @@ void ocean_mlp_destroy(ocean_mlp_t h) {
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     mlp_free_acts(h);
-    for (void* q : {(void*)h->p, (void*)h->g, (void*)h->m, (void*)h->v, (void*)h->part, (void*)h->loss})
+    for (void* q : {(void*)h->p, (void*)h->g, (void*)h->m, (void*)h->v, (void*)h->part, (void*)h->loss, (void*)h->lw})
         if (q) (void)hipFree(q);
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -405,6 +408,31 @@ int ocean_mlp_set_params(ocean_mlp_t h, const float* params) {
     if (rc == OCEAN_OK) rc = mlp_hip(hipMemsetAsync(h->v, 0, pb, h->stream), "reset");
     if (rc == OCEAN_OK) rc = mlp_hip(hipStreamSynchronize(h->stream), "set_params");
     h->t = 0;
+    return rc;
+}
+
+int ocean_mlp_set_loss_weights(ocean_mlp_t h, const float* w) {
+    if (!h) return mlp_fail("ocean_mlp_set_loss_weights: NULL handle", OCEAN_ERR_INVALID_ARG);
+    if (!w) {
+        if (h->lw) {
+            (void)hipStreamSynchronize(h->stream);
+            (void)hipFree(h->lw);
+            h->lw = nullptr;
+        }
+        return OCEAN_OK;
+    }
+    for (int j = 0; j < kSizes[kLayers]; ++j)
+        if (!std::isfinite(w[j]) || w[j] < 0.f)
+            return mlp_fail("ocean_mlp_set_loss_weights: weights must be finite and >= 0", OCEAN_ERR_INVALID_ARG);
+    (void)hipSetDevice(h->device);
+    if (!h->lw && hipMalloc((void**)&h->lw, kSizes[kLayers] * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        h->lw = nullptr;
+        return mlp_fail("ocean_mlp_set_loss_weights: hipMalloc failed", OCEAN_ERR_OUT_OF_MEMORY);
+    }
+    int rc = mlp_hip(hipMemcpyAsync(h->lw, w, kSizes[kLayers] * sizeof(float), hipMemcpyHostToDevice, h->stream),
+                     "upload");
+    if (rc == OCEAN_OK) rc = mlp_hip(hipStreamSynchronize(h->stream), "set_loss_weights");
     return rc;
 }
 

@@ -747,16 +747,17 @@ hipError_t fwd_dispatch_nt(int NT, int TC, dim3 grid, hipStream_t st, const void
 constexpr int kResWaves = 8;
 
 template <typename T>
-hipError_t fwd_res_dispatch(int NT, int TC, int TQ, dim3 grid, size_t lds, hipStream_t st, const void* U, const double* x,
-                            void* phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0, int ncb, int groups,
-                            int tiles) {
+hipError_t fwd_res_dispatch(int NT, int TC, int TQ, dim3 grid, size_t lds, hipStream_t st, const void* U,
+                            const double* x, void* phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0,
+                            int ncb, int groups, int tiles) {
+    constexpr int KC = Tiles<T>::KC;
     typedef typename Cplx<T>::c2 C2;
     const C2* u = static_cast<const C2*>(U);
     C2* p = static_cast<C2*>(phi);
     const double2* ps = reinterpret_cast<const double2*>(x);
 #define OCEAN_FWDR(nt, tc, tq) \
     if (NT == nt && TC == tc && TQ == tq) { \
-        proj_fwd_res_kernel<T, nt, tc, tq, Tiles<T>::KC, kColsPerPass, kResWaves><<<grid, 64 * kResWaves, lds, st>>>( \
+        proj_fwd_res_kernel<T, nt, tc, tq, KC, kColsPerPass, kResWaves><<<grid, 64 * kResWaves, lds, st>>>( \
             u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, groups, tiles); \
         return hipGetLastError(); \
     }
@@ -769,6 +770,7 @@ hipError_t fwd_res_dispatch(int NT, int TC, int TQ, dim3 grid, size_t lds, hipSt
 #undef OCEAN_FWDR
     return hipErrorInvalidValue;
 }
+
 
 template <typename T, int W>
 hipError_t bwd_dispatch_w(int NT, int TC, int TQ, dim3 grid, hipStream_t st, const void* U, const void* phi,

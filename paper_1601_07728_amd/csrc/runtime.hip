@@ -31,6 +31,10 @@ static int env_int(const char* name, int dflt) {
     return std::atoi(s);
 }
 
+// Haydock steps of each system captured back to back in one batched graph (OCEAN_BATCH_CHAIN
+// overrides; 1 is one graph per step with every system joined after each step).
+static constexpr int kBatchChain = 8;
+
 int prof_begin(ocean_bse_s* h, const char* name) {
     if (!h->profiling) return -1;
     int idx = -1;
@@ -897,48 +901,62 @@ int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* p
     }
     for (int s = 0; s < n_sys; ++s) OCEAN_HIP(hipStreamSynchronize(hs[s]->stream), "batch init");
 
-    // One step of every system, captured into a single graph: the systems are independent
-    // branches forked from and joined back into a master stream.
+    // `chain` steps of every system, captured into a single graph: the systems are independent
+    // branches forked from and joined back into a master stream, and within a branch the steps
+    // follow one another with no join, so a system whose steps are short does not wait for the
+    // slowest one at every step.  n_steps = q chain + r: the graph of `chain` steps is replayed
+    // q times, then a graph of r steps runs once.
     bool graph_done = false;
     const bool use_graph = !profiling && env_int("OCEAN_NO_GRAPH", 0) == 0;
+    const int chain = std::max(1, std::min(n_steps, env_int("OCEAN_BATCH_CHAIN", kBatchChain)));
     if (use_graph) {
         hipStream_t master;
         OCEAN_HIP(hipStreamCreateWithFlags(&master, hipStreamNonBlocking), "stream create");
         std::vector<hipEvent_t> ev(n_sys + 1);
         bool ok = true;
         for (auto& e : ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        if (ok && hipStreamBeginCapture(master, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        auto capture = [&](int steps, hipGraphExec_t* exec) -> bool {
+            hipGraph_t graph = nullptr;
+            *exec = nullptr;
+            if (hipStreamBeginCapture(master, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                (void)hipGetLastError();
+                return false;
+            }
             int rc = check_hip(hipEventRecord(ev[n_sys], master), "fork");
             for (int s = 0; s < n_sys && rc == OCEAN_OK; ++s) {
                 rc = check_hip(hipStreamWaitEvent(hs[s]->stream, ev[n_sys], 0), "fork");
-                if (rc == OCEAN_OK) rc = haydock_step(hs[s], n_vec[s], reorth);
+                for (int i = 0; i < steps && rc == OCEAN_OK; ++i) rc = haydock_step(hs[s], n_vec[s], reorth);
                 if (rc == OCEAN_OK) rc = check_hip(hipEventRecord(ev[s], hs[s]->stream), "join");
                 if (rc == OCEAN_OK) rc = check_hip(hipStreamWaitEvent(master, ev[s], 0), "join");
             }
             const hipError_t ec = hipStreamEndCapture(master, &graph);
-            if (rc == OCEAN_OK && ec == hipSuccess && graph &&
-                hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
-                int lrc = OCEAN_OK;
-                for (int i = 0; i < n_steps && lrc == OCEAN_OK; ++i)
-                    lrc = check_hip(hipGraphLaunch(exec, master), "graph launch");
-                if (lrc == OCEAN_OK) lrc = check_hip(hipStreamSynchronize(master), "batch");
-                graph_done = lrc == OCEAN_OK;
-                (void)hipGraphExecDestroy(exec);
-                if (!graph_done) {
-                    (void)hipGraphDestroy(graph);
-                    for (auto& e : ev) (void)hipEventDestroy(e);
-                    (void)hipStreamDestroy(master);
-                    return lrc;
-                }
-            } else {
+            const bool good = rc == OCEAN_OK && ec == hipSuccess && graph &&
+                              hipGraphInstantiate(exec, graph, nullptr, nullptr, 0) == hipSuccess;
+            if (!good) {
                 (void)hipGetLastError();
+                *exec = nullptr;
             }
             if (graph) (void)hipGraphDestroy(graph);
-        } else {
-            (void)hipGetLastError();
+            return good;
+        };
+        hipGraphExec_t full = nullptr, rest = nullptr;
+        const int q = n_steps / chain, r = n_steps - q * chain;
+        if (ok && capture(chain, &full) && (r == 0 || capture(r, &rest))) {
+            int lrc = OCEAN_OK;
+            for (int i = 0; i < q && lrc == OCEAN_OK; ++i) lrc = check_hip(hipGraphLaunch(full, master), "graph launch");
+            if (r > 0 && lrc == OCEAN_OK) lrc = check_hip(hipGraphLaunch(rest, master), "graph launch");
+            if (lrc == OCEAN_OK) lrc = check_hip(hipStreamSynchronize(master), "batch");
+            graph_done = lrc == OCEAN_OK;
+            if (!graph_done) {
+                (void)hipGraphExecDestroy(full);
+                if (rest) (void)hipGraphExecDestroy(rest);
+                for (auto& e : ev) (void)hipEventDestroy(e);
+                (void)hipStreamDestroy(master);
+                return lrc;
+            }
         }
+        if (full) (void)hipGraphExecDestroy(full);
+        if (rest) (void)hipGraphExecDestroy(rest);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
         (void)hipStreamDestroy(master);

@@ -265,6 +265,24 @@ def gpu_orthonormal_u(n_k: int, n_x: int, n_bands: int, seed: int, device="cuda"
     return u
 
 
+def gpu_orthonormal_u_batched(n_k: int, n_x: int, n_bands: int, seed: int, device="cuda"):
+    """As gpu_orthonormal_u, with every k drawn in one call and the two Cholesky-QR passes
+    batched over k (a different stream of random numbers from gpu_orthonormal_u)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    z = torch.randn((n_k, n_x, n_bands), dtype=torch.complex128, device=device, generator=g)
+    eye = torch.eye(n_bands, dtype=z.dtype, device=device).expand(n_k, n_bands, n_bands)
+    for _ in range(2):
+        gram = torch.matmul(z.conj().transpose(1, 2).contiguous(), z)
+        gram = 0.5 * (gram + gram.conj().transpose(1, 2))
+        r = torch.linalg.cholesky(gram).conj().transpose(1, 2).contiguous()       # G = R^H R
+        rinv = torch.linalg.solve_triangular(r, eye, upper=True)
+        z = torch.matmul(z, rinv.contiguous())                                  # Q = Z R^-1
+        del gram, r, rinv
+    return z.contiguous()
+
+
 # --- molecule in a box: many absorbing sites, Gamma point only ---------------------------
 
 def molecule_sites(seed: int = 0, n_atoms: int = 52, n_sites: int = 40, box: float = 30.0,
@@ -316,13 +334,24 @@ def molecule_sites(seed: int = 0, n_atoms: int = 52, n_sites: int = 40, box: flo
     return sites
 
 
+def terminator_params(seed: int) -> tuple[float, float]:
+    """(eps, band width in eV) of terminator-dataset system `seed`: eps ~ U[2, 10], width ~ U[20, 60]."""
+    rng = np.random.default_rng([seed, 7])
+    eps = float(rng.uniform(2.0, 10.0))
+    width = float(rng.uniform(20.0, 60.0))
+    return eps, width
+
+
+def terminator_omega(seed: int, n: int = 2000) -> np.ndarray:
+    """Energy grid of system `seed`'s spectrum: n points on [-15, width + 15] eV (in Ha)."""
+    return omega_grid(-15.0, terminator_params(seed)[1] + 15.0, n)
+
+
 def terminator_system(seed: int, nk=(2, 2, 2), nx=(5, 5, 5), n_bands: int = 24,
                       n_steps: int = 512, u_override=None) -> Crystal:
     """One system of the learned-terminator dataset: the SrTiO3-shaped L2,3 edge (any grid
     and band count), with eps ~ U[2, 10] and band width ~ U[20, 60] eV drawn from the seed."""
-    rng = np.random.default_rng([seed, 7])
-    eps = float(rng.uniform(2.0, 10.0))
-    width = float(rng.uniform(20.0, 60.0))
+    eps, width = terminator_params(seed)
     return config2_shape(nk=nk, nx=nx, n_bands=n_bands, seed=seed, eps=eps, n_steps=n_steps,
                          psi0="none", e_range_ev=width, u_override=u_override)
 
@@ -333,10 +362,11 @@ TERMINATOR_U_SEED_OFFSET = 1 << 20
 def terminator_system_device(seed: int, nk=(8, 8, 8), nx=(20, 20, 20), n_bands: int = 96,
                              n_steps: int = 512, device="cuda"):
     """A terminator-dataset system at the full SrTiO3-shaped size (default 8^3 k, 20^3 x,
-    96 bands), with u drawn on the device (gpu_orthonormal_u, seed + TERMINATOR_U_SEED_OFFSET).
-    Returns (Crystal, u)."""
+    96 bands), with u drawn on the device in one batch (gpu_orthonormal_u_batched, seed +
+    TERMINATOR_U_SEED_OFFSET).  Returns (Crystal, u)."""
     cr = terminator_system(seed, nk=nk, nx=nx, n_bands=n_bands, n_steps=n_steps, u_override="skip")
-    u = gpu_orthonormal_u(cr.n_k, cr.n_x, cr.n_bands, seed=seed + TERMINATOR_U_SEED_OFFSET, device=device)
+    u = gpu_orthonormal_u_batched(cr.n_k, cr.n_x, cr.n_bands, seed=seed + TERMINATOR_U_SEED_OFFSET,
+                                  device=device)
     return cr, u
 
 

@@ -99,3 +99,38 @@ def test_zero_network_extends_with_the_constant_chain():
     assert np.array_equal(ae[:, :32], a) and np.array_equal(be[:, :32], b)
     assert np.allclose(ae[:, 32:], c[:, None], rtol=0, atol=1e-15)
     assert np.allclose(be[:, 32:], s[:, None], rtol=1e-15, atol=0)
+
+
+def test_weighted_loss_gradient_matches_central_differences():
+    """Per-output weights: the gradient of sum_j w_j (y_j - t_j)^2 / n against central
+    differences, unit weights give the plain loss, and a gradient that forgets the weights
+    (planted in a copy) fails the check."""
+    rng, p, x, t = _data(4)
+    w = rng.uniform(0.1, 3.0, 448)
+    loss, g = mlp.loss_and_grad(p, x, t, w)
+    idx = np.concatenate([rng.choice(p.size, 24, replace=False), [p.size - 1, p.size - 449]])
+    worst = 0.0
+    for i in idx:
+        h = 1e-6 * max(1.0, abs(p[i]))
+        pp = p.copy()
+        pp[i] += h
+        lp = mlp.loss_and_grad(pp, x, t, w)[0]
+        pp[i] -= 2 * h
+        lm = mlp.loss_and_grad(pp, x, t, w)[0]
+        worst = max(worst, abs((lp - lm) / (2 * h) - g[i]) / max(abs(g[i]), 1e-3))
+    assert worst <= 1e-6
+    l1, g1 = mlp.loss_and_grad(p, x, t, np.ones(448))
+    l0, g0 = mlp.loss_and_grad(p, x, t)
+    assert abs(l1 - l0) <= 1e-15 * l0 and np.array_equal(g1, g0)
+    _, g_unw = mlp.loss_and_grad(p, x, t)            # the planted mistake: weights dropped
+    b4 = np.arange(p.size - 448, p.size - 440)
+    bad = 0.0
+    for i in b4:
+        h = 1e-6
+        pp = p.copy()
+        pp[i] += h
+        lp = mlp.loss_and_grad(pp, x, t, w)[0]
+        pp[i] -= 2 * h
+        lm = mlp.loss_and_grad(pp, x, t, w)[0]
+        bad = max(bad, abs((lp - lm) / (2 * h) - g_unw[i]) / max(abs(g_unw[i]), 1e-3))
+    assert bad > 0.05
