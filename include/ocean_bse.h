@@ -214,11 +214,15 @@ int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* p
 int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps);
 
 /* Current tile choices: forward rows per wave / 16, back-projection grid target, lines
- * per k-grid transform block, and row tiles per block of the FP64/FP32 forward projection that
+ * per k-grid transform block, row tiles per block of the FP64/FP32 forward projection that
  * keeps psi[k] of every band resident in LDS (0: the band-chunked forward; the resident form
- * applies only where psi[k] of a pass fits in 64 KiB).  Any pointer may be NULL.
+ * applies only where psi[k] of a pass fits in 64 KiB), and the most waves (16 bands each) per
+ * back-projection block (the 16-band groups are dealt evenly over the fewest blocks that
+ * respect it: 96 bands at 4 make two blocks of 3 waves).  Any pointer may be NULL.
+ * Environment overrides at create: OCEAN_BWD_BLOCKS, OCEAN_FWD_TILES, OCEAN_BWD_WAVES (1..8).
  * Errors: INVALID_ARG. */
-int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_lines, int* fwd_tiles);
+int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_lines, int* fwd_tiles,
+                         int* bwd_waves);
 
 /* Spectra from Haydock coefficients (section 2, eq. loss.fcn with
  * G = [w - H]^-1 as a continued fraction), evaluated on the GPU in FP64:

@@ -162,7 +162,7 @@ def lib() -> ctypes.CDLL:
     L.ocean_haydock_batch.restype = ci
     L.ocean_bse_autotune.argtypes = [vp, ci, ci]
     L.ocean_bse_autotune.restype = ci
-    L.ocean_bse_get_tuning.argtypes = [vp, vp, vp, vp, vp]
+    L.ocean_bse_get_tuning.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ocean_bse_get_tuning.restype = ci
     L.ocean_mlp_param_count.argtypes = []
     L.ocean_mlp_param_count.restype = ci
@@ -581,10 +581,11 @@ class Bse:
 
     @property
     def tuning(self):
-        m, b, f, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        m, b, f, t, w = (ctypes.c_int() for _ in range(5))
         _check(lib().ocean_bse_get_tuning(self._h, ctypes.byref(m), ctypes.byref(b), ctypes.byref(f),
-                                          ctypes.byref(t)))
-        return {"fwd_ms": m.value, "bwd_blocks": b.value, "fft_lines": f.value, "fwd_tiles": t.value}
+                                          ctypes.byref(t), ctypes.byref(w)))
+        return {"fwd_ms": m.value, "bwd_blocks": b.value, "fft_lines": f.value, "fwd_tiles": t.value,
+                "bwd_waves": w.value}
 
     def set_profiling(self, on: bool):
         _check(lib().ocean_bse_set_profiling(self._h, 1 if on else 0))

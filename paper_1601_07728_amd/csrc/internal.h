@@ -129,6 +129,7 @@ struct ocean_bse_s {
     // tuning knobs (picked at create, overridable through the environment)
     int fft_lines = 16;          // lines per block of the k-grid transform
     int bwd_target_blocks = 2048;  // back-projection grid size the x chunking aims at
+    int bwd_waves = 8;           // back-projection: at most this many waves (16 bands each) per block
     int fwd_ms = 2;              // forward projection: 16 * fwd_ms rows per wave
     int quad_tail = 1;           // FP32: a remainder of <= 4 real columns on the 4x4x1 MFMA (0: a padded tile)
     int fwd_tiles = 0;           // FP64/FP32 forward with psi[k] resident in LDS: row tiles per block
@@ -250,10 +251,11 @@ hipError_t launch_spectrum(const double* a, const double* b, const int* n_used, 
                            int n_omega, double gamma, double* sigma, hipStream_t stream);
 
 // geometry helpers
-int bwd_waves(int Nb);
+int bwd_waves_for(int Nb, int cap);
+int bwd_waves(const ocean_bse_s* h);
 int cols_per_pass(const ocean_bse_s* h, int cols);
 void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk);
-void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks, int* S, int* chunk);
+void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int W, int* band_blocks, int* S, int* chunk);
 constexpr int kMaxBwdTarget = 8192;  // largest back-projection grid target the tuner tries
 size_t fft_lds_bytes(const ocean_bse_s* h, int lines);
 size_t fwd_res_lds_bytes(const ocean_bse_s* h, int ncb);   // 0: psi[k] does not fit

@@ -822,15 +822,19 @@ hipError_t bwd_dispatch(int W, int NT, int TC, int TQ, dim3 grid, hipStream_t st
 }  // namespace
 
 
-// Backward-projection geometry: band blocks of up to 8 waves x 16 bands, and x chunks
-// (multiples of the 16-point phi x-block) so that the grid holds about bwd_target_blocks blocks.
-int bwd_waves(int Nb) {
+// Backward-projection geometry: band blocks of at most `cap` waves x 16 bands, the 16-band
+// groups dealt evenly over the fewest blocks (96 bands at cap 4: two blocks of 3 waves), and x
+// chunks (multiples of the 16-point phi x-block) so that the grid holds about
+// bwd_target_blocks blocks.
+int bwd_waves_for(int Nb, int cap) {
     const int nb16 = (Nb + 15) / 16;
-    return nb16 < 8 ? nb16 : 8;
+    const int blocks = (nb16 + cap - 1) / cap;
+    return (nb16 + blocks - 1) / blocks;
 }
 
-void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks, int* S, int* chunk) {
-    const int W = bwd_waves(h->Nb);
+int bwd_waves(const ocean_bse_s* h) { return bwd_waves_for(h->Nb, h->bwd_waves); }
+
+void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int W, int* band_blocks, int* S, int* chunk) {
     const int bb = (h->Nb + 16 * W - 1) / (16 * W);
     const long long per_chunk = (long long)h->Nk * bb;
     long long s = (target_blocks + per_chunk - 1) / per_chunk;
@@ -851,7 +855,7 @@ void bwd_geometry_for(const ocean_bse_s* h, int target_blocks, int* band_blocks,
 }
 
 void bwd_geometry(const ocean_bse_s* h, int* band_blocks, int* S, int* chunk) {
-    bwd_geometry_for(h, h->bwd_target_blocks, band_blocks, S, chunk);
+    bwd_geometry_for(h, h->bwd_target_blocks, bwd_waves(h), band_blocks, S, chunk);
 }
 
 bool is_bf16_mode(int precision) {
@@ -961,7 +965,7 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     column_split(ncb, h->precision == OCEAN_PREC_FP64, true, h->quad_tail != 0, &NT, &TC, &TQ);
     int bb, S, chunk;
     bwd_geometry(h, &bb, &S, &chunk);
-    const int W = bwd_waves(h->Nb);
+    const int W = bwd_waves(h);
     dim3 grid((unsigned)((long long)h->Nk * bb * S));
     const int slot = prof_begin(h, "proj_bwd");
     hipError_t e;

@@ -505,7 +505,7 @@ hipError_t launch_proj_bwd_bf16(ocean_bse_s* h, int nv, int col0, int ncb) {
     const int NT = (2 * ncb + 15) / 16;
     int bb, S, chunk;
     bwd_geometry(h, &bb, &S, &chunk);
-    const int W = bwd_waves(h->Nb);
+    const int W = bwd_waves(h);
     dim3 grid((unsigned)((long long)h->Nk * bb * S));
     const int slot = prof_begin(h, "proj_bwd");
     hipError_t e;

@@ -161,8 +161,10 @@ static int ensure_workspace(ocean_bse_s* h, int nv) {
     release_workspace(h);
     int bb, S, chunk, S_alloc;
     bwd_geometry(h, &bb, &S, &chunk);
-    // partials sized for the largest chunking the autotuner may select
-    bwd_geometry_for(h, std::max(h->bwd_target_blocks, kMaxBwdTarget), &bb, &S_alloc, &chunk);
+    // partials sized for the largest chunking the autotuner may select (the most waves per
+    // block give the fewest band blocks, hence the most x chunks for a grid target)
+    bwd_geometry_for(h, std::max(h->bwd_target_blocks, kMaxBwdTarget), bwd_waves_for(h->Nb, 8), &bb, &S_alloc,
+                     &chunk);
     S_alloc = std::max(S_alloc, S);
     const size_t elem = h->precision == OCEAN_PREC_FP64 ? 16 : 8;
     const size_t nx_pad = ((size_t)h->Nx + kXB - 1) / kXB * kXB;
@@ -484,6 +486,7 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
     }
     h->bwd_target_blocks = env_int("OCEAN_BWD_BLOCKS", 2048);
     h->fwd_tiles = env_int("OCEAN_FWD_TILES", 0);
+    h->bwd_waves = std::min(8, std::max(1, env_int("OCEAN_BWD_WAVES", 8)));
     h->quad_tail = env_int("OCEAN_QUAD_TAIL", 1);
 
     auto fail = [&](int rc) {
@@ -991,17 +994,18 @@ int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* p
 }
 
 // Cache lines carry this tag: choices written by another version of the kernels are not reused.
-static constexpr const char* kTuneCacheVersion = "ocean-tune-v3";
+static constexpr const char* kTuneCacheVersion = "ocean-tune-v4";
 
 // A cached choice is applied only if every knob is one the tuner itself could have picked for
 // this handle (a stale or hand-edited line is ignored and the shape is tuned again).
-static bool tuning_valid(const ocean_bse_s* h, int ms, int bt, int fl, int ft) {
+static bool tuning_valid(const ocean_bse_s* h, int ms, int bt, int fl, int ft, int bw) {
     const bool ms_ok = ms == 1 || ms == 2 || (ms == 4 && is_bf16_mode(h->precision));
     const bool bt_ok = bt == 1024 || bt == 2048 || bt == 4096 || bt == 8192;
     const bool fl_ok = (fl == 4 || fl == 8 || fl == 16 || fl == 32 || fl == 64) &&
                        (h->Nk == 1 || fft_lds_bytes(h, fl) <= 160 * 1024);
     const bool ft_ok = ft == 0 || ft == 4 || ft == 8 || ft == 16 || ft == 32;
-    return ms_ok && bt_ok && fl_ok && ft_ok;
+    const bool bw_ok = bw == 2 || bw == 4 || bw == 8;
+    return ms_ok && bt_ok && fl_ok && ft_ok && bw_ok;
 }
 
 // Project-written tile autotuner: times the candidate tile knobs of each kernel on this
@@ -1026,13 +1030,15 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
             while (std::fgets(line, sizeof line, f)) {
                 const char* sep = std::strchr(line, '|');
                 if (!sep || (size_t)(sep - line) != std::strlen(key) || std::strncmp(line, key, sep - line) != 0) continue;
-                int ms, bt, fl, ft;
-                if (std::sscanf(sep + 1, "%d %d %d %d", &ms, &bt, &fl, &ft) == 4 && tuning_valid(h, ms, bt, fl, ft)) {
+                int ms, bt, fl, ft, bw;
+                if (std::sscanf(sep + 1, "%d %d %d %d %d", &ms, &bt, &fl, &ft, &bw) == 5 &&
+                    tuning_valid(h, ms, bt, fl, ft, bw)) {
                     std::fclose(f);
                     h->fwd_ms = ms;
                     h->bwd_target_blocks = std::min(bt, kMaxBwdTarget);
                     h->fft_lines = fl;
                     h->fwd_tiles = ft;
+                    h->bwd_waves = bw;
                     return OCEAN_OK;
                 }
             }
@@ -1129,6 +1135,9 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
     // psi[k] of a pass fits in LDS
     if (rc == OCEAN_OK && fwd_res_lds_bytes(h, std::min(n_vec * h->Nc, cols_per_pass(h, n_vec * h->Nc))) > 0)
         sweep({0, 4, 8, 16, 32}, &h->fwd_tiles, {"proj_fwd"}, false);
+    // waves per back-projection block (smaller blocks pack the CU's registers and LDS more
+    // fully where the kernel's register count leaves room), then the grid size
+    if (rc == OCEAN_OK) sweep({8, 4, 2}, &h->bwd_waves, {"proj_bwd", "reduce_part", "combine"}, true);
     if (rc == OCEAN_OK) sweep({1024, 2048, 4096, 8192}, &h->bwd_target_blocks, {"proj_bwd", "reduce_part", "combine"}, true);
     if (rc == OCEAN_OK && h->Nk > 1) {
         std::vector<int> lines;
@@ -1144,14 +1153,16 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
     if (rc != OCEAN_OK) return rc;
     if (cache && *cache) {
         if (FILE* f = std::fopen(cache, "a")) {
-            std::fprintf(f, "%s|%d %d %d %d\n", key, h->fwd_ms, h->bwd_target_blocks, h->fft_lines, h->fwd_tiles);
+            std::fprintf(f, "%s|%d %d %d %d %d\n", key, h->fwd_ms, h->bwd_target_blocks, h->fft_lines, h->fwd_tiles,
+                         h->bwd_waves);
             std::fclose(f);
         }
     }
     return OCEAN_OK;
 }
 
-int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_lines, int* fwd_tiles) {
+int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_lines, int* fwd_tiles,
+                         int* bwd_waves) {
     if (!h) {
         set_error("ocean_bse_get_tuning: NULL handle");
         return OCEAN_ERR_INVALID_ARG;
@@ -1160,6 +1171,7 @@ int ocean_bse_get_tuning(ocean_bse_t h, int* fwd_ms, int* bwd_blocks, int* fft_l
     if (bwd_blocks) *bwd_blocks = h->bwd_target_blocks;
     if (fft_lines) *fft_lines = h->fft_lines;
     if (fwd_tiles) *fwd_tiles = h->fwd_tiles;
+    if (bwd_waves) *bwd_waves = h->bwd_waves;
     return OCEAN_OK;
 }
 

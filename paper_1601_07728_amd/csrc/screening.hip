@@ -12,9 +12,11 @@
 //   A_j = Psi diag(Re d_j) Psi^H,  B_j = Psi diag(Im d_j) Psi^H,  G_j = A_j + i B_j,
 // and G_j(r', r) = conj(A_j(r, r')) + i conj(B_j(r, r')), so that
 //   Re[G_j(r, r') G_j(r', r)] = |A_j(r, r')|^2 - |B_j(r, r')|^2.
-// One kernel computes, for a 48 x 48 tile pair (I <= J, the rest is the mirror) and one node, the
+// One kernel computes, for a 64 x 64 tile pair (I <= J, the rest is the mirror) and one node, the
 // two complex products on the FP64 matrix cores and folds |A|^2 - |B|^2 into a per-node partial;
 // G is never written.  A second kernel adds the node partials in node order and mirrors the tiles.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ocean {
@@ -22,26 +24,32 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = 48;          // rows (and complex columns) of a tile pair
-constexpr int kWaves = kTile / 16; // one wave per 16 rows, all 48 complex columns
-constexpr int kCT = 2 * kTile / 16;  // real column tiles of 16: (column, re/im) interleaved
+constexpr int kTile = 64;          // rows (and columns) of a tile pair
+constexpr int kWaves = 4;          // wave w: rows 16 w .. 16 w + 15 of the I tile, all 64 columns
 constexpr int kKS = 16;            // states per staged chunk
-constexpr int kRP = kTile + 1;     // LDS row pitch (complex) of a staged state: odd, spreads banks
+constexpr int kRP = kTile + 1;     // LDS pitch (double2) of a staged row-side state: odd, spreads banks
+constexpr int kCP = kTile + 4;     // LDS pitch (double) of one part of a staged column-side state
 
 // Block = (tile pair, node); blockIdx is renumbered so that the nodes of one tile pair run on one
 // XCD (blocks are dealt round-robin over the 8 XCDs), where they share the tiles' rows in L2.
-// Wave w: rows I + 16 w .. +15; lane l = i + 16 kq.  A real GEMM over k = (state s, part p):
-//   X[r][(s, p)] = (Re, Im) psi_s(r);  Y[(s, p)][(r', q)] = d_s M_pq(psi_s(r')) with
-//   M = [[Re, -Im], [Im, Re]] gives (Re, Im) of sum_s psi_s(r) conj(psi_s(r')) d_s for real d_s.
-// One 16x16x4 MFMA k-step covers two states (kq = 2 (state) + part).
-__global__ __launch_bounds__(64 * kWaves) void chi0_node_kernel(
+// A real GEMM over k = (state s, part p) whose rows are (r, q), q = 0 for the real and 1 for the
+// imaginary part of the result, and whose columns are the points r':
+//   X[(r, q)][(s, p)] = d_s * (q == 0 ? (Re, Im) psi_s(r) : (Im, -Re) psi_s(r))[p]
+//   Y[(s, p)][r']     = (Re, Im) psi_s(r')[p]
+// gives row (r, 0) = Re and row (r, 1) = Im of sum_s psi_s(r) conj(psi_s(r')) d_s for real d_s.
+// The structure sits on the row side, which a lane reads once per k-step for all of its column
+// tiles; the column side is a plain read of a planar (Re plane, Im plane) staged copy.
+// One 16x16x4 MFMA k-step covers two states (lane l = i + 16 kq, kq = 2 (state) + part).
+// Each wave holds 2 row tiles (16 complex rows) x 4 column tiles, for A and for B.
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))) void chi0_node_kernel(
     const double2* __restrict__ psi, const double* __restrict__ eps, int n_points, int n_states, double mu,
     const double* __restrict__ tnodes, const double* __restrict__ wnodes, int n_t, int n_tiles, int n_pairs,
     double* __restrict__ part) {
     __shared__ __align__(16) double2 sR[2][kKS][kRP];
-    __shared__ __align__(16) double2 sC[2][kKS][kRP];
+    __shared__ __align__(16) double sC[2][kKS][2][kCP];
     __shared__ double2 sD[2][kKS];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i = lane & 15, kq = lane >> 4;
     // XCD-aware numbering: block b runs on XCD b % 8; give each XCD a contiguous run of
     // (pair, node) items, node fastest
@@ -61,8 +69,8 @@ __global__ __launch_bounds__(64 * kWaves) void chi0_node_kernel(
     const int r0 = I * kTile, c0 = J * kTile;
     const double tj = tnodes[node];
 
-    // staging: element e of a chunk is psi[row][s0 + e % 16] for row e / 16 of the 96 rows (I's
-    // 48, then J's 48): 16 lanes read one row's 256 contiguous bytes.  The loads of the next
+    // staging: element e of a chunk is psi[row][s0 + e % 16] for row e / 16 of the 128 rows (I's
+    // 64, then J's 64): 16 lanes read one row's 256 contiguous bytes.  The loads of the next
     // chunk are issued before the current chunk's MFMAs and written to LDS after them.
     constexpr int PRE = 2 * kTile * kKS / (64 * kWaves);
     static_assert(PRE * 64 * kWaves == 2 * kTile * kKS, "staging split");
@@ -81,8 +89,12 @@ __global__ __launch_bounds__(64 * kWaves) void chi0_node_kernel(
         for (int m = 0; m < PRE; ++m) {
             const int e = threadIdx.x + 64 * kWaves * m;
             const int rl = e / kKS, sl = e - rl * kKS;
-            if (rl < kTile) sR[buf][sl][rl] = v[m];
-            else sC[buf][sl][rl - kTile] = v[m];
+            if (rl < kTile) {
+                sR[buf][sl][rl] = v[m];
+            } else {
+                sC[buf][sl][0][rl - kTile] = v[m].x;
+                sC[buf][sl][1][rl - kTile] = v[m].y;
+            }
         }
         if (threadIdx.x < kKS) {
             const int s = s0 + threadIdx.x;
@@ -97,58 +109,83 @@ __global__ __launch_bounds__(64 * kWaves) void chi0_node_kernel(
         }
     };
 
-    v4d accA[kCT], accB[kCT];
-#pragma unroll
-    for (int t = 0; t < kCT; ++t) accA[t] = accB[t] = v4d{0, 0, 0, 0};
     const int p = kq & 1;              // part of the k index this lane holds
-    const int q = i & 1;               // re/im of the output column this lane holds (B operand)
-    const int rloc = wave * 16 + i;    // A operand row within the tile
-    // M_pq: the component of psi_s(r') and its sign
-    const bool take_re = p == q;
-    const double sgn = (p == 0 && q == 1) ? -1.0 : 1.0;
+    const int q = i & 1;               // re/im row of the A operand this lane holds
+    const bool take_re = p == q;       // X[(r, q)][(s, p)] is +-Re psi when p == q, else Im psi
+    const double sgn = (p & q) ? -1.0 : 1.0;
+    // row tiles and column tiles that hold points (the last tile of the grid is ragged); the
+    // counts are wave-uniform, so the guards below are scalar branches
+    const int rows_left = n_points - (r0 + 16 * wave);
+    const int n_rt = rows_left <= 0 ? 0 : (rows_left > 8 ? 2 : 1);
+    const int n_ct = min(4, (n_points - c0 + 15) / 16);
+    const bool full = n_rt == 2 && n_ct == 4;
 
-    const int n_chunks = (n_states + kKS - 1) / kKS;
-    double2 pre[PRE];
-    load(0, pre);
-    store(0, 0, pre);
-    __syncthreads();
-    for (int ch = 0; ch < n_chunks; ++ch) {
-        const int buf = ch & 1;
-        const bool more = ch + 1 < n_chunks;
-        if (more) load((ch + 1) * kKS, pre);
+    // the whole contraction and epilogue, instantiated twice so that the full tiles run without
+    // guards and each instance gets its own register allocation
+    auto run = [&](auto guard_tag) {
+        constexpr bool guard = decltype(guard_tag)::value;
+        v4d accA[2][4], accB[2][4];
 #pragma unroll
-        for (int ks = 0; ks < kKS / 2; ++ks) {
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) accA[rt][ct] = accB[rt][ct] = v4d{0, 0, 0, 0};
+        auto kstep = [&](int buf, int ks) {
             const int sl = 2 * ks + (kq >> 1);
-            const double2 x = sR[buf][sl][rloc];
-            const double a = p ? x.y : x.x;
             const double2 d = sD[buf][sl];
             const double wa = sgn * d.x, wb = sgn * d.y;
+            double ya[4];
 #pragma unroll
-            for (int t = 0; t < kCT; ++t) {
-                const double2 y = sC[buf][sl][8 * t + (i >> 1)];
-                const double m = take_re ? y.x : y.y;
-                accA[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, wa * m, accA[t], 0, 0, 0);
-                accB[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, wb * m, accB[t], 0, 0, 0);
+            for (int ct = 0; ct < 4; ++ct) ya[ct] = sC[buf][sl][p][16 * ct + i];
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                if (guard && rt >= n_rt) continue;
+                const double2 x = sR[buf][sl][16 * wave + 8 * rt + (i >> 1)];
+                const double v = take_re ? x.x : x.y;
+                const double xa = v * wa, xb = v * wb;
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    if (guard && ct >= n_ct) continue;
+                    accA[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, ya[ct], accA[rt][ct], 0, 0, 0);
+                    accB[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb, ya[ct], accB[rt][ct], 0, 0, 0);
+                }
             }
-        }
-        if (more) store(buf ^ 1, (ch + 1) * kKS, pre);
-        __syncthreads();
-    }
+        };
 
-    // |A|^2 - |B|^2 of each complex element: lane (i, kq) register r holds row 4 r + kq and real
-    // column 16 t + i = (column 8 t + i / 2, re/im i % 2); the partner lane i ^ 1 holds the other part
-    const double c = wnodes[node] * 0.31830988618379067154;   // w_j / pi
-    double* out = part + (size_t)node * n_points * n_points;
+        const int n_chunks = (n_states + kKS - 1) / kKS;
+        double2 pre[PRE];
+        load(0, pre);
+        store(0, 0, pre);
+        __syncthreads();
+        for (int ch = 0; ch < n_chunks; ++ch) {
+            const int buf = ch & 1;
+            const bool more = ch + 1 < n_chunks;
+            if (more) load((ch + 1) * kKS, pre);
 #pragma unroll
-    for (int t = 0; t < kCT; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const double v = accA[t][r] * accA[t][r] - accB[t][r] * accB[t][r];
-            const double both = v + __shfl_xor(v, 1);
-            const int row = r0 + wave * 16 + 4 * r + kq;
-            const int col = c0 + 8 * t + (i >> 1);
-            if (q == 0 && row < n_points && col < n_points) out[(size_t)row * n_points + col] = c * both;
+            for (int ks = 0; ks < kKS / 2; ++ks) kstep(buf, ks);
+            if (more) store(buf ^ 1, (ch + 1) * kKS, pre);
+            __syncthreads();
         }
+
+        // |A|^2 - |B|^2 of each complex element: lane (i, kq) register r of tile (rt, ct) holds real
+        // row 4 r + kq of the row tile, i.e. point 8 rt + 2 r + kq / 2 of the wave's rows, part kq % 2,
+        // and column 16 ct + i; the partner lane kq ^ 1 (lane ^ 16) holds the other part
+        const double c = wnodes[node] * 0.31830988618379067154;   // w_j / pi
+        double* out = part + (size_t)node * n_points * n_points;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double v = accA[rt][ct][r] * accA[rt][ct][r] - accB[rt][ct][r] * accB[rt][ct][r];
+                    const double both = v + __shfl_xor(v, 16);
+                    const int row = r0 + 16 * wave + 8 * rt + 2 * r + (kq >> 1);
+                    const int col = c0 + 16 * ct + i;
+                    if ((kq & 1) == 0 && row < n_points && col < n_points) out[(size_t)row * n_points + col] = c * both;
+                }
+    };
+    if (full) run(std::false_type{});
+    else run(std::true_type{});
 }
 
 // chi0[r][r'] = sum over nodes of the partials, in node order; each element reads the upper

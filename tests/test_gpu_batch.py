@@ -116,7 +116,7 @@ def test_every_tuning_candidate_gives_the_same_result(tmp_path, monkeypatch, pre
     x = synth.complex_gaussian(np.random.default_rng(5), (3, cr.n_k, cr.n_bands, cr.n_core))
     refs = [orc.apply_h(cr, x[v], hc, kl) for v in range(3)]
     prec_id = {"fp64": ob.PREC_FP64, "bf16": ob.PREC_BF16}[precision]
-    key = (f"ocean-tune-v3 nk=4,4,4 nx=10,9,8 nb={cr.n_bands} nc={cr.n_core} nmu=5 prec={prec_id} "
+    key = (f"ocean-tune-v4 nk=4,4,4 nx=10,9,8 nb={cr.n_bands} nc={cr.n_core} nmu=5 prec={prec_id} "
            f"cols={3 * cr.n_core}")
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("OCEAN_AUTOTUNE_CACHE", str(cache))
@@ -126,18 +126,25 @@ def test_every_tuning_candidate_gives_the_same_result(tmp_path, monkeypatch, pre
     fwd = [(ms, 0) for ms in ((1, 2, 4) if precision == "bf16" else (1, 2))]
     if precision == "fp64":
         fwd += [(1, ft) for ft in (4, 8, 16, 32)]
+    # every back-projection grid target with every wave cap (37 bands: blocks of 3 waves, or 2
+    # and 1); the transform's lines cycle through their candidates meanwhile
+    lines = (4, 8, 16, 32, 64)
+    n = 0
     for ms, ft in fwd:
         for bt in (1024, 2048, 4096, 8192):
-            for fl in (4, 8, 16, 32, 64):
-                cache.write_text(f"{key}|{ms} {bt} {fl} {ft}\n")
+            for bw in (8, 4, 2):
+                fl = lines[n % len(lines)]
+                n += 1
+                cache.write_text(f"{key}|{ms} {bt} {fl} {ft} {bw}\n")
                 h = ob.Bse.from_crystal(cr, precision=precision)
-                assert h.autotune(n_vec=3) == {"fwd_ms": ms, "bwd_blocks": bt, "fft_lines": fl, "fwd_tiles": ft}
+                assert h.autotune(n_vec=3) == {"fwd_ms": ms, "bwd_blocks": bt, "fft_lines": fl, "fwd_tiles": ft,
+                                               "bwd_waves": bw}
                 y = h.apply(xd).cpu().numpy()
                 h.close()
                 for v in range(3):
                     err = float(np.abs(y[v] - refs[v]).max() / np.abs(refs[v]).max())
-                    assert err <= tol, (ms, ft, bt, fl, v, err)
+                    assert err <= tol, (ms, ft, bt, fl, bw, v, err)
                 if first is None:
                     first = y
                 elif precision == "fp64":
-                    assert np.abs(y - first).max() <= 1e-13 * np.abs(first).max(), (ms, ft, bt, fl)
+                    assert np.abs(y - first).max() <= 1e-13 * np.abs(first).max(), (ms, ft, bt, fl, bw)

@@ -74,8 +74,8 @@ def test_profiling_times_every_kernel_and_changes_nothing():
         assert ms > 0.0 and count == 12, (name, ms, count)
 
 
-@pytest.mark.parametrize("bad", ["0 0 0 0", "3 2048 16 0", "1 777 16 0", "1 2048 0 0", "2 1024 48 0", "1 2048 128 0",
-                                 "1 2048 16 5", "1 2048 16"])
+@pytest.mark.parametrize("bad", ["0 0 0 0 8", "3 2048 16 0 8", "1 777 16 0 8", "1 2048 0 0 8", "2 1024 48 0 8",
+                                 "1 2048 128 0 8", "1 2048 16 5 8", "1 2048 16 0 3", "1 2048 16 0 0", "1 2048 16 0"])
 def test_corrupt_autotune_cache_line_is_tuned_again(monkeypatch, tmp_path, bad):
     """A cached tile choice that the tuner could not have made (zero or odd knobs, lines past
     the transform's 160 KiB LDS budget) is ignored: the shape is tuned again, the new choice is
@@ -86,23 +86,24 @@ def test_corrupt_autotune_cache_line_is_tuned_again(monkeypatch, tmp_path, bad):
     h = ob.Bse.from_crystal(cr, precision="fp64")
     p0 = h.dipole_psi0(np.eye(3))
     y0 = h.apply(p0).cpu().numpy()
-    key = f"ocean-tune-v3 nk=2,2,2 nx=6,5,6 nb=13 nc=6 nmu=5 prec=0 cols={3 * cr.n_core}"
+    key = f"ocean-tune-v4 nk=2,2,2 nx=6,5,6 nb=13 nc=6 nmu=5 prec=0 cols={3 * cr.n_core}"
     cache = tmp_path / "tune.txt"
     cache.write_text(f"{key}|{bad}\n")
     monkeypatch.setenv("OCEAN_AUTOTUNE_CACHE", str(cache))
     h.autotune(3, reps=2)
     t = h.tuning
-    ms, bt, fl, ft = t["fwd_ms"], t["bwd_blocks"], t["fft_lines"], t["fwd_tiles"]
+    ms, bt, fl, ft, bw = t["fwd_ms"], t["bwd_blocks"], t["fft_lines"], t["fwd_tiles"], t["bwd_waves"]
     assert ms in (1, 2) and bt in (1024, 2048, 4096, 8192) and fl in (4, 8, 16, 32, 64) and ft in (0, 4, 8, 16, 32)
+    assert bw in (2, 4, 8)
     lines = cache.read_text().splitlines()
-    assert len(lines) == 2 and lines[1] == f"{key}|{ms} {bt} {fl} {ft}"
+    assert len(lines) == 2 and lines[1] == f"{key}|{ms} {bt} {fl} {ft} {bw}"
     y1 = h.apply(p0).cpu().numpy()
     assert np.abs(y1 - y0).max() <= 1e-13 * np.abs(y0).max()
     # a valid line is reused as it stands
     h2 = ob.Bse.from_crystal(cr, precision="fp64")
-    cache.write_text(f"{key}|2 4096 8 16\n")
+    cache.write_text(f"{key}|2 4096 8 16 4\n")
     h2.autotune(3, reps=2)
-    assert h2.tuning == {"fwd_ms": 2, "bwd_blocks": 4096, "fft_lines": 8, "fwd_tiles": 16}
+    assert h2.tuning == {"fwd_ms": 2, "bwd_blocks": 4096, "fft_lines": 8, "fwd_tiles": 16, "bwd_waves": 4}
     torch.cuda.synchronize()
     h.close()
     h2.close()
