@@ -449,12 +449,19 @@ long long ocean_bse_device_bytes(ocean_bse_t h);
  * B_j tile by tile (upper-triangle tile pairs) and accumulates that expression; G_j is never stored.
  * Node partials are added in node order, so results are bitwise reproducible.
  * stream: hipStream_t or NULL for the default stream; the call returns after the work has
- * finished.  Allocates n_t * n_points^2 doubles of device scratch (the node partials).
+ * finished.  Uses n_t * n_points^2 + n_states + 2 n_t doubles of device scratch (the node
+ * partials), allocated on the current device at the first call that needs that much and kept
+ * between calls until ocean_screening_release; calls are serialised by the library (they share
+ * the scratch).
  * Errors: INVALID_ARG (NULL, sizes < 1, non-finite input, negative node), OUT_OF_MEMORY,
  * DEVICE. */
 int ocean_screening_chi0(const double* psi_dev, const double* eps, int n_points, int n_states,
                          double mu, const double* t, const double* w, int n_t, double* chi0_dev,
                          void* stream);
+
+/* Free the device scratch that ocean_screening_chi0 keeps between calls, on every device that
+ * holds one.  The next build allocates it again.  Errors: DEVICE. */
+int ocean_screening_release(void);
 
 /* Measured ceilings of the current device, for the roofline of the projections of
  * Algorithm 1 (section 3.2.1), which issue FP64 matrix-core instructions, FP64 multiply-adds

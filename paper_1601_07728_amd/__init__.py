@@ -49,7 +49,7 @@ EXPORTED = [
     "ocean_mlp_param_count", "ocean_mlp_create", "ocean_mlp_destroy", "ocean_mlp_set_params",
     "ocean_mlp_get_params", "ocean_mlp_encode", "ocean_mlp_forward", "ocean_mlp_loss_grad",
     "ocean_mlp_train_step", "ocean_mlp_predict", "ocean_mlp_save", "ocean_mlp_load",
-    "ocean_device_ceilings", "ocean_screening_chi0", "ocean_local_matrix_channels",
+    "ocean_device_ceilings", "ocean_screening_chi0", "ocean_screening_release", "ocean_local_matrix_channels",
     "ocean_dipole_amplitudes_channels", "ocean_dipole_psi0_channels", "ocean_nrixs_amplitudes_channels",
     "ocean_quadrupole_amplitudes_channels", "ocean_psi0_amplitudes", "ocean_haydock_export",
     "ocean_haydock_continue", "ocean_mlp_predict_noalloc", "ocean_mlp_set_loss_weights",
@@ -124,6 +124,8 @@ def lib() -> ctypes.CDLL:
     L.ocean_device_ceilings.restype = ci
     L.ocean_screening_chi0.argtypes = [vp, vp, ci, ci, cd, vp, vp, ci, vp, vp]
     L.ocean_screening_chi0.restype = ci
+    L.ocean_screening_release.argtypes = []
+    L.ocean_screening_release.restype = ci
     L.ocean_bse_apply.argtypes = [vp, vp, vp, ci]
     L.ocean_bse_apply.restype = ci
     L.ocean_haydock.argtypes = [vp, vp, ci, ci, cu, vp, vp, vp, vp]
@@ -337,6 +339,12 @@ def screening_chi0(psi, eps, mu: float, t, w, out=None):
     _check(lib().ocean_screening_chi0(_dev_ptr(psi), _ptr(e), npt, ns, float(mu), _ptr(tt), _ptr(ww), len(tt),
                                       ctypes.c_void_p(out.data_ptr()), None))
     return out
+
+
+def screening_release():
+    """Free the device scratch the response build keeps between calls
+    (ocean_screening_release)."""
+    _check(lib().ocean_screening_release())
 
 
 def spectrum(a, b, norm2, omega, gamma: float, terminator: str = "none", n_used=None, a_inf=None,

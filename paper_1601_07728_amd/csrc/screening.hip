@@ -15,6 +15,8 @@
 // One kernel computes, for a 64 x 64 tile pair (I <= J, the rest is the mirror) and one node, the
 // two complex products on the FP64 matrix cores and folds |A|^2 - |B|^2 into a per-node partial;
 // G is never written.  A second kernel adds the node partials in node order and mirrors the tiles.
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
     const double* __restrict__ tnodes, const double* __restrict__ wnodes, int n_t, int n_tiles, int n_pairs,
     double* __restrict__ part) {
     __shared__ __align__(16) double2 sR[2][kKS][kRP];
-    __shared__ __align__(16) double sC[2][kKS][2][kCP];
+    __shared__ __align__(16) double sC[2][kKS][2 * kCP + 1];
     __shared__ double2 sD[2][kKS];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
             const int rl = e / kKS, sl = e - rl * kKS;
             const int rg = rl < kTile ? r0 + rl : c0 + rl - kTile;
             const int s = s0 + sl;
-            v[m] = (rg < n_points && s < n_states) ? psi[(size_t)rg * n_states + s] : make_double2(0.0, 0.0);
+            v[m] = psi[(size_t)min(rg, n_points - 1) * n_states + min(s, n_states - 1)];
         }
     };
     auto store = [&](int buf, int s0, const double2 (&v)[PRE]) {
@@ -92,8 +94,8 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
             if (rl < kTile) {
                 sR[buf][sl][rl] = v[m];
             } else {
-                sC[buf][sl][0][rl - kTile] = v[m].x;
-                sC[buf][sl][1][rl - kTile] = v[m].y;
+                sC[buf][sl][rl - kTile] = v[m].x;
+                sC[buf][sl][kCP + rl - kTile] = v[m].y;
             }
         }
         if (threadIdx.x < kKS) {
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
             const double wa = sgn * d.x, wb = sgn * d.y;
             double ya[4];
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) ya[ct] = sC[buf][sl][p][16 * ct + i];
+            for (int ct = 0; ct < 4; ++ct) ya[ct] = sC[buf][sl][p * kCP + 16 * ct + i];
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt) {
                 if (guard && rt >= n_rt) continue;
@@ -205,6 +207,17 @@ __global__ __launch_bounds__(256) void chi0_sum_kernel(const double* __restrict_
     }
 }
 
+// Device scratch of the response build (the node partials, then the energies, nodes and
+// weights), kept per device between calls and grown on demand, so that repeated builds do not
+// pay an allocation and a free each; ocean_screening_release gives it back.  The mutex also
+// serialises the builds, which share it.
+struct ScreeningScratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_scratch_mu;
+std::map<int, ScreeningScratch> g_scratch;   // by device
+
 }  // namespace
 }  // namespace ocean
 
@@ -235,20 +248,37 @@ extern "C" int ocean_screening_chi0(const double* psi_dev, const double* eps, in
         return OCEAN_ERR_INVALID_ARG;
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    double* part = nullptr;
-    double* dev = nullptr;   // eps [n_states], t [n_t], w [n_t]
     int rc = OCEAN_OK;
     auto fail = [&](int code, const std::string& what) {
         (void)hipGetLastError();
         set_error("ocean_screening_chi0: " + what);
         rc = code;
     };
-    if (hipMalloc((void**)&part, (size_t)n2 * n_t * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&dev, ((size_t)n_states + 2 * (size_t)n_t) * sizeof(double)) != hipSuccess)
-        fail(OCEAN_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) {
+        fail(OCEAN_ERR_DEVICE, "hipGetDevice failed");
+        return rc;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScreeningScratch& ws = g_scratch[device];
+    const size_t need = ((size_t)n2 * n_t + (size_t)n_states + 2 * (size_t)n_t) * sizeof(double);
+    if (ws.bytes < need) {
+        // the previous build on this device synchronised its stream before returning
+        if (ws.ptr) (void)hipFree(ws.ptr);
+        ws.ptr = nullptr;
+        ws.bytes = 0;
+        if (hipMalloc(&ws.ptr, need) != hipSuccess) {
+            ws.ptr = nullptr;
+            fail(OCEAN_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+            return rc;
+        }
+        ws.bytes = need;
+    }
+    double* part = static_cast<double*>(ws.ptr);   // [n_t][n_points][n_points]
+    double* dev = part + (size_t)n2 * n_t;         // eps [n_states], t [n_t], w [n_t]
     double* eps_dev = dev;
-    double* t_dev = dev ? dev + n_states : nullptr;
-    double* w_dev = dev ? t_dev + n_t : nullptr;
+    double* t_dev = dev + n_states;
+    double* w_dev = t_dev + n_t;
     if (rc == OCEAN_OK &&
         (hipMemcpyAsync(eps_dev, eps, (size_t)n_states * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
          hipMemcpyAsync(t_dev, t, (size_t)n_t * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -269,7 +299,24 @@ extern "C" int ocean_screening_chi0(const double* psi_dev, const double* eps, in
         if (hipGetLastError() != hipSuccess) fail(OCEAN_ERR_DEVICE, "sum launch");
     }
     if (rc == OCEAN_OK && hipStreamSynchronize(st) != hipSuccess) fail(OCEAN_ERR_DEVICE, "synchronize");
-    if (part) (void)hipFree(part);
-    if (dev) (void)hipFree(dev);
+    return rc;
+}
+
+extern "C" int ocean_screening_release(void) {
+    set_error("");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    int current = 0;
+    const bool have_current = hipGetDevice(&current) == hipSuccess;
+    int rc = OCEAN_OK;
+    for (auto& kv : g_scratch) {
+        if (!kv.second.ptr) continue;
+        if (hipSetDevice(kv.first) != hipSuccess || hipFree(kv.second.ptr) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("ocean_screening_release: hipFree failed");
+            rc = OCEAN_ERR_DEVICE;
+        }
+    }
+    g_scratch.clear();
+    if (have_current) (void)hipSetDevice(current);
     return rc;
 }

@@ -62,3 +62,22 @@ def test_chi0_full_grid_samples_and_properties():
     assert np.abs(c - c.T).max() <= 1e-13 * scale
     ev = torch.linalg.eigvalsh(chi).cpu().numpy()
     assert ev.max() <= 1e-12 * scale
+
+
+def test_kept_scratch_serves_builds_of_any_size_and_release():
+    """The device scratch kept between builds: a large build, a smaller one (the kept buffer
+    is larger than needed), a larger one again (it grows), then a release and a build that
+    allocates afresh; each against the oracle."""
+    import paper_1601_07728_amd as ob
+    cases = [(150, 300, 100, 32), (33, 17, 5, 8), (200, 420, 150, 40), (33, 17, 5, 8)]
+    for k, (n_points, n_states, n_occ, n_t) in enumerate(cases):
+        if k == 3:
+            ob.screening_release()
+        _say(f"[screening scratch] build {k}: n_points={n_points} n_states={n_states} n_t={n_t}")
+        psi, eps, mu, t, w = synth.screening_inputs(seed=31 + k, n_points=n_points, n_states=n_states,
+                                                    n_occ=n_occ, n_t=n_t)
+        got = _run(psi, eps, mu, t, w)
+        ref = sc.chi0_imaginary_axis(psi, eps, mu, t, w)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    ob.screening_release()
+    ob.screening_release()   # nothing held: a no-op
