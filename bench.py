@@ -186,6 +186,38 @@ def bench_screening(ob, seed, ceilings, reps=3, n_points=900, n_states=16384, n_
                          "frac_of_measured_mfma": tf / ceilings["mfma_f64_tflops"]}}
 
 
+def bench_xes(ob, seed, steps=200, reps=3):
+    """K-edge emission of an Alq3-sized site (30 bohr box, Gamma point, 48^3 grid, the 81
+    occupied bands on [-25, 0] eV, three amplitude vectors): the absorption path run over the
+    occupied window.  FP64 and BF16, one 200-step recursion of the three vectors per solve."""
+    import torch
+    import synth
+    t0 = time.time()
+    cr = synth.xes_site(seed=seed + 2)
+    log(f"xes site: {cr.n_x} points, {cr.n_bands} occupied bands, drawn in {time.time() - t0:.1f} s")
+    p0 = torch.from_numpy(np.ascontiguousarray(cr.psi0)).to("cuda")
+    out, sig = {}, {}
+    for prec in ("fp64", "bf16"):
+        h = ob.Bse.from_crystal(cr, precision=prec)
+        h.autotune(n_vec=3)
+        h.haydock(p0, steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            a, b, n2, sd, _ = h.haydock(p0, steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        h.close()
+        sig[prec] = ob.spectrum(a, b, n2, cr.omega, cr.gamma, n_used=sd)
+        out[prec] = {"ms_per_step": dt / steps * 1e3, "hv_per_s": 3 * steps / dt, "spectra_per_s": 3 / dt}
+        log(f"xes {prec}: {steps} steps x 3 vectors in {dt * 1e3:.1f} ms ({3 * steps / dt:.0f} H*v/s)")
+    out["bf16"]["spectrum_l1_vs_fp64"] = float(np.mean(
+        [np.sum(np.abs(sig["bf16"][v] - sig["fp64"][v])) / np.sum(np.abs(sig["fp64"][v])) for v in range(3)]))
+    out["workload"] = (f"K-edge emission (XES) of an Alq3-sized site: 30 bohr box, Gamma point, 48^3 grid, "
+                       f"{cr.n_bands} occupied bands on [-25, 0] eV, 2 core states, 3 vectors, {steps} steps")
+    return out
+
+
 def bench_batched(ob, seed, steps=200):
     """Molecule in a box: 40 sites (K and L2,3 edges), 3 polarisations each, uneven band
     windows, Gamma point on a 48^3 grid; all 120 solves advance together, one HIP graph per
@@ -446,6 +478,7 @@ def main():
     ap.add_argument("--no-full-basis", action="store_true")
     ap.add_argument("--no-supercell", action="store_true")
     ap.add_argument("--no-paper-shape", action="store_true")
+    ap.add_argument("--no-xes", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first stream 1 GiB through a plain elementwise kernel (1 GiB read, 1 GiB "
                          "written): the reference for scaling the HBM byte counters")
@@ -607,6 +640,7 @@ def main():
     for h in hs.values():
         h.close()
     screening = None if args.no_screening else bench_screening(ob, args.seed, ceilings)
+    xes = None if args.no_xes else bench_xes(ob, args.seed)
     if not args.no_batched:
         batched = bench_batched(ob, args.seed)
     supercell = None if args.no_supercell else bench_supercell(ob, args.seed)
@@ -639,6 +673,7 @@ def main():
         "batched": batched,
         "full_spin": full_spin,
         "screening": screening,
+        "xes": xes,
         "full_local_basis": full_basis,
         "supercell": supercell,
         "roofline_supercell": None if supercell is None else supercell["roofline"],

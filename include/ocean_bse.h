@@ -103,7 +103,11 @@ typedef struct {
                              cancels in W0 (only k - k' enters), so u_nk and E_nk at the offset
                              points are all that changes. */
     double tau[3];        /* absorbing-site position, bohr */
-    const double* energies;   /* [Nk][Nb] real, Ha: H_e eigenvalues E_nk (section 2) */
+    const double* energies;   /* [Nk][Nb] real, Ha: H_e eigenvalues E_nk (section 2) of the band
+                                 window.  Absorption passes the unoccupied bands; emission
+                                 (XES) passes the occupied bands, energies below the Fermi
+                                 level, with the same operator (the lines then sit at
+                                 E_nk - E_c, E_c = 0). */
     const double* u;          /* [Nk][Nx][Nb] complex: periodic Bloch parts u_nk(x), columns
                                  orthonormal per k (sum_x |u|^2 = 1).  Host pointer, or a
                                  device pointer with OCEAN_FLAG_BORROW_DEVICE_U. */

@@ -127,13 +127,14 @@ def make_crystal(name: str, *, a: float, tau, nk, nx, n_bands: int, n_core: int,
                  multiplet_ev: Optional[dict] = None, psi0: str = "random",
                  n_vec: int = 1, polarisations=None, n_steps: int = 100,
                  gamma_ev: float = 0.5, omega_ev=(-20.0, 40.0), n_omega: int = 2000,
-                 u_override: Optional[np.ndarray] = None) -> Crystal:
-    """Draw one synthetic crystal.  Draw order: E, then U per k (real then
-    imaginary parts), then psi0 amplitudes, then the local projectors A."""
+                 u_override: Optional[np.ndarray] = None, e_min_ev: float = 0.0) -> Crystal:
+    """Draw one synthetic crystal.  Draw order: E (uniform on [e_min, e_min + e_range] eV),
+    then U per k (real then imaginary parts), then psi0 amplitudes, then the local
+    projectors A."""
     rng = np.random.default_rng(seed)
     n_k = int(np.prod(nk))
     n_x = int(np.prod(nx))
-    energies = np.sort(rng.uniform(0.0, e_range_ev, size=(n_k, n_bands)), axis=1) / HARTREE_EV
+    energies = np.sort(rng.uniform(e_min_ev, e_min_ev + e_range_ev, size=(n_k, n_bands)), axis=1) / HARTREE_EV
     if isinstance(u_override, str) and u_override == "skip":
         u = None          # generated elsewhere (e.g. on the device); no host draw
     elif u_override is not None:
@@ -332,6 +333,19 @@ def molecule_sites(seed: int = 0, n_atoms: int = 52, n_sites: int = 40, box: flo
             u = gpu_orthonormal_u(1, grid ** 3, nb, seed=site_seed)
         sites.append((cr, u))
     return sites
+
+
+def xes_site(seed: int = 0, n_occ: int = 81, box: float = 30.0, grid: int = 48, width_ev: float = 25.0,
+             eps: float = 4.0, n_steps: int = 200, u_override=None) -> Crystal:
+    """One K-edge emission (XES) site of an Alq3-sized molecule in a periodic box (Gamma point
+    only): the band window is the occupied valence manifold, n_occ bands (81 = half of Alq3's
+    162 valence electrons) with energies uniform on [-width, 0] eV below the Fermi level, 2
+    core states (1s), no local term, three complex-normal amplitude vectors (one per
+    polarisation), the site at the box centre.  The emission lines sit at E_v - E_c <= 0."""
+    return make_crystal(f"xes{seed}-K", a=box, tau=(box / 2, box / 2, box / 2), nk=(1, 1, 1), nx=(grid,) * 3,
+                        n_bands=n_occ, n_core=2, e_range_ev=width_ev, e_min_ev=-width_ev, eps=eps, seed=seed,
+                        psi0="random", n_vec=3, n_steps=n_steps, omega_ev=(-width_ev - 12.0, 12.0),
+                        u_override=u_override)
 
 
 def terminator_params(seed: int) -> tuple[float, float]:
