@@ -533,11 +533,16 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     __shared__ __align__(16) C2 sP[R][TILE];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
-    int blk = blockIdx.x;
-    const int s = blk % S;
-    blk /= S;
-    const int bb = blk % band_blocks;
-    const int k = blk / band_blocks;
+    // XCD-aware numbering: block b runs on XCD b % 8; each XCD takes a contiguous run of
+    // (k, x chunk, band block) items, band block fastest, so that the band blocks reading the
+    // same phi' tiles run together on one XCD and share them in its L2
+    const int total = Nk * band_blocks * S;
+    const int per_xcd = (total + 7) / 8;
+    const int item = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    if (item >= total) return;   // the whole block, before any barrier
+    const int bb = item % band_blocks;
+    const int s = (item / band_blocks) % S;
+    const int k = item / (band_blocks * S);
     const int nbase = bb * 16 * W + 16 * wave;
     const int x_begin = s * chunk;
     const int x_end = min(Nx, x_begin + chunk);
@@ -966,7 +971,7 @@ hipError_t launch_proj_bwd(ocean_bse_s* h, int nv, int col0, int ncb) {
     int bb, S, chunk;
     bwd_geometry(h, &bb, &S, &chunk);
     const int W = bwd_waves(h);
-    dim3 grid((unsigned)((long long)h->Nk * bb * S));
+    dim3 grid((unsigned)(((long long)h->Nk * bb * S + 7) / 8 * 8));   // 8 XCDs, whole rounds
     const int slot = prof_begin(h, "proj_bwd");
     hipError_t e;
     if (h->precision == OCEAN_PREC_FP64)
