@@ -73,33 +73,33 @@ def proj_bytes(cr, cols, u_elem, phi_elem):
 
 
 # HBM bytes per launch at this workload (three polarisations, autotuned tiles), from two
-# rocprofv3 --pmc passes over `bench.py --copy-calibration --steps 3 --warmup 1
-# --no-cpu-baseline --no-batched --no-terminator --no-spectra`: FETCH_SIZE and WRITE_SIZE
+# rocprofv3 --pmc passes over `bench.py --copy-calibration --steps 3 --warmup 1` with every
+# optional section off (the commands are in profiles/hv_srtio3_l23_hbm_traffic.md): FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch, mean over the dispatches of the kernel), each scaled by the counter's
 # reading for the 1 GiB calibration kernel (FETCH_SIZE reads 0.5 GiB for 1 GiB read,
 # WRITE_SIZE 1.0 GiB for 1 GiB written).  A figure holds only for the kernel source it was
 # taken with (sha256 of the .hip file); for any other source the traffic is reported null.
 TRAFFIC = {
-    ("fp64", "proj_fwd"): {"bytes": 7588385450, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 2, 2, 16, 24>
-        "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
-    ("fp64", "proj_bwd"): {"bytes": 7547771731, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 16, 3, 6, 24>
-        "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
-    ("fp32", "proj_fwd"): {"bytes": 3849504435, "src": "proj.hip",  # proj_fwd_kernel<float, 1, 3, 0, 32, 24>
-        "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
-    ("fp32", "proj_bwd"): {"bytes": 3788065380, "src": "proj.hip",  # proj_bwd_kernel<float, 3, 0, 32, 3, 6, 24>
-        "sha256": "1b275749b1ff71b2ae8cf2de607c47595f100c7ea048e115585e549abd7441d9"},
-    ("split_bf16", "proj_fwd"): {"bytes": 3855217262, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<4, 3, true>
-        "sha256": "bc329187f81262ffe42d7523be8761ce4b4234907f4abd4102886b6960e1a2a6"},
-    ("split_bf16", "proj_bwd"): {"bytes": 3809242797, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
-        "sha256": "bc329187f81262ffe42d7523be8761ce4b4234907f4abd4102886b6960e1a2a6"},
-    ("bf16", "proj_fwd"): {"bytes": 2189376719, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<4, 3, false>
-        "sha256": "bc329187f81262ffe42d7523be8761ce4b4234907f4abd4102886b6960e1a2a6"},
-    ("bf16", "proj_bwd"): {"bytes": 2225063332, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
-        "sha256": "bc329187f81262ffe42d7523be8761ce4b4234907f4abd4102886b6960e1a2a6"},
-    ("fp64", "fft_w"): {"bytes": 2392659438, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
+    ("bf16", "proj_bwd"): {"bytes": 2300632530, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 3, false>
+        "sha256": "9462ca3a0a39bbf9f538bababb5c2ac93bee2124bccb9d9ca6364c9413d99b33"},
+    ("bf16", "proj_fwd"): {"bytes": 2189216184, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<4, 3, false>
+        "sha256": "9462ca3a0a39bbf9f538bababb5c2ac93bee2124bccb9d9ca6364c9413d99b33"},
+    ("fp32", "fft_w"): {"bytes": 1196250390, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
         "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
-    ("fp32", "fft_w"): {"bytes": 1196253945, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
+    ("fp32", "proj_bwd"): {"bytes": 3802232037, "src": "proj.hip",  # proj_bwd_kernel<float, 2, 0, 1, 32, 3, 3, 24>
+        "sha256": "ae1ef4e58f60d61199cd91ce28a0ef65a66b1e520fcd15ec4a5c7287748537be"},
+    ("fp32", "proj_fwd"): {"bytes": 3859524621, "src": "proj.hip",  # proj_fwd_res_kernel<float, 2, 0, 1, 32, 24, 8>
+        "sha256": "ae1ef4e58f60d61199cd91ce28a0ef65a66b1e520fcd15ec4a5c7287748537be"},
+    ("fp64", "fft_w"): {"bytes": 2392651970, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
         "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
+    ("fp64", "proj_bwd"): {"bytes": 7668325887, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 0, 16, 3, 3, 24>
+        "sha256": "ae1ef4e58f60d61199cd91ce28a0ef65a66b1e520fcd15ec4a5c7287748537be"},
+    ("fp64", "proj_fwd"): {"bytes": 7588221962, "src": "proj.hip",  # proj_fwd_kernel<double, 1, 2, 2, 16, 24>
+        "sha256": "ae1ef4e58f60d61199cd91ce28a0ef65a66b1e520fcd15ec4a5c7287748537be"},
+    ("split_bf16", "proj_bwd"): {"bytes": 3826299942, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 3, true>
+        "sha256": "9462ca3a0a39bbf9f538bababb5c2ac93bee2124bccb9d9ca6364c9413d99b33"},
+    ("split_bf16", "proj_fwd"): {"bytes": 3854362425, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<4, 3, true>
+        "sha256": "9462ca3a0a39bbf9f538bababb5c2ac93bee2124bccb9d9ca6364c9413d99b33"},
 }
 
 
