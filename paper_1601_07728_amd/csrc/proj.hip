@@ -302,10 +302,10 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 // band counts, such as 96 bands at the SrTiO3-shaped workload), a block stages psi[k] once, in
 // the MFMA order above, and then streams u for `tiles` consecutive tiles of 16 * WAVES rows of
 // that k.  Each wave owns 16 rows of every tile and walks its (tile, band chunk) items as one
-// continuous pipeline: the u loads of the next item (the next chunk, or the first chunk of the
-// next tile) are in flight while the current one is contracted.  After the staging there is no
-// barrier, and a block starts once per `tiles` tiles instead of once per tile.
-template <typename T, int NT, int TC, int TQ, int KC, int CP, int WAVES>
+// continuous pipeline: the u loads of the next RING - 1 items (the next chunks, running on into
+// the next tile) are in flight while the current one is contracted.  After the staging there is
+// no barrier, and a block starts once per `tiles` tiles instead of once per tile.
+template <typename T, int NT, int TC, int TQ, int KC, int CP, int WAVES, int RING>
 __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const double2* __restrict__ psi,
     typename Cplx<T>::c2* __restrict__ phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0,
@@ -318,6 +318,7 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
     constexpr int RPT = 16 * WAVES;            // rows per tile
     constexpr int NS = NT + TQ;                // staged column tiles: the quad tail reads the last
     static_assert(TQ == 0 || sizeof(T) == 4, "quad tail: FP32");
+    static_assert(RING == 2 || RING == 3, "ring depth");
     extern __shared__ __align__(16) unsigned char smem[];
     const int nch = (Nb + KC - 1) / KC;
     T* sB = reinterpret_cast<T*>(smem);                                   // [nch SS][NS][64][4]
@@ -397,18 +398,8 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
     for (int c = 0; c < TC; ++c) tre[c] = tim[c] = (T)0;
     T* out = reinterpret_cast<T*>(phi);
 
-    C2 a[SS][2], an[SS][2];
-    int tile = t0, ch = 0;
-    load_a(tile, ch, true, a);
-    for (;;) {
-        int ntile = tile, nchk = ch + 1;
-        if (nchk == nch) {
-            nchk = 0;
-            ++ntile;
-        }
-        const bool more = ntile < t1;
-        load_a(ntile, nchk, more, an);
-        __builtin_amdgcn_sched_barrier(0);
+    // the contraction of one item (the u values a of band chunk ch) against the resident psi[k]
+    auto contract = [&](const C2 (&a)[SS][2], int ch) {
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss) {
             const int sg = ch * SS + ss;
@@ -442,63 +433,99 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
         }
 #pragma unroll
         for (int c = 0; c < TC; ++c) asm volatile("" : "+v"(tre[c]), "+v"(tim[c]));
-        if (nchk == 0) {
-            // tile done: write its 16 rows of phi and start the next one from zero
-            const int rbase = tile * RPT + wave * 16;
+    };
+    // tile done: write its 16 rows of phi and start the next one from zero
+    auto finish_tile = [&](int tile) {
+        const int rbase = tile * RPT + wave * 16;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int jr = 16 * t + i;
-                if ((jr >> 1) < ncb) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = rbase + acc_row<T>(kq, r);
-                        if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = acc[t][r];
-                    }
-                }
-                acc[t] = ACC{0, 0, 0, 0};
-            }
-            if constexpr (TQ > 0) {
-                // sum the lane groups; lane l < 16 then holds rows 4 (l / 4) + r, real column
-                // 16 NT + l % 4
+        for (int t = 0; t < NT; ++t) {
+            const int jr = 16 * t + i;
+            if ((jr >> 1) < ncb) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    accq[r] += __shfl_xor(accq[r], 16);
-                    accq[r] += __shfl_xor(accq[r], 32);
+                    const int row = rbase + acc_row<T>(kq, r);
+                    if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = acc[t][r];
                 }
-                const int jr = 16 * NT + (lane & 3);
-                if (kq == 0 && (jr >> 1) < ncb) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = rbase + 4 * (lane >> 2) + r;
-                        if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = accq[r];
-                    }
-                }
-                accq = v4f{0.f, 0.f, 0.f, 0.f};
             }
+            acc[t] = ACC{0, 0, 0, 0};
+        }
+        if constexpr (TQ > 0) {
+            // sum the lane groups; lane l < 16 then holds rows 4 (l / 4) + r, real column
+            // 16 NT + l % 4
 #pragma unroll
-            for (int c = 0; c < TC; ++c) {
-                T re = tre[c], im = tim[c];
-                re += __shfl_xor(re, 16);
-                im += __shfl_xor(im, 16);
-                re += __shfl_xor(re, 32);
-                im += __shfl_xor(im, 32);
-                const int row = rbase + i;
-                if (kq == 0 && row < Nx) {
-                    out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c)] = re;
-                    out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c) + 1] = im;
-                }
-                tre[c] = tim[c] = (T)0;
+            for (int r = 0; r < 4; ++r) {
+                accq[r] += __shfl_xor(accq[r], 16);
+                accq[r] += __shfl_xor(accq[r], 32);
             }
-        }
-        if (!more) break;
+            const int jr = 16 * NT + (lane & 3);
+            if (kq == 0 && (jr >> 1) < ncb) {
 #pragma unroll
-        for (int ss = 0; ss < SS; ++ss) {
-            a[ss][0] = an[ss][0];
-            a[ss][1] = an[ss][1];
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rbase + 4 * (lane >> 2) + r;
+                    if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = accq[r];
+                }
+            }
+            accq = v4f{0.f, 0.f, 0.f, 0.f};
         }
-        tile = ntile;
-        ch = nchk;
+#pragma unroll
+        for (int c = 0; c < TC; ++c) {
+            T re = tre[c], im = tim[c];
+            re += __shfl_xor(re, 16);
+            im += __shfl_xor(im, 16);
+            re += __shfl_xor(re, 32);
+            im += __shfl_xor(im, 32);
+            const int row = rbase + i;
+            if (kq == 0 && row < Nx) {
+                out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c)] = re;
+                out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c) + 1] = im;
+            }
+            tre[c] = tim[c] = (T)0;
+        }
+    };
+
+    // Items are (tile, chunk) pairs in order: (t0, 0), (t0, 1), .., (t1 - 1, nch - 1).  A ring
+    // of RING register slots: while one item is contracted, the loads of the next RING - 1 are
+    // in flight.  The ring is unrolled by its length so every slot is a static register set;
+    // loads past the last item are masked (no memory access) and a turn has no exit between
+    // its steps.
+    int ct = t0, cc = 0;          // the item contracted next
+    int lt = t0, lc = 0;          // the item loaded next
+    auto advance = [&](int& t, int& c) {
+        if (++c == nch) {
+            c = 0;
+            ++t;
+        }
+    };
+    auto step = [&](const C2 (&cur)[SS][2], C2 (&nxt)[SS][2]) {
+        load_a(lt, lc, lt < t1, nxt);
+        advance(lt, lc);
+        __builtin_amdgcn_sched_barrier(0);
+        if (ct < t1) {
+            contract(cur, cc);
+            if (cc == nch - 1) finish_tile(ct);
+            advance(ct, cc);
+        }
+    };
+    const int n_items = (t1 - t0) * nch;
+    C2 s0[SS][2], s1[SS][2];
+    load_a(lt, lc, true, s0);
+    advance(lt, lc);
+    if constexpr (RING == 2) {
+        for (int j = 0; j < n_items; j += 2) {
+            step(s0, s1);
+            step(s1, s0);
+        }
+    } else {
+        C2 s2[SS][2];
+        load_a(lt, lc, lt < t1, s1);
+        advance(lt, lc);
+        for (int j = 0; j < n_items; j += 3) {
+            step(s0, s2);
+            step(s1, s0);
+            step(s2, s1);
+        }
     }
+    __builtin_amdgcn_s_waitcnt(0);   // retire the masked loads past the last item before the exit
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -718,9 +745,11 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     }
 }
 
+// KC: bands per forward chunk; XT, R: back-projection x tile and ring depth; RR: ring depth of
+// the resident forward (two items in flight while one is contracted)
 template <typename T> struct Tiles;
-template <> struct Tiles<double> { static constexpr int KC = 16, XT = 16, R = 3; };
-template <> struct Tiles<float> { static constexpr int KC = 32, XT = 32, R = 3; };
+template <> struct Tiles<double> { static constexpr int KC = 16, XT = 16, R = 3, RR = 3; };
+template <> struct Tiles<float> { static constexpr int KC = 32, XT = 32, R = 3, RR = 3; };
 
 template <typename T, int MS>
 hipError_t fwd_dispatch_nt(int NT, int TC, dim3 grid, hipStream_t st, const void* U, const double* x,
@@ -762,7 +791,7 @@ hipError_t fwd_res_dispatch(int NT, int TC, int TQ, dim3 grid, size_t lds, hipSt
     const double2* ps = reinterpret_cast<const double2*>(x);
 #define OCEAN_FWDR(nt, tc, tq) \
     if (NT == nt && TC == tc && TQ == tq) { \
-        proj_fwd_res_kernel<T, nt, tc, tq, KC, kColsPerPass, kResWaves><<<grid, 64 * kResWaves, lds, st>>>( \
+        proj_fwd_res_kernel<T, nt, tc, tq, KC, kColsPerPass, kResWaves, Tiles<T>::RR><<<grid, 64 * kResWaves, lds, st>>>( \
             u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, groups, tiles); \
         return hipGetLastError(); \
     }
