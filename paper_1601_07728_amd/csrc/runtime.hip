@@ -635,7 +635,10 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
     }
     // k-transform tile: lines per block so that the LDS tile fits
     {
+        // an override must be a power of two up to 256 (the kernels' line counts); anything
+        // else is ignored
         int L = env_int("OCEAN_FFT_LINES", 0);
+        if (L > 256 || (L & (L - 1)) != 0) L = 0;
         if (L <= 0) {
             const size_t budget = (size_t)env_int("OCEAN_FFT_LDS", 80 * 1024);
             L = 256;
