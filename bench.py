@@ -60,7 +60,7 @@ def golden_spectra(seed: int):
 
 MODES = ("fp64", "fp32", "split_bf16", "bf16")
 U_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "bf16": 4}     # per complex u element
-PHI_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "bf16": 8}   # per complex phi element
+PHI_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "bf16": 4}   # per complex phi element (stored)
 
 
 def proj_bytes(cr, cols, u_elem, phi_elem):

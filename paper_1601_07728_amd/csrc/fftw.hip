@@ -77,9 +77,9 @@ __device__ __forceinline__ void dft3(typename C2T<T>::t* buf, const typename C2T
     if (n1 > 1) { dft_pass<T, NMAX>(buf, tw_lds, n1, n2 * n3, Nk, L, inverse); __syncthreads(); }
 }
 
-template <typename T, int NMAX>
+template <typename T, typename S, int NMAX>
 __global__ __launch_bounds__(256) void fft_w_kernel(
-    typename C2T<T>::t* __restrict__ phi, const T* __restrict__ W, const double2* __restrict__ ph,
+    S* __restrict__ phi, const T* __restrict__ W, const double2* __restrict__ ph,
     const double2* __restrict__ tw, int n1, int n2, int n3, int g1, int g2, int g3, int po1,
     int po2, int po3, int to1, int to2, int to3, int Nx, int cols, int L, int phase) {
     typedef typename C2T<T>::t C2;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void fft_w_kernel(
         v.x = 0;
         v.y = 0;
         if (line < total) {
-            v = phi[phi_index(line, kk, Nk, cols)];
+            v = phi_load<C2>(&phi[phi_index(line, kk, Nk, cols)]);
         }
         if (line < total && phase) {
             const int x = (int)(line / cols);
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void fft_w_kernel(
     for (int e = threadIdx.x; e < Nk * L; e += blockDim.x) {
         const int kk = e / L, l = e - kk * L;
         const long long line = line0 + l;
-        if (line < total && !phase) phi[phi_index(line, kk, Nk, cols)] = buf[e];
+        if (line < total && !phase) phi_store(&phi[phi_index(line, kk, Nk, cols)], buf[e]);
         if (line < total && phase) {
             const int x = (int)(line / cols);
             const int j3 = x % g3, j2 = (x / g3) % g2, j1 = x / (g2 * g3);
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void fft_w_kernel(
             C2 pc;
             pc.x = (T)p.x;
             pc.y = -(T)p.y;
-            phi[phi_index(line, kk, Nk, cols)] = cmul(buf[e], pc);
+            phi_store(&phi[phi_index(line, kk, Nk, cols)], cmul(buf[e], pc));
         }
     }
 }
@@ -293,9 +293,9 @@ __device__ __forceinline__ void lds_pass_k2(typename C2T<T>::t* buf, int s1, int
     }
 }
 
-template <typename T, int NMAX>
+template <typename T, typename S, int NMAX>
 __global__ __launch_bounds__(256) void fft_w_pow2_kernel(
-    typename C2T<T>::t* __restrict__ phi, const T* __restrict__ W, const double2* __restrict__ ph,
+    S* __restrict__ phi, const T* __restrict__ W, const double2* __restrict__ ph,
     int s1, int s2, int s3, int g1, int g2, int g3, int po1, int po2, int po3, int total, int cols,
     int lL, int pad, int phase) {
     typedef typename C2T<T>::t C2;
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void fft_w_pow2_kernel(
     const double2* ph1 = ph + po1 + j1;
     const double2* ph2 = ph + po2 + j2;
     const T* wrow = W + (size_t)x * Nk;
-    C2* pl = phi + kbase + l;
+    S* pl = phi + kbase + l;
     auto lidx = [&](int k) { return (k << lL) + l + (k >> s3) * pad; };
     // e^{ik.x} = p1(i1) p2(i2) p3(i3): the k3 factors are the same for every pencil of this
     // thread's line, the (k1, k2) factor is one product per pencil
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) void fft_w_pow2_kernel(
                 const int p = p0 + q * (int)blockDim.x;
                 const int u = (p < npen3 ? p : p0) >> lL;
 #pragma unroll
-                for (int b = 0; b < NMAX; ++b) v[q][b] = pl[((u << s3) + (b < n3 ? b : 0)) * xbc];
+                for (int b = 0; b < NMAX; ++b) v[q][b] = phi_load<C2>(&pl[((u << s3) + (b < n3 ? b : 0)) * xbc]);
             }
 #pragma unroll
             for (int q = 0; q < UP; ++q) {
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(256) void fft_w_pow2_kernel(
             }
 #pragma unroll
             for (int b = 0; b < NMAX; ++b)
-                if (b < n3) pl[((u << s3) + b) * xbc] = v[b];
+                if (b < n3) phi_store(&pl[((u << s3) + b) * xbc], v[b]);
         }
     }
 }
@@ -456,9 +456,9 @@ __global__ __launch_bounds__(256) void fft_w_pow2_kernel(
 // the pencil loops unroll completely and every LDS address is a per-thread base plus a
 // constant, so the five phases are almost pure transform arithmetic.  u normally carries
 // the Bloch phase (PH = false); PH = true applies e^{+-ik.x} here for a borrowed FP64 u.
-template <typename T, int N, int L, bool PH>
+template <typename T, typename S, int N, int L, bool PH>
 __global__ __launch_bounds__(256) void fft_w_cube_kernel(
-    typename C2T<T>::t* __restrict__ phi, const T* __restrict__ W, const double2* __restrict__ ph,
+    S* __restrict__ phi, const T* __restrict__ W, const double2* __restrict__ ph,
     int g1, int g2, int g3, int po1, int po2, int po3, int total, int cols) {
     typedef typename C2T<T>::t C2;
     constexpr int NK = N * N * N, NP = N * N;   // k points; pencils of one line along an axis
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(256) void fft_w_cube_kernel(
     const bool ok = line < total;
     const int x = ok ? line / cols : 0;
     const T* wrow = W + (size_t)x * NK;
-    C2* pl = phi + kbase + l;
+    S* pl = phi + kbase + l;
 
     C2 q3[N];
     const double2* ph1 = ph + po1;
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(256) void fft_w_cube_kernel(
             const int u = u0 + j * TPL;
             if (u < NP) {
 #pragma unroll
-                for (int b = 0; b < N; ++b) v[j][b] = pl[(u * N + b) * xbc];
+                for (int b = 0; b < N; ++b) v[j][b] = phi_load<C2>(&pl[(u * N + b) * xbc]);
             }
         }
 #pragma unroll
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256) void fft_w_cube_kernel(
 #pragma unroll
             for (int b = 0; b < N; ++b) {
                 if (PH) v[b] = cmul(v[b], phase_of(u, b, true));
-                pl[(u * N + b) * xbc] = v[b];
+                phi_store(&pl[(u * N + b) * xbc], v[b]);
             }
         }
     }
@@ -606,19 +606,19 @@ size_t cube_lds_bytes() {
     return (size_t)E * ((size_t)N * N * N * L + (size_t)N * N * PAD);
 }
 
-template <typename T, int N, int L>
-hipError_t launch_cube(ocean_bse_s* h, typename C2T<T>::t* phi, const T* W, const double2* ph, int total,
+template <typename T, typename S, int N, int L>
+hipError_t launch_cube(ocean_bse_s* h, S* phi, const T* W, const double2* ph, int total,
                        int cols, bool phase) {
     const unsigned nblk = (unsigned)((total + L - 1) / L);
     const size_t lds = cube_lds_bytes<T, N, L>();
 #define OCEAN_CUBE_ARGS phi, W, ph, h->nx[0], h->nx[1], h->nx[2], h->phase_off[0], h->phase_off[1], h->phase_off[2], total, cols
     if (phase) {
         if constexpr (sizeof(T) == 8)
-            fft_w_cube_kernel<T, N, L, true><<<nblk, 256, lds, h->stream>>>(OCEAN_CUBE_ARGS);
+            fft_w_cube_kernel<T, S, N, L, true><<<nblk, 256, lds, h->stream>>>(OCEAN_CUBE_ARGS);
         else
             return hipErrorInvalidValue;  // only a borrowed FP64 u is unphased
     } else {
-        fft_w_cube_kernel<T, N, L, false><<<nblk, 256, lds, h->stream>>>(OCEAN_CUBE_ARGS);
+        fft_w_cube_kernel<T, S, N, L, false><<<nblk, 256, lds, h->stream>>>(OCEAN_CUBE_ARGS);
     }
 #undef OCEAN_CUBE_ARGS
     return hipGetLastError();
@@ -630,18 +630,18 @@ bool cube_ok(const ocean_bse_s* h, int L) {
     return h->nk[1] == n && h->nk[2] == n && (n == 4 || n == 8) && (L == 4 || L == 8 || L == 16);
 }
 
-template <typename T>
-hipError_t cube_dispatch(ocean_bse_s* h, typename C2T<T>::t* phi, const T* W, const double2* ph, int total,
+template <typename T, typename S>
+hipError_t cube_dispatch(ocean_bse_s* h, S* phi, const T* W, const double2* ph, int total,
                          int cols, int L, bool phase) {
     const int n = h->nk[0];
     if (n == 8) {
-        if (L == 4) return launch_cube<T, 8, 4>(h, phi, W, ph, total, cols, phase);
-        if (L == 8) return launch_cube<T, 8, 8>(h, phi, W, ph, total, cols, phase);
-        return launch_cube<T, 8, 16>(h, phi, W, ph, total, cols, phase);
+        if (L == 4) return launch_cube<T, S, 8, 4>(h, phi, W, ph, total, cols, phase);
+        if (L == 8) return launch_cube<T, S, 8, 8>(h, phi, W, ph, total, cols, phase);
+        return launch_cube<T, S, 8, 16>(h, phi, W, ph, total, cols, phase);
     }
-    if (L == 4) return launch_cube<T, 4, 4>(h, phi, W, ph, total, cols, phase);
-    if (L == 8) return launch_cube<T, 4, 8>(h, phi, W, ph, total, cols, phase);
-    return launch_cube<T, 4, 16>(h, phi, W, ph, total, cols, phase);
+    if (L == 4) return launch_cube<T, S, 4, 4>(h, phi, W, ph, total, cols, phase);
+    if (L == 8) return launch_cube<T, S, 4, 8>(h, phi, W, ph, total, cols, phase);
+    return launch_cube<T, S, 4, 16>(h, phi, W, ph, total, cols, phase);
 }
 
 bool is_pow2_grid(const ocean_bse_s* h) {
@@ -652,7 +652,8 @@ bool is_pow2_grid(const ocean_bse_s* h) {
     return true;
 }
 
-template <typename T>
+// T: compute type, S: stored type of phi
+template <typename T, typename S>
 hipError_t fft_dispatch(ocean_bse_s* h, int cols, const T* W) {
     typedef typename C2T<T>::t C2;
     const int phase = h->u_phased ? 0 : 1;
@@ -663,11 +664,11 @@ hipError_t fft_dispatch(ocean_bse_s* h, int cols, const T* W) {
     const unsigned nblk = (unsigned)((total + L - 1) / L);
     const size_t lds = sizeof(C2) * (3 * kMaxDft + (size_t)h->Nk * L);
     const int nmax = std::max(h->nk[0], std::max(h->nk[1], h->nk[2]));
-    C2* phi = static_cast<C2*>(h->ws.phi);
+    S* phi = static_cast<S*>(h->ws.phi);
     const double2* ph = reinterpret_cast<const double2*>(h->phase);
     const double2* tw = reinterpret_cast<const double2*>(h->twiddle);
     if (cube_ok(h, L) && total < (1LL << 31))
-        return cube_dispatch<T>(h, phi, W, ph, (int)total, cols, L, phase != 0);
+        return cube_dispatch<T, S>(h, phi, W, ph, (int)total, cols, L, phase != 0);
     if (is_pow2_grid(h) && total < (1LL << 31)) {
         const int pad = pow2_pad((int)sizeof(C2), h->nk[2], L);
         const size_t lds2 = sizeof(C2) * ((size_t)h->Nk * L + (size_t)(h->Nk / h->nk[2]) * pad);
@@ -678,13 +679,13 @@ hipError_t fft_dispatch(ocean_bse_s* h, int cols, const T* W) {
     phi, W, ph, s1, s2, s3, h->nx[0], h->nx[1], h->nx[2], h->phase_off[0], h->phase_off[1],         \
         h->phase_off[2], (int)total, cols, lL, pad, phase
         if (nmax <= 2)
-            fft_w_pow2_kernel<T, 2><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
+            fft_w_pow2_kernel<T, S, 2><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
         else if (nmax <= 4)
-            fft_w_pow2_kernel<T, 4><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
+            fft_w_pow2_kernel<T, S, 4><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
         else if (nmax <= 8)
-            fft_w_pow2_kernel<T, 8><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
+            fft_w_pow2_kernel<T, S, 8><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
         else
-            fft_w_pow2_kernel<T, 16><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
+            fft_w_pow2_kernel<T, S, 16><<<nblk, 256, lds2, h->stream>>>(OCEAN_POW2_ARGS);
 #undef OCEAN_POW2_ARGS
         return hipGetLastError();
     }
@@ -692,13 +693,13 @@ hipError_t fft_dispatch(ocean_bse_s* h, int cols, const T* W) {
     phi, W, ph, tw, h->nk[0], h->nk[1], h->nk[2], h->nx[0], h->nx[1], h->nx[2], h->phase_off[0], \
         h->phase_off[1], h->phase_off[2], h->tw_off[0], h->tw_off[1], h->tw_off[2], h->Nx, cols, L, phase
     if (nmax <= 2)
-        fft_w_kernel<T, 2><<<nblk, 256, lds, h->stream>>>(OCEAN_FFT_ARGS);
+        fft_w_kernel<T, S, 2><<<nblk, 256, lds, h->stream>>>(OCEAN_FFT_ARGS);
     else if (nmax <= 4)
-        fft_w_kernel<T, 4><<<nblk, 256, lds, h->stream>>>(OCEAN_FFT_ARGS);
+        fft_w_kernel<T, S, 4><<<nblk, 256, lds, h->stream>>>(OCEAN_FFT_ARGS);
     else if (nmax <= 8)
-        fft_w_kernel<T, 8><<<nblk, 256, lds, h->stream>>>(OCEAN_FFT_ARGS);
+        fft_w_kernel<T, S, 8><<<nblk, 256, lds, h->stream>>>(OCEAN_FFT_ARGS);
     else
-        fft_w_kernel<T, 16><<<nblk, 256, lds, h->stream>>>(OCEAN_FFT_ARGS);
+        fft_w_kernel<T, S, 16><<<nblk, 256, lds, h->stream>>>(OCEAN_FFT_ARGS);
 #undef OCEAN_FFT_ARGS
     return hipGetLastError();
 }
@@ -721,9 +722,11 @@ hipError_t launch_fft_w(ocean_bse_s* h, int cols) {
     const int slot = prof_begin(h, "fft_w");
     hipError_t e;
     if (h->precision == OCEAN_PREC_FP64)
-        e = fft_dispatch<double>(h, cols, h->W64);
+        e = fft_dispatch<double, double2>(h, cols, h->W64);
+    else if (h->precision == OCEAN_PREC_BF16)
+        e = fft_dispatch<float, bf16c>(h, cols, h->W32);
     else
-        e = fft_dispatch<float>(h, cols, h->W32);
+        e = fft_dispatch<float, float2>(h, cols, h->W32);
     prof_end(h, slot);
     return e;
 }

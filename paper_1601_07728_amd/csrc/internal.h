@@ -174,6 +174,29 @@ template <> __device__ __forceinline__ double2 bload_stream<double2>(Rsrc r, uns
 template <> __device__ __forceinline__ float2 bload_stream<float2>(Rsrc r, unsigned off) {
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, kStreamPolicy));
 }
+// The projections' intermediate phi in the BF16 mode: a complex value stored as two bf16
+// (4 bytes).  Loads widen to float2, stores round to nearest even.  In the other modes phi is
+// stored in its compute type and these are plain accesses.
+struct alignas(4) bf16c {
+    __bf16 x, y;
+};
+template <typename C2, typename S> __device__ __forceinline__ C2 phi_load(const S* p) { return *p; }
+template <> __device__ __forceinline__ float2 phi_load<float2, bf16c>(const bf16c* p) {
+    const bf16c v = *p;
+    return make_float2((float)v.x, (float)v.y);
+}
+template <typename C2, typename S> __device__ __forceinline__ void phi_store(S* p, C2 v) { *p = v; }
+template <> __device__ __forceinline__ void phi_store<float2, bf16c>(bf16c* p, float2 v) {
+    bf16c s;
+    s.x = (__bf16)v.x;
+    s.y = (__bf16)v.y;
+    *p = s;
+}
+// bytes of one stored phi element
+inline size_t phi_elem_bytes(int precision) {
+    return precision == OCEAN_PREC_FP64 ? 16 : precision == OCEAN_PREC_BF16 ? 4 : 8;
+}
+
 template <typename C2> __device__ __forceinline__ void bstore(C2 v, Rsrc r, unsigned off);
 template <> __device__ __forceinline__ void bstore<double2>(double2 v, Rsrc r, unsigned off) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r, (int)off, 0, 0);

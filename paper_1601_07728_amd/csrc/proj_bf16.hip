@@ -8,6 +8,8 @@
 //
 // A sub-step covers 16 contraction points: lane l = i + 16 kq holds points 4 kq .. 4 kq + 3,
 // slot 2 m + p = part p of point m; result register r holds column i of row 4 kq + r.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ocean {
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(256) void prep_fwd_b_bf16_kernel(const double2* __r
 template <int MS, int NT, bool LO>
 __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
     const u16* __restrict__ Uh, const u16* __restrict__ Ul, const unsigned char* __restrict__ bst,
-    float2* __restrict__ phi, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int x_tiles, int nchunks) {
+    void* __restrict__ phi, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int x_tiles, int nchunks) {
     constexpr int KC = 32, SS = KC / 16;
     constexpr int BUF = SS * NT * 64 * 8;      // bf16 values per plane
     constexpr int CB = NT * kStageTile;
@@ -216,7 +218,10 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
         buf ^= 1;
     }
 
-    float* out = reinterpret_cast<float*>(phi);
+    // phi is stored in FP32 in the split mode and in bf16 (rounded to nearest even) in the
+    // BF16 mode
+    typedef typename std::conditional<LO, float, __bf16>::type PT;
+    PT* out = reinterpret_cast<PT*>(phi);
 #pragma unroll
     for (int ms = 0; ms < MS; ++ms)
 #pragma unroll
@@ -226,7 +231,7 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = rowbase + 16 * ms + 4 * kq + r;
-                if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = acc[ms][t][r];
+                if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = (PT)acc[ms][t][r];
             }
         }
 }
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
 // 2 cl and 2 cl + 1 in both planes.
 template <int NT, int W, bool LO>
 __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
-    const u16* __restrict__ UTh, const u16* __restrict__ UTl, const float2* __restrict__ phi,
+    const u16* __restrict__ UTh, const u16* __restrict__ UTl, const void* __restrict__ phi,
     double* __restrict__ part, int Nk, int Nx, int NxP, int Nb, int cols, int col0, int ncb,
     int band_blocks, int S, int chunk) {
     constexpr int XT = 64, SS = XT / 16;
@@ -265,7 +270,10 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
     const Rsrc url = make_rsrc(LO ? UTl + plane0 : UTh + plane0, (size_t)Nb * NxP * 4);
     const int xb0 = x_begin / kXB;
     const size_t pbase_i = (size_t)xb0 * Nk * kXB * cols;
-    const Rsrc prs = make_rsrc(phi + pbase_i, (size_t)((x_end - 1) / kXB - xb0 + 1) * Nk * kXB * cols * sizeof(float2));
+    // phi' is stored as FP32 pairs in the split mode and as bf16 pairs in the BF16 mode
+    constexpr int PE = LO ? 8 : 4;
+    const Rsrc prs = make_rsrc(static_cast<const char*>(phi) + pbase_i * PE,
+                               (size_t)((x_end - 1) / kXB - xb0 + 1) * Nk * kXB * cols * PE);
 
     constexpr int NITEM = kColsPerPass * 4 * SS;
     constexpr int PER = (NITEM + 64 * W - 1) / (64 * W);
@@ -280,8 +288,14 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
             for (int m = 0; m < 4; ++m) {
                 const int x = x0 + 16 * ss + 4 * iq + m;
                 const bool ok = item && x < x_end;
-                const unsigned off = (unsigned)((phi_index_x(x, col0 + cl, k, Nk, cols) - pbase_i) * sizeof(float2));
-                bv[j][m] = bload<float2>(prs, ok ? off : kOob);
+                const unsigned off = (unsigned)((phi_index_x(x, col0 + cl, k, Nk, cols) - pbase_i) * PE);
+                if constexpr (LO) {
+                    bv[j][m] = bload<float2>(prs, ok ? off : kOob);
+                } else {
+                    // (re, im) bf16 at the lower and upper half-words; a bf16 widens by a shift
+                    const unsigned w = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(prs, (int)(ok ? off : kOob), 0, 0);
+                    bv[j][m] = make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xFFFF0000u));
+                }
             }
         }
     };
@@ -309,7 +323,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
                 }
                 const int o = ((ss * NT + t) * 64 + (jr & 15) + 16 * iq) * 8;
                 *reinterpret_cast<bf16x8*>(&sB[buf][o]) = hv;
-                *reinterpret_cast<bf16x8*>(&sB[buf][BUF + o]) = lv;
+                if (LO) *reinterpret_cast<bf16x8*>(&sB[buf][BUF + o]) = lv;   // zero in the BF16 mode
             }
         }
     };
@@ -339,10 +353,13 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_bf16_kernel(
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const bf16x8 b_h = *reinterpret_cast<const bf16x8*>(&sB[buf][((ss * NT + t) * 64 + lane) * 8]);
-                const bf16x8 b_l = *reinterpret_cast<const bf16x8*>(&sB[buf][BUF + ((ss * NT + t) * 64 + lane) * 8]);
                 acc[t] = mfma_bf16(a_h, b_h, acc[t]);
-                acc[t] = mfma_bf16(a_h, b_l, acc[t]);
-                if (LO) acc[t] = mfma_bf16(__builtin_bit_cast(bf16x8, al[ss]), b_h, acc[t]);
+                if (LO) {
+                    // the FP32 phi' residual (a bf16 phi' has none)
+                    const bf16x8 b_l = *reinterpret_cast<const bf16x8*>(&sB[buf][BUF + ((ss * NT + t) * 64 + lane) * 8]);
+                    acc[t] = mfma_bf16(a_h, b_l, acc[t]);
+                    acc[t] = mfma_bf16(__builtin_bit_cast(bf16x8, al[ss]), b_h, acc[t]);
+                }
             }
         }
     };
@@ -430,11 +447,10 @@ __global__ __launch_bounds__(256) void u_to_bf16_kernel(const double* __restrict
 template <int MS, bool LO>
 hipError_t fwd_bf16_nt(int NT, dim3 grid, hipStream_t st, const u16* uh, const u16* ul, const unsigned char* bst,
                        void* phi, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int x_tiles, int nchunks) {
-    float2* p = static_cast<float2*>(phi);
     switch (NT) {
-        case 1: proj_fwd_bf16_kernel<MS, 1, LO><<<grid, 256, 0, st>>>(uh, ul, bst, p, Nk, Nx, Nb, cols, col0, ncb, x_tiles, nchunks); break;
-        case 2: proj_fwd_bf16_kernel<MS, 2, LO><<<grid, 256, 0, st>>>(uh, ul, bst, p, Nk, Nx, Nb, cols, col0, ncb, x_tiles, nchunks); break;
-        default: proj_fwd_bf16_kernel<MS, 3, LO><<<grid, 256, 0, st>>>(uh, ul, bst, p, Nk, Nx, Nb, cols, col0, ncb, x_tiles, nchunks); break;
+        case 1: proj_fwd_bf16_kernel<MS, 1, LO><<<grid, 256, 0, st>>>(uh, ul, bst, phi, Nk, Nx, Nb, cols, col0, ncb, x_tiles, nchunks); break;
+        case 2: proj_fwd_bf16_kernel<MS, 2, LO><<<grid, 256, 0, st>>>(uh, ul, bst, phi, Nk, Nx, Nb, cols, col0, ncb, x_tiles, nchunks); break;
+        default: proj_fwd_bf16_kernel<MS, 3, LO><<<grid, 256, 0, st>>>(uh, ul, bst, phi, Nk, Nx, Nb, cols, col0, ncb, x_tiles, nchunks); break;
     }
     return hipGetLastError();
 }
@@ -443,11 +459,10 @@ template <int W, bool LO>
 hipError_t bwd_bf16_w(int NT, dim3 grid, hipStream_t st, const u16* uh, const u16* ul, const void* phi,
                       double* part, int Nk, int Nx, int NxP, int Nb, int cols, int col0, int ncb, int bb, int S,
                       int chunk) {
-    const float2* p = static_cast<const float2*>(phi);
     switch (NT) {
-        case 1: proj_bwd_bf16_kernel<1, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk); break;
-        case 2: proj_bwd_bf16_kernel<2, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk); break;
-        default: proj_bwd_bf16_kernel<3, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, p, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk); break;
+        case 1: proj_bwd_bf16_kernel<1, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, phi, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk); break;
+        case 2: proj_bwd_bf16_kernel<2, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, phi, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk); break;
+        default: proj_bwd_bf16_kernel<3, W, LO><<<grid, 64 * W, 0, st>>>(uh, ul, phi, part, Nk, Nx, NxP, Nb, cols, col0, ncb, bb, S, chunk); break;
     }
     return hipGetLastError();
 }

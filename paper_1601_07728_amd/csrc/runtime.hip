@@ -166,7 +166,7 @@ static int ensure_workspace(ocean_bse_s* h, int nv) {
     bwd_geometry_for(h, std::max(h->bwd_target_blocks, kMaxBwdTarget), bwd_waves_for(h->Nb, 8), &bb, &S_alloc,
                      &chunk);
     S_alloc = std::max(S_alloc, S);
-    const size_t elem = h->precision == OCEAN_PREC_FP64 ? 16 : 8;
+    const size_t elem = phi_elem_bytes(h->precision);
     const size_t nx_pad = ((size_t)h->Nx + kXB - 1) / kXB * kXB;
     const size_t phi_b = (size_t)h->Nk * nx_pad * cols * elem;
     const size_t part_b = (size_t)S_alloc * h->Nk * h->Nb * cols * 16;

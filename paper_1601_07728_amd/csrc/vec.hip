@@ -604,16 +604,17 @@ __global__ __launch_bounds__(256) void reduce_part_kernel(const double2* __restr
 
 // Gamma-point-only grids: the k-grid transform is the identity and W(x, R = 0) is diagonal
 // in x, so the transform and W steps of Algorithm 1 reduce to phi[x][col] *= W[x].
-template <typename C2, typename T>
-__global__ __launch_bounds__(256) void w_gamma_kernel(C2* __restrict__ phi, const T* __restrict__ W,
+// C2: compute type, S: stored type of phi
+template <typename C2, typename S, typename T>
+__global__ __launch_bounds__(256) void w_gamma_kernel(S* __restrict__ phi, const T* __restrict__ W,
                                                      long long n_elem, int cols) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
         const T w = W[e / cols];
-        C2 v = phi[e];
+        C2 v = phi_load<C2>(&phi[e]);
         v.x *= w;
         v.y *= w;
-        phi[e] = v;
+        phi_store(&phi[e], v);
     }
 }
 
@@ -670,9 +671,11 @@ hipError_t launch_w_gamma(ocean_bse_s* h, int cols) {
     const unsigned nblk = (unsigned)std::min<long long>((n_elem + 255) / 256, 65536);
     const int slot = prof_begin(h, "fft_w");
     if (h->precision == OCEAN_PREC_FP64)
-        w_gamma_kernel<double2, double><<<nblk, 256, 0, h->stream>>>(static_cast<double2*>(h->ws.phi), h->W64, n_elem, cols);
+        w_gamma_kernel<double2, double2, double><<<nblk, 256, 0, h->stream>>>(static_cast<double2*>(h->ws.phi), h->W64, n_elem, cols);
+    else if (h->precision == OCEAN_PREC_BF16)
+        w_gamma_kernel<float2, bf16c, float><<<nblk, 256, 0, h->stream>>>(static_cast<bf16c*>(h->ws.phi), h->W32, n_elem, cols);
     else
-        w_gamma_kernel<float2, float><<<nblk, 256, 0, h->stream>>>(static_cast<float2*>(h->ws.phi), h->W32, n_elem, cols);
+        w_gamma_kernel<float2, float2, float><<<nblk, 256, 0, h->stream>>>(static_cast<float2*>(h->ws.phi), h->W32, n_elem, cols);
     prof_end(h, slot);
     return hipGetLastError();
 }
