@@ -364,11 +364,13 @@ def bench_paper_shape(ob, seed, steps=200):
 
 
 def bench_terminator(ob, n_held, n_steps=512, train_epochs=5):
-    """Learned terminator at the full SrTiO3-shaped size.  The shipped network
-    (paper_1601_07728_amd/terminator_srtio3_l23.npz, trained by train_terminator.py with the
-    library's kernels on 1280 systems x 3 polarisations) is judged on n_held held-out systems
-    generated here (never trained on), against their full 512-step spectra; the per-system cost
-    of generating data and the training rate of the kernels are timed on the same sequences."""
+    """Learned terminator at the full SrTiO3-shaped size.  The shipped networks
+    (paper_1601_07728_amd/terminator_srtio3_l23*.npz, trained by train_terminator.py with the
+    library's kernels on 1280 systems x 3 polarisations; one fed levels 0-31, closing 32-step
+    recursions, one fed levels 16-47, closing 48-step ones) are judged on n_held held-out
+    systems generated here (never trained on), against their full 512-step spectra; the
+    per-system cost of generating data and the training rate of the kernels are timed on the
+    same sequences.  Returns ({window start: Mlp}, record)."""
     import torch
     import synth
     from paper_1601_07728_amd import terminator as term
@@ -382,31 +384,37 @@ def bench_terminator(ob, n_held, n_steps=512, train_epochs=5):
     omegas = [synth.terminator_omega(int(s_)) for s_ in d["seeds"]]
     gam = 0.5 / synth.HARTREE_EV
     ref = term.reference_spectra(a, b, n2, omegas, gam, n_used=sd)
-    path = os.path.join(ROOT, "paper_1601_07728_amd", tt.MODEL_FILE)
-    mlp = ob.Mlp("bf16")
     out = {"held_out_systems": len(seeds), "held_out_sequences": int(a.shape[0]), "steps": n_steps,
            "shape": "SrTiO3-shaped L2,3 edge at full size: 8^3 k, 20^3 x, 96 bands, eps U[2,10], width U[20,60] eV",
            "generation_s_per_system": per_sys,
-           "generation_s_projected_4096_sequences": per_sys * 4096 / 3}
-    l1 = {}
-    if os.path.exists(path):
+           "generation_s_projected_4096_sequences": per_sys * 4096 / 3, "networks": []}
+    mlps = {}
+    for start, fname in sorted(tt.MODEL_FILES.items()):
+        path = os.path.join(ROOT, "paper_1601_07728_amd", fname)
+        if not os.path.exists(path):
+            log(f"terminator: no trained network at {path}")
+            continue
         model = np.load(path)
-        th = term.host_targets(a, b)
+        mlp = ob.Mlp("bf16")
+        th = term.host_targets(a[:, start:start + term.DEPTH], b[:, start:start + term.DEPTH])
         mlp.set_params(term.init_params(th, np.random.default_rng(0)))
-        r0, _ = term.terminated_spectra(mlp, a, b, n2, omegas, gam)
-        l1["mlp_untrained"] = float(np.mean(term.l1(r0["mlp"], ref)))
+        r0, _ = term.terminated_spectra(mlp, a, b, n2, omegas, gam, start=start)
+        l1 = {"mlp_untrained": float(np.mean(term.l1(r0["mlp"], ref)))}
         mlp.set_params(model["params"])
-        res, valid = term.terminated_spectra(mlp, a, b, n2, omegas, gam, a_full=a, b_full=b, n_full=sd)
+        res, valid = term.terminated_spectra(mlp, a, b, n2, omegas, gam, a_full=a, b_full=b, n_full=sd,
+                                             start=start)
         for k, v in res.items():
             l1[k] = float(np.mean(term.l1(v, ref)))
         per = term.l1(res["mlp"], ref) < term.l1(res["sqrt"], ref)
-        out.update({"model": tt.MODEL_FILE, "model_train_sequences": int(model["n_sequences"]),
-                    "model_train_seconds": float(model["train_seconds"]), "invalid_predictions": int((~valid).sum()),
-                    "fraction_mlp_better_than_sqrt": float(per.mean())})
-    else:
-        log(f"terminator: no trained network at {path}")
-    out["heldout_mean_l1_vs_512_steps"] = l1
-    log(f"terminator: held-out mean L1 vs {n_steps}-step spectra: {l1}")
+        rec = {"model": fname, "recursion_steps": start + term.M_IN, "model_train_sequences": int(model["n_sequences"]),
+               "model_train_seconds": float(model["train_seconds"]), "invalid_predictions": int((~valid).sum()),
+               "fraction_mlp_better_than_sqrt": float(per.mean()), "heldout_mean_l1_vs_512_steps": l1}
+        out["networks"].append(rec)
+        log(f"terminator: {start + term.M_IN}-step recursions, held-out mean L1 vs {n_steps}-step spectra: {l1}")
+        if start == 0:
+            # the 32-step network's figures at the top level, as before
+            out.update({k: v for k, v in rec.items() if k != "recursion_steps"})
+        mlps[start] = mlp
     # training rate of the kernels: a few epochs of the recipe on these sequences (a scratch network)
     fresh = ob.Mlp("bf16")
     torch.cuda.synchronize()
@@ -416,13 +424,14 @@ def bench_terminator(ob, n_held, n_steps=512, train_epochs=5):
     dt = time.perf_counter() - t0
     out["train_sequences_per_s"] = train_epochs * (a.shape[0] // 64) * 64 / dt
     fresh.close()
-    return mlp, out
+    return mlps, out
 
 
-def spectra_gain(ob, cr, hs, psi0, mlp, gold, ref_steps=600, base_steps=300):
+def spectra_gain(ob, cr, hs, psi0, mlps, gold, ref_steps=600, base_steps=300):
     """spectra/s of the plain FP64 recursion (base_steps) against the mixed path with fewer
     steps closed by a terminator, at spectrum L1 <= 1e-3 against the reference: the CPU
-    oracle's spectra of this workload (gold), or else a ref_steps FP64 recursion."""
+    oracle's spectra of this workload (gold), or else a ref_steps FP64 recursion.  mlps maps a
+    window start to a trained network, which closes recursions of start + 32 steps."""
     from paper_1601_07728_amd import terminator as term
     n_pol = psi0.shape[0]
     h64 = hs["fp64"]
@@ -442,12 +451,13 @@ def spectra_gain(ob, cr, hs, psi0, mlp, gold, ref_steps=600, base_steps=300):
     for steps in (32, 40, 44, 48, 52, 56, 64, 96, 128, 192):
         for name, h in hs.items():
             dt, (a, b, n2, sd, _) = timed_haydock(h, psi0, steps)
-            for tname in ("sqrt", "mlp") if steps == 32 and mlp is not None else ("sqrt",):
+            start = steps - term.M_IN
+            for tname in ("sqrt", "mlp") if start in mlps else ("sqrt",):
                 t0 = time.perf_counter()
                 if tname == "sqrt":
                     sig = ob.spectrum(a, b, n2, cr.omega, cr.gamma, "sqrt", n_used=sd)
                 else:
-                    ae, be, valid = mlp.predict(a, b)
+                    ae, be, valid = term.extend(mlps[start], a, b, start)
                     sig = ob.spectrum(ae, be, n2, cr.omega, cr.gamma, "sqrt")
                 tt = dt + time.perf_counter() - t0
                 rows.append({"path": name, "steps": steps, "terminator": tname, "spectra_per_s": n_pol / tt,
@@ -631,10 +641,11 @@ def main():
 
     terminator = None
     if not args.no_terminator:
-        mlp, terminator = bench_terminator(ob, args.term_held_out)
+        mlps, terminator = bench_terminator(ob, args.term_held_out)
         if not args.no_spectra:
-            terminator["srtio3_spectra_gain"] = spectra_gain(ob, cr, hs, psi0, mlp, gold)
-        mlp.close()
+            terminator["srtio3_spectra_gain"] = spectra_gain(ob, cr, hs, psi0, mlps, gold)
+        for m in mlps.values():
+            m.close()
 
     batched = None
     for h in hs.values():

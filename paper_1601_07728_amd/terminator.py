@@ -5,13 +5,17 @@ continued fraction run in the library's HIP kernels through the C ABI.  Torch ho
 arrays and draws the minibatch order (seeded); the host computes the training set's target
 statistics that fix the loss weights and the starting point of the last layer.
 
-Three ways to close the continued fraction after m = 32 Haydock steps (section 3.2's
+Three ways to close the continued fraction after m = start + 32 Haydock steps (section 3.2's
 recursion, eq. loss.fcn's spectrum):
-  truncated  the 32 levels as they are (t = 0)
-  sqrt       the constant-chain square-root terminator on the 32 levels
-  mlp        the network extends the coefficients to 256 levels, then the square-root
-             terminator closes them; sequences the network flags invalid fall back to the
-             full-depth recursion when it is available, else to `sqrt`
+  truncated  the m levels as they are (t = 0)
+  sqrt       the constant-chain square-root terminator on the m levels
+  mlp        the network, fed the window of 32 levels starting at `start`, extends the
+             coefficients to start + 256 levels, then the square-root terminator closes them;
+             sequences the network flags invalid fall back to the full-depth recursion when it
+             is available, else to `sqrt`
+A network is trained for one window start (the training sequences are cut to levels
+start .. start + 255); the library ships one for start 0 (32 steps) and one for start 16
+(48 steps).
 
 Training recipe (measured on solver-generated SrTiO3-shaped data; see the design notes):
   * each output position j (224 a's, then 224 log b's, level n = 32 + j mod 224) is weighted by
@@ -136,6 +140,18 @@ def fit(mlp: Mlp, a, b, epochs: int = 200, batch: int = 64, lr: float = 1e-3, se
     return train(mlp, x, t, epochs=epochs, batch=batch, lr=lr, seed=seed, log_every=log_every)
 
 
+def extend(mlp: Mlp, a, b, start: int = 0):
+    """The network's extension of each sequence from its window of 32 levels starting at
+    `start`: levels 0 .. start + 255, the first start + 32 as given.  Returns (a, b, valid)."""
+    a = np.atleast_2d(a)
+    b = np.atleast_2d(b)
+    ae, be, valid = mlp.predict(np.ascontiguousarray(a[:, start:start + M_IN]),
+                                np.ascontiguousarray(b[:, start:start + M_IN]))
+    if start == 0:
+        return ae, be, valid
+    return np.concatenate([a[:, :start], ae], axis=1), np.concatenate([b[:, :start], be], axis=1), valid
+
+
 def _per_omega(fn, omegas):
     """Apply fn(rows, omega) to the groups of rows sharing one energy grid; stack the results."""
     out = [None] * len(omegas)
@@ -149,23 +165,25 @@ def _per_omega(fn, omegas):
     return np.array(out)
 
 
-def terminated_spectra(mlp: Mlp, a, b, norm2, omega, gamma, a_full=None, b_full=None, n_full=None):
-    """Spectra of each sequence closed three ways (see the module docstring).  a, b [n, >=32]
-    host arrays; omega: one grid, or a list of per-sequence grids.  Returns dict name ->
-    sigma [n, n_omega] and the validity mask."""
+def terminated_spectra(mlp: Mlp, a, b, norm2, omega, gamma, a_full=None, b_full=None, n_full=None,
+                       start: int = 0):
+    """Spectra of each sequence closed three ways after start + 32 steps (see the module
+    docstring).  a, b [n, >= start + 32] host arrays; omega: one grid, or a list of
+    per-sequence grids.  Returns dict name -> sigma [n, n_omega] and the validity mask."""
     a = np.atleast_2d(a)
     b = np.atleast_2d(b)
     n = a.shape[0]
     omegas = omega if isinstance(omega, (list, tuple)) else [omega] * n
     norm2 = np.atleast_1d(norm2)
-    m32 = np.full(n, M_IN, dtype=np.int32)
+    m = start + M_IN
+    mm = np.full(n, m, dtype=np.int32)
     out = {
-        "truncated": _per_omega(lambda r, om: spectrum(a[r, :M_IN], b[r, :M_IN], norm2[r], om, gamma, "none",
-                                                       n_used=m32[r]), omegas),
-        "sqrt": _per_omega(lambda r, om: spectrum(a[r, :M_IN], b[r, :M_IN], norm2[r], om, gamma, "sqrt",
-                                                  n_used=m32[r]), omegas),
+        "truncated": _per_omega(lambda r, om: spectrum(a[r, :m], b[r, :m], norm2[r], om, gamma, "none",
+                                                       n_used=mm[r]), omegas),
+        "sqrt": _per_omega(lambda r, om: spectrum(a[r, :m], b[r, :m], norm2[r], om, gamma, "sqrt",
+                                                  n_used=mm[r]), omegas),
     }
-    ae, be, valid = mlp.predict(a[:, :M_IN], b[:, :M_IN])
+    ae, be, valid = extend(mlp, a, b, start)
     sig = _per_omega(lambda r, om: spectrum(ae[r], be[r], norm2[r], om, gamma, "sqrt"), omegas)
     if not valid.all():
         bad = np.nonzero(~valid)[0]

@@ -124,34 +124,37 @@ def test_training_recipe_lowers_the_weighted_loss():
     m.close()
 
 
-def test_shipped_network_beats_the_square_root_terminator_on_held_out_systems():
-    """The network shipped with the library (trained by train_terminator.py with these kernels
-    on 1280 SrTiO3-shaped systems x 3 polarisations) closes the 32-step continued fraction of
-    held-out systems (never trained on) better than the square-root terminator -- the method
-    without the learned part -- and better than the untrained network (the training set's mean
-    tail), judged by the spectrum L1 against each system's full 512-step recursion on its own
-    grid [-15, width + 15] eV."""
+@pytest.mark.parametrize("start", [0, 16])
+def test_shipped_network_beats_the_square_root_terminator_on_held_out_systems(start):
+    """Each network shipped with the library (trained by train_terminator.py with these kernels
+    on 1280 SrTiO3-shaped systems x 3 polarisations; fed levels start .. start + 31) closes the
+    (start + 32)-step continued fraction of held-out systems (never trained on) better than the
+    square-root terminator -- the method without the learned part -- and better than the
+    untrained network (the training set's mean tail), judged by the spectrum L1 against each
+    system's full 512-step recursion on its own grid [-15, width + 15] eV."""
     import os
 
     import paper_1601_07728_amd as ob
     from paper_1601_07728_amd import terminator as term
     from paper_1601_07728_amd import train_terminator as tt
-    path = os.path.join(os.path.dirname(ob.__file__), tt.MODEL_FILE)
+    path = os.path.join(os.path.dirname(ob.__file__), tt.MODEL_FILES[start])
     model = np.load(path)
+    assert int(model["start"]) == start if "start" in model.files else start == 0
     d = term.generate(list(tt.HELD_OUT)[:12])
     a, b, n2, sd = d["a"], d["b"], d["norm2"], d["steps"]
     omegas = [synth.terminator_omega(int(s)) for s in d["seeds"]]
     gam = 0.5 / synth.HARTREE_EV
     ref = term.reference_spectra(a, b, n2, omegas, gam, n_used=sd)
     m = ob.Mlp("bf16")
-    m.set_params(term.init_params(term.host_targets(a, b), np.random.default_rng(0)))
-    r0, _ = term.terminated_spectra(m, a, b, n2, omegas, gam)
+    th = term.host_targets(a[:, start:start + term.DEPTH], b[:, start:start + term.DEPTH])
+    m.set_params(term.init_params(th, np.random.default_rng(0)))
+    r0, _ = term.terminated_spectra(m, a, b, n2, omegas, gam, start=start)
     m.set_params(model["params"])
-    res, valid = term.terminated_spectra(m, a, b, n2, omegas, gam, a_full=a, b_full=b, n_full=sd)
+    res, valid = term.terminated_spectra(m, a, b, n2, omegas, gam, a_full=a, b_full=b, n_full=sd, start=start)
     l1 = {k: term.l1(v, ref) for k, v in res.items()}
     l1["mlp_untrained"] = term.l1(r0["mlp"], ref)
     better = float(np.mean(l1["mlp"] < l1["sqrt"]))
-    _say("[terminator] held-out mean L1 vs 512 steps: " + ", ".join(f"{k} {np.mean(v):.2e}" for k, v in l1.items())
+    _say(f"[terminator] {start + 32}-step recursions, held-out mean L1 vs 512 steps: " + ", ".join(f"{k} {np.mean(v):.2e}" for k, v in l1.items())
          + f"; learned better than square-root on {better:.0%} of {len(ref)} sequences")
     assert valid.all()
     assert np.mean(l1["mlp"]) < 0.9 * np.mean(l1["sqrt"])
