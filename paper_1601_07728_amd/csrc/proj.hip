@@ -932,7 +932,15 @@ void column_split(int ncb, bool fp64, bool wide_tail, bool quad, int* NT, int* T
 // band does not fit in 64 KiB (or the pass is wide, or the precision is a bf16 mode, or one k of
 // u spans more than 2 GiB).
 size_t fwd_res_lds_bytes(const ocean_bse_s* h, int ncb) {
-    if (is_bf16_mode(h->precision) || ncb > kColsPerPass) return 0;
+    if (ncb > kColsPerPass) return 0;
+    if (is_bf16_mode(h->precision)) {
+        // the staged B chunks of every band (both planes), 4 KiB per chunk and column tile
+        const size_t NT = (2 * ncb + 15) / 16;
+        const int KC = fwd_band_chunk(h);
+        const size_t b = (size_t)((h->Nb + KC - 1) / KC) * NT * kStageTile;
+        if ((size_t)h->Nx * h->Nb * 4 >= (1ull << 31)) return 0;
+        return b <= 64 * 1024 ? b : 0;
+    }
     const bool fp64 = h->precision == OCEAN_PREC_FP64;
     int NT, TC, TQ;
     column_split(ncb, fp64, false, true, &NT, &TC, &TQ);

@@ -236,6 +236,140 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
         }
 }
 
+// Forward with the staged B operand resident.  When the B chunks of psi[k] for every band
+// fit in LDS (96 bands and three column tiles: 3 chunks of 12 KiB), a block copies them once
+// and then streams u for `tiles` consecutive tiles of 64 MS rows of that k.  Each wave owns
+// 16 MS rows of every tile and walks its (tile, band chunk) items as one continuous pipeline:
+// the u loads of the next item (the next chunk, or the first chunk of the next tile) are in
+// flight while the current one is contracted, and there is no barrier after the staging.
+// The MFMA sequence of every output element is the chunked kernel's.
+template <int MS, int NT, bool LO>
+__global__ __launch_bounds__(256) void proj_fwd_bf16_res_kernel(
+    const u16* __restrict__ Uh, const u16* __restrict__ Ul, const unsigned char* __restrict__ bst,
+    void* __restrict__ phi, int Nk, int Nx, int Nb, int cols, int col0, int ncb, int x_tiles, int nchunks,
+    int groups, int tiles) {
+    constexpr int KC = 32, SS = KC / 16;
+    constexpr int BUF = SS * NT * 64 * 8;      // bf16 values per plane of one chunk
+    constexpr int CB = NT * kStageTile;        // bytes of one staged chunk (both planes)
+    static_assert(2 * BUF * 2 == CB, "chunk layout");
+    extern __shared__ __align__(16) unsigned char smem[];   // [nchunks][CB]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+    const int lblk = xcd_block();
+    const int k = lblk / groups;
+    const int g = lblk - k * groups;
+    const int t0 = g * tiles, t1 = min(x_tiles, t0 + tiles);
+    if (t0 >= t1) return;   // the whole block, before any barrier
+    // u planes of this k (offsets fit 32 bits: the launcher requires Nx Nb 4 < 2^31)
+    const size_t plane0 = (size_t)k * Nx * Nb * 2;
+    const Rsrc urh = make_rsrc(Uh + plane0, (size_t)Nx * Nb * 4);
+    const Rsrc url = make_rsrc(LO ? Ul + plane0 : Uh + plane0, (size_t)Nx * Nb * 4);
+    const Rsrc br = make_rsrc(bst + (size_t)k * nchunks * CB, (size_t)nchunks * CB);
+    for (int ch = 0; ch < nchunks; ++ch) copy_chunk_lds<NT>(br, smem + (size_t)ch * CB, ch);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    // A of item (tile, chunk): as in the chunked kernel, the four points 4 kq .. 4 kq + 3 of a
+    // sub-step are four consecutive bands of row i, one 16-byte load per plane (a group that
+    // straddles Nb reads into the next row or past the plane, where B is zero); masked to zero
+    // past Nx or when !live
+    auto load_a = [&](int tile, int ch, bool live, u32x4 (&ah)[MS][SS], u32x4 (&al)[MS][SS]) {
+        const int rowbase = tile * (64 * MS) + wave * (16 * MS);
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss) {
+            const int n = ch * KC + 16 * ss + 4 * kq;
+            const bool nok = live && n < Nb;
+#pragma unroll
+            for (int ms = 0; ms < MS; ++ms) {
+                const int row = rowbase + 16 * ms + i;
+                const unsigned off = (nok && row < Nx) ? ((unsigned)row * (unsigned)Nb + (unsigned)n) * 4u : kOob;
+                ah[ms][ss] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(urh, (int)off, 0, 0));
+                if (LO) al[ms][ss] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(url, (int)off, 0, 0));
+            }
+        }
+    };
+
+    v4f acc[MS][NT];
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[ms][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    auto contract = [&](const u32x4 (&ah)[MS][SS], const u32x4 (&al)[MS][SS], int ch) {
+        const __bf16* sb = reinterpret_cast<const __bf16*>(smem + (size_t)ch * CB);
+#pragma unroll
+        for (int ss = 0; ss < SS; ++ss) {
+            bf16x8 bh[NT], bl[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                bh[t] = *reinterpret_cast<const bf16x8*>(&sb[((ss * NT + t) * 64 + lane) * 8]);
+                bl[t] = *reinterpret_cast<const bf16x8*>(&sb[BUF + ((ss * NT + t) * 64 + lane) * 8]);
+            }
+#pragma unroll
+            for (int ms = 0; ms < MS; ++ms) {
+                const bf16x8 a_h = __builtin_bit_cast(bf16x8, ah[ms][ss]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    acc[ms][t] = mfma_bf16(a_h, bh[t], acc[ms][t]);
+                    acc[ms][t] = mfma_bf16(a_h, bl[t], acc[ms][t]);
+                }
+                if (LO) {
+                    const bf16x8 a_l = __builtin_bit_cast(bf16x8, al[ms][ss]);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[ms][t] = mfma_bf16(a_l, bh[t], acc[ms][t]);
+                }
+            }
+        }
+    };
+    // tile done: write its rows of phi (FP32 in the split mode, bf16 in the BF16 mode) and
+    // start the next tile from zero
+    typedef typename std::conditional<LO, float, __bf16>::type PT;
+    PT* out = reinterpret_cast<PT*>(phi);
+    auto finish_tile = [&](int tile) {
+        const int rowbase = tile * (64 * MS) + wave * (16 * MS);
+#pragma unroll
+        for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int jr = 16 * t + i;
+                if ((jr >> 1) < ncb) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = rowbase + 16 * ms + 4 * kq + r;
+                        if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = (PT)acc[ms][t][r];
+                    }
+                }
+                acc[ms][t] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+    };
+
+    u32x4 ah[MS][SS], al[MS][SS], ahn[MS][SS], aln[MS][SS];
+    int tile = t0, ch = 0;
+    load_a(tile, ch, true, ah, al);
+    for (;;) {
+        int ntile = tile, nchk = ch + 1;
+        if (nchk == nchunks) {
+            nchk = 0;
+            ++ntile;
+        }
+        const bool more = ntile < t1;
+        load_a(ntile, nchk, more, ahn, aln);
+        __builtin_amdgcn_sched_barrier(0);
+        contract(ah, al, ch);
+        if (nchk == 0) finish_tile(tile);
+        if (!more) break;
+#pragma unroll
+        for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+            for (int ss = 0; ss < SS; ++ss) {
+                ah[ms][ss] = ahn[ms][ss];
+                if (LO) al[ms][ss] = aln[ms][ss];
+            }
+        tile = ntile;
+        ch = nchk;
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // retire the masked loads past the last item before the exit
+}
+
 // Staging item = (column cl, lane group kq, sub-step ss): the four points of that lane group
 // are loaded once, split into bf16 hi + residual, and written as the 16-byte slots of lanes
 // 2 cl and 2 cl + 1 in both planes.
@@ -455,6 +589,22 @@ hipError_t fwd_bf16_nt(int NT, dim3 grid, hipStream_t st, const u16* uh, const u
     return hipGetLastError();
 }
 
+template <int MS, bool LO>
+hipError_t fwd_bf16_res_nt(int NT, dim3 grid, size_t lds, hipStream_t st, const u16* uh, const u16* ul,
+                           const unsigned char* bst, void* phi, int Nk, int Nx, int Nb, int cols, int col0, int ncb,
+                           int x_tiles, int nchunks, int groups, int tiles) {
+#define OCEAN_FWDB_RES(nt) \
+    proj_fwd_bf16_res_kernel<MS, nt, LO><<<grid, 256, lds, st>>>(uh, ul, bst, phi, Nk, Nx, Nb, cols, col0, ncb, \
+                                                                  x_tiles, nchunks, groups, tiles)
+    switch (NT) {
+        case 1: OCEAN_FWDB_RES(1); break;
+        case 2: OCEAN_FWDB_RES(2); break;
+        default: OCEAN_FWDB_RES(3); break;
+    }
+#undef OCEAN_FWDB_RES
+    return hipGetLastError();
+}
+
 template <int W, bool LO>
 hipError_t bwd_bf16_w(int NT, dim3 grid, hipStream_t st, const u16* uh, const u16* ul, const void* phi,
                       double* part, int Nk, int Nx, int NxP, int Nb, int cols, int col0, int ncb, int bb, int S,
@@ -507,6 +657,24 @@ hipError_t launch_proj_fwd_bf16(ocean_bse_s* h, const double* x, int nv, int col
     const u16* ul = uh + (size_t)2 * h->Nk * h->Nx * h->Nb;
     const unsigned char* bst = h->ws.bst;
     const bool lo = h->precision == OCEAN_PREC_SPLIT_BF16;
+    const size_t res_lds = h->fwd_tiles > 0 ? fwd_res_lds_bytes(h, ncb) : 0;
+    if (res_lds > 0) {
+        // the resident-B form: `tiles` x tiles per block
+        const int tiles = std::min(h->fwd_tiles, x_tiles);
+        const int groups = (x_tiles + tiles - 1) / tiles;
+        dim3 rgrid((unsigned)((long long)h->Nk * groups));
+#define OCEAN_FWDB_RES_ARGS NT, rgrid, res_lds, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, \
+                            x_tiles, nchunks, groups, tiles
+        if (MS == 1)
+            e = lo ? fwd_bf16_res_nt<1, true>(OCEAN_FWDB_RES_ARGS) : fwd_bf16_res_nt<1, false>(OCEAN_FWDB_RES_ARGS);
+        else if (MS == 2)
+            e = lo ? fwd_bf16_res_nt<2, true>(OCEAN_FWDB_RES_ARGS) : fwd_bf16_res_nt<2, false>(OCEAN_FWDB_RES_ARGS);
+        else
+            e = lo ? fwd_bf16_res_nt<4, true>(OCEAN_FWDB_RES_ARGS) : fwd_bf16_res_nt<4, false>(OCEAN_FWDB_RES_ARGS);
+#undef OCEAN_FWDB_RES_ARGS
+        prof_end(h, slot);
+        return e;
+    }
     if (MS == 1)
         e = lo ? fwd_bf16_nt<1, true>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks)
                : fwd_bf16_nt<1, false>(NT, grid, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, x_tiles, nchunks);

@@ -1136,8 +1136,13 @@ int ocean_bse_autotune(ocean_bse_t h, int n_vec, int reps) {
               {"proj_fwd"}, false);
     // the resident-operand forward (row tiles per block) against the chunked one (0), where
     // psi[k] of a pass fits in LDS
-    if (rc == OCEAN_OK && fwd_res_lds_bytes(h, std::min(n_vec * h->Nc, cols_per_pass(h, n_vec * h->Nc))) > 0)
+    if (rc == OCEAN_OK && fwd_res_lds_bytes(h, std::min(n_vec * h->Nc, cols_per_pass(h, n_vec * h->Nc))) > 0) {
         sweep({0, 4, 8, 16, 32}, &h->fwd_tiles, {"proj_fwd"}, false);
+        // the bf16 resident forward has its own best rows per wave (its B operand stays in
+        // LDS, so fewer rows per wave cost no restaging)
+        if (rc == OCEAN_OK && h->fwd_tiles > 0 && is_bf16_mode(h->precision))
+            sweep({1, 2, 4}, &h->fwd_ms, {"proj_fwd"}, false);
+    }
     // waves per back-projection block (smaller blocks pack the CU's registers and LDS more
     // fully where the kernel's register count leaves room), then the grid size
     if (rc == OCEAN_OK) sweep({8, 4, 2}, &h->bwd_waves, {"proj_bwd", "reduce_part", "combine"}, true);

@@ -126,6 +126,8 @@ def test_every_tuning_candidate_gives_the_same_result(tmp_path, monkeypatch, pre
     fwd = [(ms, 0) for ms in ((1, 2, 4) if precision == "bf16" else (1, 2))]
     if precision == "fp64":
         fwd += [(1, ft) for ft in (4, 8, 16, 32)]
+    else:
+        fwd += [(ms, ft) for ms, ft in ((1, 4), (2, 8), (4, 32))]   # the resident bf16 forward
     # every back-projection grid target with every wave cap (37 bands: blocks of 3 waves, or 2
     # and 1); the transform's lines cycle through their candidates meanwhile
     lines = (4, 8, 16, 32, 64)

@@ -373,14 +373,15 @@ RES_CASES = {
 
 
 @pytest.mark.parametrize("case", list(RES_CASES))
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-5), ("split_bf16", 1e-4), ("bf16", 1e-2)])
 def test_resident_operand_forward_matches_chunked_and_oracle(case, precision, tol, monkeypatch):
-    """The forward projection with psi[k] resident in LDS (OCEAN_FWD_TILES row tiles per
-    block: one tile, several, and more than the x grid holds) gives the band-chunked kernel's
-    H*v bit for bit (the same MFMA sequence per output element; FP32 with the 4x4x1 remainder
-    tiles off on both sides), and the oracle's to the precision's tolerance with them on, for
-    1..5 vectors (6 to 30 columns: one to three column tiles, with and without the FP64
-    multiply-add tail or the FP32 4-column remainder, one or two passes)."""
+    """The forward projection with psi[k] (in the bf16 modes its staged B chunks) resident in
+    LDS (OCEAN_FWD_TILES row tiles per block: one tile, several, and more than the x grid
+    holds) gives the band-chunked kernel's H*v bit for bit (the same MFMA sequence per output
+    element; FP32 with the 4x4x1 remainder tiles off on both sides), and the oracle's to the
+    precision's tolerance with them on, for 1..5 vectors (6 to 30 columns: one to three column
+    tiles, with and without the FP64 multiply-add tail or the FP32 4-column remainder, one or
+    two passes)."""
     torch = _torch()
     ob = _ob()
     cr = RES_CASES[case]()
