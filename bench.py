@@ -80,26 +80,26 @@ def proj_bytes(cr, cols, u_elem, phi_elem):
 # WRITE_SIZE 1.0 GiB for 1 GiB written).  A figure holds only for the kernel source it was
 # taken with (sha256 of the .hip file); for any other source the traffic is reported null.
 TRAFFIC = {
-    ("bf16", "proj_bwd"): {"bytes": 2299868393, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 3, false>
-        "sha256": "9462ca3a0a39bbf9f538bababb5c2ac93bee2124bccb9d9ca6364c9413d99b33"},
-    ("bf16", "proj_fwd"): {"bytes": 2189488233, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<4, 3, false>
-        "sha256": "9462ca3a0a39bbf9f538bababb5c2ac93bee2124bccb9d9ca6364c9413d99b33"},
-    ("fp32", "fft_w"): {"bytes": 1196246930, "src": "fftw.hip",  # fft_w_cube_kernel<float, 8, 16, false>
-        "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
-    ("fp32", "proj_bwd"): {"bytes": 3797572321, "src": "proj.hip",  # proj_bwd_kernel<float, 2, 0, 1, 32, 3, 3, 24>
-        "sha256": "cac5d49f5fd168016cee362a211e973f3b240f2f7fa9a63528ea9d8929f5a601"},
-    ("fp32", "proj_fwd"): {"bytes": 3861092235, "src": "proj.hip",  # proj_fwd_res_kernel<float, 2, 0, 1, 32, 24, 8, 3>
-        "sha256": "cac5d49f5fd168016cee362a211e973f3b240f2f7fa9a63528ea9d8929f5a601"},
-    ("fp64", "fft_w"): {"bytes": 2392645730, "src": "fftw.hip",  # fft_w_cube_kernel<double, 8, 8, true>
-        "sha256": "4febec243e3704510d9c772d82f98850e2aa8d7643f84d704bf7f19ee0db9a9a"},
-    ("fp64", "proj_bwd"): {"bytes": 7663902218, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 0, 16, 3, 3, 24>
-        "sha256": "cac5d49f5fd168016cee362a211e973f3b240f2f7fa9a63528ea9d8929f5a601"},
-    ("fp64", "proj_fwd"): {"bytes": 7658788590, "src": "proj.hip",  # proj_fwd_res_kernel<double, 2, 2, 0, 16, 24, 8, 3>
-        "sha256": "cac5d49f5fd168016cee362a211e973f3b240f2f7fa9a63528ea9d8929f5a601"},
-    ("split_bf16", "proj_bwd"): {"bytes": 3826336722, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 3, true>
-        "sha256": "9462ca3a0a39bbf9f538bababb5c2ac93bee2124bccb9d9ca6364c9413d99b33"},
-    ("split_bf16", "proj_fwd"): {"bytes": 3755406373, "src": "proj_bf16.hip",  # proj_fwd_bf16_kernel<1, 3, true>
-        "sha256": "9462ca3a0a39bbf9f538bababb5c2ac93bee2124bccb9d9ca6364c9413d99b33"},
+    ("bf16", "proj_bwd"): {"bytes": 1958286900, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
+        "sha256": "d08b487d5fdee5df37109993bb0f7353fef54f8f72d8ec28194f5a8134653e98"},
+    ("bf16", "proj_fwd"): {"bytes": 1892708686, "src": "proj_bf16.hip",  # proj_fwd_bf16_res_kernel<4, 3, false>
+        "sha256": "d08b487d5fdee5df37109993bb0f7353fef54f8f72d8ec28194f5a8134653e98"},
+    ("fp32", "fft_w"): {"bytes": 1196241743, "src": "fftw.hip",  # fft_w_cube_kernel<float, HIP_vector_type<float, 2u>, 8, 16, false>
+        "sha256": "0a84dabd406301e6559ff7feaa2f508b7037160206c4e4f08fb84ae0a8f9354d"},
+    ("fp32", "proj_bwd"): {"bytes": 3791888768, "src": "proj.hip",  # proj_bwd_kernel<float, 2, 0, 1, 32, 3, 3, 24>
+        "sha256": "fdcbef2abb8ddf0cfbf39e0fd3c9173308dc8db958e0f4db6cbcfdcc3fbdf36e"},
+    ("fp32", "proj_fwd"): {"bytes": 3861183266, "src": "proj.hip",  # proj_fwd_res_kernel<float, 2, 0, 1, 32, 24, 8, 3>
+        "sha256": "fdcbef2abb8ddf0cfbf39e0fd3c9173308dc8db958e0f4db6cbcfdcc3fbdf36e"},
+    ("fp64", "fft_w"): {"bytes": 2392666687, "src": "fftw.hip",  # fft_w_cube_kernel<double, HIP_vector_type<double, 2u>, 8, 8, true>
+        "sha256": "0a84dabd406301e6559ff7feaa2f508b7037160206c4e4f08fb84ae0a8f9354d"},
+    ("fp64", "proj_bwd"): {"bytes": 7678135942, "src": "proj.hip",  # proj_bwd_kernel<double, 2, 2, 0, 16, 3, 3, 24>
+        "sha256": "fdcbef2abb8ddf0cfbf39e0fd3c9173308dc8db958e0f4db6cbcfdcc3fbdf36e"},
+    ("fp64", "proj_fwd"): {"bytes": 7622789127, "src": "proj.hip",  # proj_fwd_res_kernel<double, 2, 2, 0, 16, 24, 8, 3>
+        "sha256": "fdcbef2abb8ddf0cfbf39e0fd3c9173308dc8db958e0f4db6cbcfdcc3fbdf36e"},
+    ("split_bf16", "proj_bwd"): {"bytes": 3819521684, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
+        "sha256": "d08b487d5fdee5df37109993bb0f7353fef54f8f72d8ec28194f5a8134653e98"},
+    ("split_bf16", "proj_fwd"): {"bytes": 3798945531, "src": "proj_bf16.hip",  # proj_fwd_bf16_res_kernel<1, 3, true>
+        "sha256": "d08b487d5fdee5df37109993bb0f7353fef54f8f72d8ec28194f5a8134653e98"},
 }
 
 
