@@ -80,6 +80,8 @@ def proj_bytes(cr, cols, u_elem, phi_elem):
 # WRITE_SIZE 1.0 GiB for 1 GiB written).  A figure holds only for the kernel source it was
 # taken with (sha256 of the .hip file); for any other source the traffic is reported null.
 TRAFFIC = {
+    ("bf16", "fft_w"): {"bytes": 606791705, "src": "fftw.hip",  # fft_w_cube_kernel<float, ocean::bf16c, 8, 16, false>
+        "sha256": "0a84dabd406301e6559ff7feaa2f508b7037160206c4e4f08fb84ae0a8f9354d"},
     ("bf16", "proj_bwd"): {"bytes": 1958286900, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, false>
         "sha256": "d08b487d5fdee5df37109993bb0f7353fef54f8f72d8ec28194f5a8134653e98"},
     ("bf16", "proj_fwd"): {"bytes": 1892708686, "src": "proj_bf16.hip",  # proj_fwd_bf16_res_kernel<4, 3, false>
@@ -96,6 +98,8 @@ TRAFFIC = {
         "sha256": "fdcbef2abb8ddf0cfbf39e0fd3c9173308dc8db958e0f4db6cbcfdcc3fbdf36e"},
     ("fp64", "proj_fwd"): {"bytes": 7622789127, "src": "proj.hip",  # proj_fwd_res_kernel<double, 2, 2, 0, 16, 24, 8, 3>
         "sha256": "fdcbef2abb8ddf0cfbf39e0fd3c9173308dc8db958e0f4db6cbcfdcc3fbdf36e"},
+    ("split_bf16", "fft_w"): {"bytes": 1196241743, "src": "fftw.hip",  # fft_w_cube_kernel<float, HIP_vector_type<float, 2u>, 8, 16, false>
+        "sha256": "0a84dabd406301e6559ff7feaa2f508b7037160206c4e4f08fb84ae0a8f9354d"},
     ("split_bf16", "proj_bwd"): {"bytes": 3819521684, "src": "proj_bf16.hip",  # proj_bwd_bf16_kernel<3, 6, true>
         "sha256": "d08b487d5fdee5df37109993bb0f7353fef54f8f72d8ec28194f5a8134653e98"},
     ("split_bf16", "proj_fwd"): {"bytes": 3798945531, "src": "proj_bf16.hip",  # proj_fwd_bf16_res_kernel<1, 3, true>
