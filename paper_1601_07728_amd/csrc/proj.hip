@@ -92,7 +92,7 @@ __device__ __forceinline__ void stage_pair(T* buf, int ss, int kq, int ns, int c
 // [xt*64*MS + w*16*MS, +16*MS) and every column tile.  The bands are walked in chunks of
 // KC: the psi chunk (B operand, shared by all waves) is staged in LDS in MFMA order, double
 // buffered, while each wave keeps the u values (A operand) of the next chunk in flight.
-template <typename T, int MS, int NT, int TC, int KC, int CP>
+template <typename T, int MS, int NT, int TC, int KC, int CP, bool PAIR>
 __global__ __launch_bounds__(256) void proj_fwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const double2* __restrict__ psi,
     typename Cplx<T>::c2* __restrict__ phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0,
@@ -165,11 +165,13 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
                         aa[ms][ss][ns] = bload<C2>(ur, (nok && rval[ms]) ? urow[ms] + (unsigned)(n * sizeof(C2)) : kOob);
                 }
             } else {
-                // bands 2 kq and 2 kq + 1 in one 16-byte load (Nb even; else two 8-byte loads)
+                // bands 2 kq and 2 kq + 1 in one 16-byte load (PAIR: Nb even; else two 8-byte
+                // loads).  A compile-time choice: a branch here would merge two load counts and
+                // make the compiler's waits for the ring's slots conservative.
                 const int n = n0 + 8 * ss + 2 * kq;
 #pragma unroll
                 for (int ms = 0; ms < MS; ++ms) {
-                    if ((Nb & 1) == 0) {
+                    if constexpr (PAIR) {
                         const bool ok = n < Nb && rval[ms];
                         const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
                             ur, (int)(ok ? urow[ms] + (unsigned)(n * sizeof(C2)) : kOob), 0, 0));
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
 // continuous pipeline: the u loads of the next RING - 1 items (the next chunks, running on into
 // the next tile) are in flight while the current one is contracted.  After the staging there is
 // no barrier, and a block starts once per `tiles` tiles instead of once per tile.
-template <typename T, int NT, int TC, int TQ, int KC, int CP, int WAVES, int RING>
+template <typename T, int NT, int TC, int TQ, int KC, int CP, int WAVES, int RING, bool PAIR>
 __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const double2* __restrict__ psi,
     typename Cplx<T>::c2* __restrict__ phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0,
@@ -372,7 +374,7 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
                 }
             } else {
                 const int n = n0 + 8 * ss + 2 * kq;
-                if ((Nb & 1) == 0) {
+                if constexpr (PAIR) {   // Nb even; see proj_fwd_kernel
                     const bool ok = rok && n < Nb;
                     const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
                         ur, (int)(ok ? rb + (unsigned)(n * sizeof(C2)) : kOob), 0, 0));
@@ -396,7 +398,6 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
     T tre[TC > 0 ? TC : 1], tim[TC > 0 ? TC : 1];
 #pragma unroll
     for (int c = 0; c < TC; ++c) tre[c] = tim[c] = (T)0;
-    T* out = reinterpret_cast<T*>(phi);
 
     // the contraction of one item (the u values a of band chunk ch) against the resident psi[k]
     auto contract = [&](const C2 (&a)[SS][2], int ch) {
@@ -434,52 +435,66 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
 #pragma unroll
         for (int c = 0; c < TC; ++c) asm volatile("" : "+v"(tre[c]), "+v"(tim[c]));
     };
-    // tile done: write its 16 rows of phi and start the next one from zero
+    // tile done: write its 16 rows of phi and start the next one from zero.  Each store
+    // writes one complex value per lane: neighbouring lanes (real columns 2c and 2c + 1, the
+    // re and im parts of complex column c) swap one of two accumulator rows, so that the even
+    // lane holds column c of the first row and the odd lane column c of the second (half as
+    // many store instructions as one real value per lane; the stores, not the bytes, cost).
+    const size_t phi_bytes = (size_t)((Nx + kXB - 1) / kXB) * kXB * Nk * cols * sizeof(C2);
+    const Rsrc pw = make_rsrc(phi, phi_bytes);
+    const bool odd = lane & 1;
     auto finish_tile = [&](int tile) {
         const int rbase = tile * RPT + wave * 16;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int jr = 16 * t + i;
-            if ((jr >> 1) < ncb) {
+            const int c = 8 * t + (i >> 1);   // this lane's complex column in the pass
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = rbase + acc_row<T>(kq, r);
-                    if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = acc[t][r];
-                }
+            for (int rp = 0; rp < 2; ++rp) {
+                const T a = acc[t][2 * rp], b = acc[t][2 * rp + 1];
+                const T y = __shfl_xor(odd ? a : b, 1);
+                const C2 v = odd ? C2{y, b} : C2{a, y};
+                const int row = rbase + acc_row<T>(kq, 2 * rp + (odd ? 1 : 0));
+                const bool ok = c < ncb && row < Nx;
+                bstore<C2>(v, pw, ok ? (unsigned)(phi_index_x(row, col0 + c, k, Nk, cols) * sizeof(C2)) : kOob);
             }
             acc[t] = ACC{0, 0, 0, 0};
         }
         if constexpr (TQ > 0) {
-            // sum the lane groups; lane l < 16 then holds rows 4 (l / 4) + r, real column
-            // 16 NT + l % 4
+            // sum the lane groups (every group then holds the sums); lane (i, kq) takes
+            // register r = kq: rows 4 (i / 4) + kq, real column 16 NT + i % 4
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 accq[r] += __shfl_xor(accq[r], 16);
                 accq[r] += __shfl_xor(accq[r], 32);
             }
-            const int jr = 16 * NT + (lane & 3);
-            if (kq == 0 && (jr >> 1) < ncb) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = rbase + 4 * (lane >> 2) + r;
-                    if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = accq[r];
-                }
-            }
+            const float q = kq == 0 ? accq[0] : kq == 1 ? accq[1] : kq == 2 ? accq[2] : accq[3];
+            const float y = __shfl_xor(q, 1);
+            const int c = 8 * NT + ((i & 3) >> 1);
+            const int row = rbase + 4 * (i >> 2) + kq;
+            const bool ok = !odd && c < ncb && row < Nx;
+            bstore<C2>(C2{(T)q, (T)y}, pw, ok ? (unsigned)(phi_index_x(row, col0 + c, k, Nk, cols) * sizeof(C2)) : kOob);
             accq = v4f{0.f, 0.f, 0.f, 0.f};
         }
+        if constexpr (TC > 0) {
+            // every lane holds the sums after the butterfly; lane group kq writes tail column kq
+            T re[TC], im[TC];
 #pragma unroll
-        for (int c = 0; c < TC; ++c) {
-            T re = tre[c], im = tim[c];
-            re += __shfl_xor(re, 16);
-            im += __shfl_xor(im, 16);
-            re += __shfl_xor(re, 32);
-            im += __shfl_xor(im, 32);
-            const int row = rbase + i;
-            if (kq == 0 && row < Nx) {
-                out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c)] = re;
-                out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c) + 1] = im;
+            for (int c = 0; c < TC; ++c) {
+                re[c] = tre[c];
+                im[c] = tim[c];
+                re[c] += __shfl_xor(re[c], 16);
+                im[c] += __shfl_xor(im[c], 16);
+                re[c] += __shfl_xor(re[c], 32);
+                im[c] += __shfl_xor(im[c], 32);
+                tre[c] = tim[c] = (T)0;
             }
-            tre[c] = tim[c] = (T)0;
+            C2 v = C2{re[0], im[0]};
+#pragma unroll
+            for (int c = 1; c < TC; ++c)
+                if (kq == c) v = C2{re[c], im[c]};
+            const int row = rbase + i;
+            const bool ok = kq < TC && row < Nx;
+            bstore<C2>(v, pw, ok ? (unsigned)(phi_index_x(row, col0 + 8 * NT + kq, k, Nk, cols) * sizeof(C2)) : kOob);
         }
     };
 
@@ -517,6 +532,10 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
         }
     } else {
         C2 s2[SS][2];
+        // FP32: keep the first two items' loads in item order, so that the compiler's waits at
+        // the loop head count the second item's loads as still in flight (measured: FP32
+        // faster, FP64 0.4% slower with the same ordering)
+        if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
         load_a(lt, lc, lt < t1, s1);
         advance(lt, lc);
         for (int j = 0; j < n_items; j += 3) {
@@ -759,9 +778,14 @@ hipError_t fwd_dispatch_nt(int NT, int TC, dim3 grid, hipStream_t st, const void
     const C2* u = static_cast<const C2*>(U);
     C2* p = static_cast<C2*>(phi);
     const double2* ps = reinterpret_cast<const double2*>(x);
+    // FP32 with an even band count loads two bands per 16-byte load (PAIR)
+    const bool pair = sizeof(T) == 4 && (Nb & 1) == 0;
 #define OCEAN_FWD(nt, tc, cp) \
     if (NT == nt && TC == tc) { \
-        proj_fwd_kernel<T, MS, nt, tc, Tiles<T>::KC, cp><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); \
+        if (pair) \
+            proj_fwd_kernel<T, MS, nt, tc, Tiles<T>::KC, cp, sizeof(T) == 4><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); \
+        else \
+            proj_fwd_kernel<T, MS, nt, tc, Tiles<T>::KC, cp, false><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); \
         return hipGetLastError(); \
     }
     if (ncb <= kColsPerPass) {
@@ -789,10 +813,15 @@ hipError_t fwd_res_dispatch(int NT, int TC, int TQ, dim3 grid, size_t lds, hipSt
     const C2* u = static_cast<const C2*>(U);
     C2* p = static_cast<C2*>(phi);
     const double2* ps = reinterpret_cast<const double2*>(x);
+    const bool pair = sizeof(T) == 4 && (Nb & 1) == 0;
 #define OCEAN_FWDR(nt, tc, tq) \
     if (NT == nt && TC == tc && TQ == tq) { \
-        proj_fwd_res_kernel<T, nt, tc, tq, KC, kColsPerPass, kResWaves, Tiles<T>::RR><<<grid, 64 * kResWaves, lds, st>>>( \
-            u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, groups, tiles); \
+        if (pair) \
+            proj_fwd_res_kernel<T, nt, tc, tq, KC, kColsPerPass, kResWaves, Tiles<T>::RR, sizeof(T) == 4> \
+                <<<grid, 64 * kResWaves, lds, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, groups, tiles); \
+        else \
+            proj_fwd_res_kernel<T, nt, tc, tq, KC, kColsPerPass, kResWaves, Tiles<T>::RR, false> \
+                <<<grid, 64 * kResWaves, lds, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, groups, tiles); \
         return hipGetLastError(); \
     }
     OCEAN_FWDR(1, 0, 0) OCEAN_FWDR(2, 0, 0) OCEAN_FWDR(3, 0, 0)
@@ -929,8 +958,8 @@ void column_split(int ncb, bool fp64, bool wide_tail, bool quad, int* NT, int* T
 }
 
 // LDS bytes of the resident-operand forward for a pass of ncb columns, or 0 if psi[k] of every
-// band does not fit in 64 KiB (or the pass is wide, or the precision is a bf16 mode, or one k of
-// u spans more than 2 GiB).
+// band does not fit in 64 KiB (or the pass is wide, or one k of u spans more than 2 GiB, or in
+// FP64/FP32 phi spans 4 GiB or more).
 size_t fwd_res_lds_bytes(const ocean_bse_s* h, int ncb) {
     if (ncb > kColsPerPass) return 0;
     if (is_bf16_mode(h->precision)) {
@@ -948,6 +977,9 @@ size_t fwd_res_lds_bytes(const ocean_bse_s* h, int ncb) {
     const int KC = fp64 ? Tiles<double>::KC : Tiles<float>::KC;
     const size_t nch = (h->Nb + KC - 1) / KC;
     if ((size_t)h->Nx * h->Nb * 2 * elem >= (1ull << 31)) return 0;
+    // phi is written through a buffer descriptor with 32-bit byte offsets
+    const size_t nx_pad = ((size_t)h->Nx + kXB - 1) / kXB * kXB;
+    if ((size_t)h->Nk * nx_pad * std::max(h->ws.cols, ncb) * 2 * elem >= kOob) return 0;
     const size_t b = nch * (KC / 8) * (NT + TQ) * 256 * elem + nch * KC * TC * 2 * elem;
     return b <= 64 * 1024 ? b : 0;
 }
