@@ -39,6 +39,12 @@ __host__ __device__ inline size_t phi_index_x(int x, int col, int k, int Nk, int
     return ((size_t)((x >> 4) * Nk + k) * kXB + (x & (kXB - 1))) * cols + col;
 }
 
+// Bytes of the phi work array of a pass with `cols` columns (x padded to whole x-blocks),
+// the extent of a buffer descriptor over it.
+__host__ __device__ inline size_t phi_span_bytes(int Nx, int Nk, int cols, int elem) {
+    return (size_t)((Nx + kXB - 1) / kXB) * kXB * Nk * cols * elem;
+}
+
 // Per-vector Lanczos state kept on the device.
 struct LzState {
     double b_cur;   // b_i of the current step (b_0 = 0)

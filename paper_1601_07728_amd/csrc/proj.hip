@@ -440,8 +440,7 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
     // re and im parts of complex column c) swap one of two accumulator rows, so that the even
     // lane holds column c of the first row and the odd lane column c of the second (half as
     // many store instructions as one real value per lane; the stores, not the bytes, cost).
-    const size_t phi_bytes = (size_t)((Nx + kXB - 1) / kXB) * kXB * Nk * cols * sizeof(C2);
-    const Rsrc pw = make_rsrc(phi, phi_bytes);
+    const Rsrc pw = make_rsrc(phi, phi_span_bytes(Nx, Nk, cols, (int)sizeof(C2)));
     const bool odd = lane & 1;
     auto finish_tile = [&](int tile) {
         const int rbase = tile * RPT + wave * 16;

@@ -8,6 +8,7 @@
 //
 // A sub-step covers 16 contraction points: lane l = i + 16 kq holds points 4 kq .. 4 kq + 3,
 // slot 2 m + p = part p of point m; result register r holds column i of row 4 kq + r.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -42,6 +43,55 @@ __device__ __forceinline__ int xcd_block() {
     const unsigned nblk = gridDim.x, q8 = nblk / 8, r8 = nblk % 8;
     const unsigned xcd = blockIdx.x % 8, pos = blockIdx.x / 8;
     return (int)(xcd * q8 + (xcd < r8 ? xcd : r8) + pos);
+}
+
+// Store one 16x16 result tile of the forward projection (register r of lane i + 16 kq:
+// row 4 kq + r, real column i of the tile) as two complex columns per lane.  The four lanes
+// of a quad transpose their four registers with two exchange rounds, after which lane
+// 4 a + p holds row 4 kq + p, real columns 4 a .. 4 a + 3 (complex columns 2 a, 2 a + 1 of
+// the tile): one store instruction per tile covers it, against four with one real value per
+// lane (the store instructions, not the bytes, cost in these kernels).  phi is FP32 pairs in
+// the split mode (LO) and bf16 pairs (rounded to nearest even) in the BF16 mode.  Rows at or
+// past Nx and complex columns at or past ncb are not written: a lane whose second column is
+// past ncb writes its first one with a narrower store (offsets out of range drop a store).
+// pw covers phi from element idx0 (the block's first row and the pass's first column) on;
+// the launcher keeps a block's rows within 2 GiB of it.
+template <bool LO>
+__device__ __forceinline__ void store_fwd_tile(v4f a, Rsrc pw, size_t idx0, int lane, int rowtop, int c_tile,
+                                               int Nx, int ncb, int col0, int k, int Nk, int cols) {
+    const int i = lane & 15, kq = lane >> 4, p = i & 3;
+    float v[4] = {a[0], a[1], a[2], a[3]};
+#pragma unroll
+    for (int b = 1; b <= 2; b <<= 1) {
+#pragma unroll
+        for (int r0 = 0; r0 < 4; ++r0) {
+            if (r0 & b) continue;
+            const int r1 = r0 | b;
+            const bool hi = p & b;
+            const float t = __shfl_xor(hi ? v[r0] : v[r1], b);
+            if (hi) v[r0] = t;
+            else v[r1] = t;
+        }
+    }
+    const int row = rowtop + 4 * kq + p;
+    const int c = c_tile + 2 * (i >> 2);
+    const bool rok = row < Nx;
+    const unsigned base = (unsigned)(phi_index_x(row, col0 + c, k, Nk, cols) - idx0) * (LO ? 8u : 4u);
+    const unsigned off2 = (rok && c + 1 < ncb) ? base : kOob;
+    const unsigned off1 = (rok && c + 1 == ncb) ? base : kOob;
+    if constexpr (LO) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, f4{v[0], v[1], v[2], v[3]}), pw, (int)off2, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, f2{v[0], v[1]}),
+                                              pw, (int)off1, 0, 0);
+    } else {
+        const bf16c c0{(__bf16)v[0], (__bf16)v[1]}, c1{(__bf16)v[2], (__bf16)v[3]};
+        const unsigned w0 = __builtin_bit_cast(unsigned, c0), w1 = __builtin_bit_cast(unsigned, c1);
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(u2{w0, w1}, pw, (int)off2, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(w0, pw, (int)off1, 0, 0);
+    }
 }
 
 // Wait until at most N vector-memory loads of this wave are outstanding (vmcnt counts loads
@@ -218,22 +268,15 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_kernel(
         buf ^= 1;
     }
 
-    // phi is stored in FP32 in the split mode and in bf16 (rounded to nearest even) in the
-    // BF16 mode
-    typedef typename std::conditional<LO, float, __bf16>::type PT;
-    PT* out = reinterpret_cast<PT*>(phi);
+    // phi: FP32 pairs in the split mode, bf16 pairs in the BF16 mode (store_fwd_tile)
+    constexpr int E = LO ? 8 : 4;
+    const size_t idx0 = phi_index_x(xt * (64 * MS), col0, k, Nk, cols);
+    const Rsrc pw = make_rsrc(static_cast<unsigned char*>(phi) + idx0 * E, phi_span_bytes(Nx, Nk, cols, E) - idx0 * E);
 #pragma unroll
     for (int ms = 0; ms < MS; ++ms)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int jr = 16 * t + i;
-            if ((jr >> 1) >= ncb) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = rowbase + 16 * ms + 4 * kq + r;
-                if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = (PT)acc[ms][t][r];
-            }
-        }
+        for (int t = 0; t < NT; ++t)
+            store_fwd_tile<LO>(acc[ms][t], pw, idx0, lane, rowbase + 16 * ms, 8 * t, Nx, ncb, col0, k, Nk, cols);
 }
 
 // Forward with the staged B operand resident.  When the B chunks of psi[k] for every band
@@ -320,24 +363,18 @@ __global__ __launch_bounds__(256) void proj_fwd_bf16_res_kernel(
             }
         }
     };
-    // tile done: write its rows of phi (FP32 in the split mode, bf16 in the BF16 mode) and
-    // start the next tile from zero
-    typedef typename std::conditional<LO, float, __bf16>::type PT;
-    PT* out = reinterpret_cast<PT*>(phi);
+    // tile done: write its rows of phi (FP32 pairs in the split mode, bf16 pairs in the BF16
+    // mode; store_fwd_tile) and start the next tile from zero
+    constexpr int E = LO ? 8 : 4;
+    const size_t idx0 = phi_index_x(t0 * (64 * MS), col0, k, Nk, cols);
+    const Rsrc pw = make_rsrc(static_cast<unsigned char*>(phi) + idx0 * E, phi_span_bytes(Nx, Nk, cols, E) - idx0 * E);
     auto finish_tile = [&](int tile) {
         const int rowbase = tile * (64 * MS) + wave * (16 * MS);
 #pragma unroll
         for (int ms = 0; ms < MS; ++ms)
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const int jr = 16 * t + i;
-                if ((jr >> 1) < ncb) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = rowbase + 16 * ms + 4 * kq + r;
-                        if (row < Nx) out[2 * phi_index_x(row, col0, k, Nk, cols) + jr] = (PT)acc[ms][t][r];
-                    }
-                }
+                store_fwd_tile<LO>(acc[ms][t], pw, idx0, lane, rowbase + 16 * ms, 8 * t, Nx, ncb, col0, k, Nk, cols);
                 acc[ms][t] = v4f{0.f, 0.f, 0.f, 0.f};
             }
     };
@@ -657,10 +694,18 @@ hipError_t launch_proj_fwd_bf16(ocean_bse_s* h, const double* x, int nv, int col
     const u16* ul = uh + (size_t)2 * h->Nk * h->Nx * h->Nb;
     const unsigned char* bst = h->ws.bst;
     const bool lo = h->precision == OCEAN_PREC_SPLIT_BF16;
+    // phi offsets from a block's first row are 32-bit: a block's rows must span less than
+    // 2 GiB of phi (x-blocks of 16 points, each Nk kXB cols elements apart)
+    const size_t xb_bytes = (size_t)h->Nk * kXB * cols * (lo ? 8 : 4);
+    const size_t row_tile_bytes = (size_t)(64 * MS / kXB) * xb_bytes;
+    if (row_tile_bytes >= (1ull << 31)) {
+        prof_end(h, slot);
+        return hipErrorInvalidValue;
+    }
     const size_t res_lds = h->fwd_tiles > 0 ? fwd_res_lds_bytes(h, ncb) : 0;
     if (res_lds > 0) {
         // the resident-B form: `tiles` x tiles per block
-        const int tiles = std::min(h->fwd_tiles, x_tiles);
+        const int tiles = std::max(1, std::min({h->fwd_tiles, x_tiles, (int)((1ull << 31) / row_tile_bytes)}));
         const int groups = (x_tiles + tiles - 1) / tiles;
         dim3 rgrid((unsigned)((long long)h->Nk * groups));
 #define OCEAN_FWDB_RES_ARGS NT, rgrid, res_lds, h->stream, uh, ul, bst, h->ws.phi, h->Nk, h->Nx, h->Nb, cols, col0, ncb, \
