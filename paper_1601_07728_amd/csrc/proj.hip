@@ -435,7 +435,7 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
 #pragma unroll
         for (int c = 0; c < TC; ++c) asm volatile("" : "+v"(tre[c]), "+v"(tim[c]));
     };
-    // tile done: write its 16 rows of phi and start the next one from zero.  Each store
+    // tile done: write its 16 rows of phi and start the next one from zero.  FP64: each store
     // writes one complex value per lane: neighbouring lanes (real columns 2c and 2c + 1, the
     // re and im parts of complex column c) swap one of two accumulator rows, so that the even
     // lane holds column c of the first row and the odd lane column c of the second (half as
@@ -444,6 +444,14 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
     const bool odd = lane & 1;
     auto finish_tile = [&](int tile) {
         const int rbase = tile * RPT + wave * 16;
+        if constexpr (sizeof(T) == 4) {
+            // FP32: two complex values per lane (shared with the bf16 forwards)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                store_fwd_tile<true>(acc[t], pw, 0, lane, rbase, 8 * t, Nx, ncb, col0, k, Nk, cols);
+                acc[t] = ACC{0, 0, 0, 0};
+            }
+        } else {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int c = 8 * t + (i >> 1);   // this lane's complex column in the pass
@@ -457,6 +465,7 @@ __global__ __launch_bounds__(64 * WAVES) void proj_fwd_res_kernel(
                 bstore<C2>(v, pw, ok ? (unsigned)(phi_index_x(row, col0 + c, k, Nk, cols) * sizeof(C2)) : kOob);
             }
             acc[t] = ACC{0, 0, 0, 0};
+        }
         }
         if constexpr (TQ > 0) {
             // sum the lane groups (every group then holds the sums); lane (i, kq) takes

@@ -45,55 +45,6 @@ __device__ __forceinline__ int xcd_block() {
     return (int)(xcd * q8 + (xcd < r8 ? xcd : r8) + pos);
 }
 
-// Store one 16x16 result tile of the forward projection (register r of lane i + 16 kq:
-// row 4 kq + r, real column i of the tile) as two complex columns per lane.  The four lanes
-// of a quad transpose their four registers with two exchange rounds, after which lane
-// 4 a + p holds row 4 kq + p, real columns 4 a .. 4 a + 3 (complex columns 2 a, 2 a + 1 of
-// the tile): one store instruction per tile covers it, against four with one real value per
-// lane (the store instructions, not the bytes, cost in these kernels).  phi is FP32 pairs in
-// the split mode (LO) and bf16 pairs (rounded to nearest even) in the BF16 mode.  Rows at or
-// past Nx and complex columns at or past ncb are not written: a lane whose second column is
-// past ncb writes its first one with a narrower store (offsets out of range drop a store).
-// pw covers phi from element idx0 (the block's first row and the pass's first column) on;
-// the launcher keeps a block's rows within 2 GiB of it.
-template <bool LO>
-__device__ __forceinline__ void store_fwd_tile(v4f a, Rsrc pw, size_t idx0, int lane, int rowtop, int c_tile,
-                                               int Nx, int ncb, int col0, int k, int Nk, int cols) {
-    const int i = lane & 15, kq = lane >> 4, p = i & 3;
-    float v[4] = {a[0], a[1], a[2], a[3]};
-#pragma unroll
-    for (int b = 1; b <= 2; b <<= 1) {
-#pragma unroll
-        for (int r0 = 0; r0 < 4; ++r0) {
-            if (r0 & b) continue;
-            const int r1 = r0 | b;
-            const bool hi = p & b;
-            const float t = __shfl_xor(hi ? v[r0] : v[r1], b);
-            if (hi) v[r0] = t;
-            else v[r1] = t;
-        }
-    }
-    const int row = rowtop + 4 * kq + p;
-    const int c = c_tile + 2 * (i >> 2);
-    const bool rok = row < Nx;
-    const unsigned base = (unsigned)(phi_index_x(row, col0 + c, k, Nk, cols) - idx0) * (LO ? 8u : 4u);
-    const unsigned off2 = (rok && c + 1 < ncb) ? base : kOob;
-    const unsigned off1 = (rok && c + 1 == ncb) ? base : kOob;
-    if constexpr (LO) {
-        typedef float f4 __attribute__((ext_vector_type(4)));
-        typedef float f2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, f4{v[0], v[1], v[2], v[3]}), pw, (int)off2, 0, 0);
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, f2{v[0], v[1]}),
-                                              pw, (int)off1, 0, 0);
-    } else {
-        const bf16c c0{(__bf16)v[0], (__bf16)v[1]}, c1{(__bf16)v[2], (__bf16)v[3]};
-        const unsigned w0 = __builtin_bit_cast(unsigned, c0), w1 = __builtin_bit_cast(unsigned, c1);
-        typedef unsigned u2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(u2{w0, w1}, pw, (int)off2, 0, 0);
-        __builtin_amdgcn_raw_buffer_store_b32(w0, pw, (int)off1, 0, 0);
-    }
-}
-
 // Wait until at most N vector-memory loads of this wave are outstanding (vmcnt counts loads
 // in issue order); expcnt and lgkmcnt are left alone.
 template <int N> __device__ __forceinline__ void wait_vmcnt() {
