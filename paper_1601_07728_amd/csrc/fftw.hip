@@ -598,6 +598,154 @@ __global__ __launch_bounds__(256) void fft_w_cube_kernel(
     }
 }
 
+// Two adjacent stored phi values (lines l, l + 1 of one k row) moved as one access: 8 bytes
+// for bf16 pairs, 16 for FP32 pairs.
+template <typename S> struct PairW;
+template <> struct PairW<bf16c> { typedef uint2 t; };
+template <> struct PairW<float2> { typedef float4 t; };
+__device__ __forceinline__ void pair_unpack(uint2 w, float2& a, float2& b) {
+    a = phi_load<float2, bf16c>(reinterpret_cast<const bf16c*>(&w.x));
+    b = phi_load<float2, bf16c>(reinterpret_cast<const bf16c*>(&w.y));
+}
+__device__ __forceinline__ void pair_unpack(float4 w, float2& a, float2& b) {
+    a = make_float2(w.x, w.y);
+    b = make_float2(w.z, w.w);
+}
+__device__ __forceinline__ void pair_pack(float2 a, float2 b, uint2& w) {
+    phi_store<float2, bf16c>(reinterpret_cast<bf16c*>(&w.x), a);
+    phi_store<float2, bf16c>(reinterpret_cast<bf16c*>(&w.y), b);
+}
+__device__ __forceinline__ void pair_pack(float2 a, float2 b, float4& w) { w = make_float4(a.x, a.y, b.x, b.y); }
+
+// The cube kernel with two lines per thread (FP32 arithmetic, u carrying the Bloch phase,
+// N = 8, L >= 8): the same five phases and LDS layout, with every HBM and LDS access moving
+// the values of lines l and l + 1 together, so the block issues half as many memory
+// instructions for the same bytes.  Lines past `total` (the padding of the last x-block,
+// inside the allocation) are transformed as zeros and written back as zeros.
+template <typename S, int N, int L>
+__global__ __launch_bounds__(256) void fft_w_cube2_kernel(S* __restrict__ phi, const float* __restrict__ W,
+                                                          int total, int cols) {
+    typedef float2 C2;
+    typedef typename PairW<S>::t PW;
+    constexpr int NK = N * N * N, NP = N * N;
+    constexpr int M = 256 / (int)sizeof(C2);
+    constexpr int PAD = (M - ((N - 1) * L) % M) % M;
+    constexpr int LP = L / 2;                   // line pairs per block
+    constexpr int TPL = 256 / LP;               // pencil stride between a thread's pencils
+    constexpr int PPT = NP * LP / 256;          // pencils per thread and pass
+    constexpr int RUN = N * L + PAD;
+    static_assert(NP * LP % 256 == 0 && PAD % 2 == 0 && L % 2 == 0, "whole pencils, aligned pairs");
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2* buf = reinterpret_cast<C2*>(smem);      // element (k, l) at k L + l + (k / N) PAD
+
+    // XCD-contiguous renumbering of the workgroups (see fft_w_pow2_kernel)
+    const unsigned nblk = gridDim.x, q8 = nblk / 8, r8 = nblk % 8;
+    const unsigned xcd = blockIdx.x % 8, pos = blockIdx.x / 8;
+    const int lblk = (int)(xcd * q8 + (xcd < r8 ? xcd : r8) + pos);
+    const int line0 = lblk * L;
+    const int xbc = kXB * cols;
+    const int xblk = line0 / xbc;
+    const size_t kbase = (size_t)xblk * NK * xbc + (size_t)(line0 - xblk * xbc);
+    const int l = 2 * (threadIdx.x % LP), u0 = threadIdx.x / LP;
+    const bool ok0 = line0 + l < total, ok1 = line0 + l + 1 < total;
+    const float* w0 = W + (size_t)(ok0 ? (line0 + l) / cols : 0) * NK;
+    const float* w1 = W + (size_t)(ok1 ? (line0 + l + 1) / cols : 0) * NK;
+    S* pl = phi + kbase + l;
+    auto lds_get = [&](int e, C2& a, C2& b) {
+        const float4 q = *reinterpret_cast<const float4*>(&buf[e]);
+        a = make_float2(q.x, q.y);
+        b = make_float2(q.z, q.w);
+    };
+    auto lds_put = [&](int e, C2 a, C2 b) { *reinterpret_cast<float4*>(&buf[e]) = make_float4(a.x, a.y, b.x, b.y); };
+
+    // P1: HBM -> registers, FFT along k3 -> LDS
+    {
+        PW r[PPT][N];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+#pragma unroll
+            for (int b = 0; b < N; ++b) r[j][b] = *reinterpret_cast<const PW*>(&pl[((u0 + j * TPL) * N + b) * xbc]);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int u = u0 + j * TPL;
+            C2 va[N], vb[N];
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                pair_unpack(r[j][b], va[b], vb[b]);
+                if (!ok0) va[b].x = va[b].y = 0.f;
+                if (!ok1) vb[b].x = vb[b].y = 0.f;
+            }
+            fft_reg<float, N, N, false>(va);
+            fft_reg<float, N, N, false>(vb);
+#pragma unroll
+            for (int b = 0; b < N; ++b) lds_put(u * RUN + l + b * L, va[b], vb[b]);
+        }
+    }
+    __syncthreads();
+    auto k2_pass = [&](auto inv) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int u = u0 + j * TPL;
+            const int base = ((u / N) * NP + (u % N)) * L + l + (u / N) * N * PAD;
+            C2 va[N], vb[N];
+#pragma unroll
+            for (int b = 0; b < N; ++b) lds_get(base + b * (N * L + PAD), va[b], vb[b]);
+            fft_reg<float, N, N, decltype(inv)::value>(va);
+            fft_reg<float, N, N, decltype(inv)::value>(vb);
+#pragma unroll
+            for (int b = 0; b < N; ++b) lds_put(base + b * (N * L + PAD), va[b], vb[b]);
+        }
+    };
+    k2_pass(std::false_type{});
+    __syncthreads();
+    // P3: FFT along k1, W(x, R) of each line's point (stored [x][R2 R3][R1], 1/Nk included),
+    // inverse FFT along k1
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int u = u0 + j * TPL;
+        const int base = u * L + l + (u / N) * PAD;
+        constexpr int STEP = NP * L + N * PAD;
+        C2 va[N], vb[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) lds_get(base + b * STEP, va[b], vb[b]);
+        fft_reg<float, N, N, false>(va);
+        fft_reg<float, N, N, false>(vb);
+        const WVec<float, N> wa = reinterpret_cast<const WVec<float, N>*>(w0)[u];
+        const WVec<float, N> wb = reinterpret_cast<const WVec<float, N>*>(w1)[u];
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            const float fa = ok0 ? wa.v[b] : 0.f, fb = ok1 ? wb.v[b] : 0.f;
+            va[b].x *= fa;
+            va[b].y *= fa;
+            vb[b].x *= fb;
+            vb[b].y *= fb;
+        }
+        fft_reg<float, N, N, true>(va);
+        fft_reg<float, N, N, true>(vb);
+#pragma unroll
+        for (int b = 0; b < N; ++b) lds_put(base + b * STEP, va[b], vb[b]);
+    }
+    __syncthreads();
+    k2_pass(std::true_type{});
+    __syncthreads();
+    // P5: inverse FFT along k3 -> HBM
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int u = u0 + j * TPL;
+        C2 va[N], vb[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) lds_get(u * RUN + l + b * L, va[b], vb[b]);
+        fft_reg<float, N, N, true>(va);
+        fft_reg<float, N, N, true>(vb);
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            PW w;
+            pair_pack(va[b], vb[b], w);
+            *reinterpret_cast<PW*>(&pl[(u * N + b) * xbc]) = w;
+        }
+    }
+}
+
 template <typename T, int N, int L>
 size_t cube_lds_bytes() {
     typedef typename C2T<T>::t C2;
@@ -611,6 +759,12 @@ hipError_t launch_cube(ocean_bse_s* h, S* phi, const T* W, const double2* ph, in
                        int cols, bool phase) {
     const unsigned nblk = (unsigned)((total + L - 1) / L);
     const size_t lds = cube_lds_bytes<T, N, L>();
+    if constexpr (sizeof(T) == 4 && N == 8 && L >= 8) {
+        if (!phase && h->fft_pairs) {
+            fft_w_cube2_kernel<S, N, L><<<nblk, 256, lds, h->stream>>>(phi, W, total, cols);
+            return hipGetLastError();
+        }
+    }
 #define OCEAN_CUBE_ARGS phi, W, ph, h->nx[0], h->nx[1], h->nx[2], h->phase_off[0], h->phase_off[1], h->phase_off[2], total, cols
     if (phase) {
         if constexpr (sizeof(T) == 8)

@@ -134,6 +134,7 @@ struct ocean_bse_s {
 
     // tuning knobs (picked at create, overridable through the environment)
     int fft_lines = 16;          // lines per block of the k-grid transform
+    int fft_pairs = 1;           // FP32-arithmetic cube transform: two lines per thread
     int bwd_target_blocks = 2048;  // back-projection grid size the x chunking aims at
     int bwd_waves = 8;           // back-projection: at most this many waves (16 bands each) per block
     int fwd_ms = 2;              // forward projection: 16 * fwd_ms rows per wave

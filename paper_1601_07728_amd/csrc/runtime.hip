@@ -488,6 +488,7 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
     h->fwd_tiles = env_int("OCEAN_FWD_TILES", 0);
     h->bwd_waves = std::min(8, std::max(1, env_int("OCEAN_BWD_WAVES", 8)));
     h->quad_tail = env_int("OCEAN_QUAD_TAIL", 1);
+    h->fft_pairs = env_int("OCEAN_FFT_PAIRS", 1);
 
     auto fail = [&](int rc) {
         destroy_handle(h);
