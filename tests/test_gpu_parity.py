@@ -414,3 +414,33 @@ def test_resident_operand_forward_matches_chunked_and_oracle(case, precision, to
                 assert _rel(y[v], refs[v]) <= tol, (case, precision, nv, ft, v)
         for v in range(nv):
             assert _rel(y0[v], refs[v]) <= tol, (case, precision, nv, v)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("split_bf16", 1e-4), ("bf16", 1e-2)])
+@pytest.mark.parametrize("nx,n_core,n_vec,lines", [((3, 2, 2), 6, 3, "8"), ((5, 5, 3), 3, 1, "8"),
+                                                    ((5, 5, 3), 3, 1, "16"), ((3, 3, 3), 6, 5, "16")])
+def test_transform_line_pairs_match_single_lines(nx, n_core, n_vec, lines, precision, tol, monkeypatch):
+    """The FP32-arithmetic cube transform with two lines per thread gives the one-line-per-
+    thread kernel's H*v bit for bit, on an 8^3 k grid with an even and an odd number of lines
+    (x points times columns: 12 x 18; 75 x 3, whose last block holds padding lines; 27 x 30)
+    and 8 or 16 lines per block, and the oracle's to the precision's tolerance."""
+    ob = _ob()
+    local = n_core == 6
+    cr = synth.make_crystal("pairs", a=6.5, tau=(0.7, 1.9, 3.1), nk=(8, 8, 8), nx=nx, n_bands=6, n_core=n_core,
+                            e_range_ev=30.0, eps=5.0, seed=21, n_local=5 if local else 0,
+                            multiplet_ev=dict(synth.L_EDGE_MULTIPLET_EV) if local else None, psi0="none")
+    hc, kl = _oracle_mats(cr)
+    x = synth.complex_gaussian(np.random.default_rng(5), (n_vec, cr.n_k, cr.n_bands, cr.n_core))
+    xd = _to_dev(x)
+    monkeypatch.setenv("OCEAN_FFT_LINES", lines)
+    ys = []
+    for pairs in ("0", "1"):
+        monkeypatch.setenv("OCEAN_FFT_PAIRS", pairs)
+        _say(f"[transform line pairs] nx={nx} n_core={n_core} n_vec={n_vec} lines={lines} {precision} pairs={pairs}")
+        h = ob.Bse.from_crystal(cr, precision=precision)
+        ys.append(h.apply(xd).cpu().numpy())
+        h.close()
+    assert np.array_equal(ys[0], ys[1])
+    for v in range(n_vec):
+        ref = orc.apply_h(cr, x[v], hc, kl)
+        assert _rel(ys[1][v], ref) <= tol, (v, _rel(ys[1][v], ref))
