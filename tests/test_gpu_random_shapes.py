@@ -1,4 +1,4 @@
-"""GPU parity over a seeded spread of small shapes that the hand-picked cases do not list:
+"""GPU parity over a seeded spread of 64 small shapes that the hand-picked cases do not list:
 k grids of any size per axis (the general, power-of-two and cube transform kernels), odd
 real-space grids, band counts from 1 up, 1, 2, 3, 6 or 12 core states, with and without the
 local term (6 core states), 1 to 4 vectors, skewed cells, and every projection precision.  Each case compares one
@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-13, "fp32": 2e-5, "split_bf16": 1e-4, "bf16": 1e-2}
 
 
-def _cases(n=40, seed=2024):
+def _cases(n=64, seed=2024):
     rng = np.random.default_rng(seed)
     out = []
     for c in range(n):
