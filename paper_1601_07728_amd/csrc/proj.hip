@@ -22,6 +22,8 @@
 // On gfx950 an FP64 16x16x4 MFMA takes the issue slots of 16 wave-wide FP64 FMAs, so in FP64
 // a pass whose columns leave at most 2 complex columns after whole 16-wide tiles contracts
 // those with plain FMAs instead of a mostly empty tile.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ocean {
@@ -580,7 +582,13 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     typedef typename Cplx<T>::acc ACC;
     constexpr int SS = XT / 8;
     constexpr int TILE = 2 * XT * CP;          // complex pairs of one phi' tile
-    constexpr int PER = (XT * CP + 64 * W - 1) / (64 * W);
+    // phi' registers: FP64 one complex value per load; FP32 two adjacent columns per 16-byte
+    // load (half the load instructions for the same bytes)
+    constexpr int VC = sizeof(T) == 4 ? 2 : 1;
+    typedef typename std::conditional<sizeof(T) == 4, float4, C2>::type PV;
+    constexpr int CPV = CP / VC;               // loads per point
+    static_assert(CP % VC == 0, "column pairs");
+    constexpr int PER = (XT * CPV + 64 * W - 1) / (64 * W);
     static_assert(8 * NT + TC + 2 * TQ <= CP, "columns per pass");
     static_assert(R == 2 || R == 3, "ring depth");
     static_assert(TQ == 0 || sizeof(T) == 4, "quad tail: FP32");
@@ -611,15 +619,21 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     const Rsrc prs = make_rsrc(pbase, (size_t)((x_end - 1) / kXB - xb0 + 1) * Nk * kXB * cols * sizeof(C2));
 
     // tile loads (masked to zero past the chunk end)
-    auto issue = [&](int x0, C2 (&pp)[PER], C2 (&uu)[SS][2]) {
+    auto issue = [&](int x0, PV (&pp)[PER], C2 (&uu)[SS][2]) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 64 * W * j;
-            const int xl = e / CP, cl = e - xl * CP;
+            const int xl = e / CPV, cl = VC * (e - xl * CPV);
             const int x = x0 + xl;
             const bool ok = xl < XT && cl < ncb && x < x_end;
             const unsigned off = (unsigned)((phi_index_x(x, col0 + cl, k, Nk, cols) - (size_t)xb0 * Nk * kXB * cols) * sizeof(C2));
-            pp[j] = bload<C2>(prs, ok ? off : kOob);
+            if constexpr (VC == 2) {
+                float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(prs, (int)(ok ? off : kOob), 0, 0));
+                if (cl + 1 >= ncb) v.z = v.w = 0.f;   // past the pass: the next point's column, or nothing
+                pp[j] = v;
+            } else {
+                pp[j] = bload<C2>(prs, ok ? off : kOob);
+            }
         }
 #pragma unroll
         for (int ss = 0; ss < SS; ++ss)
@@ -631,15 +645,22 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
             }
     };
     // point xl of the tile = (sub-step xl / 8, lane group (xl % 8) / 2, pair slot xl % 2)
-    auto stage = [&](C2* dst, const C2 (&pp)[PER]) {
+    auto stage = [&](C2* dst, const PV (&pp)[PER]) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int e = threadIdx.x + 64 * W * j;
-            const int xl = e / CP, cl = e - xl * CP;
-            if (xl < XT && cl < ncb) {
-                C2* d = dst + ((((xl >> 3) * 4 + ((xl & 7) >> 1)) * CP + cl) * 2) * 2 + (xl & 1);
-                d[0] = pp[j];
-                d[2] = C2{pp[j].y, -pp[j].x};
+            const int xl = e / CPV, cl0 = VC * (e - xl * CPV);
+#pragma unroll
+            for (int q = 0; q < VC; ++q) {
+                const int cl = cl0 + q;
+                if (xl < XT && cl < ncb) {
+                    C2 v;
+                    if constexpr (VC == 2) v = q ? C2{pp[j].z, pp[j].w} : C2{pp[j].x, pp[j].y};
+                    else v = pp[j];
+                    C2* d = dst + ((((xl >> 3) * 4 + ((xl & 7) >> 1)) * CP + cl) * 2) * 2 + (xl & 1);
+                    d[0] = v;
+                    d[2] = C2{v.y, -v.x};
+                }
             }
         }
     };
@@ -698,7 +719,7 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     for (int e = threadIdx.x; e < R * TILE; e += 64 * W) (&sP[0][0])[e] = C2{0, 0};
 
     C2 ua[R][SS][2];
-    C2 pr[R][PER];
+    PV pr[R][PER];
 #pragma unroll
     for (int r = 0; r + 1 < R; ++r) issue(x_begin + r * XT, pr[r], ua[r]);
     __syncthreads();
@@ -707,8 +728,8 @@ __global__ __launch_bounds__(64 * W) void proj_bwd_kernel(
     // contract slot c, stage tile x0 + XT (slot c + 1) into its LDS buffer.  The barrier at
     // the top publishes the previous step's staging and retires every read of the buffer
     // staged now.
-    auto step = [&](int x0, C2 (&pn)[PER], C2 (&un)[SS][2], const C2* cur, const C2 (&uc)[SS][2],
-                    C2* nxt, const C2 (&p1)[PER]) {
+    auto step = [&](int x0, PV (&pn)[PER], C2 (&un)[SS][2], const C2* cur, const C2 (&uc)[SS][2],
+                    C2* nxt, const PV (&p1)[PER]) {
         __syncthreads();
         issue(x0 + (R - 1) * XT, pn, un);
         __builtin_amdgcn_sched_barrier(0);
