@@ -698,6 +698,9 @@ class Mlp:
         return loss.value, g
 
     def train_step(self, x, t, lr: float, want_loss: bool = False):
+        """One Adam step on device batch (x, t).  Without want_loss the call returns with the
+        step still queued on the network's stream, which reads x and t: keep them alive until
+        the device has been synchronised."""
         loss = ctypes.c_double()
         _check(lib().ocean_mlp_train_step(self._h, self._f32(x), self._f32(t), x.shape[0], float(lr),
                                           ctypes.byref(loss) if want_loss else None))

@@ -107,6 +107,10 @@ def train(mlp: Mlp, x, t, epochs: int, batch: int, lr: float, seed: int = 0, log
     g.manual_seed(seed)
     n = x.shape[0]
     hist = []
+    # a step without its loss returns with its work still queued on the network's stream,
+    # reading the batch: the batch stays referenced (in_use) until the synchronisation before
+    # the next step has retired that work, so torch cannot hand its memory to the next batch
+    in_use = None
     for ep in range(epochs):
         perm = torch.randperm(n, device="cuda", generator=g)
         want = log_every > 0 and (ep % log_every == 0 or ep == epochs - 1)
@@ -116,12 +120,14 @@ def train(mlp: Mlp, x, t, epochs: int, batch: int, lr: float, seed: int = 0, log
             xb = x.index_select(0, idx).contiguous()
             tb = t.index_select(0, idx).contiguous()
             torch.cuda.synchronize()
+            in_use = (xb, tb)
             lv = mlp.train_step(xb, tb, lr, want_loss=want)
             if want:
                 losses.append(lv)
         if want:
             hist.append((ep, float(np.mean(losses))))
     torch.cuda.synchronize()
+    del in_use
     return hist
 
 
