@@ -93,8 +93,10 @@ __device__ __forceinline__ void stage_pair(T* buf, int ss, int kq, int ns, int c
 // Forward projection.  Block = 4 waves and one k; wave w owns rows
 // [xt*64*MS + w*16*MS, +16*MS) and every column tile.  The bands are walked in chunks of
 // KC: the psi chunk (B operand, shared by all waves) is staged in LDS in MFMA order, double
-// buffered, while each wave keeps the u values (A operand) of the next chunk in flight.
-template <typename T, int MS, int NT, int TC, int KC, int CP, bool PAIR>
+// buffered, while each wave keeps the u values (A operand) of the next chunk in flight.  FP32
+// runs a remainder of at most 4 real columns on the 4x4x1 MFMA (TQ = 1, as the resident form
+// below does) instead of a mostly empty 16-column tile.
+template <typename T, int MS, int NT, int TC, int TQ, int KC, int CP, bool PAIR>
 __global__ __launch_bounds__(256) void proj_fwd_kernel(
     const typename Cplx<T>::c2* __restrict__ U, const double2* __restrict__ psi,
     typename Cplx<T>::c2* __restrict__ phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0,
@@ -103,7 +105,9 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
     typedef typename Cplx<T>::acc ACC;
     typedef typename Vec4<T>::t V4;
     constexpr int SS = KC / 8;                 // 8-band sub-steps per chunk
-    constexpr int BUF = SS * NT * 64 * 4;      // T values per staged chunk
+    constexpr int NS = NT + TQ;                // staged column tiles: the quad tail reads the last
+    static_assert(TQ == 0 || sizeof(T) == 4, "quad tail: FP32");
+    constexpr int BUF = SS * NS * 64 * 4;      // T values per staged chunk
     __shared__ __align__(16) T sB[2][BUF];
     __shared__ __align__(16) C2 sT[2][KC][TC > 0 ? TC : 1];   // FMA tail columns, (re, im)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
             if (nl < KC && cl < ncb) {
                 const int r8 = nl & 7;
                 const int kq8 = sizeof(T) == 8 ? (r8 & 3) : (r8 >> 1), ns8 = sizeof(T) == 8 ? (r8 >> 2) : (r8 & 1);
-                if (cl < 8 * NT) stage_pair<T, NT>(sB[buf], nl >> 3, kq8, ns8, cl, pv[j].x, pv[j].y);
+                if (cl < 8 * NS) stage_pair<T, NS>(sB[buf], nl >> 3, kq8, ns8, cl, pv[j].x, pv[j].y);
                 else if (TC > 0) sT[buf][nl][cl - 8 * NT] = C2{(T)pv[j].x, (T)pv[j].y};
             }
         }
@@ -199,6 +203,12 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
     for (int ms = 0; ms < MS; ++ms)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[ms][t] = ACC{0, 0, 0, 0};
+    // quad tail (FP32): the last <= 4 real columns on the 4x4x1 MFMA (the resident forward's
+    // layout: lane l reads the B values lane (l % 4) + 16 kq holds for the staged tile NT)
+    v4f accq[MS];
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms) accq[ms] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int qlane = (lane & 3) + (lane & 48);
     // FMA tail: lane (i, kq) sums its own bands for row i; the lane groups are added at the end
     T tre[MS][TC > 0 ? TC : 1], tim[MS][TC > 0 ? TC : 1];
 #pragma unroll
@@ -228,7 +238,9 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
             V4 bv[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-                bv[t] = *reinterpret_cast<const V4*>(&sB[buf][((ss * NT + t) * 64 + lane) * 4]);
+                bv[t] = *reinterpret_cast<const V4*>(&sB[buf][((ss * NS + t) * 64 + lane) * 4]);
+            V4 bq;
+            if constexpr (TQ > 0) bq = *reinterpret_cast<const V4*>(&sB[buf][((ss * NS + NT) * 64 + qlane) * 4]);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
 #pragma unroll
@@ -238,6 +250,10 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
                     for (int t = 0; t < NT; ++t) {
                         const T b = s == 0 ? bv[t].x : s == 1 ? bv[t].y : s == 2 ? bv[t].z : bv[t].w;
                         acc[ms][t] = mfma16(av, b, acc[ms][t]);
+                    }
+                    if constexpr (TQ > 0) {
+                        const T b = s == 0 ? bq.x : s == 1 ? bq.y : s == 2 ? bq.z : bq.w;
+                        accq[ms] = mfma_quad((float)av, (float)b, accq[ms]);
                     }
                 }
             }
@@ -299,6 +315,27 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(
                 out[2 * phi_index_x(row, col0, k, Nk, cols) + 2 * (8 * NT + c) + 1] = im;
             }
         }
+    if constexpr (TQ > 0) {
+        // sum the lane groups; lane (i, kq) takes register r = kq: row 4 (i / 4) + kq, real
+        // column 16 NT + i % 4; the even lane of each pair writes (re, im) of its complex column
+#pragma unroll
+        for (int ms = 0; ms < MS; ++ms) {
+            v4f q4 = accq[ms];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                q4[r] += __shfl_xor(q4[r], 16);
+                q4[r] += __shfl_xor(q4[r], 32);
+            }
+            const float q = kq == 0 ? q4[0] : kq == 1 ? q4[1] : kq == 2 ? q4[2] : q4[3];
+            const float y = __shfl_xor(q, 1);
+            const int c = 8 * NT + ((i & 3) >> 1);
+            const int row = rowbase + 16 * ms + 4 * (i >> 2) + kq;
+            if (!(lane & 1) && c < ncb && row < Nx) {
+                out[2 * phi_index_x(row, col0 + c, k, Nk, cols)] = (T)q;
+                out[2 * phi_index_x(row, col0 + c, k, Nk, cols) + 1] = (T)y;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -800,7 +837,7 @@ template <> struct Tiles<double> { static constexpr int KC = 16, XT = 16, R = 3,
 template <> struct Tiles<float> { static constexpr int KC = 32, XT = 32, R = 3, RR = 3; };
 
 template <typename T, int MS>
-hipError_t fwd_dispatch_nt(int NT, int TC, dim3 grid, hipStream_t st, const void* U, const double* x,
+hipError_t fwd_dispatch_nt(int NT, int TC, int TQ, dim3 grid, hipStream_t st, const void* U, const double* x,
                            void* phi, int Nk, int Nx, int Nb, int Nc, int cols, int col0, int ncb,
                            int x_tiles) {
     typedef typename Cplx<T>::c2 C2;
@@ -809,23 +846,25 @@ hipError_t fwd_dispatch_nt(int NT, int TC, dim3 grid, hipStream_t st, const void
     const double2* ps = reinterpret_cast<const double2*>(x);
     // FP32 with an even band count loads two bands per 16-byte load (PAIR)
     const bool pair = sizeof(T) == 4 && (Nb & 1) == 0;
-#define OCEAN_FWD(nt, tc, cp) \
-    if (NT == nt && TC == tc) { \
+#define OCEAN_FWD(nt, tc, tq, cp) \
+    if (NT == nt && TC == tc && TQ == tq) { \
         if (pair) \
-            proj_fwd_kernel<T, MS, nt, tc, Tiles<T>::KC, cp, sizeof(T) == 4><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); \
+            proj_fwd_kernel<T, MS, nt, tc, tq, Tiles<T>::KC, cp, sizeof(T) == 4><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); \
         else \
-            proj_fwd_kernel<T, MS, nt, tc, Tiles<T>::KC, cp, false><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); \
+            proj_fwd_kernel<T, MS, nt, tc, tq, Tiles<T>::KC, cp, false><<<grid, 256, 0, st>>>(u, ps, p, Nk, Nx, Nb, Nc, cols, col0, ncb, x_tiles); \
         return hipGetLastError(); \
     }
     if (ncb <= kColsPerPass) {
-        OCEAN_FWD(1, 0, kColsPerPass) OCEAN_FWD(2, 0, kColsPerPass) OCEAN_FWD(3, 0, kColsPerPass)
+        OCEAN_FWD(1, 0, 0, kColsPerPass) OCEAN_FWD(2, 0, 0, kColsPerPass) OCEAN_FWD(3, 0, 0, kColsPerPass)
         if constexpr (sizeof(T) == 8) {
-            OCEAN_FWD(1, 1, kColsPerPass) OCEAN_FWD(1, 2, kColsPerPass)
-            OCEAN_FWD(2, 1, kColsPerPass) OCEAN_FWD(2, 2, kColsPerPass)
+            OCEAN_FWD(1, 1, 0, kColsPerPass) OCEAN_FWD(1, 2, 0, kColsPerPass)
+            OCEAN_FWD(2, 1, 0, kColsPerPass) OCEAN_FWD(2, 2, 0, kColsPerPass)
+        } else {
+            OCEAN_FWD(1, 0, 1, kColsPerPass) OCEAN_FWD(2, 0, 1, kColsPerPass)
         }
     } else if constexpr (sizeof(T) == 8 && MS == 1) {
-        OCEAN_FWD(3, 1, kColsPerWidePass) OCEAN_FWD(3, 2, kColsPerWidePass) OCEAN_FWD(4, 0, kColsPerWidePass)
-        OCEAN_FWD(4, 1, kColsPerWidePass) OCEAN_FWD(4, 2, kColsPerWidePass) OCEAN_FWD(5, 0, kColsPerWidePass)
+        OCEAN_FWD(3, 1, 0, kColsPerWidePass) OCEAN_FWD(3, 2, 0, kColsPerWidePass) OCEAN_FWD(4, 0, 0, kColsPerWidePass)
+        OCEAN_FWD(4, 1, 0, kColsPerWidePass) OCEAN_FWD(4, 2, 0, kColsPerWidePass) OCEAN_FWD(5, 0, 0, kColsPerWidePass)
     }
 #undef OCEAN_FWD
     return hipErrorInvalidValue;
@@ -1042,20 +1081,20 @@ hipError_t launch_proj_fwd(ocean_bse_s* h, const double* x, int nv, int col0, in
     const int MS = (h->fwd_ms == 1 || ncb > kColsPerPass) ? 1 : 2;
     const int cols = nv * h->Nc;
     int NT, TC, TQ;
-    column_split(ncb, h->precision == OCEAN_PREC_FP64, false, false, &NT, &TC, &TQ);
+    column_split(ncb, h->precision == OCEAN_PREC_FP64, false, h->quad_tail != 0, &NT, &TC, &TQ);
     const int x_tiles = (h->Nx + 64 * MS - 1) / (64 * MS);
     dim3 grid((unsigned)(h->Nk * x_tiles));
     hipError_t e;
     const int slot = prof_begin(h, "proj_fwd");
     if (h->precision == OCEAN_PREC_FP64)
-        e = MS == 1 ? fwd_dispatch_nt<double, 1>(NT, TC, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
+        e = MS == 1 ? fwd_dispatch_nt<double, 1>(NT, TC, TQ, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
                                                  h->Nb, h->Nc, cols, col0, ncb, x_tiles)
-                    : fwd_dispatch_nt<double, 2>(NT, TC, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
+                    : fwd_dispatch_nt<double, 2>(NT, TC, TQ, grid, h->stream, h->U64, x, h->ws.phi, h->Nk, h->Nx,
                                                  h->Nb, h->Nc, cols, col0, ncb, x_tiles);
     else
-        e = MS == 1 ? fwd_dispatch_nt<float, 1>(NT, TC, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
+        e = MS == 1 ? fwd_dispatch_nt<float, 1>(NT, TC, TQ, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
                                                 h->Nb, h->Nc, cols, col0, ncb, x_tiles)
-                    : fwd_dispatch_nt<float, 2>(NT, TC, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
+                    : fwd_dispatch_nt<float, 2>(NT, TC, TQ, grid, h->stream, h->U32, x, h->ws.phi, h->Nk, h->Nx,
                                                 h->Nb, h->Nc, cols, col0, ncb, x_tiles);
     prof_end(h, slot);
     return e;

@@ -378,8 +378,8 @@ def test_resident_operand_forward_matches_chunked_and_oracle(case, precision, to
     """The forward projection with psi[k] (in the bf16 modes its staged B chunks) resident in
     LDS (OCEAN_FWD_TILES row tiles per block: one tile, several, and more than the x grid
     holds) gives the band-chunked kernel's H*v bit for bit (the same MFMA sequence per output
-    element; FP32 with the 4x4x1 remainder tiles off on both sides), and the oracle's to the
-    precision's tolerance with them on, for 1..5 vectors (6 to 30 columns: one to three column
+    element; FP32 with the 4x4x1 remainder tiles off on both sides, and again with them on), and
+    the oracle's to the precision's tolerance with them on, for 1..5 vectors (6 to 30 columns: one to three column
     tiles, with and without the FP64 multiply-add tail or the FP32 4-column remainder, one or
     two passes)."""
     torch = _torch()
@@ -405,13 +405,17 @@ def test_resident_operand_forward_matches_chunked_and_oracle(case, precision, to
             torch.cuda.synchronize()
             assert np.array_equal(y, y0), (case, precision, nv, ft, float(np.abs(y - y0).max()))
         monkeypatch.setenv("OCEAN_QUAD_TAIL", "1")
+        yq = {}
         for ft in ("0", "4"):
             monkeypatch.setenv("OCEAN_FWD_TILES", ft)
             h = ob.Bse.from_crystal(cr, precision=precision)
             y = h.apply(xd).cpu().numpy()
             h.close()
+            yq[ft] = y
             for v in range(nv):
                 assert _rel(y[v], refs[v]) <= tol, (case, precision, nv, ft, v)
+        # with the FP32 4x4x1 remainder on, both forward forms run it in the same order
+        assert np.array_equal(yq["0"], yq["4"]), (case, precision, nv, float(np.abs(yq["0"] - yq["4"]).max()))
         for v in range(nv):
             assert _rel(y0[v], refs[v]) <= tol, (case, precision, nv, v)
 
