@@ -271,6 +271,45 @@ def bench_batched(ob, seed, steps=200, modes=MODES):
     return out
 
 
+def bench_sites(ob, seed, prec="fp64", reps=5):
+    """The molecule-in-box sites one at a time (eager applies of the three polarisation
+    vectors, HIP-event kernel times after each site's own autotuning): the per-site projection
+    byte rates that bound the batched step."""
+    import torch
+    import synth
+    sites = synth.molecule_sites(seed=seed)
+    torch.cuda.synchronize()
+    rows, tot = [], {"proj_fwd": 0.0, "proj_bwd": 0.0, "reduce_part": 0.0, "u_bytes": 0}
+    for i, (cr, u) in enumerate(sites):
+        h = ob.Bse.from_crystal(cr, precision=prec, u=u)
+        tune = h.autotune(n_vec=3)
+        p0 = torch.from_numpy(cr.psi0).to("cuda") if cr.psi0 is not None else h.dipole_psi0(np.eye(3))
+        for _ in range(2):
+            h.apply(p0)
+        h.set_profiling(True)
+        for _ in range(reps):
+            h.apply(p0)
+        kt = h.kernel_times()
+        h.set_profiling(False)
+        h.close()
+        km = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
+        ub = cr.n_k * cr.n_x * cr.n_bands * U_BYTES[prec]
+        r = {"site": i, "n_bands": cr.n_bands, "n_core": cr.n_core, "tiles": tune,
+             "proj_fwd_ms": km["proj_fwd"], "proj_bwd_ms": km["proj_bwd"], "reduce_part_ms": km.get("reduce_part", 0.0),
+             "fwd_u_GBs": ub / (km["proj_fwd"] * 1e6), "bwd_u_GBs": ub / (km["proj_bwd"] * 1e6)}
+        rows.append(r)
+        for k in ("proj_fwd", "proj_bwd", "reduce_part"):
+            tot[k] += km.get(k, 0.0)
+        tot["u_bytes"] += ub
+        log(f"site {i}: {cr.n_bands} bands, {cr.n_core} core states, fwd {r['fwd_u_GBs']:.0f} GB/s, "
+            f"bwd {r['bwd_u_GBs']:.0f} GB/s of u")
+    return {"precision": prec, "sites": rows,
+            "sum_ms": {k: tot[k] for k in ("proj_fwd", "proj_bwd", "reduce_part")},
+            "u_GBs": {"proj_fwd": tot["u_bytes"] / (tot["proj_fwd"] * 1e6),
+                      "proj_bwd": tot["u_bytes"] / (tot["proj_bwd"] * 1e6)},
+            "workload": "the molecule-in-box sites of the batched workload, each alone, 3 vectors per apply"}
+
+
 def bench_supercell(ob, seed, steps=10, spec_steps=100):
     """One Ti L2,3 site of the 4x4x4 SrTiO3-shaped supercell: 2^3 k, 1200 bands, 64^3 x, u 40 GB
     in FP64 (drawn on the device and borrowed by the FP64 handle), three polarisations per
@@ -496,6 +535,8 @@ def main():
     ap.add_argument("--no-supercell", action="store_true")
     ap.add_argument("--no-paper-shape", action="store_true")
     ap.add_argument("--no-xes", action="store_true")
+    ap.add_argument("--per-site", action="store_true",
+                    help="also time the molecule-in-box sites one at a time (FP64 projection rates per site)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first stream 1 GiB through a plain elementwise kernel (1 GiB read, 1 GiB "
                          "written): the reference for scaling the HBM byte counters")
@@ -659,6 +700,7 @@ def main():
         h.close()
     screening = None if args.no_screening else bench_screening(ob, args.seed, ceilings)
     xes = None if args.no_xes else bench_xes(ob, args.seed)
+    per_site = bench_sites(ob, args.seed) if args.per_site else None
     if not args.no_batched:
         batched = bench_batched(ob, args.seed,
                                 modes=MODES if args.batched_bf16 else tuple(m for m in MODES if m != "bf16"))
@@ -693,6 +735,7 @@ def main():
         "full_spin": full_spin,
         "screening": screening,
         "xes": xes,
+        "batched_per_site": per_site,
         "full_local_basis": full_basis,
         "supercell": supercell,
         "roofline_supercell": None if supercell is None else supercell["roofline"],
