@@ -406,7 +406,7 @@ def bench_paper_shape(ob, seed, steps=200):
     return out
 
 
-def bench_terminator(ob, n_held, n_steps=512, train_epochs=5):
+def bench_terminator(ob, n_held, n_steps=512, train_epochs=5, seeds=None):
     """Learned terminator at the full SrTiO3-shaped size.  The shipped networks
     (paper_1601_07728_amd/terminator_srtio3_l23*.npz, trained by train_terminator.py with the
     library's kernels on 1280 systems x 3 polarisations; one fed levels 0-31, closing 32-step
@@ -418,7 +418,9 @@ def bench_terminator(ob, n_held, n_steps=512, train_epochs=5):
     import synth
     from paper_1601_07728_amd import terminator as term
     from paper_1601_07728_amd import train_terminator as tt
-    seeds = list(tt.HELD_OUT)[:n_held]
+    seeds = list(tt.HELD_OUT)[:n_held] if seeds is None else list(seeds)
+    if set(seeds) & set(range(1, tt.TRAIN_SYSTEMS + 1)):
+        raise ValueError("held-out terminator seeds overlap the training systems")
     d = term.generate(seeds, n_steps=n_steps, log=log)
     per_sys = d["seconds"] / len(seeds)
     log(f"terminator: {len(seeds)} held-out systems x 3 polarisations x {n_steps} steps in {d['seconds']:.1f} s "
@@ -427,7 +429,8 @@ def bench_terminator(ob, n_held, n_steps=512, train_epochs=5):
     omegas = [synth.terminator_omega(int(s_)) for s_ in d["seeds"]]
     gam = 0.5 / synth.HARTREE_EV
     ref = term.reference_spectra(a, b, n2, omegas, gam, n_used=sd)
-    out = {"held_out_systems": len(seeds), "held_out_sequences": int(a.shape[0]), "steps": n_steps,
+    out = {"held_out_systems": len(seeds), "held_out_seeds": [min(seeds), max(seeds)],
+           "held_out_sequences": int(a.shape[0]), "steps": n_steps,
            "shape": "SrTiO3-shaped L2,3 edge at full size: 8^3 k, 20^3 x, 96 bands, eps U[2,10], width U[20,60] eV",
            "generation_s_per_system": per_sys,
            "generation_s_projected_4096_sequences": per_sys * 4096 / 3, "networks": []}
@@ -527,6 +530,9 @@ def main():
                     help="also run the molecule-in-box batch with BF16 projections (off by default: one "
                          "full run ended in a host segmentation fault there, cause not found)")
     ap.add_argument("--term-held-out", type=int, default=32, help="held-out terminator systems (3 sequences each)")
+    ap.add_argument("--term-seeds", default=None,
+                    help="held-out terminator systems as FIRST-LAST seeds (default: the first --term-held-out "
+                         "of the seeds after the training systems), e.g. 3841-4096")
     ap.add_argument("--no-terminator", action="store_true")
     ap.add_argument("--no-spectra", action="store_true")
     ap.add_argument("--no-full-spin", action="store_true")
@@ -689,7 +695,11 @@ def main():
 
     terminator = None
     if not args.no_terminator:
-        mlps, terminator = bench_terminator(ob, args.term_held_out)
+        tseeds = None
+        if args.term_seeds:
+            lo, hi = (int(v) for v in args.term_seeds.split("-"))
+            tseeds = range(lo, hi + 1)
+        mlps, terminator = bench_terminator(ob, args.term_held_out, seeds=tseeds)
         if not args.no_spectra:
             terminator["srtio3_spectra_gain"] = spectra_gain(ob, cr, hs, psi0, mlps, gold)
         for m in mlps.values():
