@@ -669,10 +669,10 @@ def main():
             "proj_fwd": proj_bytes(cr, cols, U_BYTES[name], PHI_BYTES[name]) / (avgs[name]["proj_fwd"] * 1e6),
             "proj_bwd": proj_bytes(cr, cols, U_BYTES[name], PHI_BYTES[name]) / (avgs[name]["proj_bwd"] * 1e6),
             "fft_w": fft_bytes(cr, cols, PHI_BYTES[name]) / (avgs[name]["fft_w"] * 1e6)}
-        fft_mode = "fp64" if name == "fp64" else "fp32"   # every mixed mode runs the FP32 transform
+        # each mode's own transform entry (the BF16 mode stores phi as bf16 pairs)
         results[name]["traffic_bytes"] = {"proj_fwd": kernel_traffic(name, "proj_fwd"),
                                           "proj_bwd": kernel_traffic(name, "proj_bwd"),
-                                          "fft_w": kernel_traffic(fft_mode, "fft_w")}
+                                          "fft_w": kernel_traffic(name, "fft_w")}
     avg = avgs["fp64"]
     dom = max(("proj_fwd", "proj_bwd"), key=lambda k: avg.get(k, 0.0))
     ach = proj_bytes(cr, cols, 16, 16) / (avg[dom] * 1e-3) / 1e9
