@@ -998,7 +998,7 @@ int ocean_haydock_batch(const ocean_bse_t* hs, int n_sys, const double* const* p
 }
 
 // Cache lines carry this tag: choices written by another version of the kernels are not reused.
-static constexpr const char* kTuneCacheVersion = "ocean-tune-v4";
+static constexpr const char* kTuneCacheVersion = "ocean-tune-v5";
 
 // A cached choice is applied only if every knob is one the tuner itself could have picked for
 // this handle (a stale or hand-edited line is ignored and the shape is tuned again).

@@ -103,11 +103,11 @@ def test_terminator_systems_fullsize_prefix():
         h.close()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("bf16", 1e-2)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-5), ("bf16", 1e-2)])
 def test_every_tuning_candidate_gives_the_same_result(tmp_path, monkeypatch, precision, tol):
     """Each tile choice the autotuner can make (rows per forward wave, back-projection grid
     target, lines per transform block), forced through the cache file: H*v against the oracle,
-    and in FP64 every choice within rounding of every other."""
+    and in FP64 every choice within rounding of every other; FP64, FP32 and BF16."""
     import torch
 
     import paper_1601_07728_amd as ob
@@ -115,8 +115,8 @@ def test_every_tuning_candidate_gives_the_same_result(tmp_path, monkeypatch, pre
     hc, kl = omp.core_matrix(cr.multiplet), omp.local_matrix(cr.multiplet)
     x = synth.complex_gaussian(np.random.default_rng(5), (3, cr.n_k, cr.n_bands, cr.n_core))
     refs = [orc.apply_h(cr, x[v], hc, kl) for v in range(3)]
-    prec_id = {"fp64": ob.PREC_FP64, "bf16": ob.PREC_BF16}[precision]
-    key = (f"ocean-tune-v4 nk=4,4,4 nx=10,9,8 nb={cr.n_bands} nc={cr.n_core} nmu=5 prec={prec_id} "
+    prec_id = {"fp64": ob.PREC_FP64, "fp32": ob.PREC_FP32, "bf16": ob.PREC_BF16}[precision]
+    key = (f"ocean-tune-v5 nk=4,4,4 nx=10,9,8 nb={cr.n_bands} nc={cr.n_core} nmu=5 prec={prec_id} "
            f"cols={3 * cr.n_core}")
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("OCEAN_AUTOTUNE_CACHE", str(cache))
@@ -124,7 +124,8 @@ def test_every_tuning_candidate_gives_the_same_result(tmp_path, monkeypatch, pre
     first = None
     # the resident-operand forward (fwd_tiles > 0) with the chunked one's other knobs held
     fwd = [(ms, 0) for ms in ((1, 2, 4) if precision == "bf16" else (1, 2))]
-    if precision == "fp64":
+    if precision in ("fp64", "fp32"):
+        # (FP32: the band-chunked forms, MS = 1 and 2, run the 4x4x1 remainder of the 18 columns)
         fwd += [(1, ft) for ft in (4, 8, 16, 32)]
     else:
         fwd += [(ms, ft) for ms, ft in ((1, 4), (2, 8), (4, 32))]   # the resident bf16 forward

@@ -86,7 +86,7 @@ def test_corrupt_autotune_cache_line_is_tuned_again(monkeypatch, tmp_path, bad):
     h = ob.Bse.from_crystal(cr, precision="fp64")
     p0 = h.dipole_psi0(np.eye(3))
     y0 = h.apply(p0).cpu().numpy()
-    key = f"ocean-tune-v4 nk=2,2,2 nx=6,5,6 nb=13 nc=6 nmu=5 prec=0 cols={3 * cr.n_core}"
+    key = f"ocean-tune-v5 nk=2,2,2 nx=6,5,6 nb=13 nc=6 nmu=5 prec=0 cols={3 * cr.n_core}"
     cache = tmp_path / "tune.txt"
     cache.write_text(f"{key}|{bad}\n")
     monkeypatch.setenv("OCEAN_AUTOTUNE_CACHE", str(cache))
