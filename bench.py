@@ -608,6 +608,17 @@ def main():
             timed_haydock(hf, pf, args.warmup)
             dt, _ = timed_haydock(hf, pf, args.steps)
             full_spin[name] = {"ms_per_step": 1e3 * dt / args.steps, "hv_per_s": n_pol * args.steps / dt}
+            if name == "fp64":
+                # the wide FP64 pass (36 columns in one stream of u): its matrix-core rate
+                hf.set_profiling(True)
+                hf.haydock(pf, args.steps)
+                kt = hf.kernel_times()
+                hf.set_profiling(False)
+                km = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
+                fl = proj_flops(crf, n_pol * crf.n_core)
+                full_spin[name]["kernel_ms"] = {k: round(km[k], 4) for k in ("proj_fwd", "proj_bwd", "fft_w") if k in km}
+                full_spin[name]["proj_mfma_fp64_frac"] = {k: fl / (km[k] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS
+                                                          for k in ("proj_fwd", "proj_bwd")}
             log(f"full spin {name}: {full_spin[name]['ms_per_step']:.3f} ms/step, "
                 f"{full_spin[name]['hv_per_s']:.1f} H*v/s")
             hf.close()
