@@ -549,7 +549,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); independent solves "
-              "or x-slabs would shard across GPUs, which this build does not run", file=sys.stderr)
+              "or x-slabs would shard across GPUs; the library runs on one GPU", file=sys.stderr)
         sys.exit(2)
 
     import torch

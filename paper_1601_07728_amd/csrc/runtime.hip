@@ -394,7 +394,7 @@ static int create_impl(const ocean_bse_desc* d, void* stream, ocean_bse_t* out) 
         return OCEAN_ERR_INVALID_ARG;
     }
     if (d->precision < OCEAN_PREC_FP64 || d->precision > OCEAN_PREC_BF16) {
-        set_error("ocean_bse_create: precision not supported by this build");
+        set_error("ocean_bse_create: precision not supported by this library");
         return OCEAN_ERR_UNSUPPORTED;
     }
     // radial grid: uniform from 0
