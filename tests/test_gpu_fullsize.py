@@ -28,10 +28,12 @@ def full():
     u = synth.gpu_orthonormal_u(cr.n_k, cr.n_x, cr.n_bands, seed=1000)
     torch.cuda.synchronize()
     h64 = ob.Bse.from_crystal(cr, precision="fp64", u=u)
+    _say(f"[fullsize] fp64 tuned {h64.autotune(n_vec=3)}")   # the tiles the benchmark times
     psi0 = h64.dipole_psi0(np.eye(3))
     y64 = h64.apply(psi0).cpu().numpy()
     a, b, n2, sd, _ = h64.haydock(psi0, 2)
     h32 = ob.Bse.from_crystal(cr, precision="fp32", u=u)
+    _say(f"[fullsize] fp32 tuned {h32.autotune(n_vec=3)}")
     y32 = h32.apply(psi0).cpu().numpy()
     h32.close()
     h64.close()

@@ -67,6 +67,7 @@ def test_fp64_coefficients_and_spectra_match_the_oracle(c2):
     n_steps = ga.shape[1]
     assert np.allclose(gom, c2.omega, rtol=0, atol=1e-15)
     h = ob.Bse.from_crystal(c2, precision="fp64")
+    _say(f"[golden c2] FP64 tuned {h.autotune(n_vec=3)}")   # the tiles the benchmark times
     psi0 = h.dipole_psi0(np.eye(3))
     a, b, n2, sd, rc = h.haydock(psi0, n_steps, reorth=True)
     h.close()
@@ -96,6 +97,7 @@ def test_reduced_precision_spectra_within_1e_3_of_the_oracle(c2, precision):
     _, _, _, _, gsig = _golden()
     n_steps = 300
     h = ob.Bse.from_crystal(c2, precision=precision)
+    _say(f"[golden c2] {precision} tuned {h.autotune(n_vec=3)}")
     psi0 = h.dipole_psi0(np.eye(3))
     a, b, n2, sd, _ = h.haydock(psi0, n_steps)
     sig = ob.spectrum(a, b, n2, c2.omega, c2.gamma, n_used=sd)
